@@ -1,0 +1,475 @@
+"""ctypes binding of the CPU oracle (test infrastructure only).
+
+The oracle defines what the GPU hot path must compute: FP64 arithmetic,
+exact combinatorial predicates with symbolic tie-breaking, the paper's steps
+in the paper's order.  Only the test-suite, the smoke check and the CPU
+baseline of the benchmark may import this module; the product library never
+does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liborc.so")
+SOURCES = ["orc_exact.c", "orc_grid.c", "orc_mesh.c", "orc_step.c"]
+
+CAT_OUTER, CAT_INNER, CAT_BOUNDARY = 0, 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile liborc.so with gcc (-O2, no FP contraction, OpenMP)."""
+    srcs = [os.path.join(HERE, s) for s in SOURCES]
+    hdrs = [os.path.join(HERE, h) for h in ("orc.h", "orc_internal.h")]
+    if not force and os.path.exists(LIB):
+        t = os.path.getmtime(LIB)
+        if all(os.path.getmtime(s) <= t for s in srcs + hdrs):
+            return LIB
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+           "-shared", "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class Prim(C.Structure):
+    _fields_ = [("op", C.c_int32), ("kind", C.c_int32), ("p", C.c_double * 6),
+                ("voff", C.c_int32), ("nv", C.c_int32)]
+
+
+class Sizing(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("a0", C.c_double), ("a1", C.c_double), ("s2", C.c_double),
+                ("ncent", C.c_int32), ("cent", C.POINTER(C.c_double)), ("nholes", C.c_int32),
+                ("holes", C.POINTER(C.c_int32))]
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("x0", C.c_double), ("y0", C.c_double),
+                ("dx", C.c_double), ("dy", C.c_double), ("inv_dx", C.c_double),
+                ("inv_dy", C.c_double), ("sdf", C.POINTER(C.c_double)),
+                ("mu", C.POINTER(C.c_double)), ("cat", C.POINTER(C.c_uint8)),
+                ("hcell", C.POINTER(C.c_float)), ("h_avg", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [("fac_F", C.c_double), ("fac_voro", C.c_double), ("fac_pt", C.c_double),
+                ("fac_retria", C.c_double), ("fac_end", C.c_double), ("fac_geps", C.c_double),
+                ("T_tria", C.c_double), ("alpha_hat", C.c_double), ("T_newton", C.c_int32),
+                ("k_spring", C.c_double), ("dt", C.c_double), ("cvd_max_level", C.c_int32),
+                ("trace_max_steps", C.c_int32), ("trace_bisect", C.c_int32),
+                ("test2_mode", C.c_int32)]
+
+
+COUNTER_NAMES = ["candidates", "clip_tests", "cuts", "exact_calls", "sos_calls", "quad_points",
+                 "level_cap_hits", "newton_fail", "trace_fail", "empty_cells"]
+
+
+class Counters(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in COUNTER_NAMES]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n in COUNTER_NAMES}
+
+
+class Stats(C.Structure):
+    _fields_ = [("ntri", C.c_int64), ("min_q", C.c_double), ("mean_q", C.c_double),
+                ("half_mean_alpha", C.c_double), ("half_mean_beta", C.c_double),
+                ("max_alpha", C.c_double), ("hist_beta", C.c_double * 40)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB)
+        dp, fp, u8p, i32p, i64p = (C.POINTER(C.c_double), C.POINTER(C.c_float), C.POINTER(C.c_uint8),
+                                   C.POINTER(C.c_int32), C.POINTER(C.c_int64))
+        L.orc_default_params.argtypes = [C.POINTER(Params)]
+        L.orc_grid_build.argtypes = [C.POINTER(Prim), C.c_int32, dp, C.POINTER(Sizing), C.c_int32,
+                                     C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
+                                     C.c_int32, C.c_int64, dp, dp, u8p, fp, dp, dp]
+        L.orc_sdf_eval.argtypes = [C.POINTER(Prim), C.c_int32, dp, C.c_double, C.c_double]
+        L.orc_sdf_eval.restype = C.c_double
+        L.orc_grid_init.argtypes = [C.POINTER(Grid), C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                    C.c_double, C.c_double, dp, dp, u8p, fp, C.c_double]
+        L.orc_cells_all.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int64, dp, dp, i32p, i32p,
+                                    C.c_int, C.c_int, C.POINTER(Counters)]
+        L.orc_cells_all_pairs.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int64, dp, dp, i32p,
+                                          i32p, C.c_int]
+        L.orc_cell.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int64, dp, dp, C.c_int64, i32p,
+                               dp, dp, C.c_int, C.POINTER(Counters)]
+        L.orc_triangulate.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int64, dp, dp, i32p, u8p,
+                                      C.c_int64, i64p, i64p, i32p, C.c_int64, i64p, C.c_int,
+                                      C.POINTER(Counters)]
+        L.orc_triangle_valid.argtypes = [C.POINTER(Grid), C.POINTER(Params), dp, dp, C.c_int32,
+                                         C.c_int32, C.c_int32]
+        L.orc_fac_mu.argtypes = [C.POINTER(Grid), C.c_int64, dp, dp, i64p, i32p, dp, dp]
+        L.orc_fac_mu.restype = C.c_double
+        L.orc_dm_step.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int64, dp, dp, u8p, i64p, i32p,
+                                  dp, dp, dp, dp, u8p, dp, C.POINTER(Counters)]
+        L.orc_dm_step.restype = C.c_int64
+        L.orc_cvd_step.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int64, dp, dp, u8p, dp, dp, dp,
+                                   u8p, dp, i32p, C.c_int, C.POINTER(Counters)]
+        L.orc_cvd_centroid.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int64, dp, dp, C.c_int64,
+                                       C.c_double, dp, dp, dp, C.POINTER(Counters)]
+        L.orc_treat.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_double, C.c_double, C.c_uint8,
+                                C.c_double, C.c_double, dp, dp, u8p, C.POINTER(Counters)]
+        L.orc_point_category.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_double, C.c_double]
+        L.orc_point_category.restype = C.c_uint8
+        L.orc_quality.argtypes = [dp, dp, i32p, u8p, C.c_int64, C.POINTER(Stats)]
+        L.orc_triangle_quality.argtypes = [C.c_double] * 6 + [dp, dp]
+        L.orc_predicate.argtypes = [C.POINTER(Grid), C.POINTER(Params), dp, dp, C.c_int64, C.c_int32,
+                                    C.c_int32, C.c_int32, C.POINTER(C.c_int)]
+        L.orc_incircle_sign.argtypes = [C.c_double] * 8
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().orc_default_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@dataclass
+class OracleGrid:
+    """Grid arrays (float64 copies of the node values) and the C view."""
+    nx: int
+    ny: int
+    x0: float
+    y0: float
+    dx: float
+    dy: float
+    sdf: np.ndarray
+    mu: np.ndarray
+    cat: np.ndarray
+    hcell: np.ndarray
+    h_avg: float
+    H: float = 0.0
+
+    def c(self) -> Grid:
+        g = Grid()
+        self._keep = [np.ascontiguousarray(self.sdf, np.float64), np.ascontiguousarray(self.mu, np.float64),
+                      np.ascontiguousarray(self.cat, np.uint8), np.ascontiguousarray(self.hcell, np.float32)]
+        s, m, ca, h = self._keep
+        lib().orc_grid_init(C.byref(g), self.nx, self.ny, self.x0, self.y0, self.dx, self.dy,
+                            _p(s, C.c_double), _p(m, C.c_double), _p(ca, C.c_uint8), _p(h, C.c_float),
+                            self.h_avg)
+        return g
+
+
+def _geometry(wl):
+    poly, offs = wl.poly_array()
+    prims = (Prim * max(len(wl.prims), 1))()
+    for k, pr in enumerate(wl.prims):
+        prims[k].op = pr.op
+        prims[k].kind = pr.kind
+        for t, v in enumerate(pr.p):
+            prims[k].p[t] = float(v)
+        prims[k].voff, prims[k].nv = offs[k]
+    sz = Sizing()
+    s = wl.sizing
+    sz.kind, sz.a0, sz.a1, sz.s2 = s.kind, s.a0, s.a1, s.s2
+    cent = np.ascontiguousarray(np.asarray(s.cent, np.float64).reshape(-1))
+    holes = np.ascontiguousarray(np.asarray(s.holes, np.int32))
+    sz.ncent = len(cent) // 2
+    sz.cent = _p(cent, C.c_double)
+    sz.nholes = len(holes)
+    sz.holes = _p(holes, C.c_int32)
+    keep = (poly, cent, holes)
+    return prims, sz, poly, keep
+
+
+def build_grid(wl) -> OracleGrid:
+    g = wl.grid
+    prims, sz, poly, keep = _geometry(wl)
+    nn = g.nx * g.ny
+    sdf = np.empty(nn, np.float64)
+    mu = np.empty(nn, np.float64)
+    cat = np.empty((g.nx - 1) * (g.ny - 1), np.uint8)
+    hcell = np.empty((g.nx - 1) * (g.ny - 1), np.float32)
+    h_avg = C.c_double()
+    H = C.c_double()
+    rc = lib().orc_grid_build(prims, len(wl.prims), _p(poly, C.c_double), C.byref(sz), g.nx, g.ny, g.x0,
+                              g.y0, g.dx, g.dy, g.dtype_bytes, wl.n, _p(sdf, C.c_double),
+                              _p(mu, C.c_double), _p(cat, C.c_uint8), _p(hcell, C.c_float),
+                              C.byref(h_avg), C.byref(H))
+    if rc != 0:
+        raise RuntimeError("oracle grid build failed")
+    return OracleGrid(g.nx, g.ny, g.x0, g.y0, g.dx, g.dy, sdf, mu, cat, hcell, h_avg.value, H.value)
+
+
+def grid_from_arrays(spec, sdf, mu, cat, hcell, h_avg) -> OracleGrid:
+    """Oracle view of grid arrays produced elsewhere (the shared input)."""
+    return OracleGrid(spec.nx, spec.ny, spec.x0, spec.y0, spec.dx, spec.dy,
+                      np.asarray(sdf, np.float64).reshape(-1), np.asarray(mu, np.float64).reshape(-1),
+                      np.asarray(cat, np.uint8).reshape(-1), np.asarray(hcell, np.float32).reshape(-1),
+                      float(h_avg))
+
+
+def sdf_eval(wl, x, y) -> float:
+    prims, sz, poly, keep = _geometry(wl)
+    return lib().orc_sdf_eval(prims, len(wl.prims), _p(poly, C.c_double), float(x), float(y))
+
+
+def cells(grid: OracleGrid, x, y, cap=64, all_pairs=False, nthreads=1, params=None):
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    n = len(x)
+    cons = np.zeros((n, cap), np.int32)
+    ncons = np.zeros(n, np.int32)
+    g = grid.c()
+    prm = params or default_params()
+    cnt = Counters()
+    if all_pairs:
+        rc = lib().orc_cells_all_pairs(C.byref(g), C.byref(prm), n, _p(x, C.c_double), _p(y, C.c_double),
+                                       _p(cons, C.c_int32), _p(ncons, C.c_int32), cap)
+    else:
+        rc = lib().orc_cells_all(C.byref(g), C.byref(prm), n, _p(x, C.c_double), _p(y, C.c_double),
+                                 _p(cons, C.c_int32), _p(ncons, C.c_int32), cap, nthreads, C.byref(cnt))
+    if rc != 0:
+        raise RuntimeError("oracle cells failed")
+    return [tuple(cons[i, :ncons[i]]) for i in range(n)], cnt.as_dict()
+
+
+def cell(grid: OracleGrid, x, y, i, params=None):
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    cons = np.zeros(256, np.int32)
+    vx = np.zeros(256)
+    vy = np.zeros(256)
+    g = grid.c()
+    prm = params or default_params()
+    m = lib().orc_cell(C.byref(g), C.byref(prm), len(x), _p(x, C.c_double), _p(y, C.c_double), i,
+                       _p(cons, C.c_int32), _p(vx, C.c_double), _p(vy, C.c_double), 256, None)
+    if m < 0:
+        raise RuntimeError("oracle cell failed")
+    return cons[:m].copy(), vx[:m].copy(), vy[:m].copy()
+
+
+@dataclass
+class Mesh:
+    tri: np.ndarray     # (T, 3) owned triangles, CCW, owner first
+    valid: np.ndarray   # (T,) uint8
+    rowptr: np.ndarray  # (n+1,) int64
+    col: np.ndarray     # adjacency of valid triangles, rows sorted
+    counters: dict
+
+    def valid_tri(self):
+        return self.tri[self.valid.astype(bool)]
+
+
+def triangulate(grid: OracleGrid, x, y, nthreads=1, params=None) -> Mesh:
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    n = len(x)
+    g = grid.c()
+    prm = params or default_params()
+    tcap = 4 * n + 64
+    acap = 12 * n + 64
+    for _ in range(2):
+        tri = np.zeros((tcap, 3), np.int32)
+        valid = np.zeros(tcap, np.uint8)
+        rowptr = np.zeros(n + 1, np.int64)
+        col = np.zeros(acap, np.int32)
+        nt = C.c_int64()
+        na = C.c_int64()
+        cnt = Counters()
+        rc = lib().orc_triangulate(C.byref(g), C.byref(prm), n, _p(x, C.c_double), _p(y, C.c_double),
+                                   _p(tri, C.c_int32), _p(valid, C.c_uint8), tcap, C.byref(nt),
+                                   _p(rowptr, C.c_int64), _p(col, C.c_int32), acap, C.byref(na), nthreads,
+                                   C.byref(cnt))
+        if rc == 0:
+            return Mesh(tri[:nt.value].copy(), valid[:nt.value].copy(), rowptr, col[:na.value].copy(),
+                        cnt.as_dict())
+        if rc == -1:
+            tcap = max(tcap, nt.value)
+            acap = max(acap, na.value)
+            continue
+        raise RuntimeError("oracle triangulate failed (%d)" % rc)
+    raise RuntimeError("oracle triangulate: capacity")
+
+
+def triangle_valid(grid: OracleGrid, x, y, a, b, c, params=None) -> int:
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    g = grid.c()
+    prm = params or default_params()
+    return lib().orc_triangle_valid(C.byref(g), C.byref(prm), _p(x, C.c_double), _p(y, C.c_double), a, b, c)
+
+
+def point_categories(grid: OracleGrid, x, y, params=None) -> np.ndarray:
+    g = grid.c()
+    prm = params or default_params()
+    return np.array([lib().orc_point_category(C.byref(g), C.byref(prm), float(a), float(b))
+                     for a, b in zip(x, y)], np.uint8)
+
+
+def fac_mu(grid: OracleGrid, x, y, mesh: Mesh):
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    g = grid.c()
+    sl = C.c_double()
+    sm = C.c_double()
+    f = lib().orc_fac_mu(C.byref(g), len(x), _p(x, C.c_double), _p(y, C.c_double),
+                         _p(mesh.rowptr, C.c_int64), _p(mesh.col, C.c_int32), C.byref(sl), C.byref(sm))
+    return f, sl.value, sm.value
+
+
+def dm_step(grid: OracleGrid, x, y, cat, mesh: Mesh, xl=None, yl=None, params=None):
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    cat = np.ascontiguousarray(cat, np.uint8)
+    n = len(x)
+    xn = np.empty(n)
+    yn = np.empty(n)
+    cn = np.empty(n, np.uint8)
+    xl = np.ascontiguousarray(x if xl is None else xl, np.float64)
+    yl = np.ascontiguousarray(y if yl is None else yl, np.float64)
+    g = grid.c()
+    prm = params or default_params()
+    fm = C.c_double()
+    cnt = Counters()
+    moved = lib().orc_dm_step(C.byref(g), C.byref(prm), n, _p(x, C.c_double), _p(y, C.c_double),
+                              _p(cat, C.c_uint8), _p(mesh.rowptr, C.c_int64), _p(mesh.col, C.c_int32),
+                              _p(xl, C.c_double), _p(yl, C.c_double), _p(xn, C.c_double), _p(yn, C.c_double),
+                              _p(cn, C.c_uint8), C.byref(fm), C.byref(cnt))
+    return xn, yn, cn, int(moved), fm.value, cnt.as_dict()
+
+
+def cvd_step(grid: OracleGrid, x, y, cat, dprev, nthreads=1, params=None):
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    cat = np.ascontiguousarray(cat, np.uint8)
+    dprev = np.ascontiguousarray(dprev, np.float64)
+    n = len(x)
+    xn = np.empty(n)
+    yn = np.empty(n)
+    cn = np.empty(n, np.uint8)
+    dn = np.empty(n)
+    lev = np.empty(n, np.int32)
+    g = grid.c()
+    prm = params or default_params()
+    cnt = Counters()
+    lib().orc_cvd_step(C.byref(g), C.byref(prm), n, _p(x, C.c_double), _p(y, C.c_double), _p(cat, C.c_uint8),
+                       _p(dprev, C.c_double), _p(xn, C.c_double), _p(yn, C.c_double), _p(cn, C.c_uint8),
+                       _p(dn, C.c_double), _p(lev, C.c_int32), nthreads, C.byref(cnt))
+    return xn, yn, cn, dn, lev, cnt.as_dict()
+
+
+def cvd_centroid(grid: OracleGrid, x, y, i, dprev=-1.0, params=None):
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    g = grid.c()
+    prm = params or default_params()
+    cx = C.c_double()
+    cy = C.c_double()
+    a = C.c_double()
+    L = lib().orc_cvd_centroid(C.byref(g), C.byref(prm), len(x), _p(x, C.c_double), _p(y, C.c_double), i,
+                               dprev, C.byref(cx), C.byref(cy), C.byref(a), None)
+    return cx.value, cy.value, a.value, L
+
+
+def treat(grid: OracleGrid, xo, yo, cat_old, xn, yn, params=None):
+    g = grid.c()
+    prm = params or default_params()
+    xf = C.c_double()
+    yf = C.c_double()
+    cf = C.c_uint8()
+    lib().orc_treat(C.byref(g), C.byref(prm), xo, yo, cat_old, xn, yn, C.byref(xf), C.byref(yf), C.byref(cf),
+                    None)
+    return xf.value, yf.value, cf.value
+
+
+def quality(x, y, tri, valid=None) -> dict:
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    tri = np.ascontiguousarray(tri, np.int32)
+    st = Stats()
+    vp = _p(np.ascontiguousarray(valid, np.uint8), C.c_uint8) if valid is not None else None
+    lib().orc_quality(_p(x, C.c_double), _p(y, C.c_double), _p(tri, C.c_int32), vp, len(tri), C.byref(st))
+    return {"ntri": st.ntri, "min_q": st.min_q, "mean_q": st.mean_q, "half_mean_alpha": st.half_mean_alpha,
+            "half_mean_beta": st.half_mean_beta, "max_alpha": st.max_alpha,
+            "hist_beta": np.array(st.hist_beta[:])}
+
+
+def triangle_quality(a, b, c):
+    al = C.c_double()
+    be = C.c_double()
+    lib().orc_triangle_quality(a[0], a[1], b[0], b[1], c[0], c[1], C.byref(al), C.byref(be))
+    return al.value, be.value
+
+
+def predicate(grid: OracleGrid, x, y, i, c1, c2, c3, params=None):
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    g = grid.c()
+    prm = params or default_params()
+    ue = C.c_int(0)
+    s = lib().orc_predicate(C.byref(g), C.byref(prm), _p(x, C.c_double), _p(y, C.c_double), i, c1, c2, c3,
+                            C.byref(ue))
+    return s, ue.value
+
+
+def incircle_sign(a, b, c, d) -> int:
+    return lib().orc_incircle_sign(a[0], a[1], b[0], b[1], c[0], c[1], d[0], d[1])
+
+
+def initial_categories(grid: OracleGrid, x, y, params=None) -> np.ndarray:
+    """Initial point categories (Sec. 3.5): inner cell -> inner; boundary cell
+    -> boundary when |sdf| <= geps, else inner."""
+    return point_categories(grid, x, y, params)
+
+
+def run(grid: OracleGrid, x, y, schedule, params=None, nthreads=1, retriangulate="flag"):
+    """Full run of a fixed schedule [("dm"|"cvd", iters), ...] (Alg. 1, Alg. 2).
+
+    DistMesh triangulates on the first iteration of a segment and then only
+    when the previous iteration moved a point more than fac_retria*h since the
+    last triangulation (retriangulate="flag"), or every iteration ("always").
+    Returns final positions, categories, the last mesh and per-iteration info.
+    """
+    prm = params or default_params()
+    x = np.array(x, np.float64)
+    y = np.array(y, np.float64)
+    cat = initial_categories(grid, x, y, prm)
+    dprev = np.full(len(x), -1.0)
+    info = []
+    mesh = None
+    for method, iters in schedule:
+        retri = True
+        xl, yl = x.copy(), y.copy()
+        for _ in range(iters):
+            if method == "dm":
+                if retri or retriangulate == "always" or mesh is None:
+                    mesh = triangulate(grid, x, y, nthreads, prm)
+                    xl, yl = x.copy(), y.copy()
+                    tri_now = True
+                else:
+                    tri_now = False
+                xn, yn, cn, moved, fm, _ = dm_step(grid, x, y, cat, mesh, xl, yl, prm)
+                retri = moved > 0
+                dn = np.hypot(xn - x, yn - y)
+                info.append({"method": "dm", "triangulated": tri_now, "moved": moved, "fac_mu": fm})
+            else:
+                mesh = triangulate(grid, x, y, nthreads, prm)
+                xn, yn, cn, dn, lev, _ = cvd_step(grid, x, y, cat, dprev, nthreads, prm)
+                info.append({"method": "cvd", "triangulated": True, "max_level": int(lev.max()) if len(lev) else 0})
+            x, y, cat, dprev = xn, yn, cn, dn
+    final = triangulate(grid, x, y, nthreads, prm)
+    return x, y, cat, final, info

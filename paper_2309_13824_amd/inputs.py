@@ -1,0 +1,299 @@
+"""Seeded synthetic workloads for the mesher hot path.
+
+This module only describes inputs: the geometry (a CSG list of analytic
+primitives), the sizing/density field, the node grid that carries them and
+the initial point positions.  It holds none of the meshing arithmetic; both
+the GPU library and the CPU oracle receive the same description and the same
+initial point array.
+
+Workloads (the paper meshes its own shapes at N = 1e4..1e7, Sec. 7; these
+stand in for them with holes and strong density variation):
+
+* ``disk``      unit disk, uniform sizing, 2,000 points, 256^2 grid (FP64),
+                50 DistMesh iterations.
+* ``annulus``   annulus 0.3 <= |x| <= 1 minus 3 disks, mu = 1 + 2|sdf|,
+                1e5 points, 1024^2 grid, 30 CVD then 70 DistMesh iterations.
+* ``holes20``   unit square minus 20 disks, rho = 1 + 4 sum_k exp(-|x-c_k|^2/0.01)
+                over 5 centres, 1e6 points, 4096^2 grid, 100 CVD iterations.
+* ``ellipses``  unit square minus 200 ellipses, mu = 1 + 9 min(d_H/0.1, 1),
+                1e7 points, 8192^2 grid, 70 DistMesh then 30 CVD iterations.
+* ``stars``     512 star polygons on 512^2 grids each, log-uniform point counts.
+
+Grids are vertex-centred; spacings and origins are dyadic rationals so that
+node coordinates are exact.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# CSG operations and primitive kinds (shared numbering of the input format)
+OP_INIT, OP_UNION, OP_DIFF, OP_INTERSECT = 0, 1, 2, 3
+PRIM_DISK, PRIM_BOX, PRIM_ELLIPSE, PRIM_POLYGON = 0, 1, 2, 3
+SZ_UNIFORM, SZ_ABS_SDF, SZ_GAUSS_RHO, SZ_HOLE_RAMP = 0, 1, 2, 3
+
+
+@dataclass
+class Prim:
+    op: int
+    kind: int
+    p: tuple = ()
+    poly: np.ndarray | None = None  # (nv, 2) for polygons
+
+
+@dataclass
+class Sizing:
+    kind: int = SZ_UNIFORM
+    a0: float = 0.0
+    a1: float = 0.0
+    s2: float = 1.0
+    cent: np.ndarray = field(default_factory=lambda: np.zeros((0, 2)))
+    holes: list = field(default_factory=list)
+
+
+@dataclass
+class GridSpec:
+    nx: int
+    ny: int
+    x0: float
+    y0: float
+    dx: float
+    dy: float
+    dtype_bytes: int  # 8: float64 nodes, 4: float32 nodes
+
+
+@dataclass
+class Workload:
+    name: str
+    prims: list
+    sizing: Sizing
+    grid: GridSpec
+    n: int
+    schedule: list  # [("dm"|"cvd", iterations), ...]
+    seed: int
+    x: np.ndarray | None = None
+    y: np.ndarray | None = None
+
+    def poly_array(self):
+        """Concatenated polygon vertices and (voff, nv) per primitive."""
+        verts, offs = [], []
+        off = 0
+        for p in self.prims:
+            if p.kind == PRIM_POLYGON:
+                offs.append((off, len(p.poly)))
+                verts.append(np.asarray(p.poly, dtype=np.float64))
+                off += len(p.poly)
+            else:
+                offs.append((0, 0))
+        arr = np.concatenate(verts) if verts else np.zeros((0, 2))
+        return np.ascontiguousarray(arr, dtype=np.float64), offs
+
+
+def centred_grid(n: int, span_num: int, span_log2: int, centre: float, dtype_bytes: int) -> GridSpec:
+    """n x n nodes with spacing span_num * 2^-span_log2, centred (dyadic)."""
+    d = span_num * 2.0 ** (-span_log2)
+    x0 = centre - (n - 1) * d / 2.0
+    return GridSpec(n, n, x0, x0, d, d, dtype_bytes)
+
+
+# ---------------------------------------------------------------- sampling --
+# Inside tests and densities below are the workload definitions evaluated for
+# drawing initial points only.
+
+def _inside(wl: Workload, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    ins = None
+    for p in wl.prims:
+        if p.kind == PRIM_DISK:
+            t = (x - p.p[0]) ** 2 + (y - p.p[1]) ** 2 < p.p[2] ** 2
+        elif p.kind == PRIM_BOX:
+            t = (x > p.p[0]) & (x < p.p[2]) & (y > p.p[1]) & (y < p.p[3])
+        elif p.kind == PRIM_ELLIPSE:
+            c, s = math.cos(p.p[4]), math.sin(p.p[4])
+            u = c * (x - p.p[0]) + s * (y - p.p[1])
+            v = -s * (x - p.p[0]) + c * (y - p.p[1])
+            t = (u / p.p[2]) ** 2 + (v / p.p[3]) ** 2 < 1.0
+        else:
+            from matplotlib.path import Path  # pragma: no cover
+            t = Path(p.poly).contains_points(np.stack([x, y], 1))
+        if p.op == OP_INIT:
+            ins = t
+        elif p.op == OP_UNION:
+            ins = ins | t
+        elif p.op == OP_DIFF:
+            ins = ins & ~t
+        else:
+            ins = ins & t
+    return ins
+
+
+def _weight(wl: Workload, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Sampling weight proportional to the target point density."""
+    sz = wl.sizing
+    if sz.kind == SZ_UNIFORM:
+        return np.ones_like(x)
+    if sz.kind == SZ_GAUSS_RHO:
+        acc = np.zeros_like(x)
+        for cx, cy in sz.cent:
+            acc += np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / sz.s2)
+        return sz.a0 + sz.a1 * acc
+    if sz.kind == SZ_ABS_SDF:
+        # distance to the nearest boundary of the disks making the shape
+        d = np.full_like(x, np.inf)
+        for p in wl.prims:
+            if p.kind == PRIM_DISK:
+                d = np.minimum(d, np.abs(np.hypot(x - p.p[0], y - p.p[1]) - p.p[2]))
+        mu = sz.a0 + sz.a1 * d
+        return 1.0 / mu ** 2
+    if sz.kind == SZ_HOLE_RAMP:
+        d = np.full_like(x, np.inf)
+        for k in sz.holes:
+            p = wl.prims[k]
+            r = max(p.p[2], p.p[3]) if p.kind == PRIM_ELLIPSE else p.p[2]
+            d = np.minimum(d, np.maximum(np.hypot(x - p.p[0], y - p.p[1]) - r, 0.0))
+        mu = 1.0 + (sz.a0 - 1.0) * np.minimum(d / sz.a1, 1.0)
+        return 1.0 / mu ** 2
+    raise ValueError(sz.kind)
+
+
+def sample_points(wl: Workload, rng: np.random.Generator, bbox) -> tuple[np.ndarray, np.ndarray]:
+    """Rejection sampling proportional to the density, strictly inside."""
+    x0, y0, x1, y1 = bbox
+    xs, ys = [], []
+    need = wl.n
+    wmax = None
+    while need > 0:
+        m = max(4 * need, 1024)
+        x = rng.uniform(x0, x1, m)
+        y = rng.uniform(y0, y1, m)
+        keep = _inside(wl, x, y)
+        x, y = x[keep], y[keep]
+        w = _weight(wl, x, y)
+        if wmax is None:
+            wmax = float(w.max()) * 1.05 if len(w) else 1.0
+        u = rng.uniform(0.0, wmax, len(x))
+        keep = u < w
+        x, y = x[keep][:need], y[keep][:need]
+        xs.append(x)
+        ys.append(y)
+        need -= len(x)
+    return np.concatenate(xs), np.concatenate(ys)
+
+
+def _place_disjoint(rng, count, rmin, rmax, lo, hi, gap, ok=lambda cx, cy, r: True, max_tries=200000):
+    out = []
+    tries = 0
+    while len(out) < count:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("could not place holes")
+        r = rng.uniform(rmin, rmax)
+        cx = rng.uniform(lo + r + gap, hi - r - gap)
+        cy = rng.uniform(lo + r + gap, hi - r - gap)
+        if not ok(cx, cy, r):
+            continue
+        if all((cx - a) ** 2 + (cy - b) ** 2 > (r + c + gap) ** 2 for a, b, c in out):
+            out.append((cx, cy, r))
+    return out
+
+
+# --------------------------------------------------------------- workloads --
+
+def disk(n: int = 2000, seed: int = 1001, iters: int = 50) -> Workload:
+    wl = Workload("disk", [Prim(OP_INIT, PRIM_DISK, (0.0, 0.0, 1.0))], Sizing(SZ_UNIFORM),
+                  centred_grid(256, 5, 9, 0.0, 8), n, [("dm", iters)], seed)
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(3)[2])
+    r = np.sqrt(rng.uniform(0, 1, n))
+    t = 2 * np.pi * rng.uniform(0, 1, n)
+    wl.x, wl.y = r * np.cos(t), r * np.sin(t)
+    return wl
+
+
+def annulus(n: int = 100000, seed: int = 1002, grid_n: int = 1024) -> Workload:
+    ss = np.random.SeedSequence(seed).spawn(3)
+    g_rng = np.random.default_rng(ss[0])
+    gap = 0.02
+    holes = []
+    while len(holes) < 3:
+        r = g_rng.uniform(0.05, 0.12)
+        rc = g_rng.uniform(0.3 + r + gap, 1.0 - r - gap)
+        th = g_rng.uniform(0, 2 * np.pi)
+        cx, cy = rc * np.cos(th), rc * np.sin(th)
+        if all((cx - a) ** 2 + (cy - b) ** 2 > (r + c + gap) ** 2 for a, b, c in holes):
+            holes.append((cx, cy, r))
+    prims = [Prim(OP_INIT, PRIM_DISK, (0.0, 0.0, 1.0)), Prim(OP_DIFF, PRIM_DISK, (0.0, 0.0, 0.3))]
+    prims += [Prim(OP_DIFF, PRIM_DISK, h) for h in holes]
+    span_log2 = 11 if grid_n == 1024 else int(round(math.log2(grid_n))) + 1
+    wl = Workload("annulus", prims, Sizing(SZ_ABS_SDF, 1.0, 2.0),
+                  centred_grid(grid_n, 5, span_log2, 0.0, 4), n, [("cvd", 30), ("dm", 70)], seed)
+    wl.x, wl.y = sample_points(wl, np.random.default_rng(ss[2]), (-1, -1, 1, 1))
+    return wl
+
+
+def holes20(n: int = 1000000, seed: int = 1003, grid_n: int = 4096, iters: int = 100) -> Workload:
+    ss = np.random.SeedSequence(seed).spawn(3)
+    holes = _place_disjoint(np.random.default_rng(ss[0]), 20, 0.02, 0.08, 0.0, 1.0, 0.02)
+    cent = np.random.default_rng(ss[1]).uniform(0, 1, (5, 2))
+    prims = [Prim(OP_INIT, PRIM_BOX, (0.0, 0.0, 1.0, 1.0))]
+    prims += [Prim(OP_DIFF, PRIM_DISK, h) for h in holes]
+    log2n = int(round(math.log2(grid_n)))
+    # spacing 17 * 2^-(log2n + 4): the span covers [0, 1] with a ~3% margin
+    grid = centred_grid(grid_n, 17, log2n + 4, 0.5, 4)
+    wl = Workload("holes20", prims, Sizing(SZ_GAUSS_RHO, 1.0, 4.0, 0.01, cent), grid, n,
+                  [("cvd", iters)], seed)
+    wl.x, wl.y = sample_points(wl, np.random.default_rng(ss[2]), (0, 0, 1, 1))
+    return wl
+
+
+def ellipses(n: int = 10000000, seed: int = 1004, grid_n: int = 8192, n_holes: int = 200) -> Workload:
+    ss = np.random.SeedSequence(seed).spawn(3)
+    rng = np.random.default_rng(ss[0])
+    out = []
+    tries = 0
+    while len(out) < n_holes:
+        tries += 1
+        if tries > 1000000:
+            raise RuntimeError("could not place ellipses")
+        a, b = rng.uniform(0.005, 0.03, 2)
+        phi = rng.uniform(0, np.pi)
+        r = max(a, b)
+        cx, cy = rng.uniform(r + 0.005, 1 - r - 0.005, 2)
+        if all((cx - e[0]) ** 2 + (cy - e[1]) ** 2 > (r + max(e[2], e[3]) + 0.005) ** 2 for e in out):
+            out.append((cx, cy, a, b, phi, 0.0))
+    prims = [Prim(OP_INIT, PRIM_BOX, (0.0, 0.0, 1.0, 1.0))]
+    prims += [Prim(OP_DIFF, PRIM_ELLIPSE, e) for e in out]
+    log2n = int(round(math.log2(grid_n)))
+    grid = centred_grid(grid_n, 17, log2n + 4, 0.5, 4)
+    wl = Workload("ellipses", prims, Sizing(SZ_HOLE_RAMP, 10.0, 0.1, holes=list(range(1, n_holes + 1))),
+                  grid, n, [("dm", 70), ("cvd", 30)], seed)
+    wl.x, wl.y = sample_points(wl, np.random.default_rng(ss[2]), (0, 0, 1, 1))
+    return wl
+
+
+def square_lattice(k: int = 6, spacing: float = 0.125) -> Workload:
+    """k x k square lattice (exactly cocircular quadruples) in a uniform box."""
+    prims = [Prim(OP_INIT, PRIM_BOX, (-0.5, -0.5, 0.5 + k * spacing, 0.5 + k * spacing))]
+    wl = Workload("square_lattice", prims, Sizing(SZ_UNIFORM), centred_grid(64, 1, 4, k * spacing / 2, 8),
+                  k * k, [("dm", 1)], 0)
+    ii, jj = np.meshgrid(np.arange(k), np.arange(k), indexing="xy")
+    wl.x = (ii.ravel() * spacing).astype(np.float64)
+    wl.y = (jj.ravel() * spacing).astype(np.float64)
+    return wl
+
+
+def random_box(n: int = 30, seed: int = 7, grid_n: int = 64, lo: float = 0.0, hi: float = 1.0) -> Workload:
+    """n uniform points in a box that lies well inside the grid."""
+    span = (hi - lo) * 1.5
+    d = 2.0 ** math.ceil(math.log2(span / (grid_n - 1)))
+    grid = GridSpec(grid_n, grid_n, 0.5 * (lo + hi) - d * (grid_n - 1) / 2, 0.5 * (lo + hi) - d * (grid_n - 1) / 2,
+                    d, d, 8)
+    wl = Workload("random_box", [Prim(OP_INIT, PRIM_BOX, (lo, lo, hi, hi))], Sizing(SZ_UNIFORM), grid, n,
+                  [("dm", 1)], seed)
+    rng = np.random.default_rng(seed)
+    wl.x = rng.uniform(lo, hi, n)
+    wl.y = rng.uniform(lo, hi, n)
+    return wl
+
+
+WORKLOADS = {"disk": disk, "annulus": annulus, "holes20": holes20, "ellipses": ellipses}
