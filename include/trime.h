@@ -1,0 +1,316 @@
+/*
+ * trime.h -- C ABI of the MI355X (gfx950) library for the per-iteration hot
+ * path of the TriMe++ iterative meshers (Lu & Rycroft, "TriMe++:
+ * Multi-threaded triangular meshing in two dimensions", arXiv 2309.13824).
+ *
+ * One meshing iteration (Alg. 1 DistMesh, Alg. 2 CVD, Sec. 4.2 III hybrid):
+ *   bin the points (Voro++ block grid, Sec. 6 example)  -> trime_bin_points
+ *   bounded Voronoi cell of every point (Sec. 2.1, 4.1)  -> trime_voronoi_cells
+ *   Delaunay triangles + validity tests (Proc. I, 4.1)   -> trime_delaunay_extract
+ *   DistMesh force step / CVD centroid step + treatment -> trime_step_dm,
+ *   (Eq. 2-5, Eq. 6, Sec. 4.2, Sec. 4.3)                    trime_step_cvd,
+ *                                                          trime_step_hybrid
+ * with the geometry grid built once by trime_sdf_grid_build (Sec. 3.1-3.3,
+ * 3.7).
+ *
+ * Conventions
+ *  - Every function returns a trime_status.  Argument errors are detected on
+ *    the host before anything is launched.  Device-side conditions (capacity
+ *    overflow, FP64 fallbacks, projection failures) are counted in the
+ *    device trime_stats of the state; trime_stats_check() turns a host copy
+ *    of it into a status.
+ *  - Ownership: the caller allocates and frees all device memory.  A state
+ *    lives in one caller-allocated device workspace sized by
+ *    trime_state_workspace_bytes(); the library keeps no pointer after a
+ *    call returns, allocates no device memory in any call except
+ *    trime_sdf_grid_build (setup: one temporary buffer for the primitive
+ *    list), and never synchronises except in trime_state_bind (setup: reads
+ *    the grid scalars) and trime_stats_read.
+ *  - Streams: `stream` is a hipStream_t (passed as void*); 0 is the null
+ *    stream.  All work is enqueued on it in order.
+ *  - Layouts: structure of arrays.  Positions are float64 x[n], y[n] in both
+ *    precision modes, indexed by point id (0..n-1).  Triangles are int32
+ *    (a, b, c) counter-clockwise with the smallest id first.  Adjacency rows
+ *    are sorted by id.  Grid arrays are row-major, node (i, j) at
+ *    j*nx + i, cell (i, j) at j*(nx-1) + i.
+ *  - Precision: TRIME_FP64 evaluates everything in FP64 ("plain FP64");
+ *    TRIME_FP32 evaluates cells, quadrature and forces in FP32 and replays a
+ *    point in FP64 whenever one of its decisions falls within the stated
+ *    FP32 error bound.  In both modes cut decisions that FP64 cannot settle
+ *    are taken exactly (expansion arithmetic) with symbolic tie-breaking, so
+ *    the combinatorial output does not depend on precision, order or tuning.
+ */
+#ifndef TRIME_H
+#define TRIME_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TRIME_OK = 0,
+  TRIME_EINVAL = 1,       /* bad argument (null pointer, bad size, bad enum)   */
+  TRIME_EUNSUPPORTED = 2, /* valid request this build does not implement       */
+  TRIME_ECAPACITY = 3,    /* an output or workspace is too small               */
+  TRIME_EHIP = 4,         /* HIP runtime error; see trime_last_error()         */
+  TRIME_EDEGENERATE = 5   /* coincident points were found (results complete)   */
+} trime_status;
+
+enum { TRIME_FP64 = 0, TRIME_FP32 = 1 };
+enum { TRIME_CAT_OUTER = 0, TRIME_CAT_INNER = 1, TRIME_CAT_BOUNDARY = 2 };
+
+/* ---- geometry and sizing input (Sec. 3.1, 3.3, Eq. 9) -------------------- */
+enum { TRIME_OP_INIT = 0, TRIME_OP_UNION = 1, TRIME_OP_DIFF = 2, TRIME_OP_INTERSECT = 3 };
+enum { TRIME_PRIM_DISK = 0, TRIME_PRIM_BOX = 1, TRIME_PRIM_ELLIPSE = 2, TRIME_PRIM_POLYGON = 3 };
+
+/* One analytic primitive of the constructive geometry.  Parameters p:
+   DISK (cx, cy, r); BOX (x0, y0, x1, y1); ELLIPSE (cx, cy, a, b, phi);
+   POLYGON: vertices poly[voff .. voff+nv) of trime_geometry.poly.  The running
+   sdf s is combined with the primitive's t by op: INIT s = t, UNION min(s, t),
+   DIFF max(s, -t), INTERSECT max(s, t) (Sec. 3.1 set operations). */
+typedef struct {
+  int32_t op, kind;
+  double p[6];
+  int32_t voff, nv;
+} trime_prim;
+
+typedef struct {
+  int32_t nprims;
+  const trime_prim *prims; /* host memory, nprims entries                     */
+  int32_t npoly;
+  const double *poly;      /* host memory, npoly (x, y) pairs                 */
+} trime_geometry;
+
+enum {
+  TRIME_SZ_UNIFORM = 0,   /* mu = 1                                          */
+  TRIME_SZ_ABS_SDF = 1,   /* mu = a0 + a1 |sdf|                              */
+  TRIME_SZ_GAUSS_RHO = 2, /* rho = a0 + a1 sum_k exp(-|x - c_k|^2 / s2), mu = rho^-1/2 */
+  TRIME_SZ_HOLE_RAMP = 3  /* mu = 1 + (a0 - 1) min(d_H / a1, 1), d_H = distance to
+                             the nearest primitive listed in holes              */
+};
+typedef struct {
+  int32_t kind;
+  double a0, a1, s2;
+  int32_t ncent;
+  const double *cent;   /* host, ncent (x, y) pairs                         */
+  int32_t nholes;
+  const int32_t *holes; /* host, indices into the primitive list            */
+} trime_sizing;
+
+/* Vertex-centred node grid: node (i, j) at (x0 + i dx, y0 + j dy).  Node
+   values are float64 (dtype_bytes 8) or float32 (4). */
+typedef struct {
+  int32_t nx, ny;
+  double x0, y0, dx, dy;
+  int32_t dtype_bytes;
+} trime_grid;
+
+/* Scalars of the geometry grid (Sec. 3.7), written to device memory. */
+typedef struct {
+  double H;        /* h_cell = mu_cell * H                                  */
+  double h_avg;    /* mean h over inner + selected boundary cells           */
+  double area_sel; /* area of the selected cells                            */
+  int64_t n_sel;   /* number of selected cells                              */
+} trime_grid_scalars;
+
+/* Control parameters: Table 8 defaults (k_spring and dt, left open there, are
+   the DistMesh defaults 1 and 0.2). */
+typedef struct {
+  double fac_F, fac_voro, fac_pt, fac_retria, fac_end, fac_geps, T_tria, alpha_hat;
+  int32_t T_newton;
+  double k_spring, dt;
+  int32_t cvd_max_level;   /* quadrature level cap (12)                    */
+  int32_t trace_max_steps; /* sphere-tracing step cap (64)                  */
+  int32_t trace_bisect;    /* sphere-tracing overshoot bisections (8)       */
+  int32_t test2_mode;      /* 0: one midpoint inside -> Test 3; 1: invalid  */
+} trime_params;
+
+/* Device-side counters and statistics of a state (read with trime_stats_read). */
+typedef struct {
+  int64_t fp64_replays;    /* points recomputed in FP64 after an uncertain FP32 decision */
+  int64_t exact_points;    /* points whose cell needed the exact stage        */
+  int64_t exact_calls;     /* exact predicate evaluations                     */
+  int64_t sos_calls;       /* exact zeros resolved by symbolic perturbation   */
+  int64_t overflow_points; /* cells beyond the polygon / row capacity         */
+  int64_t newton_fail, trace_fail, level_cap_hits, empty_cells;
+  int64_t ntri;            /* owned triangles of the last extraction          */
+  int64_t nvalid;          /* of which valid                                  */
+  int64_t moved;           /* points beyond fac_retria*h since last triangulation */
+  int64_t triangulations;  /* extractions run by the step functions           */
+  int64_t iterations;
+  int32_t retri_flag;      /* re-triangulate before the next DistMesh step    */
+  int32_t error;           /* nonzero: a capacity or internal error occurred  */
+  double sum_l2, sum_mu2, fac_mu; /* Eq. 3 of the last DistMesh force step     */
+  /* mesh quality of the valid triangles (Eq. 10-11), last extraction */
+  double sum_sqrt_alpha, sum_sqrt_beta, sum_q, max_alpha;
+  int64_t nq;
+  int64_t hist_beta[40];   /* beta in [1, 3), 40 bins, last bin open           */
+} trime_stats;
+
+/* Per-point arrays of a state are kept in "slot" order: the order of the
+   last binning (points sorted by bin, then by id).  Positional arrays are
+   double-buffered per step, order arrays per binning. */
+typedef struct {
+  double *x, *y;  /* positions                                            */
+  double *dprev;  /* previous movement (CVD error bound, Sec. 4.2)        */
+  uint8_t *cat;   /* point category (Sec. 3.5)                            */
+} trime_posbuf;
+
+typedef struct {
+  int32_t *id;    /* point id of each slot                                */
+  float *span;    /* octagon span S of each point (Sec. 4.1)              */
+  double *xl, *yl;/* positions at the last triangulation (Alg. 1)         */
+} trime_ordbuf;
+
+/* Triangles are kept per owner slot: up to TRIME_TRI_PER_POINT each (the
+   owner, the smallest id, can own every triangle around it). */
+#define TRIME_TRI_PER_POINT 16
+
+/* A meshing state: configuration set by the caller, device buffers laid out
+   by trime_state_bind in one caller-allocated workspace. */
+typedef struct {
+  /* -- configuration (caller) -- */
+  int64_t n;               /* number of points                               */
+  int32_t precision;       /* TRIME_FP64 or TRIME_FP32                       */
+  int32_t max_deg;         /* adjacency row capacity (0 -> 16)               */
+  double bin_density;      /* mean points per bin (0 -> 3.3, Sec. 6 example) */
+  trime_grid grid;
+  const void *sdf;         /* device node grids from trime_sdf_grid_build    */
+  const void *mu;
+  const uint8_t *cat_grid; /* device, (nx-1)(ny-1)                           */
+  const float *hcell;      /* device, (nx-1)(ny-1)                           */
+  const trime_grid_scalars *scal; /* device                                   */
+  trime_params params;
+  /* -- laid out by trime_state_bind (device pointers into the workspace) -- */
+  trime_posbuf pos[2];
+  trime_ordbuf ord[2];
+  int32_t cur_pos, cur_ord; /* current buffers                              */
+  int32_t *adj;            /* max_deg * n, column-major rows of slots        */
+  int32_t *deg;            /* n                                              */
+  int32_t *tri;            /* 3 * TRIME_TRI_PER_POINT * n, owner slot major  */
+  uint8_t *tri_valid;      /* TRIME_TRI_PER_POINT * n                        */
+  int32_t *tri_n;          /* n: owned triangles per slot                    */
+  int32_t *perm;           /* n: new slot -> old slot of the binning         */
+  int32_t *key;            /* n                                              */
+  int32_t *rank;           /* n                                              */
+  int32_t *bin_start;      /* nkeys + 1                                      */
+  int32_t *bin_fill;       /* nkeys                                          */
+  int32_t *scan_tmp;       /* scan block sums                                */
+  int32_t *queue;          /* n: points replayed in FP64 / exactly           */
+  int32_t *counters;       /* small device counters                          */
+  double *partials;        /* per-block partial sums                         */
+  trime_stats *stats;      /* device                                         */
+  /* bin grid (Morton-ordered square bins over the node grid's box) */
+  int32_t nbx, nby, lbits;
+  double bx0, by0, bw;
+  double area_sel;         /* host copy of scal->area_sel                    */
+  int64_t nkeys;
+} trime_state;
+
+/* A fixed hybrid schedule: segments (method, iterations) run in order. */
+enum { TRIME_METHOD_DM = 0, TRIME_METHOD_CVD = 1 };
+typedef struct {
+  int32_t nseg;
+  const int32_t *method;   /* host, nseg                                     */
+  const int32_t *iters;    /* host, nseg                                     */
+} trime_schedule;
+
+/* Cells written by trime_voronoi_cells: for each point id the CCW list of
+   edge constraints (>= 0 neighbour id; -1-w wall w, w = 0..7 octagon walls
+   at outward normals 0, 45, .., 315 degrees, 8..11 box walls x <= x1,
+   y <= y1, x >= x0, y >= y0), rotated to start at its smallest entry. */
+typedef struct {
+  int32_t cap;      /* entries per point                                     */
+  int32_t *cons;    /* device, n * cap                                       */
+  int32_t *ncons;   /* device, n (-1: more than cap)                         */
+} trime_cells;
+
+/* ------------------------------------------------------------------------ */
+const char *trime_last_error(void);
+const char *trime_version(void);
+void trime_default_params(trime_params *p);
+
+/* Geometry grid (Sec. 3.1-3.3, Sec. 3.7).  Fills sdf and mu at the nodes
+   (dtype of grid), the cell categories (boundary when |sdf(mid)| <= cell
+   diagonal, else inner when sdf(mid) < 0, else outer; mid value = mean of the
+   4 corner nodes), h_cell = mu_cell * H with mu_cell the mean of the corner
+   mu nodes and H = sqrt(dx dy sum_sel mu_cell^-2 / n_total) over the
+   selected cells (inner, and boundary with sdf(mid) <= 0.5 min(dx, dy)), and
+   the scalars.  All outputs are device pointers sized by the grid. */
+trime_status trime_sdf_grid_build(const trime_geometry *g, const trime_sizing *sz,
+                                  const trime_grid *grid, int64_t n_total, void *d_sdf,
+                                  void *d_mu, uint8_t *d_cat, float *d_hcell,
+                                  trime_grid_scalars *d_scal, void *stream);
+
+/* Size of the device workspace of a configured state (bytes, 256-aligned). */
+trime_status trime_state_workspace_bytes(const trime_state *st, size_t *bytes);
+/* Lays the state's buffers out in d_ws (>= workspace bytes).  Synchronous:
+   reads the grid scalars from the device. */
+trime_status trime_state_bind(trime_state *st, void *d_ws, size_t bytes, void *stream);
+/* Copies positions (device, by id) into the state (slot = id until the first
+   binning), sets categories (Sec. 3.5), d_prev = -1 (the first CVD
+   iteration uses h) and clears the stats. */
+trime_status trime_state_load(trime_state *st, const double *d_x, const double *d_y, void *stream);
+/* Current positions and categories, scattered back to id order (device). */
+trime_status trime_export_points(const trime_state *st, double *d_x, double *d_y, uint8_t *d_cat,
+                                 void *stream);
+/* Owned triangles of the last extraction as ids (CCW, smallest id first),
+   with validity; rows in owner-slot order.  d_tri: 3*cap int32, d_valid: cap
+   bytes; *d_count receives the number (device int64). */
+trime_status trime_export_triangles(const trime_state *st, int32_t *d_tri, uint8_t *d_valid,
+                                    int64_t cap, int64_t *d_count, void *stream);
+/* Adjacency of the valid triangles by id: rows of max_deg entries (id-major,
+   d_col[i*max_deg + t]) sorted by id, d_deg[i] entries each. */
+trime_status trime_export_adjacency(const trime_state *st, int32_t *d_deg, int32_t *d_col,
+                                    void *stream);
+
+/* Sorts the points into Morton-ordered bins of the bin grid (the Voro++
+   container blocks of the paper's example code): new slot order by
+   (bin key, id).  Permutes every per-point array into it, sets the positions
+   of the last triangulation to the current ones and the span S of every
+   point (Sec. 4.1: S = fac_voro * h of the point's cell). */
+trime_status trime_bin_points(trime_state *st, void *stream);
+
+/* Bounded Voronoi cell of every point (Sec. 2.1, Sec. 4.1): the octagon
+   |u_x|, |u_y| <= S, |u_x| + |u_y| <= fl32(fl32(sqrt 2) S) around the point,
+   clipped by the node grid's box and by the bisector of every neighbour.
+   Needs trime_bin_points first.  Writes `out` (must be non-null). */
+trime_status trime_voronoi_cells(trime_state *st, const trime_cells *out, void *stream);
+
+/* Delaunay triangles of the cells (Proc. I): the circumcentre of a cell
+   vertex between the bisectors of neighbours j, k yields triangle (i, j, k)
+   when it is a vertex of all three cells; the smallest id owns it.  Runs
+   Tests 1-3 on every triangle and keeps the owned triangles with their
+   validity and the adjacency of the valid triangles (slot form; see the
+   export functions), and their quality statistics.  Needs trime_bin_points
+   first. */
+trime_status trime_delaunay_extract(trime_state *st, void *stream);
+
+/* n_iter DistMesh iterations (Alg. 1): re-triangulate (bin + extract) when
+   the flag is set (always on the first iteration of the call when
+   `fresh` != 0), Eq. 3 scaling, spring forces (Eq. 2), forward Euler (Eq. 5)
+   and treatment (Sec. 4.3); the flag is set when a point moved more than
+   fac_retria*h since the last triangulation.  always_retriangulate != 0
+   triangulates every iteration. */
+trime_status trime_step_dm(trime_state *st, int32_t n_iter, int32_t fresh,
+                           int32_t always_retriangulate, void *stream);
+/* n_iter CVD iterations (Alg. 2): bin, cells, adaptive-quadrature centroid
+   with rho = mu^-2 (Sec. 4.2 II), treatment; triangles and quality stats of
+   every iteration's cells. */
+trime_status trime_step_cvd(trime_state *st, int32_t n_iter, void *stream);
+/* A fixed schedule of DistMesh and CVD segments (Sec. 2.4, 4.2 III). */
+trime_status trime_step_hybrid(trime_state *st, const trime_schedule *sch, void *stream);
+
+/* Mesh quality of the state's valid triangles (Eq. 10-11) into stats. */
+trime_status trime_quality(trime_state *st, void *stream);
+
+/* Copies the device stats to host memory (synchronises the stream). */
+trime_status trime_stats_read(const trime_state *st, trime_stats *host, void *stream);
+trime_status trime_stats_check(const trime_stats *host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

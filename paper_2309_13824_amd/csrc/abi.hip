@@ -1,0 +1,537 @@
+// Host side of the C ABI declared in include/trime.h: argument checks,
+// workspace layout and the launch sequence of each entry point.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "trime_dev.hpp"
+
+#include "launch.hpp"
+
+using namespace trime;
+
+static thread_local char g_err[512] = "";
+
+static trime_status fail(trime_status st, const char *msg) {
+  snprintf(g_err, sizeof g_err, "%s", msg);
+  return st;
+}
+
+static trime_status check_hip(const char *where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    snprintf(g_err, sizeof g_err, "%s: %s", where, hipGetErrorString(e));
+    return TRIME_EHIP;
+  }
+  return TRIME_OK;
+}
+
+#define TRY_HIP(call, where)                                                   \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      snprintf(g_err, sizeof g_err, "%s: %s", where, hipGetErrorString(e_));   \
+      return TRIME_EHIP;                                                       \
+    }                                                                          \
+  } while (0)
+
+// entry points: C linkage from the declarations in trime.h
+
+const char *trime_last_error(void) { return g_err; }
+const char *trime_version(void) { return "trime-gfx950 0.1"; }
+
+void trime_default_params(trime_params *p) {
+  if (!p) return;
+  p->fac_F = 1.2;
+  p->fac_voro = 5.0;
+  p->fac_pt = 0.4;
+  p->fac_retria = 0.1;
+  p->fac_end = 0.001;
+  p->fac_geps = 0.01;
+  p->T_tria = 0.4;
+  p->alpha_hat = 1.0;
+  p->T_newton = 10;
+  p->k_spring = 1.0;
+  p->dt = 0.2;
+  p->cvd_max_level = 12;
+  p->trace_max_steps = 64;
+  p->trace_bisect = 8;
+  p->test2_mode = 0;
+}
+
+static bool grid_ok(const trime_grid *g) {
+  return g && g->nx >= 2 && g->ny >= 2 && g->dx > 0 && g->dy > 0 &&
+         (g->dtype_bytes == 4 || g->dtype_bytes == 8) && isfinite(g->x0) && isfinite(g->y0);
+}
+
+trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing *sz,
+                                  const trime_grid *grid, int64_t n_total, void *d_sdf, void *d_mu,
+                                  uint8_t *d_cat, float *d_hcell, trime_grid_scalars *d_scal,
+                                  void *stream) {
+  if (!geo || !sz || !grid_ok(grid) || n_total <= 0 || !d_sdf || !d_mu || !d_cat || !d_hcell || !d_scal)
+    return fail(TRIME_EINVAL, "trime_sdf_grid_build: null or invalid argument");
+  if (geo->nprims <= 0 || !geo->prims || geo->prims[0].op != TRIME_OP_INIT)
+    return fail(TRIME_EINVAL, "trime_sdf_grid_build: the first primitive must be INIT");
+  for (int k = 0; k < geo->nprims; k++) {
+    const trime_prim &p = geo->prims[k];
+    if (p.op < 0 || p.op > 3 || p.kind < 0 || p.kind > 3)
+      return fail(TRIME_EINVAL, "trime_sdf_grid_build: bad primitive op/kind");
+    if (p.kind == TRIME_PRIM_POLYGON && (p.nv < 3 || p.voff < 0 || p.voff + p.nv > geo->npoly || !geo->poly))
+      return fail(TRIME_EINVAL, "trime_sdf_grid_build: bad polygon range");
+    if ((p.kind == TRIME_PRIM_DISK && !(p.p[2] > 0)) ||
+        (p.kind == TRIME_PRIM_ELLIPSE && !(p.p[2] > 0 && p.p[3] > 0)))
+      return fail(TRIME_EINVAL, "trime_sdf_grid_build: nonpositive radius");
+  }
+  if (sz->kind < 0 || sz->kind > 3) return fail(TRIME_EINVAL, "trime_sdf_grid_build: bad sizing kind");
+  if (sz->kind == TRIME_SZ_GAUSS_RHO && (sz->ncent < 0 || (sz->ncent > 0 && !sz->cent) || !(sz->s2 > 0)))
+    return fail(TRIME_EINVAL, "trime_sdf_grid_build: bad density centres");
+  if (sz->kind == TRIME_SZ_HOLE_RAMP) {
+    if (sz->nholes <= 0 || !sz->holes || !(sz->a1 > 0))
+      return fail(TRIME_EINVAL, "trime_sdf_grid_build: bad hole list");
+    for (int k = 0; k < sz->nholes; k++)
+      if (sz->holes[k] < 0 || sz->holes[k] >= geo->nprims)
+        return fail(TRIME_EINVAL, "trime_sdf_grid_build: hole index out of range");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  // one temporary device buffer: prims | poly | cent | holes | partials
+  size_t b_prims = sizeof(trime_prim) * (size_t)geo->nprims;
+  size_t b_poly = sizeof(double) * 2 * (size_t)(geo->npoly > 0 ? geo->npoly : 0);
+  size_t b_cent = sizeof(double) * 2 * (size_t)(sz->kind == TRIME_SZ_GAUSS_RHO ? sz->ncent : 0);
+  size_t b_holes = sizeof(int32_t) * (size_t)(sz->kind == TRIME_SZ_HOLE_RAMP ? sz->nholes : 0);
+  size_t b_part = sizeof(double) * 2 * (size_t)grid_partials(grid->nx, grid->ny);
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  size_t total = al(b_prims) + al(b_poly) + al(b_cent) + al(b_holes) + al(b_part);
+  char *buf = nullptr;
+  TRY_HIP(hipMallocAsync((void **)&buf, total, s), "trime_sdf_grid_build: hipMallocAsync");
+  char *q = buf;
+  trime_prim *d_prims = (trime_prim *)q; q += al(b_prims);
+  double *d_poly = (double *)q; q += al(b_poly);
+  double *d_cent = (double *)q; q += al(b_cent);
+  int32_t *d_holes = (int32_t *)q; q += al(b_holes);
+  double *d_part = (double *)q;
+  TRY_HIP(hipMemcpyAsync(d_prims, geo->prims, b_prims, hipMemcpyHostToDevice, s), "copy prims");
+  if (b_poly) TRY_HIP(hipMemcpyAsync(d_poly, geo->poly, b_poly, hipMemcpyHostToDevice, s), "copy poly");
+  if (b_cent) TRY_HIP(hipMemcpyAsync(d_cent, sz->cent, b_cent, hipMemcpyHostToDevice, s), "copy cent");
+  if (b_holes) TRY_HIP(hipMemcpyAsync(d_holes, sz->holes, b_holes, hipMemcpyHostToDevice, s), "copy holes");
+  GridPrims g;
+  g.nprims = geo->nprims;
+  g.prims = d_prims;
+  g.poly = d_poly;
+  g.sz = *sz;
+  g.cent = d_cent;
+  g.holes = d_holes;
+  g.nx = grid->nx;
+  g.ny = grid->ny;
+  g.x0 = grid->x0;
+  g.y0 = grid->y0;
+  g.dx = grid->dx;
+  g.dy = grid->dy;
+  g.n_total = n_total;
+  launch_grid_build(g, grid->dtype_bytes, d_sdf, d_mu, d_cat, d_hcell, d_scal, d_part, s);
+  trime_status st = check_hip("trime_sdf_grid_build: launch");
+  (void)hipFreeAsync(buf, s);
+  return st;
+}
+
+// ------------------------------------------------------------ workspace --
+
+static int64_t defaults_deg(const trime_state *st) { return st->max_deg > 0 ? st->max_deg : 16; }
+
+static trime_status bin_geometry(trime_state *st, void *stream) {
+  if (st->area_sel <= 0) {
+    trime_grid_scalars h;
+    TRY_HIP(hipMemcpyAsync(&h, st->scal, sizeof h, hipMemcpyDeviceToHost, (hipStream_t)stream),
+            "read grid scalars");
+    TRY_HIP(hipStreamSynchronize((hipStream_t)stream), "read grid scalars (sync)");
+    st->area_sel = h.area_sel;
+  }
+  const trime_grid &g = st->grid;
+  double W = (g.nx - 1) * g.dx, H = (g.ny - 1) * g.dy;
+  double dens = st->bin_density > 0 ? st->bin_density : 3.3;
+  double area = st->area_sel > 0 ? st->area_sel : W * H;
+  double bw = sqrt(dens * area / (double)st->n);
+  if (!(bw > 0)) bw = fmax(W, H);
+  int nbx = (int)ceil(W / bw), nby = (int)ceil(H / bw);
+  nbx = nbx < 1 ? 1 : nbx;
+  nby = nby < 1 ? 1 : nby;
+  int lb = 0;
+  while ((1 << lb) < nbx || (1 << lb) < nby) lb++;
+  if (lb > 15) return fail(TRIME_EUNSUPPORTED, "bin grid wider than 32768 bins");
+  st->bw = bw;
+  st->nbx = nbx;
+  st->nby = nby;
+  st->lbits = lb;
+  st->nkeys = (int64_t)1 << (2 * lb);
+  st->bx0 = g.x0;
+  st->by0 = g.y0;
+  return TRIME_OK;
+}
+
+struct Layout {
+  size_t off = 0;
+  char *base;
+  template <class T> T *take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? (T *)(base + off) : nullptr;
+    off += sizeof(T) * count;
+    return p;
+  }
+};
+
+static void layout(trime_state *st, Layout &L) {
+  int64_t n = st->n;
+  int64_t md = defaults_deg(st);
+  for (int b = 0; b < 2; b++) {
+    st->pos[b].x = L.take<double>(n);
+    st->pos[b].y = L.take<double>(n);
+    st->pos[b].dprev = L.take<double>(n);
+    st->pos[b].cat = L.take<uint8_t>(n);
+    st->ord[b].id = L.take<int32_t>(n);
+    st->ord[b].span = L.take<float>(n);
+    st->ord[b].xl = L.take<double>(n);
+    st->ord[b].yl = L.take<double>(n);
+  }
+  st->adj = L.take<int32_t>(md * n);
+  st->deg = L.take<int32_t>(n);
+  st->tri = L.take<int32_t>(3 * TRIME_TRI_PER_POINT * n);
+  st->tri_valid = L.take<uint8_t>(TRIME_TRI_PER_POINT * n);
+  st->tri_n = L.take<int32_t>(n + 1);
+  st->perm = L.take<int32_t>(n + 1);
+  st->key = L.take<int32_t>(n);
+  st->rank = L.take<int32_t>(n);
+  st->bin_start = L.take<int32_t>(st->nkeys + 1);
+  st->bin_fill = L.take<int32_t>(st->nkeys);
+  int64_t scan_n = st->nkeys > n ? st->nkeys : n;
+  st->scan_tmp = L.take<int32_t>(scan_tmp_ints(scan_n) + 1);
+  st->queue = L.take<int32_t>(n + 1);
+  st->counters = L.take<int32_t>(CNT_NCOUNTERS);
+  int64_t np = dm_partials(n);
+  st->partials = L.take<double>(2 * (np > 1 ? np : 1));
+  st->stats = L.take<trime_stats>(1);
+}
+
+static trime_status state_ok(const trime_state *st) {
+  if (!st || st->n <= 0 || st->n > (int64_t)1 << 30) return fail(TRIME_EINVAL, "state: bad n");
+  if (st->precision != TRIME_FP64 && st->precision != TRIME_FP32)
+    return fail(TRIME_EINVAL, "state: bad precision");
+  if (!grid_ok(&st->grid)) return fail(TRIME_EINVAL, "state: bad grid");
+  if (!st->sdf || !st->mu || !st->cat_grid || !st->hcell || !st->scal)
+    return fail(TRIME_EINVAL, "state: grid arrays missing");
+  if (st->max_deg < 0 || st->max_deg > 64) return fail(TRIME_EINVAL, "state: max_deg out of range");
+  return TRIME_OK;
+}
+
+trime_status trime_state_workspace_bytes(const trime_state *st_in, size_t *bytes) {
+  trime_status e = state_ok(st_in);
+  if (e) return e;
+  if (!bytes) return fail(TRIME_EINVAL, "trime_state_workspace_bytes: null bytes");
+  trime_state st = *st_in;
+  e = bin_geometry(&st, 0);
+  if (e) return e;
+  Layout L;
+  L.base = nullptr;
+  layout(&st, L);
+  *bytes = (L.off + 255) & ~(size_t)255;
+  return TRIME_OK;
+}
+
+trime_status trime_state_bind(trime_state *st, void *d_ws, size_t bytes, void *stream) {
+  trime_status e = state_ok(st);
+  if (e) return e;
+  if (!d_ws) return fail(TRIME_EINVAL, "trime_state_bind: null workspace");
+  if (((uintptr_t)d_ws) & 255) return fail(TRIME_EINVAL, "trime_state_bind: workspace not 256-aligned");
+  e = bin_geometry(st, stream);
+  if (e) return e;
+  Layout probe;
+  probe.base = nullptr;
+  trime_state tmp = *st;
+  layout(&tmp, probe);
+  if (probe.off > bytes) return fail(TRIME_ECAPACITY, "trime_state_bind: workspace too small");
+  Layout L;
+  L.base = (char *)d_ws;
+  layout(st, L);
+  if (st->max_deg <= 0) st->max_deg = 16;
+  st->cur_pos = 0;
+  st->cur_ord = 0;
+  return TRIME_OK;
+}
+
+// Kernel arguments with the current buffers (cur) and the next position
+// buffers (the other set).
+static KArgs make_args(const trime_state *st) {
+  KArgs a;
+  memset(&a, 0, sizeof a);
+  const trime_posbuf &P = st->pos[st->cur_pos], &Q = st->pos[st->cur_pos ^ 1];
+  const trime_ordbuf &O = st->ord[st->cur_ord];
+  a.n = st->n;
+  a.x = P.x;
+  a.y = P.y;
+  a.dprev = P.dprev;
+  a.cat = P.cat;
+  a.xn = Q.x;
+  a.yn = Q.y;
+  a.dprevn = Q.dprev;
+  a.catn = Q.cat;
+  a.xl = O.xl;
+  a.yl = O.yl;
+  a.span = O.span;
+  a.id = O.id;
+  a.perm = st->perm;
+  a.key = st->key;
+  a.rank = st->rank;
+  a.bin_start = st->bin_start;
+  a.bin_fill = st->bin_fill;
+  a.nbx = st->nbx;
+  a.nby = st->nby;
+  a.lbits = st->lbits;
+  a.bx0 = st->bx0;
+  a.by0 = st->by0;
+  a.bw = st->bw;
+  a.inv_bw = 1.0 / st->bw;
+  const trime_grid &g = st->grid;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.gx0 = g.x0;
+  a.gy0 = g.y0;
+  a.gdx = g.dx;
+  a.gdy = g.dy;
+  a.inv_dx = 1.0 / g.dx;
+  a.inv_dy = 1.0 / g.dy;
+  a.box_x0 = g.x0;
+  a.box_y0 = g.y0;
+  a.box_x1 = g.x0 + (g.nx - 1) * g.dx;
+  a.box_y1 = g.y0 + (g.ny - 1) * g.dy;
+  a.sdf = st->sdf;
+  a.mu = st->mu;
+  a.cgrid = st->cat_grid;
+  a.hcell = st->hcell;
+  a.scal = st->scal;
+  a.max_deg = st->max_deg > 0 ? st->max_deg : 16;
+  a.adj = st->adj;
+  a.deg = st->deg;
+  a.tri = st->tri;
+  a.tri_valid = st->tri_valid;
+  a.tri_n = st->tri_n;
+  a.queue = st->queue;
+  a.counters = st->counters;
+  a.partials = st->partials;
+  a.stats = st->stats;
+  a.prm = st->params;
+  a.precision = st->precision;
+  return a;
+}
+
+static trime_status bound_ok(const trime_state *st) {
+  if (!st || !st->stats || !st->pos[0].x) return fail(TRIME_EINVAL, "state not bound");
+  return state_ok(st);
+}
+
+trime_status trime_state_load(trime_state *st, const double *d_x, const double *d_y, void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  if (!d_x || !d_y) return fail(TRIME_EINVAL, "trime_state_load: null positions");
+  hipStream_t s = (hipStream_t)stream;
+  st->cur_pos = 0;
+  st->cur_ord = 0;
+  KArgs a = make_args(st);
+  LoadArgs l;
+  l.xin = d_x;
+  l.yin = d_y;
+  l.x = st->pos[0].x;
+  l.y = st->pos[0].y;
+  l.dprev = st->pos[0].dprev;
+  l.cat = st->pos[0].cat;
+  l.id = st->ord[0].id;
+  l.span = st->ord[0].span;
+  l.xl = st->ord[0].xl;
+  l.yl = st->ord[0].yl;
+  launch_stats_reset(a, 1, s);
+  launch_load(a, l, st->grid.dtype_bytes, s);
+  launch_fill_i32(st->deg, st->n, 0, s);
+  launch_fill_i32(st->tri_n, st->n, 0, s);
+  return check_hip("trime_state_load");
+}
+
+trime_status trime_bin_points(trime_state *st, void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  hipStream_t s = (hipStream_t)stream;
+  KArgs a = make_args(st);
+  GatherArgs g;
+  const trime_posbuf &P = st->pos[st->cur_pos], &Q = st->pos[st->cur_pos ^ 1];
+  const trime_ordbuf &O = st->ord[st->cur_ord], &R = st->ord[st->cur_ord ^ 1];
+  g.x = P.x;
+  g.y = P.y;
+  g.dprev = P.dprev;
+  g.cat = P.cat;
+  g.id = O.id;
+  g.xo = Q.x;
+  g.yo = Q.y;
+  g.dprevo = Q.dprev;
+  g.cato = Q.cat;
+  g.ido = R.id;
+  g.spano = R.span;
+  g.xlo = R.xl;
+  g.ylo = R.yl;
+  launch_bin(a, g, st->nkeys, st->scan_tmp, s);
+  st->cur_pos ^= 1;
+  st->cur_ord ^= 1;
+  return check_hip("trime_bin_points");
+}
+
+trime_status trime_voronoi_cells(trime_state *st, const trime_cells *out, void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  if (!out || !out->cons || !out->ncons || out->cap <= 0)
+    return fail(TRIME_EINVAL, "trime_voronoi_cells: bad output");
+  hipStream_t s = (hipStream_t)stream;
+  KArgs a = make_args(st);
+  a.cell_cons = out->cons;
+  a.cell_n = out->ncons;
+  a.cell_cap = out->cap;
+  launch_fill_i32(st->counters, CNT_NCOUNTERS, 0, s);
+  launch_cells(a, MODE_CELLS, st->grid.dtype_bytes, s);
+  return check_hip("trime_voronoi_cells");
+}
+
+static void extract(trime_state *st, hipStream_t s) {
+  KArgs a = make_args(st);
+  launch_stats_reset(a, 0, s);
+  launch_cells(a, MODE_EXTRACT, st->grid.dtype_bytes, s);
+  launch_finish_extract(a, s);
+}
+
+trime_status trime_delaunay_extract(trime_state *st, void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  extract(st, (hipStream_t)stream);
+  return check_hip("trime_delaunay_extract");
+}
+
+static trime_status read_flag(const trime_state *st, hipStream_t s, int *flag) {
+  int32_t v = 0;
+  TRY_HIP(hipMemcpyAsync(&v, &st->stats->retri_flag, sizeof v, hipMemcpyDeviceToHost, s), "read flag");
+  TRY_HIP(hipStreamSynchronize(s), "read flag (sync)");
+  *flag = v;
+  return TRIME_OK;
+}
+
+trime_status trime_step_dm(trime_state *st, int32_t n_iter, int32_t fresh, int32_t always,
+                           void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  if (n_iter < 0) return fail(TRIME_EINVAL, "trime_step_dm: negative iteration count");
+  hipStream_t s = (hipStream_t)stream;
+  int flag = 1;
+  if (!fresh && !always) {
+    e = read_flag(st, s, &flag);
+    if (e) return e;
+  }
+  for (int it = 0; it < n_iter; it++) {
+    bool retri = always || (it == 0 && fresh) || flag;
+    if (retri) {
+      e = trime_bin_points(st, stream);
+      if (e) return e;
+      extract(st, s);
+    }
+    KArgs a = make_args(st);
+    launch_dm(a, st->grid.dtype_bytes, s);
+    st->cur_pos ^= 1;
+    e = check_hip("trime_step_dm");
+    if (e) return e;
+    if (!always && it + 1 < n_iter) {
+      e = read_flag(st, s, &flag);
+      if (e) return e;
+    }
+  }
+  return TRIME_OK;
+}
+
+trime_status trime_step_cvd(trime_state *st, int32_t n_iter, void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  if (n_iter < 0) return fail(TRIME_EINVAL, "trime_step_cvd: negative iteration count");
+  hipStream_t s = (hipStream_t)stream;
+  for (int it = 0; it < n_iter; it++) {
+    e = trime_bin_points(st, stream);
+    if (e) return e;
+    KArgs a = make_args(st);
+    launch_stats_reset(a, 0, s);
+    launch_cells(a, MODE_CVD, st->grid.dtype_bytes, s);
+    launch_finish_extract(a, s);
+    st->cur_pos ^= 1;
+    e = check_hip("trime_step_cvd");
+    if (e) return e;
+  }
+  return TRIME_OK;
+}
+
+trime_status trime_step_hybrid(trime_state *st, const trime_schedule *sch, void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  if (!sch || sch->nseg < 0 || (sch->nseg > 0 && (!sch->method || !sch->iters)))
+    return fail(TRIME_EINVAL, "trime_step_hybrid: bad schedule");
+  for (int k = 0; k < sch->nseg; k++) {
+    if (sch->iters[k] < 0) return fail(TRIME_EINVAL, "trime_step_hybrid: negative count");
+    if (sch->method[k] == TRIME_METHOD_DM)
+      e = trime_step_dm(st, sch->iters[k], 1, 0, stream);
+    else if (sch->method[k] == TRIME_METHOD_CVD)
+      e = trime_step_cvd(st, sch->iters[k], stream);
+    else
+      return fail(TRIME_EUNSUPPORTED, "trime_step_hybrid: unknown method");
+    if (e) return e;
+  }
+  return TRIME_OK;
+}
+
+trime_status trime_quality(trime_state *st, void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  launch_quality(make_args(st), (hipStream_t)stream);
+  return check_hip("trime_quality");
+}
+
+trime_status trime_export_points(const trime_state *st, double *d_x, double *d_y, uint8_t *d_cat,
+                                 void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  launch_export_points(make_args(st), d_x, d_y, d_cat, (hipStream_t)stream);
+  return check_hip("trime_export_points");
+}
+
+trime_status trime_export_triangles(const trime_state *st, int32_t *d_tri, uint8_t *d_valid, int64_t cap,
+                                    int64_t *d_count, void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  if (!d_tri || !d_valid || cap < 0) return fail(TRIME_EINVAL, "trime_export_triangles: bad output");
+  // offsets go to the perm buffer (n + 1 ints), free outside a binning
+  launch_export_tri(make_args(st), st->perm, st->scan_tmp, d_tri, d_valid, cap, d_count,
+                    (hipStream_t)stream);
+  return check_hip("trime_export_triangles");
+}
+
+trime_status trime_export_adjacency(const trime_state *st, int32_t *d_deg, int32_t *d_col, void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  if (!d_deg || !d_col) return fail(TRIME_EINVAL, "trime_export_adjacency: bad output");
+  launch_export_adj(make_args(st), d_deg, d_col, (hipStream_t)stream);
+  return check_hip("trime_export_adjacency");
+}
+
+trime_status trime_stats_read(const trime_state *st, trime_stats *host, void *stream) {
+  if (!st || !st->stats || !host) return fail(TRIME_EINVAL, "trime_stats_read: null argument");
+  TRY_HIP(hipMemcpyAsync(host, st->stats, sizeof *host, hipMemcpyDeviceToHost, (hipStream_t)stream),
+          "trime_stats_read");
+  TRY_HIP(hipStreamSynchronize((hipStream_t)stream), "trime_stats_read (sync)");
+  return TRIME_OK;
+}
+
+trime_status trime_stats_check(const trime_stats *h) {
+  if (!h) return fail(TRIME_EINVAL, "trime_stats_check: null");
+  if (h->error & (ERR_TRI_CAP | ERR_DEG_CAP | ERR_POLY_CAP | ERR_EXACT_CAP))
+    return fail(TRIME_ECAPACITY, "a device capacity was exceeded (see stats.error)");
+  if (h->empty_cells > 0) return fail(TRIME_EDEGENERATE, "coincident points (empty cells)");
+  return TRIME_OK;
+}
+
+

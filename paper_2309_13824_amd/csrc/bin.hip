@@ -1,0 +1,172 @@
+// Binning of the points into Morton-ordered square bins (the role of the
+// Voro++ container blocks, sized for ~3.3 points per block as in the paper's
+// example code), by counting sort: keys + histogram, exclusive scan, scatter,
+// then a per-bin sort by id so the new slot order is the deterministic order
+// (bin key, id).  The gather then permutes every per-point array into the
+// new slot order (coalesced: points move little between iterations).
+#include "launch.hpp"
+
+namespace trime {
+
+constexpr int SCAN_BLOCK = 1024;
+constexpr int SCAN_ITEMS = 4;  // elements per thread
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_bin_keys(KArgs a) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.n) return;
+  int bx, by;
+  bin_of(a, a.x[k], a.y[k], bx, by);
+  int key = (int)morton((uint32_t)bx, (uint32_t)by);
+  a.key[k] = key;
+  a.rank[k] = atomicAdd(&a.bin_fill[key], 1);
+}
+
+// Block-wide exclusive scan of 4096 ints per block; writes block totals.
+__device__ __forceinline__ int block_excl_scan(int v, int *smem, int &total) {
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    int y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) smem[w] = x;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    int nw = blockDim.x >> 6;
+    int s = threadIdx.x < nw ? smem[threadIdx.x] : 0;
+    for (int off = 1; off < 64; off <<= 1) {
+      int y = __shfl_up(s, off);
+      if ((int)threadIdx.x >= off) s += y;
+    }
+    if (threadIdx.x < nw) smem[threadIdx.x] = s;
+  }
+  __syncthreads();
+  int before = (w > 0 ? smem[w - 1] : 0) + x - v;
+  total = smem[(blockDim.x >> 6) - 1];
+  __syncthreads();
+  return before;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tiles(const int32_t *in, int32_t *out,
+                                                            int64_t n, int32_t *tile_sums) {
+  __shared__ int smem[SCAN_BLOCK / 64];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  int s = 0;
+#pragma unroll
+  for (int q = 0; q < SCAN_ITEMS; q++) {
+    v[q] = (base + q < n) ? in[base + q] : 0;
+    s += v[q];
+  }
+  int total;
+  int before = block_excl_scan(s, smem, total);
+#pragma unroll
+  for (int q = 0; q < SCAN_ITEMS; q++) {
+    if (base + q < n) out[base + q] = before;
+    before += v[q];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of the tile sums (any count), total at [nt].
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_sums(int32_t *sums, int64_t nt) {
+  __shared__ int smem[SCAN_BLOCK / 64];
+  int carry = 0;
+  for (int64_t base = 0; base < nt; base += SCAN_BLOCK) {
+    int64_t i = base + threadIdx.x;
+    int v = i < nt ? sums[i] : 0;
+    int total;
+    int before = block_excl_scan(v, smem, total);
+    if (i < nt) sums[i] = before + carry;
+    carry += total;
+  }
+  if (threadIdx.x == 0) sums[nt] = carry;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_add(int32_t *out, int64_t n,
+                                                          const int32_t *sums, int64_t nt) {
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int add = sums[blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < SCAN_ITEMS; q++)
+    if (base + q < n) out[base + q] += add;
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[nt];
+}
+
+// Exclusive scan of in[0..n) into out[0..n], out[n] = total.
+void scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t s) {
+  int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (nt == 0) nt = 1;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(SCAN_BLOCK), 0, s, in, out, n, tmp);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BLOCK), 0, s, tmp, nt);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(SCAN_BLOCK), 0, s, out, n, tmp, nt);
+}
+
+size_t scan_tmp_ints(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) + 2; }
+
+__global__ void k_bin_scatter(KArgs a) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.n) return;
+  a.perm[a.bin_start[a.key[k]] + a.rank[k]] = (int)k;
+}
+
+// One thread per bin: order its entries by point id (insertion sort).
+__global__ void k_bin_sort(KArgs a, int64_t nkeys) {
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nkeys) return;
+  int s0 = a.bin_start[b], s1 = a.bin_start[b + 1];
+  for (int s = s0 + 1; s < s1; s++) {
+    int v = a.perm[s];
+    int idv = a.id[v];
+    int t = s;
+    while (t > s0 && a.id[a.perm[t - 1]] > idv) {
+      a.perm[t] = a.perm[t - 1];
+      t--;
+    }
+    a.perm[t] = v;
+  }
+}
+
+// Gather every per-point array into the new slot order (writes the other
+// buffer set); the positions of the last triangulation become the current
+// ones and the octagon span S is recomputed from the point's cell.
+
+__global__ void k_bin_gather(KArgs a, GatherArgs g) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n) return;
+  int k = a.perm[s];
+  double x = g.x[k], y = g.y[k];
+  g.xo[s] = x;
+  g.yo[s] = y;
+  g.xlo[s] = x;
+  g.ylo[s] = y;
+  g.dprevo[s] = g.dprev[k];
+  g.cato[s] = g.cat[k];
+  g.ido[s] = g.id[k];
+  g.spano[s] = span_at(a, x, y);
+}
+
+void launch_bin(const KArgs &a, const GatherArgs &g, int64_t nkeys, int32_t *scan_tmp,
+                hipStream_t s) {
+  const int B = 256;
+  int nb = (int)((a.n + B - 1) / B);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1024), dim3(256), 0, s, a.bin_fill, nkeys, 0);
+  if (nb) hipLaunchKernelGGL(k_bin_keys, dim3(nb), dim3(B), 0, s, a);
+  scan_i32(a.bin_fill, a.bin_start, nkeys, scan_tmp, s);
+  if (nb) hipLaunchKernelGGL(k_bin_scatter, dim3(nb), dim3(B), 0, s, a);
+  hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((nkeys + B - 1) / B)), dim3(B), 0, s, a, nkeys);
+  if (nb) hipLaunchKernelGGL(k_bin_gather, dim3(nb), dim3(B), 0, s, a, g);
+}
+
+void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(256), dim3(256), 0, s, p, n, v);
+}
+
+}  // namespace trime

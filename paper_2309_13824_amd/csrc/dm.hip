@@ -1,0 +1,398 @@
+// DistMesh step (Sec. 2.2, Alg. 1, Eq. 2-5) and state helper kernels.
+//
+// The paper scatters each edge force to both end points with atomics
+// (Sec. 5).  Here every point gathers over its own adjacency row instead:
+// the force of an edge is computed from the same inputs at both ends (the
+// midpoint (p_i + p_j)/2 and |p_i - p_j| are symmetric in i and j), so the
+// two ends see exactly opposite forces and no atomics are needed.
+// fac_mu (Eq. 3) is an ordered two-level reduction of sum l^2 and
+// sum mu(m)^2 over the unique edges (j > i), accumulated in FP64.
+#include "geom_dev.hpp"
+#include "launch.hpp"
+
+namespace trime {
+
+constexpr int DM_BLOCK = 256;
+
+template <class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_sums(KArgs a) {
+  __shared__ double s1[DM_BLOCK / 64], s2[DM_BLOCK / 64];
+  int64_t k = (int64_t)blockIdx.x * DM_BLOCK + threadIdx.x;
+  double l2 = 0.0, m2 = 0.0;
+  if (k < a.n) {
+    double px = a.x[k], py = a.y[k];
+    int d = a.deg[k];
+    for (int t = 0; t < d; t++) {
+      int j = a.adj[(int64_t)t * a.n + k];
+      if (j <= k) continue;
+      double qx = a.x[j], qy = a.y[j];
+      double dx = px - qx, dy = py - qy;
+      double m = mu_clamped<G>(a, (px + qx) * 0.5, (py + qy) * 0.5);
+      l2 += dx * dx + dy * dy;
+      m2 += m * m;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    l2 += __shfl_down(l2, off);
+    m2 += __shfl_down(m2, off);
+  }
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    s1[w] = l2;
+    s2[w] = m2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double A = 0, B = 0;
+    for (int q = 0; q < DM_BLOCK / 64; q++) {
+      A += s1[q];
+      B += s2[q];
+    }
+    a.partials[2 * blockIdx.x] = A;
+    a.partials[2 * blockIdx.x + 1] = B;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dm_final(KArgs a, int nparts) {
+  __shared__ double s1[256], s2[256];
+  double A = 0, B = 0;
+  for (int q = threadIdx.x; q < nparts; q += 256) {
+    A += a.partials[2 * q];
+    B += a.partials[2 * q + 1];
+  }
+  s1[threadIdx.x] = A;
+  s2[threadIdx.x] = B;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.stats->sum_l2 = s1[0];
+    a.stats->sum_mu2 = s2[0];
+    a.stats->fac_mu = s2[0] > 0 ? sqrt(s1[0] / s2[0]) : 0.0;
+  }
+}
+
+// Force, forward Euler, treatment and the large-movement test of one point.
+// T is the precision of the force arithmetic; returns false when a decision
+// fell within the FP32 band (replay in FP64).
+template <class T, class G>
+TRIME_D bool dm_point(const KArgs &a, int64_t k, int &moved, TreatCount &tc) {
+  double px = a.x[k], py = a.y[k];
+  double fac_mu = a.stats->fac_mu;
+  T l0s = (T)(a.prm.fac_F * fac_mu);
+  T Fx = 0, Fy = 0;
+  int d = a.deg[k];
+  for (int t = 0; t < d; t++) {
+    int j = a.adj[(int64_t)t * a.n + k];
+    double qx = a.x[j], qy = a.y[j];
+    T dx = (T)(px - qx), dy = (T)(py - qy);
+    T l = sqrt(dx * dx + dy * dy);
+    if (l == (T)0) continue;
+    T m = (T)mu_clamped<G>(a, (px + qx) * 0.5, (py + qy) * 0.5);
+    T l0 = m * l0s;
+    T f = l < l0 ? (T)a.prm.k_spring * (l0 - l) : (T)0;
+    T w = f / l;
+    Fx += w * dx;
+    Fy += w * dy;
+  }
+  double xnew = px + a.prm.dt * (double)Fx, ynew = py + a.prm.dt * (double)Fy;
+  int64_t cell;
+  double tx, ty;
+  double band = 0.0;
+  if (sizeof(T) == 4 && locate(a, px, py, cell, tx, ty)) band = 1e-6 * (double)a.hcell[cell];
+  double xf, yf;
+  uint8_t cf;
+  bool unsure = false;
+  treat<G>(a, px, py, a.cat[k], xnew, ynew, band, xf, yf, cf, unsure, tc);
+  moved = 0;
+  if (locate(a, xf, yf, cell, tx, ty)) {
+    double h = a.prm.fac_retria * (double)a.hcell[cell];
+    double ex = xf - a.xl[k], ey = yf - a.yl[k];
+    double r2 = ex * ex + ey * ey;
+    if (sizeof(T) == 4 && fabs(r2 - h * h) <= 1e-5 * h * h) unsure = true;
+    moved = r2 > h * h;
+  }
+  if (unsure) return false;
+  a.xn[k] = xf;
+  a.yn[k] = yf;
+  a.catn[k] = cf;
+  a.dprevn[k] = sqrt((xf - px) * (xf - px) + (yf - py) * (yf - py));
+  return true;
+}
+
+template <class T, class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_force(KArgs a) {
+  int64_t k = (int64_t)blockIdx.x * DM_BLOCK + threadIdx.x;
+  int moved = 0, replay = 0;
+  TreatCount tc;
+  if (k < a.n) {
+    if (!dm_point<T, G>(a, k, moved, tc)) {
+      int q = atomicAdd(&a.counters[CNT_QUEUE], 1);
+      a.queue[q] = (int)k;
+      replay = 1;
+      moved = 0;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    moved += __shfl_down(moved, off);
+    replay += __shfl_down(replay, off);
+    tc.newton_fail += __shfl_down(tc.newton_fail, off);
+    tc.trace_fail += __shfl_down(tc.trace_fail, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (moved) atomicAdd((unsigned long long *)&a.stats->moved, (unsigned long long)moved);
+    if (replay) atomicAdd((unsigned long long *)&a.stats->fp64_replays, (unsigned long long)replay);
+    if (tc.newton_fail)
+      atomicAdd((unsigned long long *)&a.stats->newton_fail, (unsigned long long)tc.newton_fail);
+    if (tc.trace_fail)
+      atomicAdd((unsigned long long *)&a.stats->trace_fail, (unsigned long long)tc.trace_fail);
+  }
+}
+
+template <class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_force_replay(KArgs a) {
+  int nq = a.counters[CNT_QUEUE];
+  for (int w = blockIdx.x * DM_BLOCK + threadIdx.x; w < nq; w += gridDim.x * DM_BLOCK) {
+    int64_t k = a.queue[w];
+    int moved = 0;
+    TreatCount tc;
+    dm_point<double, G>(a, k, moved, tc);
+    if (moved) atomicAdd((unsigned long long *)&a.stats->moved, 1ull);
+    if (tc.newton_fail) atomicAdd((unsigned long long *)&a.stats->newton_fail, 1ull);
+    if (tc.trace_fail) atomicAdd((unsigned long long *)&a.stats->trace_fail, 1ull);
+  }
+}
+
+__global__ void k_dm_flag(KArgs a) {
+  a.stats->retri_flag = a.stats->moved > 0 ? 1 : 0;
+  a.stats->iterations++;
+}
+
+__global__ void k_dm_begin(KArgs a) {
+  a.stats->moved = 0;
+  a.counters[CNT_QUEUE] = 0;
+}
+
+template <class G> static void launch_dm_g(const KArgs &a, hipStream_t s) {
+  int nb = (int)((a.n + DM_BLOCK - 1) / DM_BLOCK);
+  hipLaunchKernelGGL(k_dm_begin, dim3(1), dim3(1), 0, s, a);
+  hipLaunchKernelGGL(k_dm_sums<G>, dim3(nb), dim3(DM_BLOCK), 0, s, a);
+  hipLaunchKernelGGL(k_dm_final, dim3(1), dim3(256), 0, s, a, nb);
+  if (a.precision == TRIME_FP32)
+    hipLaunchKernelGGL((k_dm_force<float, G>), dim3(nb), dim3(DM_BLOCK), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_dm_force<double, G>), dim3(nb), dim3(DM_BLOCK), 0, s, a);
+  hipLaunchKernelGGL(k_dm_force_replay<G>, dim3(64), dim3(DM_BLOCK), 0, s, a);
+  hipLaunchKernelGGL(k_dm_flag, dim3(1), dim3(1), 0, s, a);
+}
+
+void launch_dm(const KArgs &a, int grid_bytes, hipStream_t s) {
+  if (grid_bytes == 4)
+    launch_dm_g<float>(a, s);
+  else
+    launch_dm_g<double>(a, s);
+}
+
+int dm_partials(int64_t n) { return (int)((n + DM_BLOCK - 1) / DM_BLOCK); }
+
+// ------------------------------------------------------------ helpers ----
+
+
+template <class G> __global__ void k_load(KArgs a, LoadArgs l) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.n) return;
+  double x = l.xin[k], y = l.yin[k];
+  l.x[k] = x;
+  l.y[k] = y;
+  l.xl[k] = x;
+  l.yl[k] = y;
+  l.dprev[k] = -1.0;
+  l.id[k] = (int)k;
+  l.span[k] = span_at(a, x, y);
+  bool unsure = false;
+  l.cat[k] = point_category<G>(a, x, y, 0.0, unsure);
+}
+
+void launch_load(const KArgs &a, const LoadArgs &l, int grid_bytes, hipStream_t s) {
+  int nb = (int)((a.n + 255) / 256);
+  if (!nb) return;
+  if (grid_bytes == 4)
+    hipLaunchKernelGGL(k_load<float>, dim3(nb), dim3(256), 0, s, a, l);
+  else
+    hipLaunchKernelGGL(k_load<double>, dim3(nb), dim3(256), 0, s, a, l);
+}
+
+__global__ void k_export_points(KArgs a, double *xo, double *yo, uint8_t *co) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.n) return;
+  int i = a.id[k];
+  if (xo) xo[i] = a.x[k];
+  if (yo) yo[i] = a.y[k];
+  if (co) co[i] = a.cat[k];
+}
+
+void launch_export_points(const KArgs &a, double *xo, double *yo, uint8_t *co, hipStream_t s) {
+  int nb = (int)((a.n + 255) / 256);
+  if (nb) hipLaunchKernelGGL(k_export_points, dim3(nb), dim3(256), 0, s, a, xo, yo, co);
+}
+
+// Triangles: offsets = exclusive scan of tri_n (slot order), then ids.
+__global__ void k_export_tri(KArgs a, const int32_t *off, int32_t *out, uint8_t *valid, int64_t cap,
+                             int64_t *count) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0 && count) *count = off[a.n];
+  if (k >= a.n) return;
+  int o = off[k];
+  for (int t = 0; t < a.tri_n[k]; t++) {
+    int64_t q = o + t;
+    if (q >= cap) return;
+    int64_t b = (k * TRIME_TRI_PER_POINT + t) * 3;
+    out[3 * q + 0] = a.id[a.tri[b + 0]];
+    out[3 * q + 1] = a.id[a.tri[b + 1]];
+    out[3 * q + 2] = a.id[a.tri[b + 2]];
+    valid[q] = a.tri_valid[k * TRIME_TRI_PER_POINT + t];
+  }
+}
+
+void launch_export_tri(const KArgs &a, int32_t *off, int32_t *scan_tmp, int32_t *out,
+                       uint8_t *valid, int64_t cap, int64_t *count, hipStream_t s) {
+  scan_i32(a.tri_n, off, a.n, scan_tmp, s);
+  int nb = (int)((a.n + 255) / 256);
+  if (nb) hipLaunchKernelGGL(k_export_tri, dim3(nb), dim3(256), 0, s, a, off, out, valid, cap, count);
+}
+
+// Adjacency rows translated to ids and sorted, id-major.
+__global__ void k_export_adj(KArgs a, int32_t *deg_o, int32_t *col_o) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.n) return;
+  int i = a.id[k];
+  int d = a.deg[k];
+  int md = a.max_deg;
+  int32_t *row = col_o + (int64_t)i * md;
+  for (int t = 0; t < d; t++) {
+    int v = a.id[a.adj[(int64_t)t * a.n + k]];
+    int u = t;
+    while (u > 0 && row[u - 1] > v) {
+      row[u] = row[u - 1];
+      u--;
+    }
+    row[u] = v;
+  }
+  deg_o[i] = d;
+}
+
+void launch_export_adj(const KArgs &a, int32_t *deg_o, int32_t *col_o, hipStream_t s) {
+  int nb = (int)((a.n + 255) / 256);
+  if (nb) hipLaunchKernelGGL(k_export_adj, dim3(nb), dim3(256), 0, s, a, deg_o, col_o);
+}
+
+// Quality of the stored valid triangles with the current positions.
+__global__ __launch_bounds__(256) void k_quality(KArgs a) {
+  __shared__ int hist[40];
+  for (int b = threadIdx.x; b < 40; b += 256) hist[b] = 0;
+  __syncthreads();
+  int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double sa = 0, sb = 0, sq = 0, amax = 0;
+  int nq = 0;
+  if (k < a.n) {
+    for (int t = 0; t < a.tri_n[k]; t++) {
+      if (!a.tri_valid[k * TRIME_TRI_PER_POINT + t]) continue;
+      int64_t b = (k * TRIME_TRI_PER_POINT + t) * 3;
+      int s0 = a.tri[b], s1 = a.tri[b + 1], s2 = a.tri[b + 2];
+      double ax = a.x[s0], ay = a.y[s0], bx = a.x[s1], by = a.y[s1], cx = a.x[s2], cy = a.y[s2];
+      double l0 = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
+      double l1 = sqrt((cx - bx) * (cx - bx) + (cy - by) * (cy - by));
+      double l2 = sqrt((ax - cx) * (ax - cx) + (ay - cy) * (ay - cy));
+      double A2 = fabs((bx - ax) * (cy - ay) - (by - ay) * (cx - ax));
+      double al = (l0 * l1 * l2) * (l0 + l1 + l2) / (4.0 * A2 * A2);
+      double be = fmax(l0, fmax(l1, l2)) / fmin(l0, fmin(l1, l2));
+      sa += sqrt(al);
+      sb += sqrt(be);
+      sq += 1.0 / al;
+      amax = fmax(amax, al);
+      nq++;
+      int bin = (int)floor((be - 1.0) / 2.0 * 40.0);
+      bin = bin < 0 ? 0 : (bin > 39 ? 39 : bin);
+      atomicAdd(&hist[bin], 1);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sa += __shfl_down(sa, off);
+    sb += __shfl_down(sb, off);
+    sq += __shfl_down(sq, off);
+    amax = fmax(amax, __shfl_down(amax, off));
+    nq += __shfl_down(nq, off);
+  }
+  if ((threadIdx.x & 63) == 0 && nq) {
+    atomicAdd(&a.stats->sum_sqrt_alpha, sa);
+    atomicAdd(&a.stats->sum_sqrt_beta, sb);
+    atomicAdd(&a.stats->sum_q, sq);
+    atomicMax((unsigned long long *)&a.stats->max_alpha, (unsigned long long)__double_as_longlong(amax));
+    atomicAdd((unsigned long long *)&a.stats->nq, (unsigned long long)nq);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < 40; b += 256)
+    if (hist[b]) atomicAdd((unsigned long long *)&a.stats->hist_beta[b], (unsigned long long)hist[b]);
+}
+
+// Clears the quality part of the stats (before an extraction / quality pass).
+__global__ void k_stats_reset_quality(KArgs a, int full) {
+  trime_stats *S = a.stats;
+  int t = threadIdx.x;
+  if (t < 40) S->hist_beta[t] = 0;
+  if (t == 0) {
+    S->sum_sqrt_alpha = 0;
+    S->sum_sqrt_beta = 0;
+    S->sum_q = 0;
+    S->max_alpha = 0;
+    S->nq = 0;
+    S->ntri = 0;
+    S->nvalid = 0;
+    S->moved = 0;
+    if (full) {
+      S->fp64_replays = 0;
+      S->exact_points = 0;
+      S->exact_calls = 0;
+      S->sos_calls = 0;
+      S->overflow_points = 0;
+      S->newton_fail = 0;
+      S->trace_fail = 0;
+      S->level_cap_hits = 0;
+      S->empty_cells = 0;
+      S->triangulations = 0;
+      S->iterations = 0;
+      S->retri_flag = 1;
+      S->error = 0;
+      S->sum_l2 = 0;
+      S->sum_mu2 = 0;
+      S->fac_mu = 0;
+    }
+  }
+  if (t < CNT_NCOUNTERS) a.counters[t] = 0;
+}
+
+void launch_stats_reset(const KArgs &a, int full, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_reset_quality, dim3(1), dim3(64), 0, s, a, full);
+}
+
+void launch_quality(const KArgs &a, hipStream_t s) {
+  int nb = (int)((a.n + 255) / 256);
+  hipLaunchKernelGGL(k_stats_reset_quality, dim3(1), dim3(64), 0, s, a, 0);
+  if (nb) hipLaunchKernelGGL(k_quality, dim3(nb), dim3(256), 0, s, a);
+}
+
+// Copies the error bits of the counters into the stats and counts an
+// extraction.
+__global__ void k_finish_extract(KArgs a) {
+  a.stats->error |= a.counters[CNT_ERR];
+  a.stats->triangulations++;
+  a.counters[CNT_QUEUE] = 0;
+}
+
+void launch_finish_extract(const KArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_extract, dim3(1), dim3(1), 0, s, a);
+}
+
+}  // namespace trime

@@ -1,0 +1,310 @@
+// Geometry grid (Sec. 3.1-3.3, Sec. 3.7): the signed distance of a
+// constructive geometry at the nodes (union = min, difference = max(a, -b),
+// intersection = max), the sizing field mu (rho = mu^-2, Eq. 9), the cell
+// categories (boundary iff |sdf(mid)| <= cell diagonal, else inner iff
+// sdf(mid) < 0, else outer) and h_cell = mu_cell * H with
+// H = sqrt(dx dy sum_sel mu_cell^-2 / N) over the selected cells (inner, and
+// boundary cells with sdf(mid) <= 0.5 min(dx, dy)); h_avg is the mean h of
+// the selected cells.  Midpoint values are the means of the 4 corner nodes.
+//
+// One thread per node.  A primitive whose distance bound cannot change the
+// running value (a hole far from the node) is skipped, so hundreds of holes
+// cost a few flops each.
+#include "launch.hpp"
+
+namespace trime {
+
+
+// D. Eberly's point-ellipse distance, first quadrant, e0 >= e1.
+TRIME_D double ellipse_q1(double e0, double e1, double y0, double y1) {
+  if (y1 > 0) {
+    if (y0 > 0) {
+      double z0 = y0 / e0, z1 = y1 / e1, g = z0 * z0 + z1 * z1 - 1.0;
+      if (g == 0.0) return 0.0;
+      double r0 = (e0 / e1) * (e0 / e1);
+      double n0 = r0 * z0, s0 = z1 - 1.0, s1 = g < 0 ? 0.0 : sqrt(n0 * n0 + z1 * z1) - 1.0;
+      double s = 0.0;
+      for (int it = 0; it < 2000; it++) {
+        s = 0.5 * (s0 + s1);
+        if (s == s0 || s == s1) break;
+        double q0 = n0 / (s + r0), q1 = z1 / (s + 1.0);
+        double gg = q0 * q0 + q1 * q1 - 1.0;
+        if (gg > 0)
+          s0 = s;
+        else if (gg < 0)
+          s1 = s;
+        else
+          break;
+      }
+      double x0 = r0 * y0 / (s + r0), x1 = y1 / (s + 1.0);
+      return sqrt((x0 - y0) * (x0 - y0) + (x1 - y1) * (x1 - y1));
+    }
+    return fabs(y1 - e1);
+  }
+  double numer0 = e0 * y0, denom0 = e0 * e0 - e1 * e1;
+  if (numer0 < denom0) {
+    double xd = numer0 / denom0;
+    double x0 = e0 * xd, x1 = e1 * sqrt(1.0 - xd * xd);
+    return sqrt((x0 - y0) * (x0 - y0) + x1 * x1);
+  }
+  return fabs(y0 - e0);
+}
+
+TRIME_D double prim_sdf(const trime_prim &pr, const double *poly, double x, double y) {
+  switch (pr.kind) {
+    case TRIME_PRIM_DISK: {
+      double dx = x - pr.p[0], dy = y - pr.p[1];
+      return sqrt(dx * dx + dy * dy) - pr.p[2];
+    }
+    case TRIME_PRIM_BOX: {
+      double ex = fmax(pr.p[0] - x, x - pr.p[2]);
+      double ey = fmax(pr.p[1] - y, y - pr.p[3]);
+      if (ex <= 0 && ey <= 0) return fmax(ex, ey);
+      double qx = fmax(ex, 0.0), qy = fmax(ey, 0.0);
+      return sqrt(qx * qx + qy * qy);
+    }
+    case TRIME_PRIM_ELLIPSE: {
+      double c = cos(pr.p[4]), s = sin(pr.p[4]);
+      double u = fabs(c * (x - pr.p[0]) + s * (y - pr.p[1]));
+      double v = fabs(-s * (x - pr.p[0]) + c * (y - pr.p[1]));
+      double a = pr.p[2], b = pr.p[3];
+      double in = (u / a) * (u / a) + (v / b) * (v / b) - 1.0;
+      double d = a >= b ? ellipse_q1(a, b, u, v) : ellipse_q1(b, a, v, u);
+      return in < 0 ? -d : d;
+    }
+    default: {  // polygon: segment distance, crossing-number sign
+      const double *v = poly + 2 * (int64_t)pr.voff;
+      int nv = pr.nv;
+      double d = INFINITY;
+      bool inside = false;
+      for (int k = 0; k < nv; k++) {
+        int k1 = (k + 1 == nv) ? 0 : k + 1;
+        double ax = v[2 * k], ay = v[2 * k + 1], bx = v[2 * k1], by = v[2 * k1 + 1];
+        double ex = bx - ax, ey = by - ay, wx = x - ax, wy = y - ay;
+        double L2 = ex * ex + ey * ey;
+        double t = L2 > 0 ? (wx * ex + wy * ey) / L2 : 0.0;
+        t = fmin(fmax(t, 0.0), 1.0);
+        double qx = wx - t * ex, qy = wy - t * ey;
+        d = fmin(d, sqrt(qx * qx + qy * qy));
+        if ((ay > y) != (by > y)) {
+          double xc = ax + (y - ay) * (bx - ax) / (by - ay);
+          if (x < xc) inside = !inside;
+        }
+      }
+      return inside ? -d : d;
+    }
+  }
+}
+
+// A radius R and centre with |sdf| >= dist(x, c) - R outside the circle, for
+// disks and ellipses; other primitives have no cheap bound (R < 0).
+TRIME_D double prim_bound(const trime_prim &pr, double &cx, double &cy) {
+  if (pr.kind == TRIME_PRIM_DISK) {
+    cx = pr.p[0];
+    cy = pr.p[1];
+    return pr.p[2];
+  }
+  if (pr.kind == TRIME_PRIM_ELLIPSE) {
+    cx = pr.p[0];
+    cy = pr.p[1];
+    return fmax(pr.p[2], pr.p[3]);
+  }
+  return -1.0;
+}
+
+TRIME_D double csg_sdf(const GridPrims &g, double x, double y) {
+  double s = INFINITY;
+  for (int k = 0; k < g.nprims; k++) {
+    const trime_prim &pr = g.prims[k];
+    double cx, cy, R = prim_bound(pr, cx, cy);
+    if (R >= 0 && k > 0) {
+      double dist = sqrt((x - cx) * (x - cx) + (y - cy) * (y - cy)) - R;
+      // t >= dist (outside the bound circle)
+      if (dist > 0) {
+        if (pr.op == TRIME_OP_DIFF && -dist <= s) continue;
+        if (pr.op == TRIME_OP_UNION && dist >= s) continue;
+      }
+    }
+    double t = prim_sdf(pr, g.poly, x, y);
+    switch (pr.op) {
+      case TRIME_OP_INIT: s = t; break;
+      case TRIME_OP_UNION: s = fmin(s, t); break;
+      case TRIME_OP_DIFF: s = fmax(s, -t); break;
+      default: s = fmax(s, t); break;
+    }
+  }
+  return s;
+}
+
+TRIME_D double sizing_mu(const GridPrims &g, double x, double y, double sdf) {
+  switch (g.sz.kind) {
+    case TRIME_SZ_UNIFORM: return 1.0;
+    case TRIME_SZ_ABS_SDF: return g.sz.a0 + g.sz.a1 * fabs(sdf);
+    case TRIME_SZ_GAUSS_RHO: {
+      double acc = 0.0;
+      for (int k = 0; k < g.sz.ncent; k++) {
+        double dx = x - g.cent[2 * k], dy = y - g.cent[2 * k + 1];
+        acc += exp(-(dx * dx + dy * dy) / g.sz.s2);
+      }
+      return 1.0 / sqrt(g.sz.a0 + g.sz.a1 * acc);
+    }
+    default: {
+      double dh = INFINITY;
+      for (int k = 0; k < g.sz.nholes; k++) {
+        const trime_prim &pr = g.prims[g.holes[k]];
+        double cx, cy, R = prim_bound(pr, cx, cy);
+        if (R >= 0) {
+          double lb = sqrt((x - cx) * (x - cx) + (y - cy) * (y - cy)) - R;
+          if (lb > dh) continue;
+        }
+        dh = fmin(dh, fabs(prim_sdf(pr, g.poly, x, y)));
+      }
+      double r = fmin(dh / g.sz.a1, 1.0);
+      return 1.0 + (g.sz.a0 - 1.0) * r;
+    }
+  }
+}
+
+template <class G> __global__ void k_grid_nodes(GridPrims g, G *sdf, G *mu) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t nn = (int64_t)g.nx * g.ny;
+  if (k >= nn) return;
+  int i = (int)(k % g.nx), j = (int)(k / g.nx);
+  double x = g.x0 + i * g.dx, y = g.y0 + j * g.dy;
+  double s = csg_sdf(g, x, y);
+  sdf[k] = (G)s;
+  mu[k] = (G)sizing_mu(g, x, y, s);
+}
+
+constexpr int GB = 256;
+
+template <class G>
+__global__ __launch_bounds__(GB) void k_grid_cells(GridPrims g, const G *sdf, const G *mu,
+                                                   uint8_t *cat, double *part) {
+  __shared__ double s1[GB], s2[GB];
+  int64_t c = (int64_t)blockIdx.x * GB + threadIdx.x;
+  int cxn = g.nx - 1;
+  int64_t nc = (int64_t)cxn * (g.ny - 1);
+  double rho = 0.0, cnt = 0.0;
+  if (c < nc) {
+    int i = (int)(c % cxn), j = (int)(c / cxn);
+    int64_t n0 = (int64_t)j * g.nx + i;
+    double sm = (((double)sdf[n0] + (double)sdf[n0 + 1]) + ((double)sdf[n0 + g.nx] + (double)sdf[n0 + g.nx + 1])) * 0.25;
+    double ld = sqrt(g.dx * g.dx + g.dy * g.dy);
+    uint8_t ct = fabs(sm) <= ld ? TRIME_CAT_BOUNDARY : (sm < 0 ? TRIME_CAT_INNER : TRIME_CAT_OUTER);
+    cat[c] = ct;
+    bool sel = ct == TRIME_CAT_INNER || (ct == TRIME_CAT_BOUNDARY && sm <= 0.5 * fmin(g.dx, g.dy));
+    if (sel) {
+      double mm = (((double)mu[n0] + (double)mu[n0 + 1]) + ((double)mu[n0 + g.nx] + (double)mu[n0 + g.nx + 1])) * 0.25;
+      rho = 1.0 / (mm * mm);
+      cnt = 1.0;
+    }
+  }
+  s1[threadIdx.x] = rho;
+  s2[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int w = GB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1[0];
+    part[2 * blockIdx.x + 1] = s2[0];
+  }
+}
+
+__global__ __launch_bounds__(GB) void k_grid_reduce(GridPrims g, const double *part, int np,
+                                                    trime_grid_scalars *scal, int stage) {
+  __shared__ double s1[GB], s2[GB];
+  double A = 0, B = 0;
+  for (int q = threadIdx.x; q < np; q += GB) {
+    A += part[2 * q];
+    B += part[2 * q + 1];
+  }
+  s1[threadIdx.x] = A;
+  s2[threadIdx.x] = B;
+  __syncthreads();
+  for (int w = GB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (stage == 0) {
+      scal->H = sqrt(g.dx * g.dy * s1[0] / (double)g.n_total);
+      scal->n_sel = (int64_t)s2[0];
+      scal->area_sel = s2[0] * g.dx * g.dy;
+    } else {
+      scal->h_avg = s2[0] > 0 ? s1[0] / s2[0] : 0.0;
+    }
+  }
+}
+
+template <class G>
+__global__ __launch_bounds__(GB) void k_grid_h(GridPrims g, const G *sdf, const G *mu,
+                                               const uint8_t *cat, const trime_grid_scalars *scal,
+                                               float *hcell, double *part) {
+  __shared__ double s1[GB], s2[GB];
+  int64_t c = (int64_t)blockIdx.x * GB + threadIdx.x;
+  int cxn = g.nx - 1;
+  int64_t nc = (int64_t)cxn * (g.ny - 1);
+  double hs = 0.0, cnt = 0.0;
+  if (c < nc) {
+    int i = (int)(c % cxn), j = (int)(c / cxn);
+    int64_t n0 = (int64_t)j * g.nx + i;
+    double mm = (((double)mu[n0] + (double)mu[n0 + 1]) + ((double)mu[n0 + g.nx] + (double)mu[n0 + g.nx + 1])) * 0.25;
+    float h = (float)(mm * scal->H);
+    hcell[c] = h;
+    uint8_t ct = cat[c];
+    double sm = (((double)sdf[n0] + (double)sdf[n0 + 1]) + ((double)sdf[n0 + g.nx] + (double)sdf[n0 + g.nx + 1])) * 0.25;
+    if (ct == TRIME_CAT_INNER || (ct == TRIME_CAT_BOUNDARY && sm <= 0.5 * fmin(g.dx, g.dy))) {
+      hs = (double)h;
+      cnt = 1.0;
+    }
+  }
+  s1[threadIdx.x] = hs;
+  s2[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int w = GB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1[0];
+    part[2 * blockIdx.x + 1] = s2[0];
+  }
+}
+
+template <class G>
+static void grid_build_g(const GridPrims &g, void *sdf, void *mu, uint8_t *cat, float *hcell,
+                         trime_grid_scalars *scal, double *part, hipStream_t s) {
+  int64_t nn = (int64_t)g.nx * g.ny;
+  int64_t nc = (int64_t)(g.nx - 1) * (g.ny - 1);
+  int nbn = (int)((nn + 255) / 256);
+  int nbc = (int)((nc + GB - 1) / GB);
+  hipLaunchKernelGGL(k_grid_nodes<G>, dim3(nbn), dim3(256), 0, s, g, (G *)sdf, (G *)mu);
+  hipLaunchKernelGGL(k_grid_cells<G>, dim3(nbc), dim3(GB), 0, s, g, (const G *)sdf, (const G *)mu, cat, part);
+  hipLaunchKernelGGL(k_grid_reduce, dim3(1), dim3(GB), 0, s, g, part, nbc, scal, 0);
+  hipLaunchKernelGGL(k_grid_h<G>, dim3(nbc), dim3(GB), 0, s, g, (const G *)sdf, (const G *)mu, cat, scal, hcell, part);
+  hipLaunchKernelGGL(k_grid_reduce, dim3(1), dim3(GB), 0, s, g, part, nbc, scal, 1);
+}
+
+int64_t grid_partials(int nx, int ny) { return ((int64_t)(nx - 1) * (ny - 1) + GB - 1) / GB; }
+
+void launch_grid_build(const GridPrims &g, int dtype_bytes, void *sdf, void *mu, uint8_t *cat,
+                       float *hcell, trime_grid_scalars *scal, double *part, hipStream_t s) {
+  if (dtype_bytes == 4)
+    grid_build_g<float>(g, sdf, mu, cat, hcell, scal, part, s);
+  else
+    grid_build_g<double>(g, sdf, mu, cat, hcell, scal, part, s);
+}
+
+}  // namespace trime

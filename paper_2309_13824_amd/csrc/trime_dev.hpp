@@ -1,0 +1,141 @@
+// Internal device-side definitions of the trime library (gfx950).
+//
+// Everything here follows the definitions stated in include/trime.h; the
+// comments cite the paper (TriMe++, arXiv 2309.13824) by section/equation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/trime.h"
+
+#define TRIME_HD __host__ __device__ __forceinline__
+#define TRIME_D __device__ __forceinline__
+
+namespace trime {
+
+// Unit roundoff of the two working precisions.
+template <class T> struct U;
+template <> struct U<float> { static constexpr float v = 5.9604645e-8f; };          // 2^-24
+template <> struct U<double> { static constexpr double v = 1.1102230246251565e-16; }; // 2^-53
+
+// Everything a kernel needs, passed by value (well under the 4 KiB limit).
+struct KArgs {
+  int64_t n;
+  // per-point arrays in slot order: current positions, next positions
+  const double *x, *y;
+  double *xn, *yn;
+  const double *xl, *yl;  // positions at the last triangulation
+  const double *dprev;
+  double *dprevn;
+  const uint8_t *cat;
+  uint8_t *catn;
+  const float *span;
+  const int32_t *id;
+  // binning
+  int32_t *perm;
+  int32_t *bin_start, *bin_fill, *key, *rank;
+  int32_t nbx, nby, lbits;
+  double bx0, by0, bw, inv_bw;
+  // grid
+  int32_t nx, ny;
+  double gx0, gy0, gdx, gdy, inv_dx, inv_dy;
+  double box_x0, box_y0, box_x1, box_y1;
+  const void *sdf, *mu;
+  const uint8_t *cgrid;
+  const float *hcell;
+  const trime_grid_scalars *scal;
+  // connectivity
+  int32_t max_deg;
+  int32_t *adj, *deg;
+  int32_t *tri;  // TRIME_TRI_PER_POINT triangles per owner slot
+  uint8_t *tri_valid;
+  int32_t *tri_n;
+  // work queue / counters / stats
+  int32_t *queue;
+  int32_t *counters;  // [0] queue length, [1] triangle count, [2] error bits
+  double *partials;
+  trime_stats *stats;
+  // cell output (trime_voronoi_cells)
+  int32_t *cell_cons, *cell_n;
+  int32_t cell_cap;
+  trime_params prm;
+  int32_t precision;
+};
+
+enum { CNT_QUEUE = 0, CNT_TRI = 1, CNT_ERR = 2, CNT_MOVED = 3, CNT_NCOUNTERS = 8 };
+enum { ERR_TRI_CAP = 1, ERR_DEG_CAP = 2, ERR_POLY_CAP = 4, ERR_EXACT_CAP = 8, ERR_QUEUE = 16 };
+
+// ---------------------------------------------------------------- grid ----
+
+template <class G> TRIME_D double gval(const void *p, int64_t k) {
+  return (double)((const G *)p)[k];
+}
+
+// Cell of (x, y): f = (x - x0) * (1/dx), cell = floor(f), t = f - cell.
+// Returns false off the grid.
+TRIME_D bool locate(const KArgs &a, double x, double y, int64_t &cell, double &tx, double &ty) {
+  double fx = (x - a.gx0) * a.inv_dx;
+  double fy = (y - a.gy0) * a.inv_dy;
+  if (!(fx >= 0.0) || !(fy >= 0.0)) return false;
+  double ix = floor(fx), iy = floor(fy);
+  if (ix >= (double)(a.nx - 1) || iy >= (double)(a.ny - 1)) return false;
+  cell = (int64_t)iy * (a.nx - 1) + (int64_t)ix;
+  tx = fx - ix;
+  ty = fy - iy;
+  return true;
+}
+
+// Bilinear value inside a cell: (f00 (1-tx) + f10 tx)(1-ty) + (f01 (1-tx) + f11 tx) ty.
+template <class G>
+TRIME_D double bilinear(const KArgs &a, const void *f, int64_t cell, double tx, double ty) {
+  int64_t ci = cell % (a.nx - 1), cj = cell / (a.nx - 1);
+  int64_t n0 = cj * a.nx + ci;
+  double f00 = gval<G>(f, n0), f10 = gval<G>(f, n0 + 1);
+  double f01 = gval<G>(f, n0 + a.nx), f11 = gval<G>(f, n0 + a.nx + 1);
+  return (f00 * (1.0 - tx) + f10 * tx) * (1.0 - ty) + (f01 * (1.0 - tx) + f11 * tx) * ty;
+}
+
+// geps of a cell (Sec. 3.7): fac_geps * min(h_cell, h_avg).
+TRIME_D double geps_of(const KArgs &a, int64_t cell) {
+  return a.prm.fac_geps * fmin((double)a.hcell[cell], a.scal->h_avg);
+}
+
+// mu anywhere (cells clamped to the grid), used by the quadrature and forces.
+template <class G> TRIME_D double mu_clamped(const KArgs &a, double x, double y) {
+  double fx = (x - a.gx0) * a.inv_dx, fy = (y - a.gy0) * a.inv_dy;
+  double ix = floor(fx), iy = floor(fy);
+  ix = fmin(fmax(ix, 0.0), (double)(a.nx - 2));
+  iy = fmin(fmax(iy, 0.0), (double)(a.ny - 2));
+  double tx = fmin(fmax(fx - ix, 0.0), 1.0), ty = fmin(fmax(fy - iy, 0.0), 1.0);
+  int64_t cell = (int64_t)iy * (a.nx - 1) + (int64_t)ix;
+  return bilinear<G>(a, a.mu, cell, tx, ty);
+}
+
+// ------------------------------------------------------------- morton ----
+TRIME_HD uint32_t spread2(uint32_t v) {
+  v &= 0xffff;
+  v = (v | (v << 8)) & 0x00ff00ff;
+  v = (v | (v << 4)) & 0x0f0f0f0f;
+  v = (v | (v << 2)) & 0x33333333;
+  v = (v | (v << 1)) & 0x55555555;
+  return v;
+}
+TRIME_HD uint32_t morton(uint32_t bx, uint32_t by) { return spread2(bx) | (spread2(by) << 1); }
+
+TRIME_D void bin_of(const KArgs &a, double x, double y, int &bx, int &by) {
+  bx = (int)floor((x - a.bx0) * a.inv_bw);
+  by = (int)floor((y - a.by0) * a.inv_bw);
+  bx = bx < 0 ? 0 : (bx >= a.nbx ? a.nbx - 1 : bx);
+  by = by < 0 ? 0 : (by >= a.nby ? a.nby - 1 : by);
+}
+
+// Span S of the octagon of a point (Sec. 4.1): fac_voro * h of its cell, in
+// float; D = fl32(fl32(sqrt 2) * S).
+TRIME_D float span_at(const KArgs &a, double x, double y) {
+  int64_t cell;
+  double tx, ty;
+  if (!locate(a, x, y, cell, tx, ty)) return -1.0f;
+  return (float)a.prm.fac_voro * a.hcell[cell];
+}
+
+}  // namespace trime

@@ -1,0 +1,143 @@
+"""A meshing run on one GPU: owns the device tensors of one workload and
+calls the C ABI (paper_2309_13824_amd.trime) for every step."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import trime as T
+
+
+def _geometry(wl):
+    poly, offs = wl.poly_array()
+    prims = (T.Prim * len(wl.prims))()
+    for k, pr in enumerate(wl.prims):
+        prims[k].op = pr.op
+        prims[k].kind = pr.kind
+        for t, v in enumerate(pr.p):
+            prims[k].p[t] = float(v)
+        prims[k].voff, prims[k].nv = offs[k]
+    poly = np.ascontiguousarray(poly.reshape(-1), np.float64)
+    geo = T.Geometry(len(wl.prims), prims, len(poly) // 2, poly.ctypes.data_as(C.POINTER(C.c_double)))
+    s = wl.sizing
+    cent = np.ascontiguousarray(np.asarray(s.cent, np.float64).reshape(-1))
+    holes = np.ascontiguousarray(np.asarray(s.holes, np.int32))
+    sz = T.Sizing(s.kind, s.a0, s.a1, s.s2, len(cent) // 2, cent.ctypes.data_as(C.POINTER(C.c_double)),
+                  len(holes), holes.ctypes.data_as(C.POINTER(C.c_int32)))
+    return geo, sz, (prims, poly, cent, holes)
+
+
+class Mesher:
+    """Grid + state of one workload on the current HIP device."""
+
+    def __init__(self, wl, precision=T.FP64, max_deg=16, params=None, bin_density=0.0, device="cuda"):
+        import torch
+        T.lib()
+        self.torch = torch
+        self.wl = wl
+        self.dev = torch.device(device)
+        g = wl.grid
+        self.grid = T.Grid(g.nx, g.ny, g.x0, g.y0, g.dx, g.dy, g.dtype_bytes)
+        gd = torch.float32 if g.dtype_bytes == 4 else torch.float64
+        nn, nc = g.nx * g.ny, (g.nx - 1) * (g.ny - 1)
+        self.sdf = torch.empty(nn, dtype=gd, device=self.dev)
+        self.mu = torch.empty(nn, dtype=gd, device=self.dev)
+        self.cat = torch.empty(nc, dtype=torch.uint8, device=self.dev)
+        self.hcell = torch.empty(nc, dtype=torch.float32, device=self.dev)
+        self.scal = torch.zeros(4, dtype=torch.float64, device=self.dev)
+        geo, sz, keep = _geometry(wl)
+        T.sdf_grid_build(geo, sz, self.grid, wl.n, self.sdf, self.mu, self.cat, self.hcell, self.scal)
+        torch.cuda.synchronize()
+        del keep
+        st = T.State()
+        st.n = wl.n
+        st.precision = precision
+        st.max_deg = max_deg
+        st.bin_density = bin_density
+        st.grid = self.grid
+        st.sdf, st.mu = self.sdf.data_ptr(), self.mu.data_ptr()
+        st.cat_grid, st.hcell, st.scal = self.cat.data_ptr(), self.hcell.data_ptr(), self.scal.data_ptr()
+        st.params = params if params is not None else T.default_params()
+        self.state = st
+        nbytes = T.state_workspace_bytes(st)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.dev)
+        T.state_bind(st, self.ws)
+        self.n = wl.n
+
+    # ---------------------------------------------------------------- input
+    def load(self, x=None, y=None):
+        torch = self.torch
+        x = self.wl.x if x is None else x
+        y = self.wl.y if y is None else y
+        self.x_in = torch.as_tensor(np.ascontiguousarray(x, np.float64), device=self.dev)
+        self.y_in = torch.as_tensor(np.ascontiguousarray(y, np.float64), device=self.dev)
+        T.state_load(self.state, self.x_in, self.y_in)
+
+    # ---------------------------------------------------------------- steps
+    def bin(self):
+        T.bin_points(self.state)
+
+    def extract(self):
+        T.delaunay_extract(self.state)
+
+    def cells(self, cap=64):
+        torch = self.torch
+        cons = torch.full((self.n * cap,), -99, dtype=torch.int32, device=self.dev)
+        ncons = torch.zeros(self.n, dtype=torch.int32, device=self.dev)
+        out = T.Cells(cap, cons.data_ptr(), ncons.data_ptr())
+        T.voronoi_cells(self.state, out)
+        cons = cons.view(self.n, cap).cpu().numpy()
+        ncons = ncons.cpu().numpy()
+        return [tuple(int(v) for v in cons[i, :ncons[i]]) if ncons[i] >= 0 else None for i in range(self.n)]
+
+    def step_dm(self, n_iter, fresh=True, always=False):
+        T.step_dm(self.state, n_iter, fresh, always)
+
+    def step_cvd(self, n_iter):
+        T.step_cvd(self.state, n_iter)
+
+    def step_hybrid(self, schedule):
+        T.step_hybrid(self.state, schedule)
+
+    def quality(self):
+        T.quality(self.state)
+
+    # --------------------------------------------------------------- output
+    def grid_arrays(self):
+        return (self.sdf.double().cpu().numpy(), self.mu.double().cpu().numpy(), self.cat.cpu().numpy(),
+                self.hcell.cpu().numpy(), self.scal.cpu().numpy())
+
+    def points(self):
+        torch = self.torch
+        x = torch.empty(self.n, dtype=torch.float64, device=self.dev)
+        y = torch.empty(self.n, dtype=torch.float64, device=self.dev)
+        c = torch.empty(self.n, dtype=torch.uint8, device=self.dev)
+        T.export_points(self.state, x, y, c)
+        return x.cpu().numpy(), y.cpu().numpy(), c.cpu().numpy()
+
+    def triangles(self):
+        torch = self.torch
+        cap = self.n * T.TRI_PER_POINT
+        tri = torch.empty((cap, 3), dtype=torch.int32, device=self.dev)
+        valid = torch.empty(cap, dtype=torch.uint8, device=self.dev)
+        cnt = torch.zeros(1, dtype=torch.int64, device=self.dev)
+        T.export_triangles(self.state, tri, valid, cnt)
+        m = int(cnt.item())
+        return tri[:m].cpu().numpy(), valid[:m].cpu().numpy()
+
+    def adjacency(self):
+        torch = self.torch
+        md = self.state.max_deg
+        deg = torch.empty(self.n, dtype=torch.int32, device=self.dev)
+        col = torch.empty(self.n * md, dtype=torch.int32, device=self.dev)
+        T.export_adjacency(self.state, deg, col)
+        deg = deg.cpu().numpy()
+        col = col.view(self.n, md).cpu().numpy()
+        return [tuple(int(v) for v in col[i, :deg[i]]) for i in range(self.n)]
+
+    def stats(self) -> dict:
+        return T.stats_read(self.state).as_dict()
+
+    def stats_raw(self):
+        return T.stats_read(self.state)

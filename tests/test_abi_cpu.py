@@ -1,0 +1,118 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, and rejects bad arguments on the host before any launch."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "trime.h")
+LIB = os.path.join(ROOT, "paper_2309_13824_amd", "libtrime.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(trime_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not os.path.exists(LIB):
+        from paper_2309_13824_amd import build
+        build.build()
+    from paper_2309_13824_amd import trime
+    return trime
+
+
+def test_header_declares_the_entry_points():
+    names = declared()
+    for f in ("trime_sdf_grid_build", "trime_bin_points", "trime_voronoi_cells", "trime_delaunay_extract",
+              "trime_step_dm", "trime_step_cvd", "trime_step_hybrid"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(T):
+    L = T.lib(require_gpu=False)
+    for f in declared():
+        assert hasattr(L, f), f
+    assert set(declared()) == set(T.EXPORTED)
+
+
+def test_version_and_defaults(T):
+    L = T.lib(require_gpu=False)
+    assert L.trime_version().startswith(b"trime")
+    p = T.default_params()
+    assert (p.fac_F, p.fac_voro, p.fac_pt, p.fac_retria, p.fac_end, p.fac_geps, p.T_tria, p.alpha_hat,
+            p.T_newton) == (1.2, 5.0, 0.4, 0.1, 0.001, 0.01, 0.4, 1.0, 10)
+
+
+def test_null_and_bad_arguments_rejected_on_host(T):
+    L = T.lib(require_gpu=False)
+    # grid build with null geometry
+    g = T.Grid(16, 16, 0.0, 0.0, 0.1, 0.1, 8)
+    rc = L.trime_sdf_grid_build(None, None, C.byref(g), 100, None, None, None, None, None, None)
+    assert rc == 1 and b"null" in L.trime_last_error()
+    # bad grid dtype
+    g2 = T.Grid(16, 16, 0.0, 0.0, 0.1, 0.1, 3)
+    st = T.State()
+    st.n = 10
+    st.grid = g2
+    b = C.c_size_t()
+    assert L.trime_state_workspace_bytes(C.byref(st), C.byref(b)) == 1
+    # missing grid arrays
+    st.grid = g
+    assert L.trime_state_workspace_bytes(C.byref(st), C.byref(b)) == 1
+    # unbound state
+    st.sdf = st.mu = st.cat_grid = st.hcell = st.scal = 256
+    assert L.trime_step_cvd(C.byref(st), 1, None) == 1
+    assert L.trime_bin_points(C.byref(st), None) == 1
+    # negative n
+    st.n = -5
+    assert L.trime_state_workspace_bytes(C.byref(st), C.byref(b)) == 1
+    # bad precision
+    st.n = 10
+    st.precision = 7
+    assert L.trime_state_workspace_bytes(C.byref(st), C.byref(b)) == 1
+
+
+def test_schedule_validation(T):
+    L = T.lib(require_gpu=False)
+    st = T.State()
+    assert L.trime_step_hybrid(C.byref(st), None, None) == 1
+
+
+def test_stats_check_codes(T):
+    L = T.lib(require_gpu=False)
+    s = T.Stats()
+    assert L.trime_stats_check(C.byref(s)) == 0
+    s.error = 1
+    assert L.trime_stats_check(C.byref(s)) == 3
+    s.error = 0
+    s.empty_cells = 2
+    assert L.trime_stats_check(C.byref(s)) == 5
+
+
+def test_struct_sizes_match_header(T):
+    """The ctypes mirrors have the sizes the C compiler gives the structs."""
+    import subprocess
+    import tempfile
+    src = r'''
+#include <stdio.h>
+#include "trime.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(trime_prim), sizeof(trime_sizing), sizeof(trime_grid),
+         sizeof(trime_params), sizeof(trime_stats), sizeof(trime_state), sizeof(trime_grid_scalars));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "s.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "s")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    sizes = [int(v) for v in out]
+    assert sizes == [C.sizeof(T.Prim), C.sizeof(T.Sizing), C.sizeof(T.Grid), C.sizeof(T.Params),
+                     C.sizeof(T.Stats), C.sizeof(T.State), C.sizeof(T.GridScalars)]
