@@ -207,6 +207,9 @@ typedef struct {
   double bx0, by0, bw;
   double area_sel;         /* host copy of scal->area_sel                    */
   int64_t nkeys;
+  /* optional hipEvent_t pair (caller-owned, may be null): recorded just
+     before and after the fused cell kernel of each extraction / CVD step */
+  void *ev_cells[2];
 } trime_state;
 
 /* A fixed hybrid schedule: segments (method, iterations) run in order. */

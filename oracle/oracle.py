@@ -125,6 +125,7 @@ def lib():
                                 C.c_double, C.c_double, dp, dp, u8p, C.POINTER(Counters)]
         L.orc_point_category.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_double, C.c_double]
         L.orc_point_category.restype = C.c_uint8
+        L.orc_point_categories.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int64, dp, dp, u8p]
         L.orc_quality.argtypes = [dp, dp, i32p, u8p, C.c_int64, C.POINTER(Stats)]
         L.orc_triangle_quality.argtypes = [C.c_double] * 6 + [dp, dp]
         L.orc_predicate.argtypes = [C.POINTER(Grid), C.POINTER(Params), dp, dp, C.c_int64, C.c_int32,
@@ -314,10 +315,14 @@ def triangle_valid(grid: OracleGrid, x, y, a, b, c, params=None) -> int:
 
 
 def point_categories(grid: OracleGrid, x, y, params=None) -> np.ndarray:
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
     g = grid.c()
     prm = params or default_params()
-    return np.array([lib().orc_point_category(C.byref(g), C.byref(prm), float(a), float(b))
-                     for a, b in zip(x, y)], np.uint8)
+    out = np.empty(len(x), np.uint8)
+    lib().orc_point_categories(C.byref(g), C.byref(prm), len(x), _p(x, C.c_double), _p(y, C.c_double),
+                               _p(out, C.c_uint8))
+    return out
 
 
 def fac_mu(grid: OracleGrid, x, y, mesh: Mesh):

@@ -179,6 +179,8 @@ void orc_treat(const orc_grid *g, const orc_params *prm, double xo, double yo, u
                double xnew, double ynew, double *xf, double *yf, uint8_t *catf,
                orc_counters *cnt);
 uint8_t orc_point_category(const orc_grid *g, const orc_params *prm, double x, double y);
+void orc_point_categories(const orc_grid *g, const orc_params *prm, int64_t n, const double *x,
+                          const double *y, uint8_t *out);
 
 /* ---- mesh quality (Sec. 3.6, Eq. 10-11) ---------------------------------- */
 typedef struct {

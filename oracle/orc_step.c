@@ -409,3 +409,8 @@ int orc_cvd_step(const orc_grid *g, const orc_params *prm, int64_t n, const doub
   }
   return 0;
 }
+
+void orc_point_categories(const orc_grid *g, const orc_params *prm, int64_t n, const double *x,
+                          const double *y, uint8_t *out) {
+  for (int64_t i = 0; i < n; i++) out[i] = orc_point_category(g, prm, x[i], y[i]);
+}

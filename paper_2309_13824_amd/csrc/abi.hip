@@ -318,6 +318,8 @@ static KArgs make_args(const trime_state *st) {
   a.stats = st->stats;
   a.prm = st->params;
   a.precision = st->precision;
+  a.ev0 = st->ev_cells[0];
+  a.ev1 = st->ev_cells[1];
   return a;
 }
 

@@ -758,7 +758,9 @@ constexpr int REPLAY_VMAX = 32;
 
 template <class T, class G, int MODE> static void launch_mode(const KArgs &a, hipStream_t s) {
   int nb = (int)((a.n + FAST_BLOCK - 1) / FAST_BLOCK);
+  if (a.ev0) (void)hipEventRecord((hipEvent_t)a.ev0, s);
   if (nb > 0) hipLaunchKernelGGL((k_cells<T, G, MODE, FAST_VMAX, FAST_BLOCK>), dim3(nb), dim3(FAST_BLOCK), 0, s, a);
+  if (a.ev1) (void)hipEventRecord((hipEvent_t)a.ev1, s);
   hipLaunchKernelGGL((k_cells_replay<G, MODE, REPLAY_VMAX, REPLAY_BLOCK>), dim3(256), dim3(REPLAY_BLOCK), 0, s, a);
 }
 

@@ -60,6 +60,7 @@ struct KArgs {
   int32_t cell_cap;
   trime_params prm;
   int32_t precision;
+  void *ev0, *ev1;  // optional timing events around the fused cell kernel
 };
 
 enum { CNT_QUEUE = 0, CNT_TRI = 1, CNT_ERR = 2, CNT_MOVED = 3, CNT_NCOUNTERS = 8 };

@@ -31,7 +31,11 @@ def _geometry(wl):
 class Mesher:
     """Grid + state of one workload on the current HIP device."""
 
-    def __init__(self, wl, precision=T.FP64, max_deg=16, params=None, bin_density=0.0, device="cuda"):
+    def __init__(self, wl, precision=T.FP64, max_deg=16, params=None, bin_density=0.0, device="cuda",
+                 grid=None):
+        """grid: None builds the geometry grid on the GPU (trime_sdf_grid_build);
+        otherwise an object with sdf, mu, cat, hcell (node / cell arrays), H and
+        h_avg whose arrays are uploaded as the grid (a grid built elsewhere)."""
         import torch
         T.lib()
         self.torch = torch
@@ -41,15 +45,24 @@ class Mesher:
         self.grid = T.Grid(g.nx, g.ny, g.x0, g.y0, g.dx, g.dy, g.dtype_bytes)
         gd = torch.float32 if g.dtype_bytes == 4 else torch.float64
         nn, nc = g.nx * g.ny, (g.nx - 1) * (g.ny - 1)
-        self.sdf = torch.empty(nn, dtype=gd, device=self.dev)
-        self.mu = torch.empty(nn, dtype=gd, device=self.dev)
-        self.cat = torch.empty(nc, dtype=torch.uint8, device=self.dev)
-        self.hcell = torch.empty(nc, dtype=torch.float32, device=self.dev)
-        self.scal = torch.zeros(4, dtype=torch.float64, device=self.dev)
-        geo, sz, keep = _geometry(wl)
-        T.sdf_grid_build(geo, sz, self.grid, wl.n, self.sdf, self.mu, self.cat, self.hcell, self.scal)
-        torch.cuda.synchronize()
-        del keep
+        if grid is None:
+            self.sdf = torch.empty(nn, dtype=gd, device=self.dev)
+            self.mu = torch.empty(nn, dtype=gd, device=self.dev)
+            self.cat = torch.empty(nc, dtype=torch.uint8, device=self.dev)
+            self.hcell = torch.empty(nc, dtype=torch.float32, device=self.dev)
+            self.scal = torch.zeros(4, dtype=torch.float64, device=self.dev)
+            geo, sz, keep = _geometry(wl)
+            T.sdf_grid_build(geo, sz, self.grid, wl.n, self.sdf, self.mu, self.cat, self.hcell, self.scal)
+            torch.cuda.synchronize()
+            del keep
+        else:
+            up = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), device=self.dev).to(dt)  # noqa: E731
+            self.sdf = up(grid.sdf, gd)
+            self.mu = up(grid.mu, gd)
+            self.cat = up(grid.cat, torch.uint8)
+            self.hcell = up(grid.hcell, torch.float32)
+            area = float(np.count_nonzero(grid.cat)) * g.dx * g.dy  # bin sizing only
+            self.scal = torch.tensor([grid.H, grid.h_avg, area, 0.0], dtype=torch.float64, device=self.dev)
         st = T.State()
         st.n = wl.n
         st.precision = precision

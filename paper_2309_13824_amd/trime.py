@@ -103,7 +103,8 @@ class State(C.Structure):
                 ("bin_fill", C.c_void_p), ("scan_tmp", C.c_void_p), ("queue", C.c_void_p),
                 ("counters", C.c_void_p), ("partials", C.c_void_p), ("stats", C.c_void_p),
                 ("nbx", C.c_int32), ("nby", C.c_int32), ("lbits", C.c_int32), ("bx0", C.c_double),
-                ("by0", C.c_double), ("bw", C.c_double), ("area_sel", C.c_double), ("nkeys", C.c_int64)]
+                ("by0", C.c_double), ("bw", C.c_double), ("area_sel", C.c_double), ("nkeys", C.c_int64),
+                ("ev_cells", C.c_void_p * 2)]
 
 
 class Schedule(C.Structure):
