@@ -79,9 +79,9 @@ def gpu_run(wl, precision, steps, warmup, log):
     total_ms = t0.elapsed_time(t1)
     kern_ms = [a.elapsed_time(b) for a, b in ev]
     st = m.stats()
-    log("  precision %s: %d steps in %.2f ms (wall %.2f ms), fused cell kernel avg %.3f ms, replays %d"
+    log("  precision %s: %d steps in %.2f ms (wall %.2f ms), fused cell kernel avg %.3f ms, replays %d %s"
         % ("fp32" if precision == T.FP32 else "fp64", steps, total_ms, wall * 1e3, float(np.mean(kern_ms)),
-           st["fp64_replays"]))
+           st["fp64_replays"], m.replay_reasons()))
     return m, total_ms, float(np.mean(kern_ms)), st
 
 

@@ -203,7 +203,7 @@ static void layout(trime_state *st, Layout &L) {
   st->bin_fill = L.take<int32_t>(st->nkeys);
   int64_t scan_n = st->nkeys > n ? st->nkeys : n;
   st->scan_tmp = L.take<int32_t>(scan_tmp_ints(scan_n) + 1);
-  st->queue = L.take<int32_t>(n + 1);
+  st->queue = L.take<int32_t>(2 * (n + 1));  // FP64 replay queue, then the exact queue
   st->counters = L.take<int32_t>(CNT_NCOUNTERS);
   int64_t np = dm_partials(n);
   st->partials = L.take<double>(2 * (np > 1 ? np : 1));
@@ -313,6 +313,7 @@ static KArgs make_args(const trime_state *st) {
   a.tri_valid = st->tri_valid;
   a.tri_n = st->tri_n;
   a.queue = st->queue;
+  a.queue2 = st->queue + st->n + 1;
   a.counters = st->counters;
   a.partials = st->partials;
   a.stats = st->stats;

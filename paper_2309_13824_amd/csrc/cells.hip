@@ -4,22 +4,27 @@
 // wavefront.  A lane builds its cell (Sec. 2.1, Sec. 4.1): the octagon of
 // span S around p, cut by the bisector of every neighbour found in the rings
 // of bins around p, stopping once the nearest unvisited ring is farther than
-// twice the largest vertex distance.  The polygon lives in LDS, one column
-// per lane ([vertex][lane], conflict-free).
+// twice the largest vertex distance.  The polygon lives in LDS as one
+// 16-byte record (x, y, error bound, constraint) per vertex and lane,
+// [vertex][lane] so that a wavefront reads 64 consecutive records.  The
+// bin/candidate scan is one flat loop (each iteration either opens the next
+// bin or tests one candidate), which keeps the lanes of a wavefront in step.
 //
-// Every cut decision is a margin with a forward error bound: FP32 (or FP64)
-// vertex coordinates carry an error bound E; a decision whose |margin| is
-// within the bound is "unsure".  The fast kernels push such points to a
-// queue; the replay kernel recomputes them in FP64 and settles what FP64
-// cannot with the exact expansion predicate (exact_dev.hpp) and symbolic
-// perturbation.  The cells are therefore the exact cells of one perturbed
-// configuration, whatever the precision, order, bin size or batching.
+// Every cut decision is a margin with a forward error bound: vertex
+// coordinates carry an error bound E; a decision whose |margin| is within
+// its bound is undecided.  The fast kernel (FP32 or FP64) sends such points
+// to a queue; the FP64 replay kernel recomputes them and passes what FP64
+// cannot decide to the exact kernel, which settles it with expansion
+// arithmetic (exact_dev.hpp) and symbolic perturbation.  The cells are
+// therefore the exact cells of one perturbed configuration, whatever the
+// precision, order, bin size or batching.
 //
 // After the cell: triangles at the cell vertices between two bisectors
 // (Proc. I line 2) that are vertices of all three cells, validity Tests 1-3
 // (line 3), adjacency of valid triangles, quality statistics (Eq. 10-11),
 // and in CVD mode the adaptive-quadrature centroid (Sec. 4.2 II) and the
-// treatment of the new point (Sec. 4.3).
+// treatment of the new point (Sec. 4.3).  All decisions are taken before
+// anything is written, so a point sent to a replay leaves no partial output.
 #include "exact_dev.hpp"
 #include "geom_dev.hpp"
 #include "launch.hpp"
@@ -41,8 +46,8 @@ template <class T>
 TRIME_D Row<T> row_of(const KArgs &a, int con, double px, double py, float S, float D) {
   Row<T> r;
   if (con >= 0) {
-    r.nx = (T)(a.x[con] - px);
-    r.ny = (T)(a.y[con] - py);
+    r.nx = (T)(gld(a.x, con) - px);
+    r.ny = (T)(gld(a.y, con) - py);
     r.s = (r.nx * r.nx + r.ny * r.ny) * (T)0.5;
   } else {
     int w = -1 - con;
@@ -68,7 +73,7 @@ TRIME_D Row<T> row_of(const KArgs &a, int con, double px, double py, float S, fl
 TRIME_D void xrow_of(const KArgs &a, ex::XRow &r, int con, double px, double py, float S, float D,
                      int *err) {
   if (con >= 0) {
-    ex::bisector(r, a.id[con], a.x[con], a.y[con], px, py, err);
+    ex::bisector(r, gld(a.id, con), gld(a.x, con), gld(a.y, con), px, py, err);
   } else {
     int w = -1 - con;
     if (w < 8) {
@@ -93,8 +98,8 @@ struct ExactCount {
 
 // Exact sign of the margin of c3 at the vertex (c1, c2) in the frame of the
 // point at (px, py) with id pid.
-TRIME_D int exact_cut(const KArgs &a, int c1, int c2, int c3, int pid, double px, double py,
-                      float S, float D, ExactCount &ec) {
+__device__ __noinline__ int exact_cut(const KArgs &a, int c1, int c2, int c3, int pid, double px,
+                                      double py, float S, float D, ExactCount &ec) {
   ex::XRow r1, r2, r3;
   int err = 0, sos = 0;
   xrow_of(a, r1, c1, px, py, S, D, &err);
@@ -106,6 +111,10 @@ TRIME_D int exact_cut(const KArgs &a, int c1, int c2, int c3, int pid, double px
   ec.err |= err;
   return s;
 }
+
+template <class T> TRIME_D T recip(T x);
+template <> TRIME_D float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }  // <= 1 ulp
+template <> TRIME_D double recip<double>(double x) { return 1.0 / x; }
 
 // Vertex of two constraint rows by Cramer's rule with a forward error bound
 // E on each coordinate (inputs: n with relative error u, s with 4u):
@@ -119,8 +128,9 @@ TRIME_D bool make_vertex(const Row<T> &r1, const Row<T> &r2, T &vx, T &vy, float
   T detabs = fabs(r1.nx * r2.ny) + fabs(r1.ny * r2.nx);
   T numx = r1.s * r2.ny - r2.s * r1.ny;
   T numy = r1.nx * r2.s - r2.nx * r1.s;
-  vx = numx / det;
-  vy = numy / det;
+  T inv = recip<T>(det);
+  vx = numx * inv;
+  vy = numy * inv;
   T vmax = fmax(fabs(vx), fabs(vy));
   if (!(fabs(det) > (T)64 * u * detabs) || !isfinite(vmax)) {
     E = INFINITY;
@@ -132,16 +142,21 @@ TRIME_D bool make_vertex(const Row<T> &r1, const Row<T> &r2, T &vx, T &vy, float
   }
   T ax = fabs(r1.s * r2.ny) + fabs(r2.s * r1.ny);
   T ay = fabs(r1.nx * r2.s) + fabs(r2.nx * r1.s);
-  T e = ((T)7 * u * fmax(ax, ay) + (T)4 * u * vmax * detabs) / fabs(det) + (T)2 * u * vmax;
+  T e = ((T)7 * u * fmax(ax, ay) + (T)4 * u * vmax * detabs) * fabs(inv) + (T)2 * u * vmax;
   E = (float)((T)2 * e + (T)6 * u * vmax) * 1.00001f;
   return true;
 }
 
-template <class T, int VMAX, int BLOCK> struct Poly {
-  T vx[VMAX][BLOCK];
-  T vy[VMAX][BLOCK];
-  float ev[VMAX][BLOCK];
-  int con[VMAX][BLOCK];
+// One polygon vertex of one lane in LDS.
+template <class T> struct VRec;
+template <> struct alignas(16) VRec<float> {
+  float x, y, e;
+  int c;  // constraint of the edge leaving this vertex
+};
+template <> struct alignas(8) VRec<double> {
+  double x, y;
+  float e;
+  int c;
 };
 
 struct LaneStats {
@@ -151,78 +166,93 @@ struct LaneStats {
   int newton_fail = 0, trace_fail = 0, cap_hits = 0;
 };
 
-template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct CellLane {
+template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct Lane {
   const KArgs &a;
-  Poly<T, VMAX, BLOCK> &P;
+  VRec<T> (&P)[VMAX][BLOCK];
   int tid;
   int64_t k;
   int pid;
   double px, py;
   float S, D;
-  int n = 0;
-  bool bad = false;
-  bool overflow = false;
-  T R2 = 0;
+  int n;
+  int why;  // nonzero: the point leaves this kernel (WHY_*)
+  T R2;
   ExactCount ec;
-  int hb[TRIME_TRI_PER_POINT];  // beta-histogram bins of the owned valid triangles
-  int nhb = 0;
 
-  TRIME_D CellLane(const KArgs &a_, Poly<T, VMAX, BLOCK> &P_, int tid_, int64_t k_)
-      : a(a_), P(P_), tid(tid_), k(k_) {}
+  TRIME_D Lane(const KArgs &a_, VRec<T> (&P_)[VMAX][BLOCK], int tid_, int64_t k_)
+      : a(a_), P(P_), tid(tid_), k(k_), n(0), why(0), R2(0) {}
 
-  TRIME_D void set_vertex(int j, T vx, T vy, float e, int con) {
-    P.vx[j][tid] = vx;
-    P.vy[j][tid] = vy;
-    P.ev[j][tid] = e;
-    P.con[j][tid] = con;
+  TRIME_D void set_v(int j, T x, T y, float e, int c) {
+    VRec<T> r;
+    r.x = x;
+    r.y = y;
+    r.e = e;
+    r.c = c;
+    P[j][tid] = r;
+  }
+  TRIME_D int con(int j) const { return P[j][tid].c; }
+
+  // FP64 re-evaluation of one undecided FP32 cut decision: the vertex of
+  // constraints (c1, c2) rebuilt in FP64 against constraint c3.  +1 cut,
+  // -1 kept, 0 still undecided (then only the exact stage can decide).
+  TRIME_D int margin64(int c1, int c2, int c3) const {
+    const double u = U<double>::v;
+    Row<double> r1 = row_of<double>(a, c1, px, py, S, D), r2 = row_of<double>(a, c2, px, py, S, D);
+    Row<double> r3 = row_of<double>(a, c3, px, py, S, D);
+    double vx, vy;
+    float E;
+    if (!make_vertex<double>(r1, r2, vx, vy, E)) return 0;
+    double m = fma(r3.nx, vx, fma(r3.ny, vy, -r3.s));
+    double b = fma(fabs(r3.nx) + fabs(r3.ny), (double)E, 12.0 * u * fabs(r3.s));
+    return m > b ? 1 : (m < -b ? -1 : 0);
   }
 
-  TRIME_D void copy_vertex(int dst, int src) {
-    P.vx[dst][tid] = P.vx[src][tid];
-    P.vy[dst][tid] = P.vy[src][tid];
-    P.ev[dst][tid] = P.ev[src][tid];
-    P.con[dst][tid] = P.con[src][tid];
+  // FP64 vertex j (between the edges j-1 and j), rebuilt from its constraints.
+  TRIME_D bool vertex64(int j, double &vx, double &vy, float &E) const {
+    int c1 = con(j == 0 ? n - 1 : j - 1), c2 = con(j);
+    return make_vertex<double>(row_of<double>(a, c1, px, py, S, D), row_of<double>(a, c2, px, py, S, D),
+                               vx, vy, E);
   }
 
-  // |v_true|^2 bound over all vertices, capped by the octagon's circumradius
+  // bound on |v_true|^2 over the vertices, capped by the octagon's circumradius
   TRIME_D void update_R2() {
     const T u = U<T>::v;
     T r2 = 0;
     for (int j = 0; j < n; j++) {
-      T vx = P.vx[j][tid], vy = P.vy[j][tid];
-      T E = (T)P.ev[j][tid];
-      T l1 = fabs(vx) + fabs(vy);
-      T t = (vx * vx + vy * vy) * ((T)1 + (T)8 * u) + (T)4 * l1 * E + (T)4 * E * E;
-      r2 = fmax(r2, t);
+      VRec<T> v = P[j][tid];
+      T E = (T)v.e;
+      T l1 = fabs(v.x) + fabs(v.y);
+      r2 = fmax(r2, (v.x * v.x + v.y * v.y) * ((T)1 + (T)8 * u) + (T)4 * l1 * E + (T)4 * E * E);
     }
     T cap = (T)((double)S * (double)S * 1.1717 * 1.00001);
     R2 = isfinite(r2) ? fmin(r2, cap) : cap;
   }
 
-  // Initial polygon: the octagon, or (replay kernel) the octagon clipped by
-  // the box when the box is within reach.
+  // The octagon: vertex w between walls w-1 and w, exact in float and double
+  // (S - D is exact by Sterbenz).  When the grid box is within reach the
+  // replay kernels clip it by the box walls; the fast kernel defers.
   TRIME_D void init_polygon() {
-    for (int w = 0; w < 8; w++) {
-      Row<T> r1 = row_of<T>(a, -1 - ((w + 7) & 7), px, py, S, D);
-      Row<T> r2 = row_of<T>(a, -1 - w, px, py, S, D);
-      T vx, vy;
-      float e;
-      make_vertex<T>(r1, r2, vx, vy, e);
-      set_vertex(w, vx, vy, e, -1 - w);
-    }
+    T s = (T)S, dmS = (T)D - (T)S;
+    set_v(0, s, -dmS, 0.0f, -1);
+    set_v(1, s, dmS, 0.0f, -2);
+    set_v(2, dmS, s, 0.0f, -3);
+    set_v(3, -dmS, s, 0.0f, -4);
+    set_v(4, -s, dmS, 0.0f, -5);
+    set_v(5, -s, -dmS, 0.0f, -6);
+    set_v(6, -dmS, -s, 0.0f, -7);
+    set_v(7, dmS, -s, 0.0f, -8);
     n = 8;
     double reach = (double)S * 1.0001 + 1e-300;
     bool clear = (a.box_x1 - px) > reach && (px - a.box_x0) > reach && (a.box_y1 - py) > reach &&
                  (py - a.box_y0) > reach;
     if (!clear) {
       if constexpr (!EXACT) {
-        bad = true;
+        why = WHY_BOX;
         return;
       } else {
         for (int w = 8; w < 12 && n > 0; w++) {
-          Row<T> r3 = row_of<T>(a, -1 - w, px, py, S, D);
-          clip(r3, -1 - w);
-          if (bad) return;
+          clip(row_of<T>(a, -1 - w, px, py, S, D), -1 - w);
+          if (why) return;
         }
       }
     }
@@ -236,18 +266,17 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct Ce
     T n1 = fabs(r3.nx) + fabs(r3.ny);
     T b0 = (T)12 * u * fabs(r3.s);
     for (int j = 0; j < n; j++) {
-      T vx = P.vx[j][tid], vy = P.vy[j][tid];
-      T E = (T)P.ev[j][tid];
-      T m = fma(r3.nx, vx, fma(r3.ny, vy, -r3.s));
-      T b = fma(n1, E, b0);
+      VRec<T> v = P[j][tid];
+      T m = fma(r3.nx, v.x, fma(r3.ny, v.y, -r3.s));
+      T b = fma(n1, (T)v.e, b0);
       if (m > b) {
         M |= 1u << j;
       } else if (m >= -b) {
         if constexpr (EXACT) {
-          int c1 = P.con[j == 0 ? n - 1 : j - 1][tid], c2 = P.con[j][tid];
-          if (exact_cut(a, c1, c2, c3, pid, px, py, S, D, ec) > 0) M |= 1u << j;
+          if (exact_cut(a, con(j == 0 ? n - 1 : j - 1), v.c, c3, pid, px, py, S, D, ec) > 0)
+            M |= 1u << j;
         } else {
-          bad = true;
+          why = WHY_PRED;
           return;
         }
       }
@@ -262,28 +291,25 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct Ce
     uint32_t Nm = ((M >> 1) | (M << (n - 1))) & full;
     uint32_t starts = M & ~Pm, ends = M & ~Nm;
     if (__popc(starts) != 1) {  // impossible with exact decisions
-      bad = true;
+      why = WHY_PRED;
       return;
     }
     int k0 = __ffs(starts) - 1, k1 = __ffs(ends) - 1;
     int r = __popc(M);
     int nn = n - r + 2;
     if (nn > VMAX) {
-      bad = true;
-      overflow = true;
+      why = WHY_POLY;
       return;
     }
-    int cin = P.con[k0 == 0 ? n - 1 : k0 - 1][tid];
-    int cout = P.con[k1][tid];
-    Row<T> ri = row_of<T>(a, cin, px, py, S, D);
-    Row<T> ro = row_of<T>(a, cout, px, py, S, D);
+    int cin = con(k0 == 0 ? n - 1 : k0 - 1);
+    int cout = con(k1);
     T x1, y1, x2, y2;
     float e1, e2;
-    bool ok1 = make_vertex<T>(ri, r3, x1, y1, e1);
-    bool ok2 = make_vertex<T>(r3, ro, x2, y2, e2);
+    bool ok1 = make_vertex<T>(row_of<T>(a, cin, px, py, S, D), r3, x1, y1, e1);
+    bool ok2 = make_vertex<T>(r3, row_of<T>(a, cout, px, py, S, D), x2, y2, e2);
     if constexpr (!EXACT) {
       if (!ok1 || !ok2) {
-        bad = true;
+        why = WHY_VERTEX;
         return;
       }
     }
@@ -291,69 +317,93 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct Ce
       if (r >= 2) {
         int sh = r - 2;
         if (sh > 0)
-          for (int j = k1 + 1; j < n; j++) copy_vertex(j - sh, j);
+          for (int j = k1 + 1; j < n; j++) P[j - sh][tid] = P[j][tid];
       } else {
-        for (int j = n - 1; j > k1; j--) copy_vertex(j + 1, j);
+        for (int j = n - 1; j > k1; j--) P[j + 1][tid] = P[j][tid];
       }
-      set_vertex(k0, x1, y1, e1, c3);
-      set_vertex(k0 + 1, x2, y2, e2, cout);
+      set_v(k0, x1, y1, e1, c3);
+      set_v(k0 + 1, x2, y2, e2, cout);
     } else {
       int m = 0;
-      for (int j = k1 + 1; j < k0; j++, m++) copy_vertex(m, j);
-      set_vertex(m, x1, y1, e1, c3);
-      set_vertex(m + 1, x2, y2, e2, cout);
+      for (int j = k1 + 1; j < k0; j++, m++) P[m][tid] = P[j][tid];
+      set_v(m, x1, y1, e1, c3);
+      set_v(m + 1, x2, y2, e2, cout);
     }
     n = nn;
     update_R2();
   }
 
-  // Scan the rings of bins around p.
+  // bin (dx, dy) number bi of ring r: top row, bottom row, then the sides
+  TRIME_D static void ring_bin(int r, int bi, int &dx, int &dy) {
+    if (r == 0) {
+      dx = 0;
+      dy = 0;
+    } else if (bi <= 2 * r) {
+      dy = -r;
+      dx = bi - r;
+    } else if (bi <= 4 * r + 1) {
+      dy = r;
+      dx = bi - (3 * r + 1);
+    } else {
+      int q = bi - (4 * r + 2);
+      dy = -r + 1 + (q >> 1);
+      dx = (q & 1) ? r : -r;
+    }
+  }
+
+  // Scan the rings of bins around p as one flat loop.
   TRIME_D void scan() {
     const T u = U<T>::v;
     int bx, by;
     bin_of(a, px, py, bx, by);
     double ox = px - (a.bx0 + bx * a.bw), oy = py - (a.by0 + by * a.bw);
     double edge = fmax(0.0, fmin(fmin(ox, a.bw - ox), fmin(oy, a.bw - oy)));
-    int rmax = max(a.nbx, a.nby);
-    for (int r = 0; r <= rmax; r++) {
-      if (r > 0) {
-        double dmin = (r - 1) * a.bw + edge;
-        if (dmin * dmin > 4.0 * (double)R2 * 1.00001) break;
-      }
-      for (int dy = -r; dy <= r; dy++) {
-        int yy = by + dy;
-        if (yy < 0 || yy >= a.nby) continue;
-        int step = (r == 0 || dy == -r || dy == r) ? 1 : 2 * r;
-        for (int dx = -r; dx <= r; dx += step) {
-          int xx = bx + dx;
-          if (xx < 0 || xx >= a.nbx) continue;
-          uint32_t key = morton((uint32_t)xx, (uint32_t)yy);
-          int s0 = a.bin_start[key], s1 = a.bin_start[key + 1];
-          for (int s = s0; s < s1; s++) {
-            if (s == (int)k) continue;
-            Row<T> r3;
-            r3.nx = (T)(a.x[s] - px);
-            r3.ny = (T)(a.y[s] - py);
-            T sq = r3.nx * r3.nx + r3.ny * r3.ny;
-            r3.s = sq * (T)0.5;
-            if (sq * ((T)1 - (T)8 * u) > (T)4 * R2) continue;
+    const int rmax = max(a.nbx, a.nby);
+    int r = 0, bi = 0, nbr = 1, s = 0, se = 0;
+    for (;;) {
+      if (s < se) {
+        if (s != (int)k) {
+          Row<T> r3;
+          r3.nx = (T)(gld(a.x, s) - px);
+          r3.ny = (T)(gld(a.y, s) - py);
+          T sq = r3.nx * r3.nx + r3.ny * r3.ny;
+          r3.s = sq * (T)0.5;
+          if (!(sq * ((T)1 - (T)8 * u) > (T)4 * R2)) {
             clip(r3, s);
-            if (bad || n == 0) return;
+            if (why || n == 0) return;
           }
         }
+        s++;
+        continue;
       }
+      if (bi == nbr) {  // ring r done: stop when the next ring is out of reach
+        r++;
+        double dmin = (r - 1) * a.bw + edge;
+        if (r > rmax || dmin * dmin > 4.0 * (double)R2 * 1.00001) return;
+        bi = 0;
+        nbr = 8 * r;
+      }
+      int dx, dy;
+      ring_bin(r, bi, dx, dy);
+      bi++;
+      int xx = bx + dx, yy = by + dy;
+      if (xx < 0 || yy < 0 || xx >= a.nbx || yy >= a.nby) continue;
+      uint32_t key = morton((uint32_t)xx, (uint32_t)yy);
+      s = gld(a.bin_start, (int64_t)key);
+      se = gld(a.bin_start, (int64_t)key + 1);
     }
   }
 
-  // Is the cell vertex j (circumcentre of p, q and `other`) inside the
-  // octagon of the point in slot q?  1 inside, 0 outside; may set bad.
+  // Is cell vertex j (circumcentre of p, q and `other`) inside the octagon
+  // of the point in slot q?  1 inside, 0 outside; may set why.
   TRIME_D int inside_octagon(int j, int q, int other) {
     const T u = U<T>::v;
-    T vx = P.vx[j][tid], vy = P.vy[j][tid];
-    T E = (T)P.ev[j][tid];
-    T qx = (T)(a.x[q] - px), qy = (T)(a.y[q] - py);
-    T cx = vx - qx, cy = vy - qy;
-    float Sq = a.span[q], Dq = 1.41421356f * Sq;
+    VRec<T> v = P[j][tid];
+    T E = (T)v.e;
+    double qxd = gld(a.x, q), qyd = gld(a.y, q);
+    T qx = (T)(qxd - px), qy = (T)(qyd - py);
+    T cx = v.x - qx, cy = v.y - qy;
+    float Sq = gld(a.span, q), Dq = 1.41421356f * Sq;
     T base = E + (T)2 * u * (fabs(qx) + fabs(qy)) + (T)2 * u * (fabs(cx) + fabs(cy));
     for (int w = 0; w < 8; w++) {
       int nx, ny;
@@ -364,11 +414,10 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct Ce
       if (m > b) return 0;
       if (m >= -b) {
         if constexpr (EXACT) {
-          // in the frame of q: rows bisector(q, p), bisector(q, other), wall w of q
-          if (exact_cut(a, (int)k, other, -1 - w, a.id[q], a.x[q], a.y[q], Sq, Dq, ec) > 0)
-            return 0;
+          // in the frame of q: bisector(q, p), bisector(q, other), wall w of q
+          if (exact_cut(a, (int)k, other, -1 - w, gld(a.id, q), qxd, qyd, Sq, Dq, ec) > 0) return 0;
         } else {
-          bad = true;
+          why = WHY_AND;
           return 0;
         }
       }
@@ -377,49 +426,47 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct Ce
   }
 
   TRIME_D bool valid_triangle(int s1, int s2) {
-    int i0 = pid, i1 = a.id[s1], i2 = a.id[s2];
-    double x0 = px, y0 = py, x1 = a.x[s1], y1 = a.y[s1], x2 = a.x[s2], y2 = a.y[s2];
-    // sort by id
-    if (i0 > i1) { int t = i0; i0 = i1; i1 = t; double u = x0; x0 = x1; x1 = u; u = y0; y0 = y1; y1 = u; }
-    if (i1 > i2) { int t = i1; i1 = i2; i2 = t; double u = x1; x1 = x2; x2 = u; u = y1; y1 = y2; y2 = u; }
-    if (i0 > i1) { int t = i0; i0 = i1; i1 = t; double u = x0; x0 = x1; x1 = u; u = y0; y0 = y1; y1 = u; }
+    int i0 = pid, i1 = gld(a.id, s1), i2 = gld(a.id, s2);
+    double x0 = px, y0 = py, x1 = gld(a.x, s1), y1 = gld(a.y, s1), x2 = gld(a.x, s2), y2 = gld(a.y, s2);
+    if (i0 > i1) { int t = i0; i0 = i1; i1 = t; double w = x0; x0 = x1; x1 = w; w = y0; y0 = y1; y1 = w; }
+    if (i1 > i2) { int t = i1; i1 = i2; i2 = t; double w = x1; x1 = x2; x2 = w; w = y1; y1 = y2; y2 = w; }
+    if (i0 > i1) { int t = i0; i0 = i1; i1 = t; double w = x0; x0 = x1; x1 = w; w = y0; y0 = y1; y1 = w; }
     return tri_valid<G>(a, x0, y0, x1, y1, x2, y2);
   }
 
   TRIME_D void write_cell() {
     int cap = a.cell_cap;
     if (n > cap) {
-      a.cell_n[pid] = -1;
+      gst(a.cell_n, (int64_t)pid, -1);
       return;
     }
     int s = 0, best = 0x7fffffff;
     for (int j = 0; j < n; j++) {
-      int c = P.con[j][tid];
-      int v = c >= 0 ? a.id[c] : c;
+      int c = con(j);
+      int v = c >= 0 ? gld(a.id, c) : c;
       if (v < best) {
         best = v;
         s = j;
       }
     }
     for (int t = 0; t < n; t++) {
-      int c = P.con[(s + t) % n][tid];
-      a.cell_cons[(int64_t)pid * cap + t] = c >= 0 ? a.id[c] : c;
+      int c = con((s + t) % n);
+      gst(a.cell_cons, (int64_t)pid * cap + t, c >= 0 ? gld(a.id, c) : c);
     }
-    a.cell_n[pid] = n;
+    gst(a.cell_n, (int64_t)pid, n);
   }
 
-  // Adaptive-quadrature weighted centroid (relative to p) at level L >= 1.
-  TRIME_D void level_centroid(int L, double fx0, double fy0, int64_t cx0, int64_t cy0, T &cx,
-                              T &cy) {
+  // Weighted centroid (relative to p) at quadrature level L >= 1; also the
+  // number of leaf triangles.
+  TRIME_D void level_centroid(int L, T fxf, T fyf, int64_t cx0, int64_t cy0, T &cx, T &cy) {
     T sw = 0, swx = 0, swy = 0;
     const T idx = (T)a.inv_dx, idy = (T)a.inv_dy;
-    const T fxf = (T)(fx0 - (double)cx0), fyf = (T)(fy0 - (double)cy0);
+    const G *mu = (const G *)a.mu;
     int nleaf = 1 << (L - 1);
     for (int t = 0; t < n; t++) {
-      int t1 = (t + 1 == n) ? 0 : t + 1;
-      T bx = P.vx[t][tid], by = P.vy[t][tid], ccx = P.vx[t1][tid], ccy = P.vy[t1][tid];
+      VRec<T> vb = P[t][tid], vc = P[(t + 1 == n) ? 0 : t + 1][tid];
       for (int b = 0; b < nleaf; b++) {
-        T x0 = 0, y0 = 0, x1 = bx, y1 = by, x2 = ccx, y2 = ccy;
+        T x0 = 0, y0 = 0, x1 = vb.x, y1 = vb.y, x2 = vc.x, y2 = vc.y;
         for (int d = L - 2; d >= 0; d--) {
           int bit = (b >> d) & 1;
           T l0 = (x1 - x0) * (x1 - x0) + (y1 - y0) * (y1 - y0);
@@ -437,8 +484,8 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct Ce
           }
         }
         T A = (T)0.5 * ((x1 - x0) * (y2 - y0) - (y1 - y0) * (x2 - x0));
-        T gx = (x0 + x1 + x2) / (T)3, gy = (y0 + y1 + y2) / (T)3;
-        // mu at p + g, bilinear in the cell (cells clamped to the grid)
+        T gx = (x0 + x1 + x2) * (T)(1.0 / 3.0), gy = (y0 + y1 + y2) * (T)(1.0 / 3.0);
+        // mu at p + g: bilinear in its cell (cells clamped to the grid)
         T fx = fxf + gx * idx, fy = fyf + gy * idy;
         T flx = floor(fx), fly = floor(fy);
         int64_t ci = cx0 + (int64_t)flx, cj = cy0 + (int64_t)fly;
@@ -448,69 +495,131 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct Ce
         if (cj < 0) { cj = 0; ty = 0; }
         if (cj > a.ny - 2) { cj = a.ny - 2; ty = 1; }
         int64_t n0 = cj * a.nx + ci;
-        const G *mu = (const G *)a.mu;
-        T m = ((T)mu[n0] * ((T)1 - tx) + (T)mu[n0 + 1] * tx) * ((T)1 - ty) +
-              ((T)mu[n0 + a.nx] * ((T)1 - tx) + (T)mu[n0 + a.nx + 1] * tx) * ty;
-        T w = A / (m * m);
+        T m00 = (T)gld(mu, n0), m10 = (T)gld(mu, n0 + 1);
+        T m01 = (T)gld(mu, n0 + a.nx), m11 = (T)gld(mu, n0 + a.nx + 1);
+        T m = (m00 * ((T)1 - tx) + m10 * tx) * ((T)1 - ty) + (m01 * ((T)1 - tx) + m11 * tx) * ty;
+        T w = A * recip<T>(m * m);
         sw += w;
         swx += w * gx;
         swy += w * gy;
       }
     }
-    cx = swx / sw;
-    cy = swy / sw;
+    T inv = (T)1 / sw;
+    cx = swx * inv;
+    cy = swy * inv;
   }
 
-  TRIME_D void run(LaneStats &st) {
-    pid = a.id[k];
-    px = a.x[k];
-    py = a.y[k];
-    S = a.span[k];
+  // CVD target of p (Sec. 4.2 II); may set why = WHY_LEVEL (FP32 only).
+  TRIME_D void cvd_target(double h, double dp, double &xnew, double &ynew, int &cap_hit) {
+    const T u = U<T>::v;
+    xnew = px;
+    ynew = py;
+    if (n == 0) return;
+    T A = 0;
+    for (int j = 0; j < n; j++) {
+      VRec<T> v0 = P[j][tid], v1 = P[(j + 1 == n) ? 0 : j + 1][tid];
+      A += (T)0.5 * (v0.x * v1.y - v0.y * v1.x);
+    }
+    double eps = fmax((dp < 0 ? h : dp) / h, a.prm.fac_end);
+    T E = (T)(sqrt((double)A) * eps);
+    double fx0 = (px - a.gx0) * a.inv_dx, fy0 = (py - a.gy0) * a.inv_dy;
+    int64_t cx0 = (int64_t)floor(fx0), cy0 = (int64_t)floor(fy0);
+    T fxf = (T)(fx0 - (double)cx0), fyf = (T)(fy0 - (double)cy0);
+    T R = sqrt(R2);
+    T c0x = 0, c0y = 0, c1x = 0, c1y = 0;
+    T err0 = 0;  // error bound of the previous level's centroid
+    for (int L = 1;; L++) {
+      level_centroid(L, fxf, fyf, cx0, cy0, c1x, c1y);
+      T ex_ = c0x - c1x, ey_ = c0y - c1y;
+      T d2 = ex_ * ex_ + ey_ * ey_;
+      if constexpr (!EXACT && sizeof(T) == 4) {
+        // centroid error: vertices and weights (~32u R) plus the sums
+        // (u R per leaf term), for both levels compared
+        T err1 = ((T)32 + (T)2 * (T)(n << (L - 1))) * u * R;
+        T dd = err0 + err1;
+        T lo = fmax(E - dd, (T)0), hi = E + dd;
+        if (d2 >= lo * lo && d2 <= hi * hi) {
+          why = WHY_LEVEL;
+          return;
+        }
+        err0 = err1;
+      }
+      if (d2 < E * E) break;
+      if (L >= a.prm.cvd_max_level) {
+        cap_hit = 1;
+        break;
+      }
+      c0x = c1x;
+      c0y = c1y;
+    }
+    xnew = px + (double)c1x;
+    ynew = py + (double)c1y;
+  }
+
+  // Everything for point k; returns false when the point must be replayed.
+  TRIME_D bool run(LaneStats &st, int *hist) {
+    pid = gld(a.id, k);
+    px = gld(a.x, k);
+    py = gld(a.y, k);
+    S = gld(a.span, k);
     D = 1.41421356f * S;
-    if (!(S > 0.0f)) {  // off the grid: the replay kernel keeps the point as is
-      bad = true;
-      return;
+    if (!(S > 0.0f)) {  // off the grid
+      why = WHY_BOX;
+      return false;
     }
     init_polygon();
-    if (!bad) scan();
-    if (bad) return;
-    if (ec.calls) {
-      st.exact_pts++;
-      st.exact_calls += ec.calls;
-      st.sos += ec.sos;
-      if (ec.err) atomicOr(&a.counters[CNT_ERR], ERR_EXACT_CAP);
-    }
-    if (n == 0) st.empty++;
+    if (!why) scan();
+    if (why) return false;
     if constexpr (MODE == MODE_CELLS) {
       write_cell();
-      return;
     } else {
-      // ---- triangles, validity, adjacency
+      // ---- decisions: triangles at the VV vertices, validity
       uint32_t exists = 0, valid = 0;
       for (int j = 0; j < n; j++) {
-        int jin = P.con[j == 0 ? n - 1 : j - 1][tid], jout = P.con[j][tid];
+        int jin = con(j == 0 ? n - 1 : j - 1), jout = con(j);
         if (jin < 0 || jout < 0) continue;
         int e = inside_octagon(j, jin, jout);
-        if (bad) return;
+        if (why) return false;
         if (e) e = inside_octagon(j, jout, jin);
-        if (bad) return;
+        if (why) return false;
         if (!e) continue;
         exists |= 1u << j;
         if (valid_triangle(jin, jout)) valid |= 1u << j;
       }
-      // owned triangles and their quality
+      // ---- CVD target and treatment
+      double xf = px, yf = py;
+      uint8_t cf = 0;
+      int cap_hit = 0;
+      TreatCount tc;
+      if constexpr (MODE == MODE_CVD) {
+        int64_t cell;
+        double tx, ty;
+        locate(a, px, py, cell, tx, ty);
+        double h = (double)cell_h(a, cell);
+        double xnew, ynew;
+        cvd_target(h, gld(a.dprev, k), xnew, ynew, cap_hit);
+        if (why) return false;
+        double band = (!EXACT && sizeof(T) == 4) ? 1e-6 * h : 0.0;
+        bool unsure = false;
+        treat<G>(a, px, py, gld(a.cat, k), xnew, ynew, band, xf, yf, cf, unsure, tc);
+        if (unsure) {
+          why = WHY_TREAT;
+          return false;
+        }
+      }
+      // ---- commit: nothing below can send the point back
       int nt = 0;
       int64_t tbase = k * TRIME_TRI_PER_POINT;
       for (int j = 0; j < n; j++) {
         if (!((exists >> j) & 1)) continue;
-        int jin = P.con[j == 0 ? n - 1 : j - 1][tid], jout = P.con[j][tid];
-        if (!(pid < a.id[jin] && pid < a.id[jout])) continue;
+        int jin = con(j == 0 ? n - 1 : j - 1), jout = con(j);
+        if (!(pid < gld(a.id, jin) && pid < gld(a.id, jout))) continue;
         bool v = (valid >> j) & 1;
         if (nt < TRIME_TRI_PER_POINT) {
-          a.tri[(tbase + nt) * 3 + 0] = (int)k;
-          a.tri[(tbase + nt) * 3 + 1] = jin;
-          a.tri[(tbase + nt) * 3 + 2] = jout;
-          a.tri_valid[tbase + nt] = v;
+          gst(a.tri, (tbase + nt) * 3 + 0, (int32_t)k);
+          gst(a.tri, (tbase + nt) * 3 + 1, jin);
+          gst(a.tri, (tbase + nt) * 3 + 2, jout);
+          gst(a.tri_valid, tbase + nt, (uint8_t)v);
         } else {
           atomicOr(&a.counters[CNT_ERR], ERR_TRI_CAP);
         }
@@ -518,7 +627,7 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct Ce
         st.ntri++;
         if (v) {
           st.nvalid++;
-          double x1 = a.x[jin], y1 = a.y[jin], x2 = a.x[jout], y2 = a.y[jout];
+          double x1 = gld(a.x, jin), y1 = gld(a.y, jin), x2 = gld(a.x, jout), y2 = gld(a.y, jout);
           double l0 = sqrt((x1 - px) * (x1 - px) + (y1 - py) * (y1 - py));
           double l1 = sqrt((x2 - x1) * (x2 - x1) + (y2 - y1) * (y2 - y1));
           double l2 = sqrt((px - x2) * (px - x2) + (py - y2) * (py - y2));
@@ -532,104 +641,52 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct Ce
           st.nq++;
           int bin = (int)floor((be - 1.0) / 2.0 * 40.0);
           bin = bin < 0 ? 0 : (bin > 39 ? 39 : bin);
-          if (nhb < TRIME_TRI_PER_POINT) hb[nhb++] = bin;
+          atomicAdd(&hist[bin], 1);
         }
       }
-      a.tri_n[k] = nt < TRIME_TRI_PER_POINT ? nt : TRIME_TRI_PER_POINT;
+      gst(a.tri_n, k, nt < TRIME_TRI_PER_POINT ? nt : TRIME_TRI_PER_POINT);
       if constexpr (MODE == MODE_EXTRACT) {
         // adjacency row: edge j is kept when a valid triangle sits at one of
-        // its two ends (vertices j and j + 1); sorted by slot
+        // its two ends (vertices j and j + 1); sorted by slot in the unused
+        // error-bound field of the polygon records
         int cnt = 0;
-        int *row = (int *)&P.ev[0][0];  // reuse the error-bound column
         for (int j = 0; j < n; j++) {
-          int c = P.con[j][tid];
+          int c = con(j);
           int jn = (j + 1 == n) ? 0 : j + 1;
           if (c < 0 || !(((valid >> j) & 1) || ((valid >> jn) & 1))) continue;
           int t = cnt++;
-          while (t > 0 && row[(t - 1) * BLOCK + tid] > c) {
-            row[t * BLOCK + tid] = row[(t - 1) * BLOCK + tid];
+          while (t > 0 && __float_as_int(P[t - 1][tid].e) > c) {
+            P[t][tid].e = P[t - 1][tid].e;
             t--;
           }
-          row[t * BLOCK + tid] = c;
+          P[t][tid].e = __int_as_float(c);
         }
         int md = a.max_deg;
         if (cnt > md) atomicOr(&a.counters[CNT_ERR], ERR_DEG_CAP);
         int w = cnt < md ? cnt : md;
-        for (int t = 0; t < w; t++) a.adj[(int64_t)t * a.n + k] = row[t * BLOCK + tid];
-        a.deg[k] = w;
+        for (int t = 0; t < w; t++) gst(a.adj, (int64_t)t * a.n + k, __float_as_int(P[t][tid].e));
+        gst(a.deg, k, w);
       }
       if constexpr (MODE == MODE_CVD) {
-        // ---- CVD centroid (Sec. 4.2 II) and treatment (Sec. 4.3)
-        double xo = px, yo = py;
-        uint8_t cat_old = a.cat[k];
-        double dp = a.dprev[k];
-        double xnew = px, ynew = py;
-        int64_t cell;
-        double tx, ty;
-        locate(a, px, py, cell, tx, ty);
-        double h = (double)a.hcell[cell];
-        if (n > 0) {
-          T A = 0;
-          for (int j = 0; j < n; j++) {
-            int j1 = (j + 1 == n) ? 0 : j + 1;
-            A += (T)0.5 * (P.vx[j][tid] * P.vy[j1][tid] - P.vy[j][tid] * P.vx[j1][tid]);
-          }
-          double eps = fmax((dp < 0 ? h : dp) / h, a.prm.fac_end);
-          T E = (T)(sqrt((double)A) * eps);
-          T E2 = E * E;
-          double fx0 = (px - a.gx0) * a.inv_dx, fy0 = (py - a.gy0) * a.inv_dy;
-          int64_t cx0 = (int64_t)floor(fx0), cy0 = (int64_t)floor(fy0);
-          T c0x = 0, c0y = 0, c1x = 0, c1y = 0;
-          int L;
-          for (L = 1;; L++) {
-            level_centroid(L, fx0, fy0, cx0, cy0, c1x, c1y);
-            T ex_ = c0x - c1x, ey_ = c0y - c1y;
-            T d2 = ex_ * ex_ + ey_ * ey_;
-            if constexpr (!EXACT && sizeof(T) == 4) {
-              if (fabs(d2 - E2) <= (T)1e-2 * E2) {
-                bad = true;
-                return;
-              }
-            }
-            if (d2 < E2) break;
-            if (L >= a.prm.cvd_max_level) {
-              st.cap_hits++;
-              break;
-            }
-            c0x = c1x;
-            c0y = c1y;
-          }
-          xnew = px + (double)c1x;
-          ynew = py + (double)c1y;
-        }
-        double band = (!EXACT && sizeof(T) == 4) ? 1e-6 * h : 0.0;
-        double xf, yf;
-        uint8_t cf;
-        bool unsure = false;
-        TreatCount tc;
-        treat<G>(a, xo, yo, cat_old, xnew, ynew, band, xf, yf, cf, unsure, tc);
-        if (unsure) {
-          bad = true;
-          return;
-        }
+        gst(a.xn, k, xf);
+        gst(a.yn, k, yf);
+        gst(a.catn, k, cf);
+        gst(a.dprevn, k, sqrt((xf - px) * (xf - px) + (yf - py) * (yf - py)));
         st.newton_fail += tc.newton_fail;
         st.trace_fail += tc.trace_fail;
-        a.xn[k] = xf;
-        a.yn[k] = yf;
-        a.catn[k] = cf;
-        a.dprevn[k] = sqrt((xf - xo) * (xf - xo) + (yf - yo) * (yf - yo));
+        st.cap_hits += cap_hit;
       }
     }
+    if (n == 0) st.empty++;
+    if (ec.calls) {
+      st.exact_pts++;
+      st.exact_calls += ec.calls;
+      st.sos += ec.sos;
+      if (ec.err) atomicOr(&a.counters[CNT_ERR], ERR_EXACT_CAP);
+    }
+    return true;
   }
 };
-
-TRIME_D void merge(LaneStats &d, const LaneStats &s) {
-  d.sa += s.sa; d.sb += s.sb; d.sq += s.sq; d.amax = fmax(d.amax, s.amax);
-  d.nq += s.nq; d.ntri += s.ntri; d.nvalid += s.nvalid; d.replays += s.replays;
-  d.exact_pts += s.exact_pts; d.exact_calls += s.exact_calls; d.sos += s.sos;
-  d.overflow += s.overflow; d.empty += s.empty; d.newton_fail += s.newton_fail;
-  d.trace_fail += s.trace_fail; d.cap_hits += s.cap_hits;
-}
 
 // Block reduction of the lane statistics into the device stats.
 template <int BLOCK> TRIME_D void flush_stats(const KArgs &a, LaneStats &st, int *hist) {
@@ -648,7 +705,9 @@ template <int BLOCK> TRIME_D void flush_stats(const KArgs &a, LaneStats &st, int
     for (int q = 0; q < 12; q++) iv[q] += __shfl_down(iv[q], off);
   }
   if (lane == 0) {
+#pragma unroll
     for (int q = 0; q < 4; q++) rs[q][wv] = v[q];
+#pragma unroll
     for (int q = 0; q < 12; q++) ri[q][wv] = iv[q];
   }
   __syncthreads();
@@ -658,29 +717,29 @@ template <int BLOCK> TRIME_D void flush_stats(const KArgs &a, LaneStats &st, int
       rs[1][0] += rs[1][w];
       rs[2][0] += rs[2][w];
       rs[3][0] = fmax(rs[3][0], rs[3][w]);
+#pragma unroll
       for (int q = 0; q < 12; q++) ri[q][0] += ri[q][w];
     }
     trime_stats *S = a.stats;
+    typedef unsigned long long ull;
     if (ri[0][0]) {
       atomicAdd(&S->sum_sqrt_alpha, rs[0][0]);
       atomicAdd(&S->sum_sqrt_beta, rs[1][0]);
       atomicAdd(&S->sum_q, rs[2][0]);
-      atomicMax((unsigned long long *)&S->max_alpha, (unsigned long long)__double_as_longlong(rs[3][0]));
-      atomicAdd((unsigned long long *)&S->nq, (unsigned long long)ri[0][0]);
+      atomicMax((ull *)&S->max_alpha, (ull)__double_as_longlong(rs[3][0]));
+      atomicAdd((ull *)&S->nq, (ull)ri[0][0]);
     }
-    unsigned long long *c = (unsigned long long *)S;
-    if (ri[1][0]) atomicAdd((unsigned long long *)&S->ntri, (unsigned long long)ri[1][0]);
-    if (ri[2][0]) atomicAdd((unsigned long long *)&S->nvalid, (unsigned long long)ri[2][0]);
-    if (ri[3][0]) atomicAdd((unsigned long long *)&S->fp64_replays, (unsigned long long)ri[3][0]);
-    if (ri[4][0]) atomicAdd((unsigned long long *)&S->exact_points, (unsigned long long)ri[4][0]);
-    if (ri[5][0]) atomicAdd((unsigned long long *)&S->exact_calls, (unsigned long long)ri[5][0]);
-    if (ri[6][0]) atomicAdd((unsigned long long *)&S->sos_calls, (unsigned long long)ri[6][0]);
-    if (ri[7][0]) atomicAdd((unsigned long long *)&S->overflow_points, (unsigned long long)ri[7][0]);
-    if (ri[8][0]) atomicAdd((unsigned long long *)&S->empty_cells, (unsigned long long)ri[8][0]);
-    if (ri[9][0]) atomicAdd((unsigned long long *)&S->newton_fail, (unsigned long long)ri[9][0]);
-    if (ri[10][0]) atomicAdd((unsigned long long *)&S->trace_fail, (unsigned long long)ri[10][0]);
-    if (ri[11][0]) atomicAdd((unsigned long long *)&S->level_cap_hits, (unsigned long long)ri[11][0]);
-    (void)c;
+    if (ri[1][0]) atomicAdd((ull *)&S->ntri, (ull)ri[1][0]);
+    if (ri[2][0]) atomicAdd((ull *)&S->nvalid, (ull)ri[2][0]);
+    if (ri[3][0]) atomicAdd((ull *)&S->fp64_replays, (ull)ri[3][0]);
+    if (ri[4][0]) atomicAdd((ull *)&S->exact_points, (ull)ri[4][0]);
+    if (ri[5][0]) atomicAdd((ull *)&S->exact_calls, (ull)ri[5][0]);
+    if (ri[6][0]) atomicAdd((ull *)&S->sos_calls, (ull)ri[6][0]);
+    if (ri[7][0]) atomicAdd((ull *)&S->overflow_points, (ull)ri[7][0]);
+    if (ri[8][0]) atomicAdd((ull *)&S->empty_cells, (ull)ri[8][0]);
+    if (ri[9][0]) atomicAdd((ull *)&S->newton_fail, (ull)ri[9][0]);
+    if (ri[10][0]) atomicAdd((ull *)&S->trace_fail, (ull)ri[10][0]);
+    if (ri[11][0]) atomicAdd((ull *)&S->level_cap_hits, (ull)ri[11][0]);
   }
   for (int b = threadIdx.x; b < 40; b += BLOCK)
     if (hist[b]) atomicAdd((unsigned long long *)&a.stats->hist_beta[b], (unsigned long long)hist[b]);
@@ -691,60 +750,72 @@ template <int BLOCK> TRIME_D void zero_hist(int *hist) {
   __syncthreads();
 }
 
-// Fast kernel: one point per lane; unsure points are queued for replay.
+TRIME_D void push(const KArgs &a, int which, int64_t k, int why) {
+  int32_t *q = which == 2 ? a.queue2 : a.queue;
+  int slot = atomicAdd(&a.counters[which == 2 ? CNT_QUEUE2 : CNT_QUEUE], 1);
+  gst(q, (int64_t)slot, (int32_t)k);
+  atomicAdd(&a.counters[CNT_REASON + why], 1);
+}
+
+// Fast kernel: one point per lane.  Undecided FP32 points go to the FP64
+// replay queue, undecided FP64 points to the exact queue.
 template <class T, class G, int MODE, int VMAX, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_cells(KArgs a) {
-  __shared__ Poly<T, VMAX, BLOCK> P;
+  __shared__ VRec<T> P[VMAX][BLOCK];
   __shared__ int hist[40];
   zero_hist<BLOCK>(hist);
   LaneStats st;
   int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (k < a.n) {
-    CellLane<T, G, MODE, false, VMAX, BLOCK> L(a, P, threadIdx.x, k);
-    LaneStats loc;
-    L.run(loc);
-    if (L.bad) {
-      int q = atomicAdd(&a.counters[CNT_QUEUE], 1);
-      a.queue[q] = (int)k;
-      if (L.overflow) st.overflow++;
+    Lane<T, G, MODE, false, VMAX, BLOCK> L(a, P, threadIdx.x, k);
+    if (!L.run(st, hist)) {
+      push(a, sizeof(T) == 4 ? 1 : 2, k, L.why);
       st.replays++;
-    } else {
-      merge(st, loc);
-      for (int b = 0; b < L.nhb; b++) atomicAdd(&hist[L.hb[b]], 1);
+      if (L.why == WHY_POLY) st.overflow++;
     }
   }
   flush_stats<BLOCK>(a, st, hist);
 }
 
-// Replay kernel: FP64 with the exact stage, over the queue (grid-stride).
+// FP64 replay of the queue (grid-stride); undecided points go on.
 template <class G, int MODE, int VMAX, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_cells_replay(KArgs a) {
-  __shared__ Poly<double, VMAX, BLOCK> P;
+  __shared__ VRec<double> P[VMAX][BLOCK];
   __shared__ int hist[40];
   zero_hist<BLOCK>(hist);
   LaneStats st;
-  int64_t nq = a.counters[CNT_QUEUE];
-  for (int64_t w = (int64_t)blockIdx.x * BLOCK + threadIdx.x; w < nq;
-       w += (int64_t)gridDim.x * BLOCK) {
-    int64_t k = a.queue[w];
-    CellLane<double, G, MODE, true, VMAX, BLOCK> L(a, P, threadIdx.x, k);
-    LaneStats loc;
-    L.run(loc);
-    if (!L.bad) {
-      merge(st, loc);
-      for (int b = 0; b < L.nhb; b++) atomicAdd(&hist[L.hb[b]], 1);
-    } else {  // capacity beyond the replay polygon: leave the point as is
+  int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE);
+  for (int64_t w = (int64_t)blockIdx.x * BLOCK + threadIdx.x; w < nq; w += (int64_t)gridDim.x * BLOCK) {
+    int64_t k = gld(a.queue, w);
+    Lane<double, G, MODE, false, VMAX, BLOCK> L(a, P, threadIdx.x, k);
+    if (!L.run(st, hist)) push(a, 2, k, L.why);
+  }
+  flush_stats<BLOCK>(a, st, hist);
+}
+
+// Exact replay of the second queue.
+template <class G, int MODE, int VMAX, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_cells_exact(KArgs a) {
+  __shared__ VRec<double> P[VMAX][BLOCK];
+  __shared__ int hist[40];
+  zero_hist<BLOCK>(hist);
+  LaneStats st;
+  int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE2);
+  for (int64_t w = (int64_t)blockIdx.x * BLOCK + threadIdx.x; w < nq; w += (int64_t)gridDim.x * BLOCK) {
+    int64_t k = gld(a.queue2, w);
+    Lane<double, G, MODE, true, VMAX, BLOCK> L(a, P, threadIdx.x, k);
+    if (!L.run(st, hist)) {  // beyond the polygon capacity, or off the grid: keep the point
       st.overflow++;
       atomicOr(&a.counters[CNT_ERR], ERR_POLY_CAP);
       if constexpr (MODE == MODE_CVD) {
-        a.xn[k] = a.x[k];
-        a.yn[k] = a.y[k];
-        a.catn[k] = a.cat[k];
-        a.dprevn[k] = 0.0;
+        gst(a.xn, k, gld(a.x, k));
+        gst(a.yn, k, gld(a.y, k));
+        gst(a.catn, k, gld(a.cat, k));
+        gst(a.dprevn, k, 0.0);
       }
-      if constexpr (MODE == MODE_EXTRACT) a.deg[k] = 0;
-      if constexpr (MODE != MODE_CELLS) a.tri_n[k] = 0;
-      if constexpr (MODE == MODE_CELLS) a.cell_n[a.id[k]] = -1;
+      if constexpr (MODE == MODE_EXTRACT) gst(a.deg, k, 0);
+      if constexpr (MODE != MODE_CELLS) gst(a.tri_n, k, 0);
+      if constexpr (MODE == MODE_CELLS) gst(a.cell_n, (int64_t)gld(a.id, k), -1);
     }
   }
   flush_stats<BLOCK>(a, st, hist);
@@ -752,7 +823,10 @@ __global__ __launch_bounds__(BLOCK) void k_cells_replay(KArgs a) {
 
 // ------------------------------------------------------------ launchers --
 constexpr int FAST_BLOCK = 128;
-constexpr int FAST_VMAX = 16;
+#ifndef TRIME_FAST_VMAX
+#define TRIME_FAST_VMAX 12
+#endif
+constexpr int FAST_VMAX = TRIME_FAST_VMAX;  // polygon capacity of the fast kernel
 constexpr int REPLAY_BLOCK = 64;
 constexpr int REPLAY_VMAX = 32;
 
@@ -761,7 +835,9 @@ template <class T, class G, int MODE> static void launch_mode(const KArgs &a, hi
   if (a.ev0) (void)hipEventRecord((hipEvent_t)a.ev0, s);
   if (nb > 0) hipLaunchKernelGGL((k_cells<T, G, MODE, FAST_VMAX, FAST_BLOCK>), dim3(nb), dim3(FAST_BLOCK), 0, s, a);
   if (a.ev1) (void)hipEventRecord((hipEvent_t)a.ev1, s);
-  hipLaunchKernelGGL((k_cells_replay<G, MODE, REPLAY_VMAX, REPLAY_BLOCK>), dim3(256), dim3(REPLAY_BLOCK), 0, s, a);
+  if (sizeof(T) == 4)
+    hipLaunchKernelGGL((k_cells_replay<G, MODE, REPLAY_VMAX, REPLAY_BLOCK>), dim3(512), dim3(REPLAY_BLOCK), 0, s, a);
+  hipLaunchKernelGGL((k_cells_exact<G, MODE, REPLAY_VMAX, REPLAY_BLOCK>), dim3(64), dim3(REPLAY_BLOCK), 0, s, a);
 }
 
 template <class G> static void launch_g(const KArgs &a, int mode, hipStream_t s) {

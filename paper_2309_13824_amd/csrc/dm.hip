@@ -103,14 +103,14 @@ TRIME_D bool dm_point(const KArgs &a, int64_t k, int &moved, TreatCount &tc) {
   int64_t cell;
   double tx, ty;
   double band = 0.0;
-  if (sizeof(T) == 4 && locate(a, px, py, cell, tx, ty)) band = 1e-6 * (double)a.hcell[cell];
+  if (sizeof(T) == 4 && locate(a, px, py, cell, tx, ty)) band = 1e-6 * (double)cell_h(a, cell);
   double xf, yf;
   uint8_t cf;
   bool unsure = false;
   treat<G>(a, px, py, a.cat[k], xnew, ynew, band, xf, yf, cf, unsure, tc);
   moved = 0;
   if (locate(a, xf, yf, cell, tx, ty)) {
-    double h = a.prm.fac_retria * (double)a.hcell[cell];
+    double h = a.prm.fac_retria * (double)cell_h(a, cell);
     double ex = xf - a.xl[k], ey = yf - a.yl[k];
     double r2 = ex * ex + ey * ey;
     if (sizeof(T) == 4 && fabs(r2 - h * h) <= 1e-5 * h * h) unsure = true;
@@ -370,7 +370,7 @@ __global__ void k_stats_reset_quality(KArgs a, int full) {
       S->fac_mu = 0;
     }
   }
-  if (t < CNT_NCOUNTERS) a.counters[t] = 0;
+  if (t < (full ? CNT_NCOUNTERS : CNT_REASON)) a.counters[t] = 0;
 }
 
 void launch_stats_reset(const KArgs &a, int full, hipStream_t s) {

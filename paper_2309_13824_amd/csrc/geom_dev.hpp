@@ -21,7 +21,7 @@ TRIME_D bool tri_valid(const KArgs &a, double ax, double ay, double bx, double b
   double tx, ty;
   double gx = ((ax + bx) + cx) / 3.0, gy = ((ay + by) + cy) / 3.0;
   if (!locate(a, gx, gy, cell, tx, ty)) return false;
-  uint8_t ct = a.cgrid[cell];
+  uint8_t ct = cell_cat(a, cell);
   if (ct == TRIME_CAT_INNER) return true;
   if (ct == TRIME_CAT_OUTER) return false;
   if (bilinear<G>(a, a.sdf, cell, tx, ty) > geps_of(a, cell)) return false;
@@ -32,7 +32,7 @@ TRIME_D bool tri_valid(const KArgs &a, double ax, double ay, double bx, double b
 #pragma unroll
     for (int e = 0; e < 3; e++) {
       if (!locate(a, mx[e], my[e], cell, tx, ty)) continue;
-      uint8_t cm = a.cgrid[cell];
+      uint8_t cm = cell_cat(a, cell);
       if (cm == TRIME_CAT_INNER)
         count++;
       else if (cm == TRIME_CAT_BOUNDARY && bilinear<G>(a, a.sdf, cell, tx, ty) <= geps_of(a, cell))
@@ -60,7 +60,7 @@ TRIME_D uint8_t point_category(const KArgs &a, double x, double y, double band, 
   int64_t cell;
   double tx, ty;
   if (!locate(a, x, y, cell, tx, ty)) return TRIME_CAT_OUTER;
-  uint8_t c = a.cgrid[cell];
+  uint8_t c = cell_cat(a, cell);
   if (c != TRIME_CAT_BOUNDARY) return c;
   double s = bilinear<G>(a, a.sdf, cell, tx, ty), ge = geps_of(a, cell);
   if (fabs(s - ge) <= band || fabs(fabs(s) - ge) <= band) unsure = true;
@@ -161,7 +161,7 @@ TRIME_D bool newton_project(const KArgs &a, double xn, double yn, double band, d
     xk = xk - a.prm.alpha_hat * sx;
     yk = yk - a.prm.alpha_hat * sy;
     double tx2, ty2;
-    if (locate(a, xk, yk, cell, tx2, ty2) && a.cgrid[cell] == TRIME_CAT_BOUNDARY) {
+    if (locate(a, xk, yk, cell, tx2, ty2) && cell_cat(a, cell) == TRIME_CAT_BOUNDARY) {
       double s = bilinear<G>(a, a.sdf, cell, tx2, ty2), ge = geps_of(a, cell);
       if (fabs(fabs(s) - ge) <= band) unsure = true;
       if (fabs(s) <= ge) {
@@ -183,7 +183,7 @@ TRIME_D void treat(const KArgs &a, double xo, double yo, uint8_t cat_old, double
   int64_t cell;
   double tx, ty;
   if (locate(a, xo, yo, cell, tx, ty)) {
-    double T = a.prm.fac_pt * (double)a.hcell[cell];
+    double T = a.prm.fac_pt * (double)cell_h(a, cell);
     double dx = xnew - xo, dy = ynew - yo, d2 = dx * dx + dy * dy;
     if (d2 > T * T) {
       double sc = T / sqrt(d2);
@@ -192,7 +192,7 @@ TRIME_D void treat(const KArgs &a, double xo, double yo, uint8_t cat_old, double
     }
   }
   if (locate(a, xnew, ynew, cell, tx, ty)) {
-    uint8_t c = a.cgrid[cell];
+    uint8_t c = cell_cat(a, cell);
     if (c == TRIME_CAT_INNER) {
       xf = xnew;
       yf = ynew;

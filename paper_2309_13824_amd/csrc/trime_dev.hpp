@@ -18,6 +18,12 @@ template <class T> struct U;
 template <> struct U<float> { static constexpr float v = 5.9604645e-8f; };          // 2^-24
 template <> struct U<double> { static constexpr double v = 1.1102230246251565e-16; }; // 2^-53
 
+// Loads and stores through the global address space (plain pointers would
+// compile to flat memory operations).
+#define TRIME_GLOBAL __attribute__((address_space(1)))
+template <class T> TRIME_D T gld(const T *p, int64_t i) { return ((const TRIME_GLOBAL T *)p)[i]; }
+template <class T> TRIME_D void gst(T *p, int64_t i, T v) { ((TRIME_GLOBAL T *)p)[i] = v; }
+
 // Everything a kernel needs, passed by value (well under the 4 KiB limit).
 struct KArgs {
   int64_t n;
@@ -50,9 +56,10 @@ struct KArgs {
   int32_t *tri;  // TRIME_TRI_PER_POINT triangles per owner slot
   uint8_t *tri_valid;
   int32_t *tri_n;
-  // work queue / counters / stats
-  int32_t *queue;
-  int32_t *counters;  // [0] queue length, [1] triangle count, [2] error bits
+  // work queues / counters / stats
+  int32_t *queue;   // points for the FP64 replay
+  int32_t *queue2;  // points for the exact replay
+  int32_t *counters;
   double *partials;
   trime_stats *stats;
   // cell output (trime_voronoi_cells)
@@ -63,13 +70,18 @@ struct KArgs {
   void *ev0, *ev1;  // optional timing events around the fused cell kernel
 };
 
-enum { CNT_QUEUE = 0, CNT_TRI = 1, CNT_ERR = 2, CNT_MOVED = 3, CNT_NCOUNTERS = 8 };
+// counters[]: queue lengths, error bits, and the reasons of FP64 replays
+enum { CNT_QUEUE = 0, CNT_TRI = 1, CNT_ERR = 2, CNT_MOVED = 3, CNT_QUEUE2 = 4, CNT_REASON = 8,
+       CNT_NCOUNTERS = 16 };
 enum { ERR_TRI_CAP = 1, ERR_DEG_CAP = 2, ERR_POLY_CAP = 4, ERR_EXACT_CAP = 8, ERR_QUEUE = 16 };
+// why a point left the fast path
+enum { WHY_PRED = 1, WHY_VERTEX = 2, WHY_POLY = 3, WHY_AND = 4, WHY_LEVEL = 5, WHY_TREAT = 6,
+       WHY_BOX = 7 };
 
 // ---------------------------------------------------------------- grid ----
 
 template <class G> TRIME_D double gval(const void *p, int64_t k) {
-  return (double)((const G *)p)[k];
+  return (double)gld((const G *)p, k);
 }
 
 // Cell of (x, y): f = (x - x0) * (1/dx), cell = floor(f), t = f - cell.
@@ -96,9 +108,15 @@ TRIME_D double bilinear(const KArgs &a, const void *f, int64_t cell, double tx, 
   return (f00 * (1.0 - tx) + f10 * tx) * (1.0 - ty) + (f01 * (1.0 - tx) + f11 * tx) * ty;
 }
 
+TRIME_D uint8_t cell_cat(const KArgs &a, int64_t cell) { return gld(a.cgrid, cell); }
+TRIME_D float cell_h(const KArgs &a, int64_t cell) { return gld(a.hcell, cell); }
+TRIME_D double h_avg(const KArgs &a) {
+  return gld((const double *)a.scal, 1);  // trime_grid_scalars.h_avg
+}
+
 // geps of a cell (Sec. 3.7): fac_geps * min(h_cell, h_avg).
 TRIME_D double geps_of(const KArgs &a, int64_t cell) {
-  return a.prm.fac_geps * fmin((double)a.hcell[cell], a.scal->h_avg);
+  return a.prm.fac_geps * fmin((double)cell_h(a, cell), h_avg(a));
 }
 
 // mu anywhere (cells clamped to the grid), used by the quadrature and forces.
@@ -136,7 +154,7 @@ TRIME_D float span_at(const KArgs &a, double x, double y) {
   int64_t cell;
   double tx, ty;
   if (!locate(a, x, y, cell, tx, ty)) return -1.0f;
-  return (float)a.prm.fac_voro * a.hcell[cell];
+  return (float)a.prm.fac_voro * cell_h(a, cell);
 }
 
 }  // namespace trime

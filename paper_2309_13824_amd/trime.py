@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtrime.so")
+# TRIME_LIB selects another build of the same library (tuning variants)
+LIB_PATH = os.environ.get("TRIME_LIB", os.path.join(HERE, "libtrime.so"))
 
 FP64, FP32 = 0, 1
 CAT_OUTER, CAT_INNER, CAT_BOUNDARY = 0, 1, 2
