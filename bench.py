@@ -82,6 +82,10 @@ def gpu_run(wl, precision, steps, warmup, log):
     log("  precision %s: %d steps in %.2f ms (wall %.2f ms), fused cell kernel avg %.3f ms, replays %d %s"
         % ("fp32" if precision == T.FP32 else "fp64", steps, total_ms, wall * 1e3, float(np.mean(kern_ms)),
            st["fp64_replays"], m.replay_reasons()))
+    pts = float(wl.n * steps)
+    log("  work per point-iteration: candidates %.2f margins %.2f cuts %.2f leaves %.2f; level cap hits %d, "
+        "exact points %d" % (st["work_candidates"] / pts, st["work_margins"] / pts, st["work_cuts"] / pts,
+                             st["work_leaves"] / pts, st["level_cap_hits"], st["exact_points"]))
     return m, total_ms, float(np.mean(kern_ms)), st
 
 

@@ -147,6 +147,10 @@ typedef struct {
   double sum_sqrt_alpha, sum_sqrt_beta, sum_q, max_alpha;
   int64_t nq;
   int64_t hist_beta[40];   /* beta in [1, 3), 40 bins, last bin open           */
+  /* work of the cell passes that produced the committed results, since the
+     last load: neighbours tested against the search range, vertex margins
+     evaluated, polygon cuts, quadrature leaf triangles (Sec. 4.2 II) */
+  int64_t work_candidates, work_margins, work_cuts, work_leaves;
 } trime_stats;
 
 /* Per-point arrays of a state are kept in "slot" order: the order of the
@@ -195,6 +199,8 @@ typedef struct {
   int32_t *perm;           /* n: new slot -> old slot of the binning         */
   int32_t *key;            /* n                                              */
   int32_t *rank;           /* n                                              */
+  int32_t *order;          /* n: slots in the order the cell kernels take them
+                              (points on the boundary first, they cost most) */
   int32_t *bin_start;      /* nkeys + 1                                      */
   int32_t *bin_fill;       /* nkeys                                          */
   int32_t *scan_tmp;       /* scan block sums                                */

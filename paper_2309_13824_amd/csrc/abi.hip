@@ -199,6 +199,7 @@ static void layout(trime_state *st, Layout &L) {
   st->perm = L.take<int32_t>(n + 1);
   st->key = L.take<int32_t>(n);
   st->rank = L.take<int32_t>(n);
+  st->order = L.take<int32_t>(n);
   st->bin_start = L.take<int32_t>(st->nkeys + 1);
   st->bin_fill = L.take<int32_t>(st->nkeys);
   int64_t scan_n = st->nkeys > n ? st->nkeys : n;
@@ -279,6 +280,7 @@ static KArgs make_args(const trime_state *st) {
   a.perm = st->perm;
   a.key = st->key;
   a.rank = st->rank;
+  a.order = st->order;
   a.bin_start = st->bin_start;
   a.bin_fill = st->bin_fill;
   a.nbx = st->nbx;

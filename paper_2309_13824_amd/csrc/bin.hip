@@ -153,6 +153,26 @@ __global__ void k_bin_gather(KArgs a, GatherArgs g) {
   g.spano[s] = span_at(a, x, y);
 }
 
+// Processing order of the cell kernels: the slots of points on the boundary
+// first (their cells reach the octagon walls outside the domain, so they scan
+// the most bins), then all others, each group in slot order.  Heavy points
+// then share wavefronts and start first instead of holding back 64-point
+// wavefronts of light ones.
+__global__ void k_order_flags(KArgs a, const uint8_t *cat) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n) return;
+  a.key[s] = cat[s] == TRIME_CAT_BOUNDARY ? 1 : 0;
+}
+
+__global__ void k_order_scatter(KArgs a) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n) return;
+  int before = a.perm[s];  // heavy slots before s
+  int heavy = a.perm[a.n];
+  int64_t w = a.key[s] ? before : heavy + (s - before);
+  a.order[w] = (int)s;
+}
+
 void launch_bin(const KArgs &a, const GatherArgs &g, int64_t nkeys, int32_t *scan_tmp,
                 hipStream_t s) {
   const int B = 256;
@@ -163,6 +183,9 @@ void launch_bin(const KArgs &a, const GatherArgs &g, int64_t nkeys, int32_t *sca
   if (nb) hipLaunchKernelGGL(k_bin_scatter, dim3(nb), dim3(B), 0, s, a);
   hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((nkeys + B - 1) / B)), dim3(B), 0, s, a, nkeys);
   if (nb) hipLaunchKernelGGL(k_bin_gather, dim3(nb), dim3(B), 0, s, a, g);
+  if (nb) hipLaunchKernelGGL(k_order_flags, dim3(nb), dim3(B), 0, s, a, (const uint8_t *)g.cato);
+  scan_i32(a.key, a.perm, a.n, scan_tmp, s);
+  if (nb) hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(B), 0, s, a);
 }
 
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {

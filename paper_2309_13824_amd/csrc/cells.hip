@@ -12,10 +12,12 @@
 //
 // Every cut decision is a margin with a forward error bound: vertex
 // coordinates carry an error bound E; a decision whose |margin| is within
-// its bound is undecided.  The fast kernel (FP32 or FP64) sends such points
-// to a queue; the FP64 replay kernel recomputes them and passes what FP64
-// cannot decide to the exact kernel, which settles it with expansion
-// arithmetic (exact_dev.hpp) and symbolic perturbation.  The cells are
+// its bound is undecided.  The fast kernel (FP32 or FP64) re-evaluates an
+// undecided FP32 cut or octagon test in FP64 on the spot and sends what is
+// left to a queue; the FP64 replay kernel (one wavefront per point)
+// recomputes those points and passes what FP64 cannot decide to the exact
+// kernel, which settles it with expansion arithmetic (exact_dev.hpp) and
+// symbolic perturbation.  The cells are
 // therefore the exact cells of one perturbed configuration, whatever the
 // precision, order, bin size or batching.
 //
@@ -164,7 +166,69 @@ struct LaneStats {
   int nq = 0, ntri = 0, nvalid = 0;
   int replays = 0, exact_pts = 0, exact_calls = 0, sos = 0, overflow = 0, empty = 0;
   int newton_fail = 0, trace_fail = 0, cap_hits = 0;
+  int candidates = 0, margins = 0, cuts = 0, leaves = 0;
 };
+
+// Algorithmic work of one point: neighbours tested against the range,
+// vertex margins evaluated, cuts, quadrature leaf triangles.
+struct Work {
+  int candidates = 0, margins = 0, cuts = 0, leaves = 0;
+};
+
+// Longest-edge bisection of the triangle (x0, y0), (x1, y1), (x2, y2)
+// (Sec. 4.2 II): the longest edge (ties to the first of l01, l12, l20) is
+// split at its midpoint m; child 0 keeps the endpoint of lower vertex index
+// and child 1 the other.
+template <class V>
+TRIME_D void longest_edge(V x0, V y0, V x1, V y1, V x2, V y2, int &e, V &mx, V &my) {
+  V l0 = (x1 - x0) * (x1 - x0) + (y1 - y0) * (y1 - y0);
+  V l1 = (x2 - x1) * (x2 - x1) + (y2 - y1) * (y2 - y1);
+  V l2 = (x0 - x2) * (x0 - x2) + (y0 - y2) * (y0 - y2);
+  if (l0 >= l1 && l0 >= l2) {
+    e = 0;
+    mx = (x0 + x1) * (V)0.5;
+    my = (y0 + y1) * (V)0.5;
+  } else if (l1 >= l2) {
+    e = 1;
+    mx = (x1 + x2) * (V)0.5;
+    my = (y1 + y2) * (V)0.5;
+  } else {
+    e = 2;
+    mx = (x2 + x0) * (V)0.5;
+    my = (y2 + y0) * (V)0.5;
+  }
+}
+
+template <class V>
+TRIME_D void take_child(int e, int bit, V mx, V my, V &x0, V &y0, V &x1, V &y1, V &x2, V &y2) {
+  // the vertex replaced by the midpoint, as selects (no indexed temporaries)
+  int r = e == 0 ? (bit ? 0 : 1) : (e == 1 ? (bit ? 1 : 2) : (bit ? 0 : 2));
+  x0 = r == 0 ? mx : x0;
+  y0 = r == 0 ? my : y0;
+  x1 = r == 1 ? mx : x1;
+  y1 = r == 1 ? my : y1;
+  x2 = r == 2 ? mx : x2;
+  y2 = r == 2 ? my : y2;
+}
+
+// All leaves K bisections below a triangle, child 0 first (the order of the
+// leaf sums is the depth-first order of the bisection tree at every level).
+template <int K, class V, class Leaf>
+TRIME_D void subtree(V x0, V y0, V x1, V y1, V x2, V y2, Leaf &leaf) {
+  if constexpr (K == 0) {
+    leaf(x0, y0, x1, y1, x2, y2);
+  } else {
+    int e;
+    V mx, my;
+    longest_edge(x0, y0, x1, y1, x2, y2, e, mx, my);
+#pragma unroll 1
+    for (int bit = 0; bit < 2; bit++) {
+      V a0 = x0, b0 = y0, a1 = x1, b1 = y1, a2 = x2, b2 = y2;
+      take_child(e, bit, mx, my, a0, b0, a1, b1, a2, b2);
+      subtree<K - 1>(a0, b0, a1, b1, a2, b2, leaf);
+    }
+  }
+}
 
 template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct Lane {
   const KArgs &a;
@@ -178,6 +242,7 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   int why;  // nonzero: the point leaves this kernel (WHY_*)
   T R2;
   ExactCount ec;
+  Work wk;
 
   TRIME_D Lane(const KArgs &a_, VRec<T> (&P_)[VMAX][BLOCK], int tid_, int64_t k_)
       : a(a_), P(P_), tid(tid_), k(k_), n(0), why(0), R2(0) {}
@@ -212,6 +277,24 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     int c1 = con(j == 0 ? n - 1 : j - 1), c2 = con(j);
     return make_vertex<double>(row_of<double>(a, c1, px, py, S, D), row_of<double>(a, c2, px, py, S, D),
                                vx, vy, E);
+  }
+
+  // The octagon test of vertex j against wall w of the point q at (qxd, qyd)
+  // in FP64, from the FP64 vertex: +1 outside, -1 inside, 0 undecided.
+  TRIME_D int oct_margin64(int j, double qxd, double qyd, float Sq, float Dq, int w) const {
+    const double u = U<double>::v;
+    double vx, vy;
+    float E;
+    if (!vertex64(j, vx, vy, E)) return 0;
+    double qx = qxd - px, qy = qyd - py;
+    double cx = vx - qx, cy = vy - qy;
+    int nx, ny;
+    oct_normal(w, nx, ny);
+    double s = (w & 1) ? (double)Dq : (double)Sq;
+    double base = (double)E + 2 * u * (fabs(qx) + fabs(qy)) + 2 * u * (fabs(cx) + fabs(cy));
+    double m = (double)nx * cx + (double)ny * cy - s;
+    double b = 2 * ((double)(abs(nx) + abs(ny)) * base + 2 * u * s);
+    return m > b ? 1 : (m < -b ? -1 : 0);
   }
 
   // bound on |v_true|^2 over the vertices, capped by the octagon's circumradius
@@ -276,12 +359,19 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
           if (exact_cut(a, con(j == 0 ? n - 1 : j - 1), v.c, c3, pid, px, py, S, D, ec) > 0)
             M |= 1u << j;
         } else {
-          why = WHY_PRED;
-          return;
+          int s64 = sizeof(T) == 4 ? margin64(con(j == 0 ? n - 1 : j - 1), v.c, c3) : 0;
+          if (s64 > 0) {
+            M |= 1u << j;
+          } else if (s64 == 0) {
+            why = WHY_PRED;
+            return;
+          }
         }
       }
     }
+    wk.margins += n;
     if (M == 0) return;
+    wk.cuts++;
     uint32_t full = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
     if (M == full) {
       n = 0;
@@ -363,6 +453,7 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     for (;;) {
       if (s < se) {
         if (s != (int)k) {
+          wk.candidates++;
           Row<T> r3;
           r3.nx = (T)(gld(a.x, s) - px);
           r3.ny = (T)(gld(a.y, s) - py);
@@ -417,8 +508,12 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
           // in the frame of q: bisector(q, p), bisector(q, other), wall w of q
           if (exact_cut(a, (int)k, other, -1 - w, gld(a.id, q), qxd, qyd, Sq, Dq, ec) > 0) return 0;
         } else {
-          why = WHY_AND;
-          return 0;
+          int s64 = sizeof(T) == 4 ? oct_margin64(j, qxd, qyd, Sq, Dq, w) : 0;
+          if (s64 > 0) return 0;
+          if (s64 == 0) {
+            why = WHY_AND;
+            return 0;
+          }
         }
       }
     }
@@ -456,92 +551,130 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     gst(a.cell_n, (int64_t)pid, n);
   }
 
-  // Weighted centroid (relative to p) at quadrature level L >= 1; also the
-  // number of leaf triangles.
-  TRIME_D void level_centroid(int L, T fxf, T fyf, int64_t cx0, int64_t cy0, T &cx, T &cy) {
-    T sw = 0, swx = 0, swy = 0;
-    const T idx = (T)a.inv_dx, idy = (T)a.inv_dy;
+  // Weighted centroid (relative to p) at quadrature level L >= 1: the fan
+  // triangles (p, v_t, v_t+1) bisected L - 1 times, one midpoint sample of
+  // rho = mu^-2 per leaf.  getv(t, x, y) yields vertex t in V arithmetic.
+  // Below QK bisections a leaf is reached by its bit path from the fan
+  // triangle; deeper levels walk subtrees of QK bisections depth first, so
+  // each bisection is done once.  Leaves are summed in the same order
+  // either way.
+  static constexpr int QK = 3;
+
+  template <class V, class GetV>
+  TRIME_D void level_centroid(int L, V fxf, V fyf, int64_t cx0, int64_t cy0, GetV &getv, V &cx, V &cy) {
+    V sw = 0, swx = 0, swy = 0;
+    const V idx = (V)a.inv_dx, idy = (V)a.inv_dy;
     const G *mu = (const G *)a.mu;
-    int nleaf = 1 << (L - 1);
-    for (int t = 0; t < n; t++) {
-      VRec<T> vb = P[t][tid], vc = P[(t + 1 == n) ? 0 : t + 1][tid];
-      for (int b = 0; b < nleaf; b++) {
-        T x0 = 0, y0 = 0, x1 = vb.x, y1 = vb.y, x2 = vc.x, y2 = vc.y;
-        for (int d = L - 2; d >= 0; d--) {
-          int bit = (b >> d) & 1;
-          T l0 = (x1 - x0) * (x1 - x0) + (y1 - y0) * (y1 - y0);
-          T l1 = (x2 - x1) * (x2 - x1) + (y2 - y1) * (y2 - y1);
-          T l2 = (x0 - x2) * (x0 - x2) + (y0 - y2) * (y0 - y2);
-          if (l0 >= l1 && l0 >= l2) {
-            T mx = (x0 + x1) * (T)0.5, my = (y0 + y1) * (T)0.5;
-            if (!bit) { x1 = mx; y1 = my; } else { x0 = mx; y0 = my; }
-          } else if (l1 >= l2) {
-            T mx = (x1 + x2) * (T)0.5, my = (y1 + y2) * (T)0.5;
-            if (!bit) { x2 = mx; y2 = my; } else { x1 = mx; y1 = my; }
-          } else {
-            T mx = (x2 + x0) * (T)0.5, my = (y2 + y0) * (T)0.5;
-            if (!bit) { x2 = mx; y2 = my; } else { x0 = mx; y0 = my; }
-          }
-        }
-        T A = (T)0.5 * ((x1 - x0) * (y2 - y0) - (y1 - y0) * (x2 - x0));
-        T gx = (x0 + x1 + x2) * (T)(1.0 / 3.0), gy = (y0 + y1 + y2) * (T)(1.0 / 3.0);
-        // mu at p + g: bilinear in its cell (cells clamped to the grid)
-        T fx = fxf + gx * idx, fy = fyf + gy * idy;
-        T flx = floor(fx), fly = floor(fy);
-        int64_t ci = cx0 + (int64_t)flx, cj = cy0 + (int64_t)fly;
-        T tx = fx - flx, ty = fy - fly;
-        if (ci < 0) { ci = 0; tx = 0; }
-        if (ci > a.nx - 2) { ci = a.nx - 2; tx = 1; }
-        if (cj < 0) { cj = 0; ty = 0; }
-        if (cj > a.ny - 2) { cj = a.ny - 2; ty = 1; }
-        int64_t n0 = cj * a.nx + ci;
-        T m00 = (T)gld(mu, n0), m10 = (T)gld(mu, n0 + 1);
-        T m01 = (T)gld(mu, n0 + a.nx), m11 = (T)gld(mu, n0 + a.nx + 1);
-        T m = (m00 * ((T)1 - tx) + m10 * tx) * ((T)1 - ty) + (m01 * ((T)1 - tx) + m11 * tx) * ty;
-        T w = A * recip<T>(m * m);
-        sw += w;
-        swx += w * gx;
-        swy += w * gy;
+    const int64_t nxc = a.nx - 2, nyc = a.ny - 2;
+    int64_t last = -1;  // the four node values of the last grid cell are kept
+    V m00 = 0, m10 = 0, m01 = 0, m11 = 0;
+    auto leaf = [&](V x0, V y0, V x1, V y1, V x2, V y2) {
+      V A = (V)0.5 * ((x1 - x0) * (y2 - y0) - (y1 - y0) * (x2 - x0));
+      V gx = (x0 + x1 + x2) * (V)(1.0 / 3.0), gy = (y0 + y1 + y2) * (V)(1.0 / 3.0);
+      // mu at p + g: bilinear in its cell (cells clamped to the grid)
+      V fx = fxf + gx * idx, fy = fyf + gy * idy;
+      V flx = floor(fx), fly = floor(fy);
+      int64_t ci = cx0 + (int64_t)flx, cj = cy0 + (int64_t)fly;
+      V tx = fx - flx, ty = fy - fly;
+      if (ci < 0) { ci = 0; tx = 0; }
+      if (ci > nxc) { ci = nxc; tx = 1; }
+      if (cj < 0) { cj = 0; ty = 0; }
+      if (cj > nyc) { cj = nyc; ty = 1; }
+      int64_t n0 = cj * a.nx + ci;
+      if (n0 != last) {
+        m00 = (V)gld(mu, n0);
+        m10 = (V)gld(mu, n0 + 1);
+        m01 = (V)gld(mu, n0 + a.nx);
+        m11 = (V)gld(mu, n0 + a.nx + 1);
+        last = n0;
       }
+      V m = (m00 * ((V)1 - tx) + m10 * tx) * ((V)1 - ty) + (m01 * ((V)1 - tx) + m11 * tx) * ty;
+      V w = A * recip<V>(m * m);
+      sw += w;
+      swx += w * gx;
+      swy += w * gy;
+    };
+    const int D = L - 1;
+    V vx0, vy0, ax, ay;
+    getv(0, vx0, vy0);
+    ax = vx0;
+    ay = vy0;
+    for (int t = 0; t < n; t++) {
+      V bx, by;
+      if (t + 1 == n) {
+        bx = vx0;
+        by = vy0;
+      } else {
+        getv(t + 1, bx, by);
+      }
+      const int top = D < QK ? D : D - QK;  // bisections by bit path
+      const int nb = 1 << top;
+      for (int b = 0; b < nb; b++) {
+        V x0 = 0, y0 = 0, x1 = ax, y1 = ay, x2 = bx, y2 = by;
+        for (int d = top - 1; d >= 0; d--) {
+          int e;
+          V mx, my;
+          longest_edge(x0, y0, x1, y1, x2, y2, e, mx, my);
+          take_child(e, (b >> d) & 1, mx, my, x0, y0, x1, y1, x2, y2);
+        }
+        if (D < QK)
+          leaf(x0, y0, x1, y1, x2, y2);
+        else
+          subtree<QK>(x0, y0, x1, y1, x2, y2, leaf);
+      }
+      ax = bx;
+      ay = by;
     }
-    T inv = (T)1 / sw;
+    wk.leaves += n << D;
+    V inv = (V)1 / sw;
     cx = swx * inv;
     cy = swy * inv;
   }
 
-  // CVD target of p (Sec. 4.2 II); may set why = WHY_LEVEL (FP32 only).
-  TRIME_D void cvd_target(double h, double dp, double &xnew, double &ynew, int &cap_hit) {
-    const T u = U<T>::v;
-    xnew = px;
-    ynew = py;
-    if (n == 0) return;
-    T A = 0;
-    for (int j = 0; j < n; j++) {
-      VRec<T> v0 = P[j][tid], v1 = P[(j + 1 == n) ? 0 : j + 1][tid];
-      A += (T)0.5 * (v0.x * v1.y - v0.y * v1.x);
+  // The adaptive level loop of the CVD target (Sec. 4.2 II) in V arithmetic.
+  // BAND (FP32): false when a level decision lies within the error bound of
+  // the two centroids compared; the caller then redoes it in FP64.
+  template <class V, bool BAND, class GetV>
+  TRIME_D bool cvd_levels(double h, double dp, GetV &getv, double &xnew, double &ynew, int &cap_hit) {
+    const V u = U<V>::v;
+    V A = 0;
+    {
+      V x0, y0, xa, ya;
+      getv(0, x0, y0);
+      xa = x0;
+      ya = y0;
+      for (int j = 0; j < n; j++) {
+        V xb, yb;
+        if (j + 1 == n) {
+          xb = x0;
+          yb = y0;
+        } else {
+          getv(j + 1, xb, yb);
+        }
+        A += (V)0.5 * (xa * yb - ya * xb);
+        xa = xb;
+        ya = yb;
+      }
     }
     double eps = fmax((dp < 0 ? h : dp) / h, a.prm.fac_end);
-    T E = (T)(sqrt((double)A) * eps);
+    V E = (V)(sqrt((double)A) * eps);
     double fx0 = (px - a.gx0) * a.inv_dx, fy0 = (py - a.gy0) * a.inv_dy;
     int64_t cx0 = (int64_t)floor(fx0), cy0 = (int64_t)floor(fy0);
-    T fxf = (T)(fx0 - (double)cx0), fyf = (T)(fy0 - (double)cy0);
-    T R = sqrt(R2);
-    T c0x = 0, c0y = 0, c1x = 0, c1y = 0;
-    T err0 = 0;  // error bound of the previous level's centroid
+    V fxf = (V)(fx0 - (double)cx0), fyf = (V)(fy0 - (double)cy0);
+    V R = sqrt((V)R2);
+    V c0x = 0, c0y = 0, c1x = 0, c1y = 0;
+    V err0 = 0;  // error bound of the previous level's centroid
     for (int L = 1;; L++) {
-      level_centroid(L, fxf, fyf, cx0, cy0, c1x, c1y);
-      T ex_ = c0x - c1x, ey_ = c0y - c1y;
-      T d2 = ex_ * ex_ + ey_ * ey_;
-      if constexpr (!EXACT && sizeof(T) == 4) {
+      level_centroid<V>(L, fxf, fyf, cx0, cy0, getv, c1x, c1y);
+      V ex_ = c0x - c1x, ey_ = c0y - c1y;
+      V d2 = ex_ * ex_ + ey_ * ey_;
+      if constexpr (BAND) {
         // centroid error: vertices and weights (~32u R) plus the sums
         // (u R per leaf term), for both levels compared
-        T err1 = ((T)32 + (T)2 * (T)(n << (L - 1))) * u * R;
-        T dd = err0 + err1;
-        T lo = fmax(E - dd, (T)0), hi = E + dd;
-        if (d2 >= lo * lo && d2 <= hi * hi) {
-          why = WHY_LEVEL;
-          return;
-        }
+        V err1 = ((V)32 + (V)2 * (V)(n << (L - 1))) * u * R;
+        V dd = err0 + err1;
+        V lo = fmax(E - dd, (V)0), hi = E + dd;
+        if (d2 >= lo * lo && d2 <= hi * hi) return false;
         err0 = err1;
       }
       if (d2 < E * E) break;
@@ -554,10 +687,34 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     }
     xnew = px + (double)c1x;
     ynew = py + (double)c1y;
+    return true;
+  }
+
+  // CVD target of p (Sec. 4.2 II).  An FP32 level decision within its error
+  // bound sends the point to the FP64 replay (WHY_LEVEL).
+  TRIME_D void cvd_target(double h, double dp, double &xnew, double &ynew, int &cap_hit) {
+    xnew = px;
+    ynew = py;
+    if (n == 0) return;
+    auto getT = [&](int t, T &x, T &y) {
+      VRec<T> v = P[t][tid];
+      x = v.x;
+      y = v.y;
+    };
+    constexpr bool band = !EXACT && sizeof(T) == 4;
+    if (!cvd_levels<T, band>(h, dp, getT, xnew, ynew, cap_hit)) why = WHY_LEVEL;
   }
 
   // Everything for point k; returns false when the point must be replayed.
   TRIME_D bool run(LaneStats &st, int *hist) {
+    if (!begin()) return false;
+    scan();
+    if (why) return false;
+    return finish(st, hist);
+  }
+
+  // The point and its initial polygon; false when the point must leave.
+  TRIME_D bool begin() {
     pid = gld(a.id, k);
     px = gld(a.x, k);
     py = gld(a.y, k);
@@ -568,8 +725,90 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       return false;
     }
     init_polygon();
-    if (!why) scan();
-    if (why) return false;
+    return !why;
+  }
+
+  // The ring scan of a whole wavefront for one point: every lane holds the
+  // same lane state and polygon (LDS writes of equal values), the candidates
+  // of a ring are loaded and range-tested 64 at a time, one per lane, and the
+  // ones in range are clipped in lane order by all lanes together.  The cell
+  // does not depend on the clip order (every decision is exact).
+  TRIME_D void scan_wave(int lane, int *sh_s0, int *sh_incl) {
+    const T u = U<T>::v;
+    int bx, by;
+    bin_of(a, px, py, bx, by);
+    double ox = px - (a.bx0 + bx * a.bw), oy = py - (a.by0 + by * a.bw);
+    double edge = fmax(0.0, fmin(fmin(ox, a.bw - ox), fmin(oy, a.bw - oy)));
+    const int rmax = max(a.nbx, a.nby);
+    for (int r = 0;; r++) {
+      if (r > 0) {
+        double dmin = (r - 1) * a.bw + edge;
+        if (r > rmax || dmin * dmin > 4.0 * (double)R2 * 1.00001) return;
+      }
+      const int nbr = r == 0 ? 1 : 8 * r;
+      for (int b0 = 0; b0 < nbr; b0 += 64) {
+        int bi = b0 + lane, s0 = 0, cnt = 0;
+        if (bi < nbr) {
+          int dx, dy;
+          ring_bin(r, bi, dx, dy);
+          int xx = bx + dx, yy = by + dy;
+          if (xx >= 0 && yy >= 0 && xx < a.nbx && yy < a.nby) {
+            uint32_t key = morton((uint32_t)xx, (uint32_t)yy);
+            s0 = gld(a.bin_start, (int64_t)key);
+            cnt = gld(a.bin_start, (int64_t)key + 1) - s0;
+          }
+        }
+        int incl = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+          int y = __shfl_up(incl, off);
+          if (lane >= off) incl += y;
+        }
+        const int total = __shfl(incl, 63);
+        sh_s0[lane] = s0;
+        sh_incl[lane] = incl;
+        __syncthreads();
+        for (int c0 = 0; c0 < total; c0 += 64) {
+          int c = c0 + lane, sl = -1;
+          bool pass = false;
+          if (c < total) {
+            int lo = 0, hi = 63;  // first bin with incl > c
+            while (lo < hi) {
+              int mid = (lo + hi) >> 1;
+              if (sh_incl[mid] > c) hi = mid; else lo = mid + 1;
+            }
+            int first = lo > 0 ? sh_incl[lo - 1] : 0;
+            sl = sh_s0[lo] + (c - first);
+            if (sl != (int)k) {
+              T nx = (T)(gld(a.x, sl) - px), ny = (T)(gld(a.y, sl) - py);
+              T sq = nx * nx + ny * ny;
+              pass = !(sq * ((T)1 - (T)8 * u) > (T)4 * R2);
+            }
+          }
+          wk.candidates += __popcll(__ballot(c < total && sl != (int)k));
+          uint64_t m = __ballot(pass);
+          while (m) {
+            int j = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            int sj = __shfl(sl, j);
+            Row<T> r3;
+            r3.nx = (T)(gld(a.x, sj) - px);
+            r3.ny = (T)(gld(a.y, sj) - py);
+            T sq = r3.nx * r3.nx + r3.ny * r3.ny;
+            r3.s = sq * (T)0.5;
+            if (!(sq * ((T)1 - (T)8 * u) > (T)4 * R2)) {
+              clip(r3, sj);
+              if (why || n == 0) return;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  // Everything after the cell: decisions, CVD target and treatment, then
+  // the commit of the outputs; false when the point must leave.
+  TRIME_D bool finish(LaneStats &st, int *hist) {
     if constexpr (MODE == MODE_CELLS) {
       write_cell();
     } else {
@@ -678,6 +917,10 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       }
     }
     if (n == 0) st.empty++;
+    st.candidates += wk.candidates;
+    st.margins += wk.margins;
+    st.cuts += wk.cuts;
+    st.leaves += wk.leaves;
     if (ec.calls) {
       st.exact_pts++;
       st.exact_calls += ec.calls;
@@ -691,10 +934,11 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
 // Block reduction of the lane statistics into the device stats.
 template <int BLOCK> TRIME_D void flush_stats(const KArgs &a, LaneStats &st, int *hist) {
   __shared__ double rs[4][BLOCK / 64];
-  __shared__ int ri[12][BLOCK / 64];
+  __shared__ int ri[16][BLOCK / 64];
   double v[4] = {st.sa, st.sb, st.sq, st.amax};
-  int iv[12] = {st.nq, st.ntri, st.nvalid, st.replays, st.exact_pts, st.exact_calls,
-                st.sos, st.overflow, st.empty, st.newton_fail, st.trace_fail, st.cap_hits};
+  int iv[16] = {st.nq,  st.ntri,        st.nvalid,     st.replays,   st.exact_pts,  st.exact_calls,
+                st.sos, st.overflow,    st.empty,      st.newton_fail, st.trace_fail, st.cap_hits,
+                st.candidates, st.margins, st.cuts, st.leaves};
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int off = 32; off > 0; off >>= 1) {
     v[0] += __shfl_down(v[0], off);
@@ -702,13 +946,13 @@ template <int BLOCK> TRIME_D void flush_stats(const KArgs &a, LaneStats &st, int
     v[2] += __shfl_down(v[2], off);
     v[3] = fmax(v[3], __shfl_down(v[3], off));
 #pragma unroll
-    for (int q = 0; q < 12; q++) iv[q] += __shfl_down(iv[q], off);
+    for (int q = 0; q < 16; q++) iv[q] += __shfl_down(iv[q], off);
   }
   if (lane == 0) {
 #pragma unroll
     for (int q = 0; q < 4; q++) rs[q][wv] = v[q];
 #pragma unroll
-    for (int q = 0; q < 12; q++) ri[q][wv] = iv[q];
+    for (int q = 0; q < 16; q++) ri[q][wv] = iv[q];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -718,7 +962,7 @@ template <int BLOCK> TRIME_D void flush_stats(const KArgs &a, LaneStats &st, int
       rs[2][0] += rs[2][w];
       rs[3][0] = fmax(rs[3][0], rs[3][w]);
 #pragma unroll
-      for (int q = 0; q < 12; q++) ri[q][0] += ri[q][w];
+      for (int q = 0; q < 16; q++) ri[q][0] += ri[q][w];
     }
     trime_stats *S = a.stats;
     typedef unsigned long long ull;
@@ -740,6 +984,10 @@ template <int BLOCK> TRIME_D void flush_stats(const KArgs &a, LaneStats &st, int
     if (ri[9][0]) atomicAdd((ull *)&S->newton_fail, (ull)ri[9][0]);
     if (ri[10][0]) atomicAdd((ull *)&S->trace_fail, (ull)ri[10][0]);
     if (ri[11][0]) atomicAdd((ull *)&S->level_cap_hits, (ull)ri[11][0]);
+    if (ri[12][0]) atomicAdd((ull *)&S->work_candidates, (ull)ri[12][0]);
+    if (ri[13][0]) atomicAdd((ull *)&S->work_margins, (ull)ri[13][0]);
+    if (ri[14][0]) atomicAdd((ull *)&S->work_cuts, (ull)ri[14][0]);
+    if (ri[15][0]) atomicAdd((ull *)&S->work_leaves, (ull)ri[15][0]);
   }
   for (int b = threadIdx.x; b < 40; b += BLOCK)
     if (hist[b]) atomicAdd((unsigned long long *)&a.stats->hist_beta[b], (unsigned long long)hist[b]);
@@ -757,19 +1005,21 @@ TRIME_D void push(const KArgs &a, int which, int64_t k, int why) {
   atomicAdd(&a.counters[CNT_REASON + why], 1);
 }
 
-// Fast kernel: one point per lane.  Undecided FP32 points go to the FP64
-// replay queue, undecided FP64 points to the exact queue.
+// Fast kernel: one point per lane, slots in the processing order.  Points it
+// cannot finish (an undecided decision, a polygon beyond its capacity, the
+// grid box within reach) go to the FP64 replay queue.
 template <class T, class G, int MODE, int VMAX, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_cells(KArgs a) {
   __shared__ VRec<T> P[VMAX][BLOCK];
   __shared__ int hist[40];
   zero_hist<BLOCK>(hist);
   LaneStats st;
-  int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (k < a.n) {
+  int64_t w = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (w < a.n) {
+    int64_t k = gld(a.order, w);
     Lane<T, G, MODE, false, VMAX, BLOCK> L(a, P, threadIdx.x, k);
     if (!L.run(st, hist)) {
-      push(a, sizeof(T) == 4 ? 1 : 2, k, L.why);
+      push(a, 1, k, L.why);
       st.replays++;
       if (L.why == WHY_POLY) st.overflow++;
     }
@@ -777,20 +1027,33 @@ __global__ __launch_bounds__(BLOCK) void k_cells(KArgs a) {
   flush_stats<BLOCK>(a, st, hist);
 }
 
-// FP64 replay of the queue (grid-stride); undecided points go on.
-template <class G, int MODE, int VMAX, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_cells_replay(KArgs a) {
-  __shared__ VRec<double> P[VMAX][BLOCK];
+// FP64 replay of the queue, one wavefront per point (grid-stride over the
+// queue): the ring scan is shared by the 64 lanes, the rest of the point runs
+// on lane 0.  Points FP64 cannot decide go on to the exact queue.
+template <class G, int MODE, int VMAX>
+__global__ __launch_bounds__(64) void k_cells_wave(KArgs a) {
+  __shared__ VRec<double> P[VMAX][1];
   __shared__ int hist[40];
-  zero_hist<BLOCK>(hist);
+  __shared__ int sh_s0[64], sh_incl[64];
+  zero_hist<64>(hist);
   LaneStats st;
+  const int lane = threadIdx.x;
   int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE);
-  for (int64_t w = (int64_t)blockIdx.x * BLOCK + threadIdx.x; w < nq; w += (int64_t)gridDim.x * BLOCK) {
+  for (int64_t w = blockIdx.x; w < nq; w += gridDim.x) {
     int64_t k = gld(a.queue, w);
-    Lane<double, G, MODE, false, VMAX, BLOCK> L(a, P, threadIdx.x, k);
-    if (!L.run(st, hist)) push(a, 2, k, L.why);
+    Lane<double, G, MODE, false, VMAX, 1> L(a, P, 0, k);
+    bool ok = L.begin();
+    if (ok) {
+      L.scan_wave(lane, sh_s0, sh_incl);
+      ok = !L.why;
+    }
+    if (lane == 0) {
+      if (ok) ok = L.finish(st, hist);
+      if (!ok) push(a, 2, k, L.why);
+    }
+    __syncthreads();
   }
-  flush_stats<BLOCK>(a, st, hist);
+  flush_stats<64>(a, st, hist);
 }
 
 // Exact replay of the second queue.
@@ -829,14 +1092,14 @@ constexpr int FAST_BLOCK = 128;
 constexpr int FAST_VMAX = TRIME_FAST_VMAX;  // polygon capacity of the fast kernel
 constexpr int REPLAY_BLOCK = 64;
 constexpr int REPLAY_VMAX = 32;
+constexpr int WAVE_VMAX = 64;
 
 template <class T, class G, int MODE> static void launch_mode(const KArgs &a, hipStream_t s) {
   int nb = (int)((a.n + FAST_BLOCK - 1) / FAST_BLOCK);
   if (a.ev0) (void)hipEventRecord((hipEvent_t)a.ev0, s);
   if (nb > 0) hipLaunchKernelGGL((k_cells<T, G, MODE, FAST_VMAX, FAST_BLOCK>), dim3(nb), dim3(FAST_BLOCK), 0, s, a);
   if (a.ev1) (void)hipEventRecord((hipEvent_t)a.ev1, s);
-  if (sizeof(T) == 4)
-    hipLaunchKernelGGL((k_cells_replay<G, MODE, REPLAY_VMAX, REPLAY_BLOCK>), dim3(512), dim3(REPLAY_BLOCK), 0, s, a);
+  hipLaunchKernelGGL((k_cells_wave<G, MODE, WAVE_VMAX>), dim3(1024), dim3(64), 0, s, a);
   hipLaunchKernelGGL((k_cells_exact<G, MODE, REPLAY_VMAX, REPLAY_BLOCK>), dim3(64), dim3(REPLAY_BLOCK), 0, s, a);
 }
 

@@ -210,6 +210,7 @@ template <class G> __global__ void k_load(KArgs a, LoadArgs l) {
   l.yl[k] = y;
   l.dprev[k] = -1.0;
   l.id[k] = (int)k;
+  a.order[k] = (int)k;
   l.span[k] = span_at(a, x, y);
   bool unsure = false;
   l.cat[k] = point_category<G>(a, x, y, 0.0, unsure);
@@ -368,6 +369,10 @@ __global__ void k_stats_reset_quality(KArgs a, int full) {
       S->sum_l2 = 0;
       S->sum_mu2 = 0;
       S->fac_mu = 0;
+      S->work_candidates = 0;
+      S->work_margins = 0;
+      S->work_cuts = 0;
+      S->work_leaves = 0;
     }
   }
   if (t < (full ? CNT_NCOUNTERS : CNT_REASON)) a.counters[t] = 0;

@@ -40,6 +40,7 @@ struct KArgs {
   // binning
   int32_t *perm;
   int32_t *bin_start, *bin_fill, *key, *rank;
+  int32_t *order;  // processing order of the slots in the cell kernels
   int32_t nbx, nby, lbits;
   double bx0, by0, bw, inv_bw;
   // grid

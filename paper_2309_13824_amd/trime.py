@@ -72,7 +72,8 @@ class Stats(C.Structure):
                 ("error", C.c_int32), ("sum_l2", C.c_double), ("sum_mu2", C.c_double),
                 ("fac_mu", C.c_double), ("sum_sqrt_alpha", C.c_double), ("sum_sqrt_beta", C.c_double),
                 ("sum_q", C.c_double), ("max_alpha", C.c_double), ("nq", C.c_int64),
-                ("hist_beta", C.c_int64 * 40)]
+                ("hist_beta", C.c_int64 * 40), ("work_candidates", C.c_int64), ("work_margins", C.c_int64),
+                ("work_cuts", C.c_int64), ("work_leaves", C.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "hist_beta"}
@@ -100,7 +101,7 @@ class State(C.Structure):
                 ("params", Params), ("pos", PosBuf * 2), ("ord", OrdBuf * 2), ("cur_pos", C.c_int32),
                 ("cur_ord", C.c_int32), ("adj", C.c_void_p), ("deg", C.c_void_p), ("tri", C.c_void_p),
                 ("tri_valid", C.c_void_p), ("tri_n", C.c_void_p), ("perm", C.c_void_p),
-                ("key", C.c_void_p), ("rank", C.c_void_p), ("bin_start", C.c_void_p),
+                ("key", C.c_void_p), ("rank", C.c_void_p), ("order", C.c_void_p), ("bin_start", C.c_void_p),
                 ("bin_fill", C.c_void_p), ("scan_tmp", C.c_void_p), ("queue", C.c_void_p),
                 ("counters", C.c_void_p), ("partials", C.c_void_p), ("stats", C.c_void_p),
                 ("nbx", C.c_int32), ("nby", C.c_int32), ("lbits", C.c_int32), ("bx0", C.c_double),
