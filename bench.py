@@ -25,12 +25,47 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "point-iterations/s at 1e6 pts (FP32+FP64-fallback vs FP64); % of roofline"
-PEAK = {"f32": 157.3e12, "f64": 78.6e12}  # MI355X vector FP32 / FP64 FLOP/s
+PEAK_FP32 = 157.3e12  # MI355X vector FP32 FLOP/s (published)
+PEAK_HBM = 8.0e12     # MI355X HBM3E bytes/s (published)
 
 # Algorithmic FP operations per counted event of the fused cell kernel
-# (FMA = 2, add/mul/div/sqrt = 1, compares free); counts per point come from
-# the instrumented oracle on the same workload.
-FLOPS_PER = {"candidates": 7, "clip_tests": 6, "cuts": 130, "quad_points": 45, "point": 900}
+# (FMA = 2, add/mul/div/sqrt/rcp = 1, compares and selects free), read off the
+# arithmetic of each step; the event counts are the kernel's own work counters
+# over the timed iterations.
+#   candidate: offset (2), |q-p|^2 (3), range test (2)
+#   margin:    n.v - s (4), its error bound (2)
+#   cut:       two vertices by Cramer's rule with bounds (2 x 32), the rows of
+#              the neighbouring constraints (10), the radius bound over ~8
+#              vertices (8 x 10), the record shifts (0)
+#   leaf:      area (5), centroid (6), grid coordinates (8), bilinear mu (11),
+#              weight mu^-2 (3), three sums (5), its share of the bisections
+#              (longest edge 15 + midpoint 4)
+#   point:     octagon tests of ~6 vertices at two neighbours (6 x 2 x 8 x 8),
+#              validity of ~2 triangles (2 x 60), quality of ~2 (2 x 45), area
+#              and level loop (~40), treatment (~40), setup (~30)
+FLOPS_PER = {"candidates": 7, "margins": 6, "cuts": 154, "leaves": 57, "point": 1088}
+
+# Algorithmic bytes per point of the fused kernel: its own state read once
+# (x, y, dprev 24 + cat 1 + id 4 + span 4 + order 4), the new state written
+# (x, y, dprev 24 + cat 1), ~2 owned triangles (2 x 13) + count 4, and the
+# distinct mu nodes of its cell (~16 x 4); neighbour positions are counted
+# once, with the point that owns them.
+BYTES_PER_POINT = 37 + 25 + 30 + 64
+
+# HBM traffic of one launch of the fused kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (first two CVD iterations, scaled by a 1 GiB copy: FETCH x 2.0,
+# WRITE x 1.0), valid for the kernel sources with this digest only.
+TRAFFIC = {"sha1": "6f57a283ffae7bc39ed5adabcda963518ddefe7d", "bytes_per_launch": 515635209.0}
+KERNEL_SOURCES = ["cells.hip", "trime_dev.hpp", "geom_dev.hpp", "exact_dev.hpp", "launch.hpp"]
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2309_13824_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def parse():
@@ -43,7 +78,24 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(mib, log):
+    """A plain device-to-device copy of known size, three times: the reference
+    the FETCH_SIZE / WRITE_SIZE counters of the cell kernel are scaled by."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy probe: %d MiB read + %d MiB written per copy, 3 copies" % (mib, mib))
+    print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3}), flush=True)
 
 
 def gpu_run(wl, precision, steps, warmup, log):
@@ -89,25 +141,30 @@ def gpu_run(wl, precision, steps, warmup, log):
     return m, total_ms, float(np.mean(kern_ms)), st
 
 
+CPU_ITERS = 3
+
+
 def cpu_baseline(wl, threads, log):
-    """The oracle as it stands: one CVD iteration (triangulation + centroids
-    + treatment) over every point, on the host cores."""
+    """The oracle as it stands: the first CPU_ITERS CVD iterations from the
+    seeded start (triangulation with validity and quality, centroids,
+    treatment) over every point, on the host cores; setup not timed."""
     from oracle import oracle as orc
     t = time.perf_counter()
     og = orc.build_grid(wl)
-    x0, y0 = wl.x, wl.y
-    cats = orc.initial_categories(og, x0, y0)
+    x, y = wl.x, wl.y
+    cats = orc.initial_categories(og, x, y)
+    dprev = np.full(wl.n, -1.0)
     log("  cpu oracle setup (grid, categories) %.1f s" % (time.perf_counter() - t))
-    t = time.perf_counter()
-    mesh = orc.triangulate(og, x0, y0, nthreads=threads)
-    t_tri = time.perf_counter() - t
-    t = time.perf_counter()
-    xr, yr, cr, dr, lev, cnt = orc.cvd_step(og, x0, y0, cats, np.full(wl.n, -1.0), nthreads=threads)
-    t_cvd = time.perf_counter() - t
-    secs = t_tri + t_cvd
-    log("  cpu oracle: triangulate %.2f s + cvd %.2f s on %d threads" % (t_tri, t_cvd, threads))
-    per_pt = {k: cnt[k] / wl.n for k in ("candidates", "clip_tests", "cuts", "quad_points")}
-    return secs, per_pt, mesh, (xr, yr)
+    secs = 0.0
+    for it in range(CPU_ITERS):
+        t = time.perf_counter()
+        mesh = orc.triangulate(og, x, y, nthreads=threads)
+        orc.quality(x, y, mesh.tri, mesh.valid)
+        x, y, cats, dprev, _, _ = orc.cvd_step(og, x, y, cats, dprev, nthreads=threads)
+        dt = time.perf_counter() - t
+        secs += dt
+        log("  cpu oracle iteration %d: %.2f s on %d threads" % (it + 1, dt, threads))
+    return secs
 
 
 def main():
@@ -117,6 +174,9 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe, log)
+        return
     import torch
     from paper_2309_13824_amd import inputs as I
     from paper_2309_13824_amd import trime as T
@@ -138,23 +198,35 @@ def main():
 
     threads = args.cpu_threads or min(16, os.cpu_count() or 1)
     cpu = None
-    per_pt = None
     if not args.no_cpu_baseline:
         del m32
         torch.cuda.empty_cache()
-        secs, per_pt, _, _ = cpu_baseline(wl, threads, log)
-        cpu = {"value": wl.n / secs, "unit": "point-iterations/s", "cores": threads, "kind": "oracle",
-               "sample": "one CVD iteration (cells, triangles + Tests 1-3, centroids, treatment) over all "
-                         "%d points of the holes20 workload, FP64 with exact predicates" % wl.n}
+        secs = cpu_baseline(wl, threads, log)
+        cpu = {"value": wl.n * CPU_ITERS / secs, "unit": "point-iterations/s", "cores": threads, "kind": "oracle",
+               "sample": "the first %d CVD iterations from the seeded start (cells, triangles with Tests 1-3 "
+                         "and quality, centroids, treatment) over all %d points of the holes20 workload, "
+                         "FP64 with exact predicates" % (CPU_ITERS, wl.n)}
 
-    roof = None
-    if per_pt is not None:
-        flops_pt = (FLOPS_PER["point"] + sum(FLOPS_PER[k] * per_pt[k] for k in per_pt))
+    # roofline of the fused cell kernel: algorithmic flops from its own work
+    # counters, algorithmic bytes from the per-point model; the larger time
+    # names the bound
+    pts = float(wl.n * args.steps)
+    per_pt = {k: st32["work_" + k] / pts for k in ("candidates", "margins", "cuts", "leaves")}
+    flops_pt = FLOPS_PER["point"] + sum(FLOPS_PER[k] * per_pt[k] for k in per_pt)
+    t_alu = flops_pt * wl.n / PEAK_FP32
+    t_hbm = BYTES_PER_POINT * wl.n / PEAK_HBM
+    traffic = TRAFFIC["bytes_per_launch"] if kernel_digest() == TRAFFIC["sha1"] else None
+    if t_alu >= t_hbm:
         achieved = flops_pt * wl.n / (k32 * 1e-3)
-        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["f32"] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK["f32"], "traffic": None,
-                "kernel": "k_cells<float,float,CVD> (fused cells+extraction+centroid)",
-                "kernel_ms": k32, "flops_per_point": flops_pt, "counts_per_point": per_pt}
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32}
+    else:
+        achieved = BYTES_PER_POINT * wl.n / (k32 * 1e-3)
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM}
+    roof.update({"traffic": traffic, "kernel": "k_cells<float, float, CVD> (cells, extraction, centroid, "
+                 "treatment)", "kernel_ms": k32, "flops_per_point": flops_pt,
+                 "bytes_per_point": BYTES_PER_POINT, "counts_per_point": per_pt})
 
     out.update({
         "value": pit, "unit": "point-iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -204,7 +204,8 @@ typedef struct {
   int32_t *bin_start;      /* nkeys + 1                                      */
   int32_t *bin_fill;       /* nkeys                                          */
   int32_t *scan_tmp;       /* scan block sums                                */
-  int32_t *queue;          /* n: points replayed in FP64 / exactly           */
+  int32_t *queue;          /* 3(n+1) + 16n: points replayed in FP64, exactly,
+                              and FP32 cells whose centroid is redone in FP64 */
   int32_t *counters;       /* small device counters                          */
   double *partials;        /* per-block partial sums                         */
   trime_stats *stats;      /* device                                         */

@@ -204,7 +204,8 @@ static void layout(trime_state *st, Layout &L) {
   st->bin_fill = L.take<int32_t>(st->nkeys);
   int64_t scan_n = st->nkeys > n ? st->nkeys : n;
   st->scan_tmp = L.take<int32_t>(scan_tmp_ints(scan_n) + 1);
-  st->queue = L.take<int32_t>(2 * (n + 1));  // FP64 replay queue, then the exact queue
+  // FP64 replay queue, exact queue, deferred-centroid queue and its cells
+  st->queue = L.take<int32_t>(3 * (n + 1) + (size_t)CQ_STRIDE * n);
   st->counters = L.take<int32_t>(CNT_NCOUNTERS);
   int64_t np = dm_partials(n);
   st->partials = L.take<double>(2 * (np > 1 ? np : 1));
@@ -316,6 +317,8 @@ static KArgs make_args(const trime_state *st) {
   a.tri_n = st->tri_n;
   a.queue = st->queue;
   a.queue2 = st->queue + st->n + 1;
+  a.queue3 = st->queue + 2 * (st->n + 1);
+  a.cq_cons = st->queue + 3 * (st->n + 1);
   a.counters = st->counters;
   a.partials = st->partials;
   a.stats = st->stats;

@@ -705,6 +705,70 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     if (!cvd_levels<T, band>(h, dp, getT, xnew, ynew, cap_hit)) why = WHY_LEVEL;
   }
 
+  // CVD target (Sec. 4.2 II) and treatment (Sec. 4.3) of p; false when an
+  // FP32 decision lies within its error bound (why = WHY_LEVEL / WHY_TREAT).
+  TRIME_D bool target_and_treat(double &xf, double &yf, uint8_t &cf, int &cap_hit, TreatCount &tc) {
+    int64_t cell;
+    double tx, ty;
+    locate(a, px, py, cell, tx, ty);
+    double h = (double)cell_h(a, cell);
+    double xnew, ynew;
+    cvd_target(h, gld(a.dprev, k), xnew, ynew, cap_hit);
+    if (why) return false;
+    double band = (!EXACT && sizeof(T) == 4) ? 1e-6 * h : 0.0;
+    bool unsure = false;
+    treat<G>(a, px, py, gld(a.cat, k), xnew, ynew, band, xf, yf, cf, unsure, tc);
+    if (unsure) {
+      why = WHY_TREAT;
+      return false;
+    }
+    return true;
+  }
+
+  TRIME_D void write_cvd(double xf, double yf, uint8_t cf) {
+    gst(a.xn, k, xf);
+    gst(a.yn, k, yf);
+    gst(a.catn, k, cf);
+    gst(a.dprevn, k, sqrt((xf - px) * (xf - px) + (yf - py) * (yf - py)));
+  }
+
+  // The FP64 centroid pass of one deferred point: its cell's constraints
+  // (entry cb of the deferred queue) give the FP64 vertices, then the CVD
+  // target and the treatment run in FP64.
+  TRIME_D void centroid_replay(LaneStats &st, int64_t cb) {
+    pid = gld(a.id, k);
+    px = gld(a.x, k);
+    py = gld(a.y, k);
+    S = gld(a.span, k);
+    D = 1.41421356f * S;
+    n = gld(a.cq_cons, cb);
+    for (int j = 0; j < n; j++) P[j][tid].c = gld(a.cq_cons, cb + 1 + j);
+    bool bad = false;
+    for (int j = 0; j < n; j++) {
+      double vx, vy;
+      float E;
+      if (!vertex64(j, vx, vy, E)) bad = true;
+      P[j][tid].x = vx;
+      P[j][tid].y = vy;
+      P[j][tid].e = E;
+    }
+    double xf = px, yf = py;
+    uint8_t cf = gld(a.cat, k);
+    int cap_hit = 0;
+    TreatCount tc;
+    if (bad || !target_and_treat(xf, yf, cf, cap_hit, tc)) {  // cannot happen in FP64: keep p
+      atomicOr(&a.counters[CNT_ERR], ERR_POLY_CAP);
+      xf = px;
+      yf = py;
+      cf = gld(a.cat, k);
+    }
+    write_cvd(xf, yf, cf);
+    st.newton_fail += tc.newton_fail();
+    st.trace_fail += tc.trace_fail();
+    st.cap_hits += cap_hit;
+    st.leaves += wk.leaves;
+  }
+
   // Everything for point k; returns false when the point must be replayed.
   TRIME_D bool run(LaneStats &st, int *hist) {
     if (!begin()) return false;
@@ -825,26 +889,17 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
         exists |= 1u << j;
         if (valid_triangle(jin, jout)) valid |= 1u << j;
       }
-      // ---- CVD target and treatment
+      // ---- CVD target and treatment; an FP32 decision within its bound
+      // defers them to the FP64 centroid pass (the cell is final)
       double xf = px, yf = py;
       uint8_t cf = 0;
       int cap_hit = 0;
       TreatCount tc;
+      bool defer = false;
       if constexpr (MODE == MODE_CVD) {
-        int64_t cell;
-        double tx, ty;
-        locate(a, px, py, cell, tx, ty);
-        double h = (double)cell_h(a, cell);
-        double xnew, ynew;
-        cvd_target(h, gld(a.dprev, k), xnew, ynew, cap_hit);
-        if (why) return false;
-        double band = (!EXACT && sizeof(T) == 4) ? 1e-6 * h : 0.0;
-        bool unsure = false;
-        treat<G>(a, px, py, gld(a.cat, k), xnew, ynew, band, xf, yf, cf, unsure, tc);
-        if (unsure) {
-          why = WHY_TREAT;
-          return false;
-        }
+        int leaves0 = wk.leaves;
+        defer = !target_and_treat(xf, yf, cf, cap_hit, tc);
+        if (defer) wk.leaves = leaves0;
       }
       // ---- commit: nothing below can send the point back
       int nt = 0;
@@ -907,13 +962,22 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
         gst(a.deg, k, w);
       }
       if constexpr (MODE == MODE_CVD) {
-        gst(a.xn, k, xf);
-        gst(a.yn, k, yf);
-        gst(a.catn, k, cf);
-        gst(a.dprevn, k, sqrt((xf - px) * (xf - px) + (yf - py) * (yf - py)));
-        st.newton_fail += tc.newton_fail;
-        st.trace_fail += tc.trace_fail;
-        st.cap_hits += cap_hit;
+        if (defer) {
+          int w = atomicAdd(&a.counters[CNT_QUEUE3], 1);
+          gst(a.queue3, (int64_t)w, (int32_t)k);
+          int64_t cb = (int64_t)w * CQ_STRIDE;
+          gst(a.cq_cons, cb, n);
+          for (int j = 0; j < n; j++) gst(a.cq_cons, cb + 1 + j, con(j));
+          atomicAdd(&a.counters[CNT_REASON + why], 1);
+        } else {
+          write_cvd(xf, yf, cf);
+        }
+        // the same fields on both paths (no per-path stores to the stats)
+        int kept = defer ? 0 : 1;
+        st.replays += 1 - kept;
+        st.newton_fail += kept & tc.newton_fail();
+        st.trace_fail += kept & tc.trace_fail();
+        st.cap_hits += kept & cap_hit;
       }
     }
     if (n == 0) st.empty++;
@@ -1027,6 +1091,26 @@ __global__ __launch_bounds__(BLOCK) void k_cells(KArgs a) {
   flush_stats<BLOCK>(a, st, hist);
 }
 
+// FP64 centroid pass over the deferred queue (grid-stride, one lane per
+// point): FP64 vertices from the stored constraints, FP64 CVD target and
+// treatment.  The cells and triangles of these points were committed by the
+// fast kernel.
+template <class G, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_cells_centroid(KArgs a) {
+  constexpr int V = CQ_STRIDE - 1;
+  __shared__ VRec<double> P[V][BLOCK];
+  __shared__ int hist[40];
+  zero_hist<BLOCK>(hist);
+  LaneStats st;
+  int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE3);
+  for (int64_t w = (int64_t)blockIdx.x * BLOCK + threadIdx.x; w < nq; w += (int64_t)gridDim.x * BLOCK) {
+    int64_t k = gld(a.queue3, w);
+    Lane<double, G, MODE_CVD, false, V, BLOCK> L(a, P, threadIdx.x, k);
+    L.centroid_replay(st, w * CQ_STRIDE);
+  }
+  flush_stats<BLOCK>(a, st, hist);
+}
+
 // FP64 replay of the queue, one wavefront per point (grid-stride over the
 // queue): the ring scan is shared by the 64 lanes, the rest of the point runs
 // on lane 0.  Points FP64 cannot decide go on to the exact queue.
@@ -1093,12 +1177,16 @@ constexpr int FAST_VMAX = TRIME_FAST_VMAX;  // polygon capacity of the fast kern
 constexpr int REPLAY_BLOCK = 64;
 constexpr int REPLAY_VMAX = 32;
 constexpr int WAVE_VMAX = 64;
+constexpr int CENTROID_BLOCK = 64;
+static_assert(FAST_VMAX < CQ_STRIDE, "a deferred cell must fit its queue entry");
 
 template <class T, class G, int MODE> static void launch_mode(const KArgs &a, hipStream_t s) {
   int nb = (int)((a.n + FAST_BLOCK - 1) / FAST_BLOCK);
   if (a.ev0) (void)hipEventRecord((hipEvent_t)a.ev0, s);
   if (nb > 0) hipLaunchKernelGGL((k_cells<T, G, MODE, FAST_VMAX, FAST_BLOCK>), dim3(nb), dim3(FAST_BLOCK), 0, s, a);
   if (a.ev1) (void)hipEventRecord((hipEvent_t)a.ev1, s);
+  if (MODE == MODE_CVD && sizeof(T) == 4)
+    hipLaunchKernelGGL((k_cells_centroid<G, CENTROID_BLOCK>), dim3(256), dim3(CENTROID_BLOCK), 0, s, a);
   hipLaunchKernelGGL((k_cells_wave<G, MODE, WAVE_VMAX>), dim3(1024), dim3(64), 0, s, a);
   hipLaunchKernelGGL((k_cells_exact<G, MODE, REPLAY_VMAX, REPLAY_BLOCK>), dim3(64), dim3(REPLAY_BLOCK), 0, s, a);
 }

@@ -134,21 +134,21 @@ template <class T, class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_for
       a.queue[q] = (int)k;
       replay = 1;
       moved = 0;
+      tc.fail = 0;
     }
   }
+  int nf = tc.newton_fail(), tf = tc.trace_fail();
   for (int off = 32; off > 0; off >>= 1) {
     moved += __shfl_down(moved, off);
     replay += __shfl_down(replay, off);
-    tc.newton_fail += __shfl_down(tc.newton_fail, off);
-    tc.trace_fail += __shfl_down(tc.trace_fail, off);
+    nf += __shfl_down(nf, off);
+    tf += __shfl_down(tf, off);
   }
   if ((threadIdx.x & 63) == 0) {
     if (moved) atomicAdd((unsigned long long *)&a.stats->moved, (unsigned long long)moved);
     if (replay) atomicAdd((unsigned long long *)&a.stats->fp64_replays, (unsigned long long)replay);
-    if (tc.newton_fail)
-      atomicAdd((unsigned long long *)&a.stats->newton_fail, (unsigned long long)tc.newton_fail);
-    if (tc.trace_fail)
-      atomicAdd((unsigned long long *)&a.stats->trace_fail, (unsigned long long)tc.trace_fail);
+    if (nf) atomicAdd((unsigned long long *)&a.stats->newton_fail, (unsigned long long)nf);
+    if (tf) atomicAdd((unsigned long long *)&a.stats->trace_fail, (unsigned long long)tf);
   }
 }
 
@@ -160,8 +160,8 @@ template <class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_force_replay
     TreatCount tc;
     dm_point<double, G>(a, k, moved, tc);
     if (moved) atomicAdd((unsigned long long *)&a.stats->moved, 1ull);
-    if (tc.newton_fail) atomicAdd((unsigned long long *)&a.stats->newton_fail, 1ull);
-    if (tc.trace_fail) atomicAdd((unsigned long long *)&a.stats->trace_fail, 1ull);
+    if (tc.newton_fail()) atomicAdd((unsigned long long *)&a.stats->newton_fail, 1ull);
+    if (tc.trace_fail()) atomicAdd((unsigned long long *)&a.stats->trace_fail, 1ull);
   }
 }
 

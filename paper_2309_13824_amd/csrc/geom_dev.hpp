@@ -68,8 +68,12 @@ TRIME_D uint8_t point_category(const KArgs &a, double x, double y, double band, 
   return fabs(s) <= ge ? TRIME_CAT_BOUNDARY : TRIME_CAT_INNER;
 }
 
+// Failures of one treatment as bits of one word (bit 0 sphere tracing, bit 1
+// Newton), so the two paths update one register rather than two fields.
 struct TreatCount {
-  int trace_fail = 0, newton_fail = 0;
+  int fail = 0;
+  TRIME_D int trace_fail() const { return fail & 1; }
+  TRIME_D int newton_fail() const { return (fail >> 1) & 1; }
 };
 
 template <class G>
@@ -128,7 +132,7 @@ TRIME_D void sphere_trace(const KArgs &a, double xo, double yo, double xn, doubl
     }
     t_in = lo;
   }
-  tc.trace_fail++;
+  tc.fail |= 1;
   xf = xo + t_in * ux;
   yf = yo + t_in * uy;
 }
@@ -218,7 +222,7 @@ TRIME_D void treat(const KArgs &a, double xo, double yo, uint8_t cat_old, double
     if (newton_project<G>(a, xnew, ynew, band, xf, yf, unsure)) {
       catf = TRIME_CAT_BOUNDARY;
     } else {
-      tc.newton_fail++;
+      tc.fail |= 2;
       xf = xo;
       yf = yo;
       catf = cat_old;

@@ -60,6 +60,8 @@ struct KArgs {
   // work queues / counters / stats
   int32_t *queue;   // points for the FP64 replay
   int32_t *queue2;  // points for the exact replay
+  int32_t *queue3;  // points whose centroid and treatment are redone in FP64
+  int32_t *cq_cons; // per queue3 entry: n, then the n constraints of the cell
   int32_t *counters;
   double *partials;
   trime_stats *stats;
@@ -72,8 +74,10 @@ struct KArgs {
 };
 
 // counters[]: queue lengths, error bits, and the reasons of FP64 replays
-enum { CNT_QUEUE = 0, CNT_TRI = 1, CNT_ERR = 2, CNT_MOVED = 3, CNT_QUEUE2 = 4, CNT_REASON = 8,
-       CNT_NCOUNTERS = 16 };
+enum { CNT_QUEUE = 0, CNT_TRI = 1, CNT_ERR = 2, CNT_MOVED = 3, CNT_QUEUE2 = 4, CNT_QUEUE3 = 5,
+       CNT_REASON = 8, CNT_NCOUNTERS = 16 };
+// ints per entry of the deferred-centroid queue (count + constraints)
+constexpr int CQ_STRIDE = 16;
 enum { ERR_TRI_CAP = 1, ERR_DEG_CAP = 2, ERR_POLY_CAP = 4, ERR_EXACT_CAP = 8, ERR_QUEUE = 16 };
 // why a point left the fast path
 enum { WHY_PRED = 1, WHY_VERTEX = 2, WHY_POLY = 3, WHY_AND = 4, WHY_LEVEL = 5, WHY_TREAT = 6,
