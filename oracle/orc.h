@@ -10,9 +10,9 @@
  * test-suite, the smoke check and the CPU-baseline leg of the benchmark may
  * load it.  It shares no code, header, table or helper with the GPU library.
  *
- * Every function names the passage of the paper it follows.  Readings of
- * passages where the paper is silent or ambiguous are listed in the repo's
- * design notes and repeated here where they apply.
+ * Every function names the passage of the paper it follows.  Where the paper
+ * is silent or ambiguous, the reading taken is stated at the function it
+ * affects.
  */
 #ifndef ORC_H
 #define ORC_H
