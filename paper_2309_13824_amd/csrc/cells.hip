@@ -297,18 +297,25 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     return m > b ? 1 : (m < -b ? -1 : 0);
   }
 
-  // bound on |v_true|^2 over the vertices, capped by the octagon's circumradius
-  TRIME_D void update_R2() {
+  // bound on |v_true|^2 of one vertex with error bound e
+  TRIME_D static T vert_r2(T x, T y, float e) {
     const T u = U<T>::v;
+    T E = (T)e;
+    T l1 = fabs(x) + fabs(y);
+    return (x * x + y * y) * ((T)1 + (T)8 * u) + (T)4 * l1 * E + (T)4 * E * E;
+  }
+  // R2 from the largest vertex bound, capped by the octagon's circumradius
+  TRIME_D void set_R2(T r2) {
+    T cap = (T)((double)S * (double)S * 1.1717 * 1.00001);
+    R2 = isfinite(r2) ? fmin(r2, cap) : cap;
+  }
+  TRIME_D void update_R2() {
     T r2 = 0;
     for (int j = 0; j < n; j++) {
       VRec<T> v = P[j][tid];
-      T E = (T)v.e;
-      T l1 = fabs(v.x) + fabs(v.y);
-      r2 = fmax(r2, (v.x * v.x + v.y * v.y) * ((T)1 + (T)8 * u) + (T)4 * l1 * E + (T)4 * E * E);
+      r2 = fmax(r2, vert_r2(v.x, v.y, v.e));
     }
-    T cap = (T)((double)S * (double)S * 1.1717 * 1.00001);
-    R2 = isfinite(r2) ? fmin(r2, cap) : cap;
+    set_R2(r2);
   }
 
   // The octagon: vertex w between walls w-1 and w, exact in float and double
@@ -342,8 +349,95 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     update_R2();
   }
 
-  // Cut the polygon by constraint c3 (row r3).
+  // Cut the polygon by constraint c3 (row r3).  Small polygons go through
+  // registers: all records are read at once, the margins are taken with
+  // every load in flight, and the kept records are written back to their new
+  // places (no dependent LDS round trips per vertex).
   TRIME_D void clip(const Row<T> &r3, int c3) {
+    if constexpr (VMAX <= 16 && !EXACT)
+      clip_reg(r3, c3);
+    else
+      clip_lds(r3, c3);
+  }
+
+  TRIME_D void clip_reg(const Row<T> &r3, int c3) {
+    const T u = U<T>::v;
+    VRec<T> v[VMAX];
+#pragma unroll
+    for (int j = 0; j < VMAX; j++) v[j] = P[j][tid];
+    const T n1 = fabs(r3.nx) + fabs(r3.ny);
+    const T b0 = (T)12 * u * fabs(r3.s);
+    uint32_t M = 0, Un = 0;
+#pragma unroll
+    for (int j = 0; j < VMAX; j++) {
+      T m = fma(r3.nx, v[j].x, fma(r3.ny, v[j].y, -r3.s));
+      T b = fma(n1, (T)v[j].e, b0);
+      bool in = j < n;
+      if (in && m > b) M |= 1u << j;
+      else if (in && m >= -b) Un |= 1u << j;
+    }
+    wk.margins += n;
+    while (Un) {  // undecided in the kernel's precision: FP64 in place
+      int j = __ffs(Un) - 1;
+      Un &= Un - 1;
+      int s64 = sizeof(T) == 4 ? margin64(con(j == 0 ? n - 1 : j - 1), con(j), c3) : 0;
+      if (s64 > 0) {
+        M |= 1u << j;
+      } else if (s64 == 0) {
+        why = WHY_PRED;
+        return;
+      }
+    }
+    if (M == 0) return;
+    wk.cuts++;
+    uint32_t full = (1u << n) - 1u;
+    if (M == full) {
+      n = 0;
+      return;
+    }
+    uint32_t Pm = ((M << 1) | (M >> (n - 1))) & full;
+    uint32_t Nm = ((M >> 1) | (M << (n - 1))) & full;
+    uint32_t starts = M & ~Pm, ends = M & ~Nm;
+    if (__popc(starts) != 1) {  // impossible with exact decisions
+      why = WHY_PRED;
+      return;
+    }
+    int k0 = __ffs(starts) - 1, k1 = __ffs(ends) - 1;
+    int r = __popc(M);
+    int nn = n - r + 2;
+    if (nn > VMAX) {
+      why = WHY_POLY;
+      return;
+    }
+    int cin = con(k0 == 0 ? n - 1 : k0 - 1);
+    int cout = con(k1);
+    T x1, y1, x2, y2;
+    float e1, e2;
+    bool ok1 = make_vertex<T>(row_of<T>(a, cin, px, py, S, D), r3, x1, y1, e1);
+    bool ok2 = make_vertex<T>(r3, row_of<T>(a, cout, px, py, S, D), x2, y2, e2);
+    if (!ok1 || !ok2) {
+      why = WHY_VERTEX;
+      return;
+    }
+    // kept vertex j moves to d(j); the two new vertices go to dn, dn + 1
+    const bool plain = k0 <= k1;
+    const int dn = plain ? k0 : k0 - k1 - 1;
+    T r2 = fmax(vert_r2(x1, y1, e1), vert_r2(x2, y2, e2));
+#pragma unroll
+    for (int j = 0; j < VMAX; j++) {
+      if (j < n && !((M >> j) & 1)) {
+        int d = plain ? (j < k0 ? j : j - r + 2) : j - (k1 + 1);
+        P[d][tid] = v[j];
+        r2 = fmax(r2, vert_r2(v[j].x, v[j].y, v[j].e));
+      }
+    }
+    set_v(dn, x1, y1, e1, c3);
+    set_v(dn + 1, x2, y2, e2, cout);
+    n = nn;
+    set_R2(r2);
+  }
+
+  TRIME_D void clip_lds(const Row<T> &r3, int c3) {
     const T u = U<T>::v;
     uint32_t M = 0;
     T n1 = fabs(r3.nx) + fabs(r3.ny);
