@@ -320,6 +320,23 @@ trime_status trime_quality(trime_state *st, void *stream);
 trime_status trime_stats_read(const trime_state *st, trime_stats *host, void *stream);
 trime_status trime_stats_check(const trime_stats *host);
 
+/* ---- autotuner (tuning only: no result depends on it) ----------------------
+   The bin size sets how many neighbours a cell scans and how far; the cells
+   do not depend on it (every cut decision is exact and the centroid sums run
+   in a canonical order).  trime_autotune times n_iter CVD iterations (Alg. 2)
+   from the positions (d_x, d_y) for every candidate density (points per bin)
+   and leaves the state bound to d_ws with the fastest one and loaded with
+   (d_x, d_y).  d_ws must hold trime_autotune_workspace_bytes() bytes (the
+   largest layout of the candidates).  Synchronises the stream once per
+   candidate; creates and destroys two HIP events; allocates no device
+   memory.  ms_out (host, nd entries, may be null) receives each candidate's
+   time per iteration. */
+trime_status trime_autotune_workspace_bytes(const trime_state *st, const double *densities, int32_t nd,
+                                            size_t *bytes);
+trime_status trime_autotune(trime_state *st, void *d_ws, size_t bytes, const double *d_x, const double *d_y,
+                            const double *densities, int32_t nd, int32_t n_iter, double *best_density,
+                            float *ms_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

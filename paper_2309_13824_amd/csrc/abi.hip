@@ -534,6 +534,71 @@ trime_status trime_stats_read(const trime_state *st, trime_stats *host, void *st
   return TRIME_OK;
 }
 
+trime_status trime_autotune_workspace_bytes(const trime_state *st_in, const double *dens, int32_t nd,
+                                            size_t *bytes) {
+  if (!st_in || !dens || nd <= 0 || !bytes) return fail(TRIME_EINVAL, "trime_autotune_workspace_bytes: bad argument");
+  size_t most = 0;
+  for (int i = 0; i < nd; i++) {
+    if (!(dens[i] > 0)) return fail(TRIME_EINVAL, "trime_autotune_workspace_bytes: density must be positive");
+    trime_state st = *st_in;
+    st.bin_density = dens[i];
+    size_t b = 0;
+    trime_status e = trime_state_workspace_bytes(&st, &b);
+    if (e) return e;
+    most = b > most ? b : most;
+  }
+  *bytes = most;
+  return TRIME_OK;
+}
+
+trime_status trime_autotune(trime_state *st, void *d_ws, size_t bytes, const double *d_x, const double *d_y,
+                            const double *dens, int32_t nd, int32_t n_iter, double *best_density, float *ms_out,
+                            void *stream) {
+  if (!st || !d_ws || !d_x || !d_y || !dens || nd <= 0 || n_iter <= 0 || !best_density)
+    return fail(TRIME_EINVAL, "trime_autotune: bad argument");
+  size_t need = 0;
+  trime_status e = trime_autotune_workspace_bytes(st, dens, nd, &need);
+  if (e) return e;
+  if (bytes < need) return fail(TRIME_ECAPACITY, "trime_autotune: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  TRY_HIP(hipEventCreate(&t0), "trime_autotune: event");
+  if (hipEventCreate(&t1) != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return fail(TRIME_EHIP, "trime_autotune: event");
+  }
+  double best = dens[0];
+  float best_ms = INFINITY;
+  for (int i = 0; i < nd && !e; i++) {
+    st->bin_density = dens[i];
+    e = trime_state_bind(st, d_ws, bytes, stream);
+    if (!e) e = trime_state_load(st, d_x, d_y, stream);
+    if (!e) e = trime_step_cvd(st, 1, stream);  // warm-up
+    if (!e && hipEventRecord(t0, s) != hipSuccess) e = fail(TRIME_EHIP, "trime_autotune: record");
+    if (!e) e = trime_step_cvd(st, n_iter, stream);
+    if (!e && hipEventRecord(t1, s) != hipSuccess) e = fail(TRIME_EHIP, "trime_autotune: record");
+    if (!e && hipEventSynchronize(t1) != hipSuccess) e = fail(TRIME_EHIP, "trime_autotune: sync");
+    float ms = 0;
+    if (!e && hipEventElapsedTime(&ms, t0, t1) != hipSuccess) e = fail(TRIME_EHIP, "trime_autotune: time");
+    if (e) break;
+    ms /= (float)n_iter;
+    if (ms_out) ms_out[i] = ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = dens[i];
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (e) return e;
+  st->bin_density = best;
+  e = trime_state_bind(st, d_ws, bytes, stream);
+  if (!e) e = trime_state_load(st, d_x, d_y, stream);
+  if (e) return e;
+  *best_density = best;
+  return TRIME_OK;
+}
+
 trime_status trime_stats_check(const trime_stats *h) {
   if (!h) return fail(TRIME_EINVAL, "trime_stats_check: null");
   if (h->error & (ERR_TRI_CAP | ERR_DEG_CAP | ERR_POLY_CAP | ERR_EXACT_CAP))

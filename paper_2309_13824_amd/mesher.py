@@ -104,6 +104,21 @@ class Mesher:
         ncons = ncons.cpu().numpy()
         return [tuple(int(v) for v in cons[i, :ncons[i]]) if ncons[i] >= 0 else None for i in range(self.n)]
 
+    def autotune(self, densities=(2.0, 3.3, 5.0, 8.0), n_iter=3, x=None, y=None):
+        """Picks the bin density (points per bin) with the fastest CVD
+        iterations on this workload; the state is left loaded with (x, y).
+        The results do not depend on the choice."""
+        torch = self.torch
+        need = T.autotune_workspace_bytes(self.state, densities)
+        if need > self.ws.numel():
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.dev)
+        x = self.wl.x if x is None else x
+        y = self.wl.y if y is None else y
+        self.x_in = torch.as_tensor(np.ascontiguousarray(x, np.float64), device=self.dev)
+        self.y_in = torch.as_tensor(np.ascontiguousarray(y, np.float64), device=self.dev)
+        best, ms = T.autotune(self.state, self.ws, self.x_in, self.y_in, densities, n_iter)
+        return best, dict(zip(densities, ms))
+
     def step_dm(self, n_iter, fresh=True, always=False):
         T.step_dm(self.state, n_iter, fresh, always)
 

@@ -121,7 +121,8 @@ EXPORTED = ["trime_last_error", "trime_version", "trime_default_params", "trime_
             "trime_state_workspace_bytes", "trime_state_bind", "trime_state_load", "trime_export_points",
             "trime_export_triangles", "trime_export_adjacency", "trime_bin_points", "trime_voronoi_cells",
             "trime_delaunay_extract", "trime_step_dm", "trime_step_cvd", "trime_step_hybrid",
-            "trime_quality", "trime_stats_read", "trime_stats_check"]
+            "trime_quality", "trime_stats_read", "trime_stats_check", "trime_autotune_workspace_bytes",
+            "trime_autotune"]
 
 _lib = None
 
@@ -158,6 +159,10 @@ def lib(require_gpu: bool = True):
         L.trime_quality.argtypes = [st, vp]
         L.trime_stats_read.argtypes = [st, C.POINTER(Stats), vp]
         L.trime_stats_check.argtypes = [C.POINTER(Stats)]
+        dp = C.POINTER(C.c_double)
+        L.trime_autotune_workspace_bytes.argtypes = [st, dp, C.c_int32, C.POINTER(C.c_size_t)]
+        L.trime_autotune.argtypes = [st, vp, C.c_size_t, vp, vp, dp, C.c_int32, C.c_int32, dp,
+                                     C.POINTER(C.c_float), vp]
         for f in EXPORTED:
             if f not in ("trime_last_error", "trime_version", "trime_default_params"):
                 getattr(L, f).restype = C.c_int
@@ -254,6 +259,23 @@ def export_triangles(state, tri, valid, count, stream=None):
 
 def export_adjacency(state, deg, col, stream=None):
     _check(lib().trime_export_adjacency(C.byref(state), _ptr(deg), _ptr(col), _stream(stream)))
+
+
+def autotune_workspace_bytes(state, densities) -> int:
+    d = (C.c_double * len(densities))(*densities)
+    n = C.c_size_t(0)
+    _check(lib().trime_autotune_workspace_bytes(C.byref(state), d, len(densities), C.byref(n)))
+    return n.value
+
+
+def autotune(state, ws, x, y, densities, n_iter, stream=None):
+    """Returns (best density, ms per iteration of each candidate)."""
+    d = (C.c_double * len(densities))(*densities)
+    ms = (C.c_float * len(densities))()
+    best = C.c_double(0)
+    _check(lib().trime_autotune(C.byref(state), _ptr(ws), ws.numel() * ws.element_size(), _ptr(x), _ptr(y), d,
+                                len(densities), int(n_iter), C.byref(best), ms, _stream(stream)))
+    return best.value, list(ms)
 
 
 def stats_read(state, stream=None) -> Stats:
