@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--tune", type=str, default="1.0,1.4,2.0,2.8",
+                    help="bin densities (points per bin) the autotuner tries before the timed run; "
+                         "empty for the default 3.3")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -98,12 +101,18 @@ def copy_probe(mib, log):
     print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3}), flush=True)
 
 
-def gpu_run(wl, precision, steps, warmup, log):
+def gpu_run(wl, precision, steps, warmup, log, tune=()):
     import torch
     from paper_2309_13824_amd import trime as T
     from paper_2309_13824_amd.mesher import Mesher
 
     m = Mesher(wl, precision=precision)
+    density = 3.3
+    if tune:
+        density, ms = m.autotune(tune, n_iter=3)
+        log("  autotune (%s): %s -> %.2f points per bin" % (
+            "fp32" if precision == T.FP32 else "fp64",
+            ", ".join("%.2f: %.3f ms" % (d, t) for d, t in sorted(ms.items())), density))
     m.load()
     for _ in range(warmup):
         m.step_cvd(1)
@@ -138,7 +147,7 @@ def gpu_run(wl, precision, steps, warmup, log):
     log("  work per point-iteration: candidates %.2f margins %.2f cuts %.2f leaves %.2f; level cap hits %d, "
         "exact points %d" % (st["work_candidates"] / pts, st["work_margins"] / pts, st["work_cuts"] / pts,
                              st["work_leaves"] / pts, st["level_cap_hits"], st["exact_points"]))
-    return m, total_ms, float(np.mean(kern_ms)), st
+    return m, total_ms, float(np.mean(kern_ms)), st, density
 
 
 CPU_ITERS = 3
@@ -185,14 +194,15 @@ def main():
     wl = I.holes20(n=args.n, grid_n=args.grid, iters=args.steps)
     log("workload %s: %d points, %d^2 grid (%.1f s to sample)" % (wl.name, wl.n, wl.grid.nx, time.perf_counter() - t))
 
-    m32, ms32, k32, st32 = gpu_run(wl, T.FP32, args.steps, args.warmup, log)
+    tune = tuple(float(v) for v in args.tune.split(",") if v.strip())
+    m32, ms32, k32, st32, dens32 = gpu_run(wl, T.FP32, args.steps, args.warmup, log, tune)
     out = {"metric": METRIC}
     pit = wl.n * args.steps / (ms32 * 1e-3)
     fp64 = None
     if not args.no_fp64:
-        m64, ms64, k64, st64 = gpu_run(wl, T.FP64, args.steps, args.warmup, log)
+        m64, ms64, k64, st64, dens64 = gpu_run(wl, T.FP64, args.steps, args.warmup, log, tune)
         fp64 = {"value": wl.n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps,
-                "kernel_ms": k64, "fp32_over_fp64": ms64 / ms32}
+                "kernel_ms": k64, "fp32_over_fp64": ms64 / ms32, "bin_density": dens64}
         del m64
         torch.cuda.empty_cache()
 
@@ -235,7 +245,7 @@ def main():
         "config": {"workload": "holes20: unit square minus 20 disks, %d^2 f32 sdf grid, %d points, "
                                "Gaussian density, CVD iterations" % (args.grid, args.n),
                    "n_points": wl.n, "grid": args.grid, "method": "cvd",
-                   "precision": "fp32 + fp64 replay", "seed": wl.seed},
+                   "precision": "fp32 + fp64 replay", "seed": wl.seed, "bin_density": dens32},
         "roofline": roof, "cpu_baseline": cpu, "fp64": fp64,
         "fp64_replays_per_step": st32["fp64_replays"] / max(args.steps, 1),
         "quality": {k: st32[k] for k in ("half_mean_alpha", "half_mean_beta", "min_q", "mean_q", "nvalid")},
