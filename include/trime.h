@@ -25,7 +25,7 @@
  *    call returns, allocates no device memory in any call except
  *    trime_sdf_grid_build (setup: one temporary buffer for the primitive
  *    list), and never synchronises except in trime_state_bind (setup: reads
- *    the grid scalars) and trime_stats_read.
+ *    the grid scalars), trime_stats_read and trime_autotune (tuning).
  *  - Streams: `stream` is a hipStream_t (passed as void*); 0 is the null
  *    stream.  All work is enqueued on it in order.
  *  - Layouts: structure of arrays.  Positions are float64 x[n], y[n] in both
@@ -303,7 +303,10 @@ trime_status trime_delaunay_extract(trime_state *st, void *stream);
    `fresh` != 0), Eq. 3 scaling, spring forces (Eq. 2), forward Euler (Eq. 5)
    and treatment (Sec. 4.3); the flag is set when a point moved more than
    fac_retria*h since the last triangulation.  always_retriangulate != 0
-   triangulates every iteration. */
+   triangulates every iteration.  The flag is read on the device (binning
+   and extraction are launched every iteration and do their work only when
+   it is raised), so the call makes no host reads and can be captured in a
+   HIP graph. */
 trime_status trime_step_dm(trime_state *st, int32_t n_iter, int32_t fresh,
                            int32_t always_retriangulate, void *stream);
 /* n_iter CVD iterations (Alg. 2): bin, cells, adaptive-quadrature centroid

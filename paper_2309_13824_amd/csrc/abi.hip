@@ -360,11 +360,12 @@ trime_status trime_state_load(trime_state *st, const double *d_x, const double *
   return check_hip("trime_state_load");
 }
 
-trime_status trime_bin_points(trime_state *st, void *stream) {
-  trime_status e = bound_ok(st);
-  if (e) return e;
-  hipStream_t s = (hipStream_t)stream;
+// Binning; with cond set it runs only if *cond != 0 on the device (else the
+// buffer sets are copied in place order), and the host-side swap of the
+// buffer sets is the same either way.
+static void bin_points(trime_state *st, hipStream_t s, const int32_t *cond) {
   KArgs a = make_args(st);
+  a.cond = cond;
   GatherArgs g;
   const trime_posbuf &P = st->pos[st->cur_pos], &Q = st->pos[st->cur_pos ^ 1];
   const trime_ordbuf &O = st->ord[st->cur_ord], &R = st->ord[st->cur_ord ^ 1];
@@ -381,9 +382,18 @@ trime_status trime_bin_points(trime_state *st, void *stream) {
   g.spano = R.span;
   g.xlo = R.xl;
   g.ylo = R.yl;
+  g.xl = O.xl;
+  g.yl = O.yl;
+  g.span = O.span;
   launch_bin(a, g, st->nkeys, st->scan_tmp, s);
   st->cur_pos ^= 1;
   st->cur_ord ^= 1;
+}
+
+trime_status trime_bin_points(trime_state *st, void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  bin_points(st, (hipStream_t)stream, nullptr);
   return check_hip("trime_bin_points");
 }
 
@@ -402,8 +412,9 @@ trime_status trime_voronoi_cells(trime_state *st, const trime_cells *out, void *
   return check_hip("trime_voronoi_cells");
 }
 
-static void extract(trime_state *st, hipStream_t s) {
+static void extract(trime_state *st, hipStream_t s, const int32_t *cond = nullptr) {
   KArgs a = make_args(st);
+  a.cond = cond;
   launch_stats_reset(a, 0, s);
   launch_cells(a, MODE_EXTRACT, st->grid.dtype_bytes, s);
   launch_finish_extract(a, s);
@@ -416,41 +427,25 @@ trime_status trime_delaunay_extract(trime_state *st, void *stream) {
   return check_hip("trime_delaunay_extract");
 }
 
-static trime_status read_flag(const trime_state *st, hipStream_t s, int *flag) {
-  int32_t v = 0;
-  TRY_HIP(hipMemcpyAsync(&v, &st->stats->retri_flag, sizeof v, hipMemcpyDeviceToHost, s), "read flag");
-  TRY_HIP(hipStreamSynchronize(s), "read flag (sync)");
-  *flag = v;
-  return TRIME_OK;
-}
-
 trime_status trime_step_dm(trime_state *st, int32_t n_iter, int32_t fresh, int32_t always,
                            void *stream) {
   trime_status e = bound_ok(st);
   if (e) return e;
   if (n_iter < 0) return fail(TRIME_EINVAL, "trime_step_dm: negative iteration count");
   hipStream_t s = (hipStream_t)stream;
-  int flag = 1;
-  if (!fresh && !always) {
-    e = read_flag(st, s, &flag);
-    if (e) return e;
-  }
+  // the re-triangulation decision stays on the device: binning and
+  // extraction run every iteration and do their work only when the flag
+  // (set by the previous iteration's large-movement test) is raised
+  const int32_t *flag = &st->stats->retri_flag;
   for (int it = 0; it < n_iter; it++) {
-    bool retri = always || (it == 0 && fresh) || flag;
-    if (retri) {
-      e = trime_bin_points(st, stream);
-      if (e) return e;
-      extract(st, s);
-    }
+    if (always || (it == 0 && fresh)) launch_set_flag(make_args(st), s);
+    bin_points(st, s, flag);
+    extract(st, s, flag);
     KArgs a = make_args(st);
     launch_dm(a, st->grid.dtype_bytes, s);
     st->cur_pos ^= 1;
     e = check_hip("trime_step_dm");
     if (e) return e;
-    if (!always && it + 1 < n_iter) {
-      e = read_flag(st, s, &flag);
-      if (e) return e;
-    }
   }
   return TRIME_OK;
 }
@@ -461,8 +456,7 @@ trime_status trime_step_cvd(trime_state *st, int32_t n_iter, void *stream) {
   if (n_iter < 0) return fail(TRIME_EINVAL, "trime_step_cvd: negative iteration count");
   hipStream_t s = (hipStream_t)stream;
   for (int it = 0; it < n_iter; it++) {
-    e = trime_bin_points(st, stream);
-    if (e) return e;
+    bin_points(st, s, nullptr);
     KArgs a = make_args(st);
     launch_stats_reset(a, 0, s);
     launch_cells(a, MODE_CVD, st->grid.dtype_bytes, s);

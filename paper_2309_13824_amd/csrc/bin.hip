@@ -18,9 +18,16 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     p[i] = v;
 }
 
+__global__ void k_fill_cond(KArgs a, int32_t *p, int64_t n) {
+  if (cond_off(a)) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
 __global__ void k_bin_keys(KArgs a) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.n) return;
+  if (k >= a.n || cond_off(a)) return;
   int bx, by;
   bin_of(a, a.x[k], a.y[k], bx, by);
   int key = (int)morton((uint32_t)bx, (uint32_t)by);
@@ -55,8 +62,10 @@ __device__ __forceinline__ int block_excl_scan(int v, int *smem, int &total) {
 }
 
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tiles(const int32_t *in, int32_t *out,
-                                                            int64_t n, int32_t *tile_sums) {
+                                                            int64_t n, int32_t *tile_sums,
+                                                            const int32_t *cond) {
   __shared__ int smem[SCAN_BLOCK / 64];
+  if (cond && *cond == 0) return;
   int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   int v[SCAN_ITEMS];
   int s = 0;
@@ -76,8 +85,9 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tiles(const int32_t *in, in
 }
 
 // Single block: exclusive scan of the tile sums (any count), total at [nt].
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_sums(int32_t *sums, int64_t nt) {
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_sums(int32_t *sums, int64_t nt, const int32_t *cond) {
   __shared__ int smem[SCAN_BLOCK / 64];
+  if (cond && *cond == 0) return;
   int carry = 0;
   for (int64_t base = 0; base < nt; base += SCAN_BLOCK) {
     int64_t i = base + threadIdx.x;
@@ -91,7 +101,9 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_sums(int32_t *sums, int64_t
 }
 
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_add(int32_t *out, int64_t n,
-                                                          const int32_t *sums, int64_t nt) {
+                                                          const int32_t *sums, int64_t nt,
+                                                          const int32_t *cond) {
+  if (cond && *cond == 0) return;
   int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   int add = sums[blockIdx.x];
 #pragma unroll
@@ -100,27 +112,29 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_add(int32_t *out, int64_t n
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[nt];
 }
 
-// Exclusive scan of in[0..n) into out[0..n], out[n] = total.
-void scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t s) {
+// Exclusive scan of in[0..n) into out[0..n], out[n] = total; skipped when
+// cond is set and *cond == 0.
+void scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t s,
+              const int32_t *cond) {
   int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
   if (nt == 0) nt = 1;
-  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(SCAN_BLOCK), 0, s, in, out, n, tmp);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BLOCK), 0, s, tmp, nt);
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(SCAN_BLOCK), 0, s, out, n, tmp, nt);
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(SCAN_BLOCK), 0, s, in, out, n, tmp, cond);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BLOCK), 0, s, tmp, nt, cond);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(SCAN_BLOCK), 0, s, out, n, tmp, nt, cond);
 }
 
 size_t scan_tmp_ints(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) + 2; }
 
 __global__ void k_bin_scatter(KArgs a) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.n) return;
+  if (k >= a.n || cond_off(a)) return;
   a.perm[a.bin_start[a.key[k]] + a.rank[k]] = (int)k;
 }
 
 // One thread per bin: order its entries by point id (insertion sort).
 __global__ void k_bin_sort(KArgs a, int64_t nkeys) {
   int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nkeys) return;
+  if (b >= nkeys || cond_off(a)) return;
   int s0 = a.bin_start[b], s1 = a.bin_start[b + 1];
   for (int s = s0 + 1; s < s1; s++) {
     int v = a.perm[s];
@@ -136,11 +150,24 @@ __global__ void k_bin_sort(KArgs a, int64_t nkeys) {
 
 // Gather every per-point array into the new slot order (writes the other
 // buffer set); the positions of the last triangulation become the current
-// ones and the octagon span S is recomputed from the point's cell.
-
+// ones and the octagon span S is recomputed from the point's cell.  A
+// conditional binning without work copies every array in place order
+// instead (the buffer sets still swap), keeping the last-triangulation
+// positions and spans.
 __global__ void k_bin_gather(KArgs a, GatherArgs g) {
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= a.n) return;
+  if (cond_off(a)) {
+    g.xo[s] = g.x[s];
+    g.yo[s] = g.y[s];
+    g.dprevo[s] = g.dprev[s];
+    g.cato[s] = g.cat[s];
+    g.ido[s] = g.id[s];
+    g.xlo[s] = g.xl[s];
+    g.ylo[s] = g.yl[s];
+    g.spano[s] = g.span[s];
+    return;
+  }
   int k = a.perm[s];
   double x = g.x[k], y = g.y[k];
   g.xo[s] = x;
@@ -160,13 +187,13 @@ __global__ void k_bin_gather(KArgs a, GatherArgs g) {
 // wavefronts of light ones.
 __global__ void k_order_flags(KArgs a, const uint8_t *cat) {
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.n) return;
+  if (s >= a.n || cond_off(a)) return;
   a.key[s] = cat[s] == TRIME_CAT_BOUNDARY ? 1 : 0;
 }
 
 __global__ void k_order_scatter(KArgs a) {
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.n) return;
+  if (s >= a.n || cond_off(a)) return;
   int before = a.perm[s];  // heavy slots before s
   int heavy = a.perm[a.n];
   int64_t w = a.key[s] ? before : heavy + (s - before);
@@ -177,14 +204,14 @@ void launch_bin(const KArgs &a, const GatherArgs &g, int64_t nkeys, int32_t *sca
                 hipStream_t s) {
   const int B = 256;
   int nb = (int)((a.n + B - 1) / B);
-  hipLaunchKernelGGL(k_fill_i32, dim3(1024), dim3(256), 0, s, a.bin_fill, nkeys, 0);
+  hipLaunchKernelGGL(k_fill_cond, dim3(1024), dim3(256), 0, s, a, a.bin_fill, nkeys);
   if (nb) hipLaunchKernelGGL(k_bin_keys, dim3(nb), dim3(B), 0, s, a);
-  scan_i32(a.bin_fill, a.bin_start, nkeys, scan_tmp, s);
+  scan_i32(a.bin_fill, a.bin_start, nkeys, scan_tmp, s, a.cond);
   if (nb) hipLaunchKernelGGL(k_bin_scatter, dim3(nb), dim3(B), 0, s, a);
   hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((nkeys + B - 1) / B)), dim3(B), 0, s, a, nkeys);
   if (nb) hipLaunchKernelGGL(k_bin_gather, dim3(nb), dim3(B), 0, s, a, g);
   if (nb) hipLaunchKernelGGL(k_order_flags, dim3(nb), dim3(B), 0, s, a, (const uint8_t *)g.cato);
-  scan_i32(a.key, a.perm, a.n, scan_tmp, s);
+  scan_i32(a.key, a.perm, a.n, scan_tmp, s, a.cond);
   if (nb) hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(B), 0, s, a);
 }
 

@@ -1168,6 +1168,7 @@ TRIME_D void push(const KArgs &a, int which, int64_t k, int why) {
 // grid box within reach) go to the FP64 replay queue.
 template <class T, class G, int MODE, int VMAX, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_cells(KArgs a) {
+  if (cond_off(a)) return;
   __shared__ VRec<T> P[VMAX][BLOCK];
   __shared__ int hist[40];
   zero_hist<BLOCK>(hist);
@@ -1191,6 +1192,7 @@ __global__ __launch_bounds__(BLOCK) void k_cells(KArgs a) {
 // fast kernel.
 template <class G, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_cells_centroid(KArgs a) {
+  if (cond_off(a)) return;
   constexpr int V = CQ_STRIDE - 1;
   __shared__ VRec<double> P[V][BLOCK];
   __shared__ int hist[40];
@@ -1210,6 +1212,7 @@ __global__ __launch_bounds__(BLOCK) void k_cells_centroid(KArgs a) {
 // on lane 0.  Points FP64 cannot decide go on to the exact queue.
 template <class G, int MODE, int VMAX>
 __global__ __launch_bounds__(64) void k_cells_wave(KArgs a) {
+  if (cond_off(a)) return;
   __shared__ VRec<double> P[VMAX][1];
   __shared__ int hist[40];
   __shared__ int sh_s0[64], sh_incl[64];
@@ -1237,6 +1240,7 @@ __global__ __launch_bounds__(64) void k_cells_wave(KArgs a) {
 // Exact replay of the second queue.
 template <class G, int MODE, int VMAX, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_cells_exact(KArgs a) {
+  if (cond_off(a)) return;
   __shared__ VRec<double> P[VMAX][BLOCK];
   __shared__ int hist[40];
   zero_hist<BLOCK>(hist);

@@ -170,6 +170,12 @@ __global__ void k_dm_flag(KArgs a) {
   a.stats->iterations++;
 }
 
+// Sets the re-triangulation flag (the first iteration of a segment, or
+// every iteration when asked to).
+__global__ void k_set_flag(KArgs a) { a.stats->retri_flag = 1; }
+
+void launch_set_flag(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, s, a); }
+
 __global__ void k_dm_begin(KArgs a) {
   a.stats->moved = 0;
   a.counters[CNT_QUEUE] = 0;
@@ -340,6 +346,7 @@ __global__ __launch_bounds__(256) void k_quality(KArgs a) {
 
 // Clears the quality part of the stats (before an extraction / quality pass).
 __global__ void k_stats_reset_quality(KArgs a, int full) {
+  if (cond_off(a)) return;
   trime_stats *S = a.stats;
   int t = threadIdx.x;
   if (t < 40) S->hist_beta[t] = 0;
@@ -391,6 +398,7 @@ void launch_quality(const KArgs &a, hipStream_t s) {
 // Copies the error bits of the counters into the stats and counts an
 // extraction.
 __global__ void k_finish_extract(KArgs a) {
+  if (cond_off(a)) return;
   a.stats->error |= a.counters[CNT_ERR];
   a.stats->triangulations++;
   a.counters[CNT_QUEUE] = 0;

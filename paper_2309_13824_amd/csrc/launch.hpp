@@ -11,6 +11,8 @@ struct GatherArgs {
   const double *x, *y, *dprev;
   const uint8_t *cat;
   const int32_t *id;
+  const double *xl, *yl;  // current last-triangulation positions and spans
+  const float *span;
   double *xo, *yo, *dprevo, *xlo, *ylo;
   uint8_t *cato;
   int32_t *ido;
@@ -41,7 +43,8 @@ struct GridPrims {
 void launch_cells(const KArgs &a, int mode, int grid_bytes, hipStream_t s);
 void launch_bin(const KArgs &a, const GatherArgs &g, int64_t nkeys, int32_t *scan_tmp, hipStream_t s);
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
-void scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t s);
+void scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t s,
+              const int32_t *cond = nullptr);
 size_t scan_tmp_ints(int64_t n);
 void launch_dm(const KArgs &a, int grid_bytes, hipStream_t s);
 int dm_partials(int64_t n);
@@ -53,6 +56,7 @@ void launch_export_adj(const KArgs &a, int32_t *deg_o, int32_t *col_o, hipStream
 void launch_quality(const KArgs &a, hipStream_t s);
 void launch_stats_reset(const KArgs &a, int full, hipStream_t s);
 void launch_finish_extract(const KArgs &a, hipStream_t s);
+void launch_set_flag(const KArgs &a, hipStream_t s);
 int64_t grid_partials(int nx, int ny);
 void launch_grid_build(const GridPrims &g, int dtype_bytes, void *sdf, void *mu, uint8_t *cat,
                        float *hcell, trime_grid_scalars *scal, double *part, hipStream_t s);

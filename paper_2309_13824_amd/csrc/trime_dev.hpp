@@ -71,7 +71,13 @@ struct KArgs {
   trime_params prm;
   int32_t precision;
   void *ev0, *ev1;  // optional timing events around the fused cell kernel
+  // When set, the binning and extraction kernels work only if *cond != 0
+  // (the re-triangulation flag of a DistMesh step, read on the device).
+  const int32_t *cond;
 };
+
+// Whether a conditional launch has work (uniform over the grid).
+TRIME_D bool cond_off(const KArgs &a) { return a.cond && gld(a.cond, 0) == 0; }
 
 // counters[]: queue lengths, error bits, and the reasons of FP64 replays
 enum { CNT_QUEUE = 0, CNT_TRI = 1, CNT_ERR = 2, CNT_MOVED = 3, CNT_QUEUE2 = 4, CNT_QUEUE3 = 5,

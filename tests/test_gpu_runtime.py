@@ -126,3 +126,33 @@ def test_graph_capture_replays_match_eager(orc, T):
         x, y, c = m.points()
         assert np.array_equal(x, want[r][0]) and np.array_equal(y, want[r][1]), r
         assert np.array_equal(c, want[r][2]), r
+
+
+def test_graph_capture_dm_replays_match_eager(orc, T):
+    """DistMesh iterations keep the re-triangulation decision on the device,
+    so they can be captured too: replays of two captured iterations (flag
+    mode, after a first fresh iteration) equal eager execution."""
+    import torch
+    wl = I.disk()
+    og = orc.build_grid(wl)
+    eager = mesher(wl, FP64, grid=og)
+    eager.step_dm(1, fresh=True)
+    want = []
+    for _ in range(3):
+        eager.step_dm(2, fresh=False)
+        want.append(eager.points())
+    m = mesher(wl, FP64, grid=og)
+    m.step_dm(1, fresh=True)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        T.step_dm(m.state, 2, fresh=False, stream=s)
+    for r in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        x, y, c = m.points()
+        assert np.array_equal(x, want[r][0]) and np.array_equal(y, want[r][1]), r
+        assert np.array_equal(c, want[r][2]), r
+    st = m.stats_raw()
+    assert st.error == 0
