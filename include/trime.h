@@ -323,6 +323,25 @@ trime_status trime_quality(trime_state *st, void *stream);
 trime_status trime_stats_read(const trime_state *st, trime_stats *host, void *stream);
 trime_status trime_stats_check(const trime_stats *host);
 
+/* ---- batches of shapes in one graph ----------------------------------------
+   Many shapes of uneven size are meshed by one HIP graph launch: the graph
+   holds n_iter iterations (method TRIME_METHOD_DM: Alg. 1 DistMesh in flag
+   mode; TRIME_METHOD_CVD: Alg. 2) of
+   every state, the states spread round-robin over nstreams concurrent
+   branches, so small shapes fill the GPU together.  n_iter must be even (the
+   double-buffered arrays then return to the same buffers and the graph can
+   be launched again for the next n_iter iterations).  Creation captures on
+   `stream`, which must not be the null stream; it creates nstreams-1 side
+   streams (default priority) and nstreams events and instantiates the
+   graph: setup, not the hot path.  The states must be bound and loaded, and
+   must not request timing events.  trime_graph_destroy frees everything
+   the graph owns; the states stay the caller's. */
+typedef struct trime_graph trime_graph;
+trime_status trime_batch_graph_create(trime_state *const *states, int32_t nstates, int32_t method,
+                                      int32_t n_iter, int32_t nstreams, trime_graph **out, void *stream);
+trime_status trime_graph_launch(trime_graph *g, void *stream);
+trime_status trime_graph_destroy(trime_graph *g);
+
 /* ---- autotuner (tuning only: no result depends on it) ----------------------
    The bin size sets how many neighbours a cell scans and how far; the cells
    do not depend on it (every cut decision is exact and the centroid sums run

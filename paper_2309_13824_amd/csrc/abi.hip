@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/trime.h: argument checks,
 // workspace layout and the launch sequence of each entry point.
 #include <math.h>
+#include <new>
 #include <stdio.h>
 #include <string.h>
 
@@ -525,6 +526,96 @@ trime_status trime_stats_read(const trime_state *st, trime_stats *host, void *st
   TRY_HIP(hipMemcpyAsync(host, st->stats, sizeof *host, hipMemcpyDeviceToHost, (hipStream_t)stream),
           "trime_stats_read");
   TRY_HIP(hipStreamSynchronize((hipStream_t)stream), "trime_stats_read (sync)");
+  return TRIME_OK;
+}
+
+struct trime_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int nside = 0;
+  hipStream_t side[64] = {};
+  hipEvent_t ev[65] = {};
+};
+
+trime_status trime_graph_destroy(trime_graph *g) {
+  if (!g) return fail(TRIME_EINVAL, "trime_graph_destroy: null graph");
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  for (int i = 0; i < g->nside; i++)
+    if (g->side[i]) (void)hipStreamDestroy(g->side[i]);
+  for (int i = 0; i < 65; i++)
+    if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
+  delete g;
+  return TRIME_OK;
+}
+
+trime_status trime_batch_graph_create(trime_state *const *states, int32_t nstates, int32_t method,
+                                      int32_t n_iter, int32_t nstreams, trime_graph **out, void *stream) {
+  if (!states || nstates <= 0 || !out || !stream)
+    return fail(TRIME_EINVAL, "trime_batch_graph_create: bad argument (the stream must not be null)");
+  if (method != TRIME_METHOD_DM && method != TRIME_METHOD_CVD)
+    return fail(TRIME_EINVAL, "trime_batch_graph_create: bad method");
+  if (n_iter <= 0 || (n_iter & 1)) return fail(TRIME_EINVAL, "trime_batch_graph_create: n_iter must be even");
+  if (nstreams < 1 || nstreams > 64) return fail(TRIME_EINVAL, "trime_batch_graph_create: 1 <= nstreams <= 64");
+  for (int k = 0; k < nstates; k++) {
+    trime_status e = bound_ok(states[k]);
+    if (e) return e;
+    if (states[k]->ev_cells[0] || states[k]->ev_cells[1])
+      return fail(TRIME_EINVAL, "trime_batch_graph_create: a state requests timing events");
+  }
+  *out = nullptr;
+  trime_graph *g = new (std::nothrow) trime_graph;
+  if (!g) return fail(TRIME_EINVAL, "trime_batch_graph_create: out of host memory");
+  hipStream_t cap = (hipStream_t)stream;
+  trime_status e = TRIME_OK;
+  g->nside = nstreams - 1;
+  for (int i = 0; i < g->nside && !e; i++)
+    if (hipStreamCreateWithFlags(&g->side[i], hipStreamNonBlocking) != hipSuccess)
+      e = fail(TRIME_EHIP, "trime_batch_graph_create: stream");
+  for (int i = 0; i < nstreams && !e; i++)
+    if (hipEventCreateWithFlags(&g->ev[i], hipEventDisableTiming) != hipSuccess)
+      e = fail(TRIME_EHIP, "trime_batch_graph_create: event");
+  if (e) {
+    trime_graph_destroy(g);
+    return e;
+  }
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    trime_graph_destroy(g);
+    return fail(TRIME_EHIP, "trime_batch_graph_create: begin capture");
+  }
+  // fork: every side stream joins the capture after the first event
+  if (hipEventRecord(g->ev[0], cap) != hipSuccess) e = fail(TRIME_EHIP, "trime_batch_graph_create: fork");
+  for (int i = 0; i < g->nside && !e; i++)
+    if (hipStreamWaitEvent(g->side[i], g->ev[0], 0) != hipSuccess) e = fail(TRIME_EHIP, "trime_batch_graph_create: fork");
+  for (int k = 0; k < nstates && !e; k++) {
+    int b = k % nstreams;
+    void *s = b == 0 ? (void *)cap : (void *)g->side[b - 1];
+    e = method == TRIME_METHOD_DM ? trime_step_dm(states[k], n_iter, 0, 0, s)
+                                       : trime_step_cvd(states[k], n_iter, s);
+  }
+  // join: the capture stream waits for every side stream
+  for (int i = 0; i < g->nside && !e; i++) {
+    if (hipEventRecord(g->ev[i + 1], g->side[i]) != hipSuccess ||
+        hipStreamWaitEvent(cap, g->ev[i + 1], 0) != hipSuccess)
+      e = fail(TRIME_EHIP, "trime_batch_graph_create: join");
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t ec = hipStreamEndCapture(cap, &graph);
+  g->graph = graph;
+  if (!e && ec != hipSuccess) e = fail(TRIME_EHIP, "trime_batch_graph_create: end capture");
+  if (!e && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+    e = fail(TRIME_EHIP, "trime_batch_graph_create: instantiate");
+  if (e) {
+    trime_graph_destroy(g);
+    return e;
+  }
+  *out = g;
+  return TRIME_OK;
+}
+
+trime_status trime_graph_launch(trime_graph *g, void *stream) {
+  if (!g || !g->exec) return fail(TRIME_EINVAL, "trime_graph_launch: null graph");
+  TRY_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream), "trime_graph_launch");
   return TRIME_OK;
 }
 

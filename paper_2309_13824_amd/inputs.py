@@ -102,6 +102,20 @@ def centred_grid(n: int, span_num: int, span_log2: int, centre: float, dtype_byt
 # Inside tests and densities below are the workload definitions evaluated for
 # drawing initial points only.
 
+def _in_polygon(poly: np.ndarray, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Even-odd (crossing number) inside test of a closed polygon."""
+    ins = np.zeros(x.shape, dtype=bool)
+    nv = len(poly)
+    for a in range(nv):
+        ax, ay = poly[a]
+        bx, by = poly[(a + 1) % nv]
+        cross = (ay > y) != (by > y)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            xi = ax + (y - ay) * (bx - ax) / (by - ay)
+        ins ^= cross & (x < xi)
+    return ins
+
+
 def _inside(wl: Workload, x: np.ndarray, y: np.ndarray) -> np.ndarray:
     ins = None
     for p in wl.prims:
@@ -115,8 +129,7 @@ def _inside(wl: Workload, x: np.ndarray, y: np.ndarray) -> np.ndarray:
             v = -s * (x - p.p[0]) + c * (y - p.p[1])
             t = (u / p.p[2]) ** 2 + (v / p.p[3]) ** 2 < 1.0
         else:
-            from matplotlib.path import Path  # pragma: no cover
-            t = Path(p.poly).contains_points(np.stack([x, y], 1))
+            t = _in_polygon(np.asarray(p.poly, np.float64), x, y)
         if p.op == OP_INIT:
             ins = t
         elif p.op == OP_UNION:
@@ -269,6 +282,33 @@ def ellipses(n: int = 10000000, seed: int = 1004, grid_n: int = 8192, n_holes: i
                   grid, n, [("dm", 70), ("cvd", 30)], seed)
     wl.x, wl.y = sample_points(wl, np.random.default_rng(ss[2]), (0, 0, 1, 1))
     return wl
+
+
+def stars(count: int = 512, seed: int = 1005, grid_n: int = 512, iters: int = 60,
+          n_range=(3.0, 5.0)) -> list:
+    """A batch of star-shaped polygons, each on its own grid: n_v ~ U{8..64}
+    vertices at angles 2 pi (j + u_j) / n_v, u_j ~ U[-0.3, 0.3], radii
+    U[0.5, 1]; point counts round(10^U[3, 5]) (log-uniform); uniform sizing;
+    DistMesh iterations."""
+    ss = np.random.SeedSequence(seed).spawn(3)
+    g_rng = np.random.default_rng(ss[0])
+    n_rng = np.random.default_rng(ss[1])
+    p_seeds = ss[2].spawn(count)
+    out = []
+    for s_ in range(count):
+        nv = int(g_rng.integers(8, 65))
+        u = g_rng.uniform(-0.3, 0.3, nv)
+        th = 2.0 * np.pi * (np.arange(nv) + u) / nv
+        r = g_rng.uniform(0.5, 1.0, nv)
+        poly = np.stack([r * np.cos(th), r * np.sin(th)], 1)
+        n = int(round(10.0 ** n_rng.uniform(*n_range)))
+        wl = Workload("star%d" % s_, [Prim(OP_INIT, PRIM_POLYGON, (), poly)], Sizing(SZ_UNIFORM),
+                      centred_grid(grid_n, 5, int(round(math.log2(grid_n))) + 1, 0.0, 4), n, [("dm", iters)],
+                      seed)
+        rng = np.random.default_rng(p_seeds[s_])
+        wl.x, wl.y = sample_points(wl, rng, (-1.0, -1.0, 1.0, 1.0))
+        out.append(wl)
+    return out
 
 
 def square_lattice(k: int = 6, spacing: float = 0.125) -> Workload:

@@ -178,3 +178,38 @@ class Mesher:
         off = self.state.counters - self.ws.data_ptr()
         c = self.ws[off:off + 64].view(self.torch.int32).cpu().numpy()
         return {name: int(c[8 + k]) for k, name in self.REASONS.items()}
+
+
+class Batch:
+    """Many shapes meshed by one graph launch per n_iter iterations
+    (trime_batch_graph_create); the Meshers stay usable one by one."""
+
+    def __init__(self, meshers, method="dm", n_iter=2, nstreams=8):
+        import torch
+        self.torch = torch
+        self.meshers = list(meshers)
+        self.n_iter = n_iter
+        self.stream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        meth = T.METHOD_DM if method == "dm" else T.METHOD_CVD
+        self.graph = T.batch_graph_create([m.state for m in self.meshers], meth, n_iter, nstreams, self.stream)
+        torch.cuda.synchronize()
+
+    def run(self, iters):
+        """iters iterations of every shape (a multiple of n_iter)."""
+        if iters % self.n_iter:
+            raise ValueError("iters must be a multiple of %d" % self.n_iter)
+        for _ in range(iters // self.n_iter):
+            T.graph_launch(self.graph, self.stream)
+
+    def close(self):
+        if self.graph is not None:
+            self.torch.cuda.synchronize()
+            T.graph_destroy(self.graph)
+            self.graph = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -122,7 +122,7 @@ EXPORTED = ["trime_last_error", "trime_version", "trime_default_params", "trime_
             "trime_export_triangles", "trime_export_adjacency", "trime_bin_points", "trime_voronoi_cells",
             "trime_delaunay_extract", "trime_step_dm", "trime_step_cvd", "trime_step_hybrid",
             "trime_quality", "trime_stats_read", "trime_stats_check", "trime_autotune_workspace_bytes",
-            "trime_autotune"]
+            "trime_autotune", "trime_batch_graph_create", "trime_graph_launch", "trime_graph_destroy"]
 
 _lib = None
 
@@ -163,6 +163,10 @@ def lib(require_gpu: bool = True):
         L.trime_autotune_workspace_bytes.argtypes = [st, dp, C.c_int32, C.POINTER(C.c_size_t)]
         L.trime_autotune.argtypes = [st, vp, C.c_size_t, vp, vp, dp, C.c_int32, C.c_int32, dp,
                                      C.POINTER(C.c_float), vp]
+        L.trime_batch_graph_create.argtypes = [C.POINTER(st), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                               C.POINTER(vp), vp]
+        L.trime_graph_launch.argtypes = [vp, vp]
+        L.trime_graph_destroy.argtypes = [vp]
         for f in EXPORTED:
             if f not in ("trime_last_error", "trime_version", "trime_default_params"):
                 getattr(L, f).restype = C.c_int
@@ -276,6 +280,24 @@ def autotune(state, ws, x, y, densities, n_iter, stream=None):
     _check(lib().trime_autotune(C.byref(state), _ptr(ws), ws.numel() * ws.element_size(), _ptr(x), _ptr(y), d,
                                 len(densities), int(n_iter), C.byref(best), ms, _stream(stream)))
     return best.value, list(ms)
+
+
+def batch_graph_create(states, method, n_iter, nstreams, stream):
+    """One graph of n_iter iterations of every state (method METHOD_DM or
+    METHOD_CVD), captured on `stream` (not the null stream)."""
+    arr = (C.POINTER(State) * len(states))(*[C.pointer(s) for s in states])
+    g = C.c_void_p()
+    _check(lib().trime_batch_graph_create(arr, len(states), int(method), int(n_iter), int(nstreams), C.byref(g),
+                                          _stream(stream)))
+    return g
+
+
+def graph_launch(g, stream=None):
+    _check(lib().trime_graph_launch(g, _stream(stream)))
+
+
+def graph_destroy(g):
+    _check(lib().trime_graph_destroy(g))
 
 
 def stats_read(state, stream=None) -> Stats:

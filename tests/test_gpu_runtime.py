@@ -156,3 +156,44 @@ def test_graph_capture_dm_replays_match_eager(orc, T):
         assert np.array_equal(c, want[r][2]), r
     st = m.stats_raw()
     assert st.error == 0
+
+
+def test_star_polygon_dm_matches_oracle(orc, T):
+    """A star-shaped polygon (the batch workload's shapes): three FP64
+    DistMesh iterations follow the oracle's run to FP64 rounding."""
+    wl = I.stars(count=1, grid_n=256, n_range=(3.3, 3.3))[0]
+    og = orc.build_grid(wl)
+    m = mesher(wl, FP64, grid=og)
+    m.step_dm(3)
+    gx, gy, gc = m.points()
+    x, y, cat, fin, info = orc.run(og, wl.x, wl.y, [("dm", 3)], nthreads=8)
+    err = np.hypot(gx - x, gy - y) / h_of(og, x, y)
+    assert err.max() <= 1e-10, err.max()
+    assert np.array_equal(gc, cat)
+
+
+@pytest.mark.parametrize("method", ["dm", "cvd"])
+def test_batch_graph_matches_per_shape_runs(orc, T, method):
+    """Shapes of uneven size in one graph launch give, shape by shape, the
+    results of running each shape alone."""
+    from paper_2309_13824_amd.mesher import Batch
+    wls = I.stars(count=6, grid_n=256, n_range=(3.0, 3.6))
+    grids = [orc.build_grid(w) for w in wls]
+    alone = []
+    for w, g in zip(wls, grids):
+        m = mesher(w, FP32, grid=g)
+        if method == "dm":
+            m.step_dm(4, fresh=False)
+        else:
+            m.step_cvd(4)
+        alone.append(m.points())
+    ms = [mesher(w, FP32, grid=g) for w, g in zip(wls, grids)]
+    b = Batch(ms, method=method, n_iter=2, nstreams=3)
+    b.run(4)
+    import torch
+    torch.cuda.synchronize()
+    for k, m in enumerate(ms):
+        x, y, c = m.points()
+        assert np.array_equal(x, alone[k][0]) and np.array_equal(y, alone[k][1]), k
+        assert np.array_equal(c, alone[k][2]), k
+    b.close()
