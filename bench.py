@@ -81,6 +81,11 @@ def parse():
     ap.add_argument("--tune", type=str, default="1.0,1.4,2.0,2.8",
                     help="bin densities (points per bin) the autotuner tries before the timed run; "
                          "empty for the default 3.3")
+    ap.add_argument("--workload", default="holes20", choices=["holes20", "stars", "disk", "annulus", "ellipses"],
+                    help="holes20: the headline CVD run; stars: the batch of 512 star polygons "
+                         "(DistMesh), batched in one graph vs per-shape launches; disk, annulus, "
+                         "ellipses: their fixed schedules, one JSON line each")
+    ap.add_argument("--shapes", type=int, default=512)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -176,6 +181,148 @@ def cpu_baseline(wl, threads, log):
     return secs
 
 
+def stars_run(args, log):
+    """The star-polygon batch: every shape on its own 512^2 grid, 60
+    DistMesh iterations; one graph launch per two iterations of all shapes
+    (FP32 + FP64 replay) against per-shape launches (FP32 and FP64)."""
+    import torch
+    from paper_2309_13824_amd import inputs as I
+    from paper_2309_13824_amd import trime as T
+    from paper_2309_13824_amd.mesher import Batch, Mesher
+    iters = 60
+    t = time.perf_counter()
+    wls = I.stars(count=args.shapes, grid_n=512, iters=iters)
+    total = sum(w.n for w in wls)
+    log("stars: %d shapes, %d points in total (%.1f s to sample)" % (len(wls), total, time.perf_counter() - t))
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    out = {}
+    for prec, name in ((T.FP32, "fp32"), (T.FP64, "fp64")):
+        t = time.perf_counter()
+        ms = [Mesher(w, precision=prec) for w in wls]
+        for m in ms:
+            m.load()
+        torch.cuda.synchronize()
+        log("  %s: %d grids built and states loaded in %.1f s" % (name, len(ms), time.perf_counter() - t))
+
+        def per_shape():
+            for m in ms:
+                T.step_dm(m.state, iters, fresh=False)
+        per_ms = timed(per_shape)
+        out["per_shape_" + name] = total * iters / (per_ms * 1e-3)
+        log("  %s per-shape launches: %.1f ms for %d iterations" % (name, per_ms, iters))
+        if prec == T.FP32:
+            for m in ms:
+                m.load()
+            t = time.perf_counter()
+            b = Batch(ms, method="dm", n_iter=2, nstreams=8)
+            log("  graph of 2 iterations x %d shapes captured and instantiated in %.1f s" % (len(ms), time.perf_counter() - t))
+            b.run(2)  # warm-up launch
+            for m in ms:
+                m.load()
+            torch.cuda.synchronize()
+            bat_ms = timed(lambda: b.run(iters))
+            b.close()
+            out["batched_fp32"] = total * iters / (bat_ms * 1e-3)
+            out["batched_ms"] = bat_ms
+            log("  fp32 batched graph: %.1f ms for %d iterations" % (bat_ms, iters))
+        del ms
+        torch.cuda.empty_cache()
+    line = {
+        "metric": "point-iterations/s, batch of %d star polygons, DistMesh" % len(wls),
+        "value": out["batched_fp32"], "unit": "point-iterations/s", "n_gpus": 1, "steps": iters, "warmup": 2,
+        "ms_per_step": out["batched_ms"] / iters, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "stars: %d star polygons (8-64 vertices, radii U[0.5,1]) on 512^2 f32 grids, "
+                               "log-uniform point counts in [1e3, 1e5], %d points in total, 60 DistMesh "
+                               "iterations" % (len(wls), total), "shapes": len(wls), "total_points": total,
+                   "seed": 1005},
+        "per_shape_fp32": out["per_shape_fp32"], "per_shape_fp64": out["per_shape_fp64"],
+        "batched_over_per_shape_fp32": out["batched_fp32"] / out["per_shape_fp32"],
+        "batched_fp32_over_per_shape_fp64": out["batched_fp32"] / out["per_shape_fp64"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+def schedule_run(args, log):
+    """disk (DistMesh, FP64, CPU oracle timed beside it), annulus (30 CVD then
+    70 DistMesh as configured, and the paper's order 70 DistMesh then 30
+    CVD; FP32 + FP64 replay vs FP64) or ellipses (70 DistMesh then 30 CVD,
+    10^7 points, autotuned bin size, FP32 + FP64 replay)."""
+    import torch
+    from paper_2309_13824_amd import inputs as I
+    from paper_2309_13824_amd import trime as T
+    from paper_2309_13824_amd.mesher import Mesher
+    which = args.workload
+    t = time.perf_counter()
+    wl = {"disk": I.disk, "annulus": I.annulus, "ellipses": I.ellipses}[which]()
+    log("workload %s: %d points (%.1f s to sample)" % (wl.name, wl.n, time.perf_counter() - t))
+    schedules = [wl.schedule]
+    if which == "annulus":
+        schedules.append([("dm", 70), ("cvd", 30)])
+    precs = [T.FP64] if which == "disk" else [T.FP32, T.FP64]
+    res = {}
+    for prec in precs:
+        pname = "fp32" if prec == T.FP32 else "fp64"
+        m = Mesher(wl, precision=prec)
+        dens = 3.3
+        if which == "ellipses":
+            dens, ms = m.autotune((1.4, 2.0, 2.8), n_iter=2)
+            log("  autotune (%s): %s -> %.2f" % (pname, ", ".join("%.1f: %.2f ms" % kv for kv in sorted(ms.items())), dens))
+        for sch in schedules:
+            iters = sum(k for _, k in sch)
+            m.load()
+            m.step_hybrid([(sch[0][0], 2)])  # warm-up
+            m.load()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            w0 = time.perf_counter()
+            a.record()
+            m.step_hybrid(sch)
+            b.record()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - w0
+            ms_ = a.elapsed_time(b)
+            st = m.stats()
+            key = "%s %s" % (pname, "+".join("%d %s" % (k, meth) for meth, k in sch))
+            res[key] = {"value": wl.n * iters / (ms_ * 1e-3), "ms_per_step": ms_ / iters, "wall_s": wall,
+                        "triangulations": st["triangulations"], "fp64_replays": st["fp64_replays"],
+                        "bin_density": dens, "mean_q": st["mean_q"], "min_q": st["min_q"]}
+            log("  %s: %.1f ms for %d iterations (%d triangulations), mean q %.4f" % (
+                key, ms_, iters, st["triangulations"], st["mean_q"]))
+        del m
+        torch.cuda.empty_cache()
+    first = res[next(iter(res))]
+    cpu = None
+    if which == "disk" and not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        og = orc.build_grid(wl)
+        t = time.perf_counter()
+        orc.run(og, wl.x, wl.y, wl.schedule, nthreads=threads)
+        secs = time.perf_counter() - t
+        cpu = {"value": wl.n * 50 / secs, "unit": "point-iterations/s", "cores": threads, "kind": "oracle",
+               "sample": "the full 50-iteration DistMesh run of the disk workload (2000 points), FP64 with "
+                         "exact predicates"}
+        log("  cpu oracle: full run %.2f s on %d threads" % (secs, threads))
+    line = {"metric": "point-iterations/s, %s workload" % wl.name, "value": first["value"],
+            "unit": "point-iterations/s", "n_gpus": 1, "steps": sum(k for _, k in wl.schedule), "warmup": 2,
+            "ms_per_step": first["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64" if which == "disk" else "f32", "data": "synthetic",
+            "config": {"workload": "%s, %d points, %d^2 grid, schedule %s" % (
+                wl.name, wl.n, wl.grid.nx, wl.schedule), "seed": wl.seed},
+            "runs": res, "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
@@ -185,6 +332,12 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe, log)
+        return
+    if args.workload == "stars":
+        stars_run(args, log)
+        return
+    if args.workload in ("disk", "annulus", "ellipses"):
+        schedule_run(args, log)
         return
     import torch
     from paper_2309_13824_amd import inputs as I

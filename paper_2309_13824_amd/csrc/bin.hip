@@ -196,6 +196,7 @@ __global__ void k_order_scatter(KArgs a) {
   if (s >= a.n || cond_off(a)) return;
   int before = a.perm[s];  // heavy slots before s
   int heavy = a.perm[a.n];
+  if (s == 0) a.counters[CNT_HEAVY] = heavy;
   int64_t w = a.key[s] ? before : heavy + (s - before);
   a.order[w] = (int)s;
 }

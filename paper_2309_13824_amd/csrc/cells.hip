@@ -31,6 +31,10 @@
 #include "geom_dev.hpp"
 #include "launch.hpp"
 
+#ifndef TRIME_HEAVY_WAVE
+#define TRIME_HEAVY_WAVE 0  // 1: boundary points go to the wavefront-per-point kernel
+#endif
+
 namespace trime {
 
 template <class T> struct Row {
@@ -689,6 +693,41 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       swy += w * gy;
     };
     const int D = L - 1;
+    if constexpr (BLOCK == 1) {
+      // one polygon per wavefront: leaf i of the n 2^D leaves goes to lane
+      // i mod 64 (bit path from its fan triangle); the partial sums meet in
+      // a fixed-order tree at lane 0 and are broadcast
+      const int lane = threadIdx.x & 63;
+      const int64_t total = (int64_t)n << D;
+      for (int64_t i = lane; i < total; i += 64) {
+        int t = (int)(i >> D);
+        int64_t b = i & (((int64_t)1 << D) - 1);
+        V bx, by, cx_, cy_;
+        getv(t, bx, by);
+        getv(t + 1 == n ? 0 : t + 1, cx_, cy_);
+        V x0 = 0, y0 = 0, x1 = bx, y1 = by, x2 = cx_, y2 = cy_;
+        for (int d = D - 1; d >= 0; d--) {
+          int e;
+          V mx, my;
+          longest_edge(x0, y0, x1, y1, x2, y2, e, mx, my);
+          take_child(e, (int)((b >> d) & 1), mx, my, x0, y0, x1, y1, x2, y2);
+        }
+        leaf(x0, y0, x1, y1, x2, y2);
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        sw += __shfl_down(sw, off);
+        swx += __shfl_down(swx, off);
+        swy += __shfl_down(swy, off);
+      }
+      sw = __shfl(sw, 0);
+      swx = __shfl(swx, 0);
+      swy = __shfl(swy, 0);
+      wk.leaves += n << D;
+      V inv = (V)1 / sw;
+      cx = swx * inv;
+      cy = swy * inv;
+      return;
+    }
     V vx0, vy0, ax, ay;
     getv(0, vx0, vy0);
     ax = vx0;
@@ -812,7 +851,8 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     double band = (!EXACT && sizeof(T) == 4) ? 1e-6 * h : 0.0;
     bool unsure = false;
     treat<G>(a, px, py, gld(a.cat, k), xnew, ynew, band, xf, yf, cf, unsure, tc);
-    if (unsure) {
+    // with band 0 (FP64) the comparisons as evaluated are the decisions
+    if (unsure && band > 0.0) {
       why = WHY_TREAT;
       return false;
     }
@@ -863,6 +903,125 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     st.leaves += wk.leaves;
   }
 
+  // Quality of the valid triangle (p, jin, jout) (Eq. 10-11) into the lane
+  // statistics and the beta histogram.
+  TRIME_D void tri_quality(LaneStats &st, int *hist, int jin, int jout) const {
+    st.nvalid++;
+    double x1 = gld(a.x, jin), y1 = gld(a.y, jin), x2 = gld(a.x, jout), y2 = gld(a.y, jout);
+    double l0 = sqrt((x1 - px) * (x1 - px) + (y1 - py) * (y1 - py));
+    double l1 = sqrt((x2 - x1) * (x2 - x1) + (y2 - y1) * (y2 - y1));
+    double l2 = sqrt((px - x2) * (px - x2) + (py - y2) * (py - y2));
+    double A2 = fabs((x1 - px) * (y2 - py) - (y1 - py) * (x2 - px));
+    double al = (l0 * l1 * l2) * (l0 + l1 + l2) / (4.0 * A2 * A2);
+    double be = fmax(l0, fmax(l1, l2)) / fmin(l0, fmin(l1, l2));
+    st.sa += sqrt(al);
+    st.sb += sqrt(be);
+    st.sq += 1.0 / al;
+    st.amax = fmax(st.amax, al);
+    st.nq++;
+    int bin = (int)floor((be - 1.0) / 2.0 * 40.0);
+    bin = bin < 0 ? 0 : (bin > 39 ? 39 : bin);
+    atomicAdd(&hist[bin], 1);
+  }
+
+  // Everything after the cell for the wavefront-per-point kernel: every lane
+  // holds the same lane state; lane j takes the octagon and validity tests
+  // of vertex j and commits its triangle, the quadrature leaves are spread
+  // over the lanes, and lane 0 writes the per-point outputs.  The same
+  // decisions and outputs as finish().
+  TRIME_D bool finish_wave(int lane, LaneStats &st, int *hist) {
+    static_assert(BLOCK == 1 && VMAX <= 64, "one polygon per wavefront, at most one vertex per lane");
+    if constexpr (MODE == MODE_CELLS) {
+      if (lane == 0) {
+        write_cell();
+        if (n == 0) st.empty++;
+        st.candidates += wk.candidates;
+        st.margins += wk.margins;
+        st.cuts += wk.cuts;
+      }
+      return true;
+    } else {
+      bool ex = false, va = false;
+      int jin = -1, jout = -1;
+      if (lane < n) {
+        jin = con(lane == 0 ? n - 1 : lane - 1);
+        jout = con(lane);
+        if (jin >= 0 && jout >= 0) {
+          int e = inside_octagon(lane, jin, jout);
+          if (!why && e) e = inside_octagon(lane, jout, jin);
+          if (!why && e) {
+            ex = true;
+            va = valid_triangle(jin, jout);
+          }
+        }
+      }
+      if (__ballot(why != 0)) {  // an FP64-undecided octagon test: the exact stage takes the point
+        why = WHY_AND;
+        return false;
+      }
+      const uint64_t valid = __ballot(va);
+      double xf = px, yf = py;
+      uint8_t cf = 0;
+      int cap_hit = 0;
+      TreatCount tc;
+      if constexpr (MODE == MODE_CVD) target_and_treat(xf, yf, cf, cap_hit, tc);  // FP64: cannot defer
+      // triangles: lane j owns the one at vertex j when p has the smallest id
+      bool own = ex && pid < gld(a.id, jin) && pid < gld(a.id, jout);
+      const uint64_t owners = __ballot(own);
+      const int nt_all = __popcll(owners);
+      int64_t tbase = k * TRIME_TRI_PER_POINT;
+      if (own) {
+        int nt = __popcll(owners & ((1ull << lane) - 1ull));
+        if (nt < TRIME_TRI_PER_POINT) {
+          gst(a.tri, (tbase + nt) * 3 + 0, (int32_t)k);
+          gst(a.tri, (tbase + nt) * 3 + 1, jin);
+          gst(a.tri, (tbase + nt) * 3 + 2, jout);
+          gst(a.tri_valid, tbase + nt, (uint8_t)va);
+        } else {
+          atomicOr(&a.counters[CNT_ERR], ERR_TRI_CAP);
+        }
+        st.ntri++;
+        if (va) tri_quality(st, hist, jin, jout);
+      }
+      if (lane == 0) gst(a.tri_n, k, nt_all < TRIME_TRI_PER_POINT ? nt_all : TRIME_TRI_PER_POINT);
+      if constexpr (MODE == MODE_EXTRACT) {
+        // adjacency: edge j kept when a valid triangle sits at vertex j or
+        // j + 1; lane j writes it at its rank by slot
+        int jn = (lane + 1 >= n) ? 0 : lane + 1;
+        bool keep = lane < n && jout >= 0 && (va || ((valid >> jn) & 1ull));
+        const uint64_t kept = __ballot(keep);
+        const int cnt = __popcll(kept);
+        const int md = a.max_deg;
+        if (keep) {
+          int rank = 0;
+          for (uint64_t m = kept; m; m &= m - 1) {
+            int i = __ffsll((unsigned long long)m) - 1;
+            rank += con(i) < jout;
+          }
+          if (rank < md) gst(a.adj, (int64_t)rank * a.n + k, jout);
+        }
+        if (lane == 0) {
+          if (cnt > md) atomicOr(&a.counters[CNT_ERR], ERR_DEG_CAP);
+          gst(a.deg, k, cnt < md ? cnt : md);
+        }
+      }
+      if (lane == 0) {
+        if constexpr (MODE == MODE_CVD) {
+          write_cvd(xf, yf, cf);
+          st.newton_fail += tc.newton_fail();
+          st.trace_fail += tc.trace_fail();
+          st.cap_hits += cap_hit;
+        }
+        if (n == 0) st.empty++;
+        st.candidates += wk.candidates;
+        st.margins += wk.margins;
+        st.cuts += wk.cuts;
+        st.leaves += wk.leaves;
+      }
+      return true;
+    }
+  }
+
   // Everything for point k; returns false when the point must be replayed.
   TRIME_D bool run(LaneStats &st, int *hist) {
     if (!begin()) return false;
@@ -891,10 +1050,45 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   // of a ring are loaded and range-tested 64 at a time, one per lane, and the
   // ones in range are clipped in lane order by all lanes together.  The cell
   // does not depend on the clip order (every decision is exact).
-  TRIME_D void scan_wave(int lane, int *sh_s0, int *sh_incl) {
+  //
+  // Candidates are range-tested against a bound per direction.  q cuts a
+  // vertex v only if q . v > |q|^2 / 2, which needs v within 90 degrees of
+  // q and |q|^2 < 4 |v|^2.  q lies within 22.5 degrees of the nearest of 8
+  // directions, so the bound of that direction is the largest |v|^2 over
+  // the vertices within 112.5 degrees of it (23 degrees are used, for
+  // rounding in the choice of the direction).  For a point on the boundary,
+  // whose cell reaches the octagon outside the shape, neighbours inside the
+  // shape then meet the small inner part of the cell, not the octagon's
+  // corners.
+  TRIME_D static int sector8(T x, T y) {
+    const T ax = fabs(x), ay = fabs(y), t = (T)0.41421356;  // tan 22.5 deg
+    if (ay <= t * ax) return x >= 0 ? 0 : 4;
+    if (ax <= t * ay) return y >= 0 ? 2 : 6;
+    if (x >= 0) return y >= 0 ? 1 : 7;
+    return y >= 0 ? 3 : 5;
+  }
+
+  TRIME_D void update_sectors(int lane, T *sh_ro) {
+    if (lane < 8) {
+      const T c = (T)0.70710678118654752;
+      const T dx = lane == 0 ? (T)1 : (lane == 4 ? (T)-1 : (lane == 2 || lane == 6 ? (T)0 : (lane == 1 || lane == 7 ? c : -c)));
+      const T dy = lane == 2 ? (T)1 : (lane == 6 ? (T)-1 : (lane == 0 || lane == 4 ? (T)0 : (lane == 1 || lane == 3 ? c : -c)));
+      T best = 0;
+      for (int j = 0; j < n; j++) {
+        VRec<T> v = P[j][tid];
+        T vn = sqrt(v.x * v.x + v.y * v.y);
+        if (v.x * dx + v.y * dy >= (T)-0.39073113 * vn - (T)2 * (T)v.e) best = fmax(best, vert_r2(v.x, v.y, v.e));
+      }
+      sh_ro[lane] = fmin(best, R2);
+    }
+    __syncthreads();
+  }
+
+  TRIME_D void scan_wave(int lane, int *sh_s0, int *sh_incl, T *sh_ro) {
     const T u = U<T>::v;
     int bx, by;
     bin_of(a, px, py, bx, by);
+    update_sectors(lane, sh_ro);
     double ox = px - (a.bx0 + bx * a.bw), oy = py - (a.by0 + by * a.bw);
     double edge = fmax(0.0, fmin(fmin(ox, a.bw - ox), fmin(oy, a.bw - oy)));
     const int rmax = max(a.nbx, a.nby);
@@ -939,7 +1133,7 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
             if (sl != (int)k) {
               T nx = (T)(gld(a.x, sl) - px), ny = (T)(gld(a.y, sl) - py);
               T sq = nx * nx + ny * ny;
-              pass = !(sq * ((T)1 - (T)8 * u) > (T)4 * R2);
+              pass = !(sq * ((T)1 - (T)8 * u) > (T)4 * sh_ro[sector8(nx, ny)]);
             }
           }
           wk.candidates += __popcll(__ballot(c < total && sl != (int)k));
@@ -953,9 +1147,11 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
             r3.ny = (T)(gld(a.y, sj) - py);
             T sq = r3.nx * r3.nx + r3.ny * r3.ny;
             r3.s = sq * (T)0.5;
-            if (!(sq * ((T)1 - (T)8 * u) > (T)4 * R2)) {
+            if (!(sq * ((T)1 - (T)8 * u) > (T)4 * sh_ro[sector8(r3.nx, r3.ny)])) {
+              int cuts0 = wk.cuts;
               clip(r3, sj);
               if (why || n == 0) return;
+              if (wk.cuts != cuts0) update_sectors(lane, sh_ro);
             }
           }
         }
@@ -1056,6 +1252,13 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
         gst(a.deg, k, w);
       }
       if constexpr (MODE == MODE_CVD) {
+        if (defer && n >= CQ_STRIDE) {  // cannot happen: only FP32 lanes (n <= 12) defer
+          atomicOr(&a.counters[CNT_ERR], ERR_POLY_CAP);
+          defer = false;
+          xf = px;
+          yf = py;
+          cf = gld(a.cat, k);
+        }
         if (defer) {
           int w = atomicAdd(&a.counters[CNT_QUEUE3], 1);
           gst(a.queue3, (int64_t)w, (int32_t)k);
@@ -1174,7 +1377,12 @@ __global__ __launch_bounds__(BLOCK) void k_cells(KArgs a) {
   zero_hist<BLOCK>(hist);
   LaneStats st;
   int64_t w = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (w < a.n) {
+  if (w < a.n && TRIME_HEAVY_WAVE && w < gld(a.counters, (int64_t)CNT_HEAVY)) {
+    // points on the boundary (first in the order) scan the most bins: one
+    // wavefront per point loads their candidates 64 at a time
+    int64_t k = gld(a.order, w);
+    push(a, 1, k, WHY_HEAVY);
+  } else if (w < a.n) {
     int64_t k = gld(a.order, w);
     Lane<T, G, MODE, false, VMAX, BLOCK> L(a, P, threadIdx.x, k);
     if (!L.run(st, hist)) {
@@ -1216,6 +1424,7 @@ __global__ __launch_bounds__(64) void k_cells_wave(KArgs a) {
   __shared__ VRec<double> P[VMAX][1];
   __shared__ int hist[40];
   __shared__ int sh_s0[64], sh_incl[64];
+  __shared__ double sh_ro[8];
   zero_hist<64>(hist);
   LaneStats st;
   const int lane = threadIdx.x;
@@ -1225,13 +1434,11 @@ __global__ __launch_bounds__(64) void k_cells_wave(KArgs a) {
     Lane<double, G, MODE, false, VMAX, 1> L(a, P, 0, k);
     bool ok = L.begin();
     if (ok) {
-      L.scan_wave(lane, sh_s0, sh_incl);
+      L.scan_wave(lane, sh_s0, sh_incl, sh_ro);
       ok = !L.why;
     }
-    if (lane == 0) {
-      if (ok) ok = L.finish(st, hist);
-      if (!ok) push(a, 2, k, L.why);
-    }
+    if (ok) ok = L.finish_wave(lane, st, hist);
+    if (!ok && lane == 0) push(a, 2, k, L.why);
     __syncthreads();
   }
   flush_stats<64>(a, st, hist);
@@ -1275,6 +1482,7 @@ constexpr int FAST_VMAX = TRIME_FAST_VMAX;  // polygon capacity of the fast kern
 constexpr int REPLAY_BLOCK = 64;
 constexpr int REPLAY_VMAX = 32;
 constexpr int WAVE_VMAX = 64;
+constexpr int WAVE_GRID = 4096;
 constexpr int CENTROID_BLOCK = 64;
 static_assert(FAST_VMAX < CQ_STRIDE, "a deferred cell must fit its queue entry");
 
@@ -1285,7 +1493,7 @@ template <class T, class G, int MODE> static void launch_mode(const KArgs &a, hi
   if (a.ev1) (void)hipEventRecord((hipEvent_t)a.ev1, s);
   if (MODE == MODE_CVD && sizeof(T) == 4)
     hipLaunchKernelGGL((k_cells_centroid<G, CENTROID_BLOCK>), dim3(256), dim3(CENTROID_BLOCK), 0, s, a);
-  hipLaunchKernelGGL((k_cells_wave<G, MODE, WAVE_VMAX>), dim3(1024), dim3(64), 0, s, a);
+  hipLaunchKernelGGL((k_cells_wave<G, MODE, WAVE_VMAX>), dim3(WAVE_GRID), dim3(64), 0, s, a);
   hipLaunchKernelGGL((k_cells_exact<G, MODE, REPLAY_VMAX, REPLAY_BLOCK>), dim3(64), dim3(REPLAY_BLOCK), 0, s, a);
 }
 

@@ -81,13 +81,13 @@ TRIME_D bool cond_off(const KArgs &a) { return a.cond && gld(a.cond, 0) == 0; }
 
 // counters[]: queue lengths, error bits, and the reasons of FP64 replays
 enum { CNT_QUEUE = 0, CNT_TRI = 1, CNT_ERR = 2, CNT_MOVED = 3, CNT_QUEUE2 = 4, CNT_QUEUE3 = 5,
-       CNT_REASON = 8, CNT_NCOUNTERS = 16 };
+       CNT_REASON = 8, CNT_HEAVY = 24, CNT_NCOUNTERS = 32 };
 // ints per entry of the deferred-centroid queue (count + constraints)
 constexpr int CQ_STRIDE = 16;
 enum { ERR_TRI_CAP = 1, ERR_DEG_CAP = 2, ERR_POLY_CAP = 4, ERR_EXACT_CAP = 8, ERR_QUEUE = 16 };
 // why a point left the fast path
 enum { WHY_PRED = 1, WHY_VERTEX = 2, WHY_POLY = 3, WHY_AND = 4, WHY_LEVEL = 5, WHY_TREAT = 6,
-       WHY_BOX = 7 };
+       WHY_BOX = 7, WHY_HEAVY = 8 };
 
 // ---------------------------------------------------------------- grid ----
 

@@ -116,7 +116,68 @@ def _in_polygon(poly: np.ndarray, x: np.ndarray, y: np.ndarray) -> np.ndarray:
     return ins
 
 
+class _Buckets:
+    """Points bucketed on a uniform grid so that a primitive is evaluated only
+    at the points inside its bounding box (many small holes)."""
+
+    def __init__(self, x, y, nb=256):
+        self.x0, self.y0 = float(x.min()), float(y.min())
+        self.w = max(float(x.max()) - self.x0, float(y.max()) - self.y0, 1e-12) / nb * (1 + 1e-9)
+        self.nb = nb
+        ix = np.minimum(((x - self.x0) / self.w).astype(np.int64), nb - 1)
+        iy = np.minimum(((y - self.y0) / self.w).astype(np.int64), nb - 1)
+        cell = iy * nb + ix
+        self.order = np.argsort(cell, kind="stable")
+        self.start = np.searchsorted(cell[self.order], np.arange(nb * nb + 1))
+
+    def points_in(self, bx0, by0, bx1, by1):
+        nb = self.nb
+        i0 = max(int((bx0 - self.x0) / self.w), 0)
+        i1 = min(int((bx1 - self.x0) / self.w), nb - 1)
+        j0 = max(int((by0 - self.y0) / self.w), 0)
+        j1 = min(int((by1 - self.y0) / self.w), nb - 1)
+        if i1 < i0 or j1 < j0:
+            return np.zeros(0, np.int64)
+        parts = [self.order[self.start[j * nb + i0]:self.start[j * nb + i1 + 1]] for j in range(j0, j1 + 1)]
+        return np.concatenate(parts)
+
+
+def _prim_bbox(p, pad=0.0):
+    if p.kind == PRIM_DISK:
+        r = p.p[2] + pad
+        return p.p[0] - r, p.p[1] - r, p.p[0] + r, p.p[1] + r
+    if p.kind == PRIM_ELLIPSE:
+        r = max(p.p[2], p.p[3]) + pad
+        return p.p[0] - r, p.p[1] - r, p.p[0] + r, p.p[1] + r
+    if p.kind == PRIM_BOX:
+        return p.p[0] - pad, p.p[1] - pad, p.p[2] + pad, p.p[3] + pad
+    poly = np.asarray(p.poly)
+    return poly[:, 0].min() - pad, poly[:, 1].min() - pad, poly[:, 0].max() + pad, poly[:, 1].max() + pad
+
+
+def _prim_inside(p, x, y):
+    if p.kind == PRIM_DISK:
+        return (x - p.p[0]) ** 2 + (y - p.p[1]) ** 2 < p.p[2] ** 2
+    if p.kind == PRIM_BOX:
+        return (x > p.p[0]) & (x < p.p[2]) & (y > p.p[1]) & (y < p.p[3])
+    if p.kind == PRIM_ELLIPSE:
+        c, s_ = math.cos(p.p[4]), math.sin(p.p[4])
+        u = c * (x - p.p[0]) + s_ * (y - p.p[1])
+        v = -s_ * (x - p.p[0]) + c * (y - p.p[1])
+        return (u / p.p[2]) ** 2 + (v / p.p[3]) ** 2 < 1.0
+    return _in_polygon(np.asarray(p.poly, np.float64), x, y)
+
+
 def _inside(wl: Workload, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    if len(wl.prims) > 16 and all(p.op == OP_DIFF for p in wl.prims[1:]) and len(x) > 0:
+        # a base shape minus many holes: each hole is tested near itself only
+        ins = _prim_inside(wl.prims[0], x, y)
+        bk = _Buckets(x, y)
+        for p in wl.prims[1:]:
+            idx = bk.points_in(*_prim_bbox(p))
+            if len(idx):
+                ins[idx] &= ~_prim_inside(p, x[idx], y[idx])
+        return ins
     ins = None
     for p in wl.prims:
         if p.kind == PRIM_DISK:
@@ -160,11 +221,15 @@ def _weight(wl: Workload, x: np.ndarray, y: np.ndarray) -> np.ndarray:
         mu = sz.a0 + sz.a1 * d
         return 1.0 / mu ** 2
     if sz.kind == SZ_HOLE_RAMP:
+        # holes farther than a1 leave mu at a0: each hole is visited near itself
         d = np.full_like(x, np.inf)
+        bk = _Buckets(x, y) if len(x) else None
         for k in sz.holes:
             p = wl.prims[k]
             r = max(p.p[2], p.p[3]) if p.kind == PRIM_ELLIPSE else p.p[2]
-            d = np.minimum(d, np.maximum(np.hypot(x - p.p[0], y - p.p[1]) - r, 0.0))
+            idx = bk.points_in(*_prim_bbox(p, sz.a1)) if bk is not None else np.zeros(0, np.int64)
+            if len(idx):
+                d[idx] = np.minimum(d[idx], np.maximum(np.hypot(x[idx] - p.p[0], y[idx] - p.p[1]) - r, 0.0))
         mu = 1.0 + (sz.a0 - 1.0) * np.minimum(d / sz.a1, 1.0)
         return 1.0 / mu ** 2
     raise ValueError(sz.kind)

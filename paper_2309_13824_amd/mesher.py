@@ -171,12 +171,12 @@ class Mesher:
         return T.stats_read(self.state)
 
     REASONS = {1: "predicate", 2: "vertex", 3: "polygon", 4: "and_test", 5: "cvd_level", 6: "treatment",
-               7: "box"}
+               7: "box", 8: "heavy"}
 
     def replay_reasons(self) -> dict:
         """Points sent from the fast kernels to a replay, by reason (since load)."""
         off = self.state.counters - self.ws.data_ptr()
-        c = self.ws[off:off + 64].view(self.torch.int32).cpu().numpy()
+        c = self.ws[off:off + 128].view(self.torch.int32).cpu().numpy()
         return {name: int(c[8 + k]) for k, name in self.REASONS.items()}
 
 
