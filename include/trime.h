@@ -154,7 +154,8 @@ typedef struct {
 } trime_stats;
 
 /* Per-point arrays of a state are kept in "slot" order: the order of the
-   last binning (points sorted by bin, then by id).  Positional arrays are
+   last binning (points sorted by bin, then by their previous slot; the
+   first binning after a load orders them by id).  Positional arrays are
    double-buffered per step, order arrays per binning. */
 typedef struct {
   double *x, *y;  /* positions                                            */

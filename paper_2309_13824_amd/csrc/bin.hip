@@ -1,8 +1,8 @@
 // Binning of the points into Morton-ordered square bins (the role of the
-// Voro++ container blocks, sized for ~3.3 points per block as in the paper's
-// example code), by counting sort: keys + histogram, exclusive scan, scatter,
-// then a per-bin sort by id so the new slot order is the deterministic order
-// (bin key, id).  The gather then permutes every per-point array into the
+// Voro++ container blocks, ~3.3 points per block as in the paper's example
+// code unless tuned), by counting sort: keys + histogram, exclusive scan,
+// scatter, then a per-bin sort by previous slot so the new slot order is the
+// deterministic order (bin key, previous slot).  The gather then permutes every per-point array into the
 // new slot order (coalesced: points move little between iterations).
 #include "launch.hpp"
 
@@ -25,14 +25,34 @@ __global__ void k_fill_cond(KArgs a, int32_t *p, int64_t n) {
     p[i] = 0;
 }
 
+// Keys and ranks within the bins.  The points arrive in the previous slot
+// order, so runs of equal keys fill a wavefront: the first lane of each run
+// takes the run's ranks with one atomic and hands them out.
 __global__ void k_bin_keys(KArgs a) {
+  if (cond_off(a)) return;
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.n || cond_off(a)) return;
-  int bx, by;
-  bin_of(a, a.x[k], a.y[k], bx, by);
-  int key = (int)morton((uint32_t)bx, (uint32_t)by);
-  a.key[k] = key;
-  a.rank[k] = atomicAdd(&a.bin_fill[key], 1);
+  const int lane = threadIdx.x & 63;
+  const bool valid = k < a.n;
+  int key = -1;
+  if (valid) {
+    int bx, by;
+    bin_of(a, a.x[k], a.y[k], bx, by);
+    key = (int)morton((uint32_t)bx, (uint32_t)by);
+    a.key[k] = key;
+  }
+  const int prev = __shfl_up(key, 1);
+  const bool head = valid && (lane == 0 || prev != key);
+  const uint64_t H = __ballot(head), V = __ballot(valid);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);  // lanes 0..lane
+  int base = 0;
+  if (head) {
+    uint64_t above = (H | ~V) & ~upto;  // the next head or the first lane past the end
+    int nxt = above ? __ffsll((unsigned long long)above) - 1 : 64;
+    base = atomicAdd(&a.bin_fill[key], nxt - lane);
+  }
+  const int hl = 63 - __clzll((unsigned long long)(H & upto));
+  const int b = __shfl(base, hl < 0 ? 0 : hl);
+  if (valid) a.rank[k] = b + (lane - hl);
 }
 
 // Block-wide exclusive scan of 4096 ints per block; writes block totals.
@@ -131,16 +151,17 @@ __global__ void k_bin_scatter(KArgs a) {
   a.perm[a.bin_start[a.key[k]] + a.rank[k]] = (int)k;
 }
 
-// One thread per bin: order its entries by point id (insertion sort).
+// One thread per bin: order its entries by their previous slot (insertion
+// sort), so the new slot order is (key, previous slot): deterministic,
+// whatever order the atomics took.
 __global__ void k_bin_sort(KArgs a, int64_t nkeys) {
   int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nkeys || cond_off(a)) return;
   int s0 = a.bin_start[b], s1 = a.bin_start[b + 1];
   for (int s = s0 + 1; s < s1; s++) {
     int v = a.perm[s];
-    int idv = a.id[v];
     int t = s;
-    while (t > s0 && a.id[a.perm[t - 1]] > idv) {
+    while (t > s0 && a.perm[t - 1] > v) {
       a.perm[t] = a.perm[t - 1];
       t--;
     }
