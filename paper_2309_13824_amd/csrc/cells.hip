@@ -1394,52 +1394,49 @@ __global__ __launch_bounds__(BLOCK) void k_cells(KArgs a) {
   flush_stats<BLOCK>(a, st, hist);
 }
 
-// FP64 centroid pass over the deferred queue (grid-stride, one lane per
-// point): FP64 vertices from the stored constraints, FP64 CVD target and
-// treatment.  The cells and triangles of these points were committed by the
-// fast kernel.
-template <class G, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_cells_centroid(KArgs a) {
+// The passes after the fast kernel, in one launch so that they overlap:
+//  - blocks [0, WAVE_GRID): FP64 replay of the queue, one wavefront per point
+//    (grid-stride): the ring scan, the tests, triangles and quadrature are
+//    shared by the 64 lanes.  Points FP64 cannot decide go on to the exact
+//    queue.
+//  - blocks [WAVE_GRID, WAVE_GRID + CENTROID_GRID) (CVD): the deferred FP32
+//    centroids, one lane per point: FP64 vertices from the stored
+//    constraints, FP64 CVD target and treatment.  The cells and triangles of
+//    these points were committed by the fast kernel.
+template <class G, int MODE, int VMAX, int WGRID>
+__global__ __launch_bounds__(64) void k_cells_post(KArgs a) {
   if (cond_off(a)) return;
   constexpr int V = CQ_STRIDE - 1;
-  __shared__ VRec<double> P[V][BLOCK];
-  __shared__ int hist[40];
-  zero_hist<BLOCK>(hist);
-  LaneStats st;
-  int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE3);
-  for (int64_t w = (int64_t)blockIdx.x * BLOCK + threadIdx.x; w < nq; w += (int64_t)gridDim.x * BLOCK) {
-    int64_t k = gld(a.queue3, w);
-    Lane<double, G, MODE_CVD, false, V, BLOCK> L(a, P, threadIdx.x, k);
-    L.centroid_replay(st, w * CQ_STRIDE);
-  }
-  flush_stats<BLOCK>(a, st, hist);
-}
-
-// FP64 replay of the queue, one wavefront per point (grid-stride over the
-// queue): the ring scan is shared by the 64 lanes, the rest of the point runs
-// on lane 0.  Points FP64 cannot decide go on to the exact queue.
-template <class G, int MODE, int VMAX>
-__global__ __launch_bounds__(64) void k_cells_wave(KArgs a) {
-  if (cond_off(a)) return;
   __shared__ VRec<double> P[VMAX][1];
+  __shared__ VRec<double> PC[V][64];
   __shared__ int hist[40];
   __shared__ int sh_s0[64], sh_incl[64];
   __shared__ double sh_ro[8];
   zero_hist<64>(hist);
   LaneStats st;
   const int lane = threadIdx.x;
-  int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE);
-  for (int64_t w = blockIdx.x; w < nq; w += gridDim.x) {
-    int64_t k = gld(a.queue, w);
-    Lane<double, G, MODE, false, VMAX, 1> L(a, P, 0, k);
-    bool ok = L.begin();
-    if (ok) {
-      L.scan_wave(lane, sh_s0, sh_incl, sh_ro);
-      ok = !L.why;
+  if ((int)blockIdx.x < WGRID) {
+    int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE);
+    for (int64_t w = blockIdx.x; w < nq; w += WGRID) {
+      int64_t k = gld(a.queue, w);
+      Lane<double, G, MODE, false, VMAX, 1> L(a, P, 0, k);
+      bool ok = L.begin();
+      if (ok) {
+        L.scan_wave(lane, sh_s0, sh_incl, sh_ro);
+        ok = !L.why;
+      }
+      if (ok) ok = L.finish_wave(lane, st, hist);
+      if (!ok && lane == 0) push(a, 2, k, L.why);
+      __syncthreads();
     }
-    if (ok) ok = L.finish_wave(lane, st, hist);
-    if (!ok && lane == 0) push(a, 2, k, L.why);
-    __syncthreads();
+  } else if constexpr (MODE == MODE_CVD) {
+    const int64_t cb = (int64_t)blockIdx.x - WGRID, cg = (int64_t)gridDim.x - WGRID;
+    int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE3);
+    for (int64_t w = cb * 64 + lane; w < nq; w += cg * 64) {
+      int64_t k = gld(a.queue3, w);
+      Lane<double, G, MODE_CVD, false, V, 64> L(a, PC, lane, k);
+      L.centroid_replay(st, w * CQ_STRIDE);
+    }
   }
   flush_stats<64>(a, st, hist);
 }
@@ -1482,8 +1479,8 @@ constexpr int FAST_VMAX = TRIME_FAST_VMAX;  // polygon capacity of the fast kern
 constexpr int REPLAY_BLOCK = 64;
 constexpr int REPLAY_VMAX = 32;
 constexpr int WAVE_VMAX = 64;
-constexpr int WAVE_GRID = 4096;
-constexpr int CENTROID_BLOCK = 64;
+constexpr int WAVE_GRID = TRIME_HEAVY_WAVE ? 4096 : 1024;
+constexpr int CENTROID_GRID = 256;
 static_assert(FAST_VMAX < CQ_STRIDE, "a deferred cell must fit its queue entry");
 
 template <class T, class G, int MODE> static void launch_mode(const KArgs &a, hipStream_t s) {
@@ -1491,9 +1488,8 @@ template <class T, class G, int MODE> static void launch_mode(const KArgs &a, hi
   if (a.ev0) (void)hipEventRecord((hipEvent_t)a.ev0, s);
   if (nb > 0) hipLaunchKernelGGL((k_cells<T, G, MODE, FAST_VMAX, FAST_BLOCK>), dim3(nb), dim3(FAST_BLOCK), 0, s, a);
   if (a.ev1) (void)hipEventRecord((hipEvent_t)a.ev1, s);
-  if (MODE == MODE_CVD && sizeof(T) == 4)
-    hipLaunchKernelGGL((k_cells_centroid<G, CENTROID_BLOCK>), dim3(256), dim3(CENTROID_BLOCK), 0, s, a);
-  hipLaunchKernelGGL((k_cells_wave<G, MODE, WAVE_VMAX>), dim3(WAVE_GRID), dim3(64), 0, s, a);
+  const int post = WAVE_GRID + (MODE == MODE_CVD && sizeof(T) == 4 ? CENTROID_GRID : 0);
+  hipLaunchKernelGGL((k_cells_post<G, MODE, WAVE_VMAX, WAVE_GRID>), dim3(post), dim3(64), 0, s, a);
   hipLaunchKernelGGL((k_cells_exact<G, MODE, REPLAY_VMAX, REPLAY_BLOCK>), dim3(64), dim3(REPLAY_BLOCK), 0, s, a);
 }
 
