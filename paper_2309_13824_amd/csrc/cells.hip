@@ -376,9 +376,11 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     for (int j = 0; j < VMAX; j++) {
       T m = fma(r3.nx, v[j].x, fma(r3.ny, v[j].y, -r3.s));
       T b = fma(n1, (T)v[j].e, b0);
-      bool in = j < n;
-      if (in && m > b) M |= 1u << j;
-      else if (in && m >= -b) Un |= 1u << j;
+      // as bits, not branches: one exec-mask branch per vertex would cost
+      // more than the comparisons
+      uint32_t in = j < n, gt = m > b, ge = m >= -b;
+      M |= (in & gt) << j;
+      Un |= (in & ge & (gt ^ 1u)) << j;
     }
     wk.margins += n;
     while (Un) {  // undecided in the kernel's precision: FP64 in place
@@ -539,7 +541,52 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     }
   }
 
-  // Scan the rings of bins around p as one flat loop.
+  // bin (dx, dy) number bi of ring r, nearest first: rings 1 and 2 take the
+  // bins that share a side with the inner rings before the corners (packed
+  // tables: 2 bits per coordinate in ring 1, 3 bits in ring 2); rings from 3
+  // on use the plain order
+  TRIME_D static void ring_bin_near(int r, int bi, int &dx, int &dy) {
+    if (r == 1) {
+      uint32_t e = (0xa8206491u >> (4 * bi)) & 15u;
+      dx = (int)(e & 3u) - 1;
+      dy = (int)(e >> 2) - 1;
+    } else if (r == 2) {
+      uint64_t w = bi < 8 ? 0x8e10c1510882ull : 0x92010070c608ull;
+      uint32_t e = (uint32_t)(w >> (6 * (bi & 7))) & 63u;
+      dx = (int)(e & 7u) - 2;
+      dy = (int)(e >> 3) - 2;
+    } else {
+      ring_bin(r, bi, dx, dy);
+    }
+  }
+
+  // Scan the rings of bins around p, one bin per step, nearest bins first.
+  // The scan is bound by the latency of dependent loads, so the range of
+  // the next bin is loaded while the candidates of the current bin are
+  // clipped, and the candidates of a bin are loaded two at a time (four
+  // would take the FP32 kernel past the registers of three wavefronts per
+  // SIMD).  A bin whose distance from p exceeds the reach 2 R (R of the
+  // cell when the bin is fetched, never smaller than later) is not loaded.
+  // The loop is one bin per trip with a single back edge: branches that
+  // skip a bin inside the loop let the compiler split it into nested loops
+  // in which the lanes wait on each other's loads.
+  TRIME_D void fetch_bin(int r, int bi, int bx, int by, double ox, double oy, int &s, int &se) const {
+    int dx, dy;
+    ring_bin_near(r, bi, dx, dy);
+    int xx = bx + dx, yy = by + dy;
+    double gx = dx > 0 ? (dx - 1) * a.bw + (a.bw - ox) : (dx < 0 ? (-dx - 1) * a.bw + ox : 0.0);
+    double gy = dy > 0 ? (dy - 1) * a.bw + (a.bw - oy) : (dy < 0 ? (-dy - 1) * a.bw + oy : 0.0);
+    gx = fmax(gx, 0.0);
+    gy = fmax(gy, 0.0);
+    s = 0;
+    se = 0;
+    if (xx >= 0 && yy >= 0 && xx < a.nbx && yy < a.nby && !(gx * gx + gy * gy > 4.0 * (double)R2 * 1.00001)) {
+      uint32_t key = morton((uint32_t)xx, (uint32_t)yy);
+      s = gld(a.bin_start, (int64_t)key);
+      se = gld(a.bin_start, (int64_t)key + 1);
+    }
+  }
+
   TRIME_D void scan() {
     const T u = U<T>::v;
     int bx, by;
@@ -547,14 +594,35 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     double ox = px - (a.bx0 + bx * a.bw), oy = py - (a.by0 + by * a.bw);
     double edge = fmax(0.0, fmin(fmin(ox, a.bw - ox), fmin(oy, a.bw - oy)));
     const int rmax = max(a.nbx, a.nby);
-    int r = 0, bi = 0, nbr = 1, s = 0, se = 0;
+    int r = 0, bi = 0, nbr = 1;
+    int cs, ce;
+    fetch_bin(0, 0, bx, by, ox, oy, cs, ce);
     for (;;) {
-      if (s < se) {
+      int r1 = r, bi1 = bi + 1, nbr1 = nbr;
+      if (bi1 == nbr1) {
+        r1++;
+        bi1 = 0;
+        nbr1 = 8 * r1;
+      }
+      int ns, ne;
+      fetch_bin(r1, bi1, bx, by, ox, oy, ns, ne);
+      double qx0 = 0, qx1 = 0, qy0 = 0, qy1 = 0;
+      for (int s = cs; s < ce; s++) {
+        const int t = (s - cs) & 1;
+        if (t == 0) {  // the next two candidates of the bin, loads in flight together
+          int s1 = min(s + 1, ce - 1);
+          qx0 = gld(a.x, s);
+          qy0 = gld(a.y, s);
+          qx1 = gld(a.x, s1);
+          qy1 = gld(a.y, s1);
+        }
+        double qx = t == 0 ? qx0 : qx1;
+        double qy = t == 0 ? qy0 : qy1;
         if (s != (int)k) {
           wk.candidates++;
           Row<T> r3;
-          r3.nx = (T)(gld(a.x, s) - px);
-          r3.ny = (T)(gld(a.y, s) - py);
+          r3.nx = (T)(qx - px);
+          r3.ny = (T)(qy - py);
           T sq = r3.nx * r3.nx + r3.ny * r3.ny;
           r3.s = sq * (T)0.5;
           if (!(sq * ((T)1 - (T)8 * u) > (T)4 * R2)) {
@@ -562,24 +630,16 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
             if (why || n == 0) return;
           }
         }
-        s++;
-        continue;
       }
-      if (bi == nbr) {  // ring r done: stop when the next ring is out of reach
-        r++;
+      r = r1;
+      bi = bi1;
+      nbr = nbr1;
+      cs = ns;
+      ce = ne;
+      if (bi == 0) {  // ring r - 1 done: stop when ring r is out of reach
         double dmin = (r - 1) * a.bw + edge;
         if (r > rmax || dmin * dmin > 4.0 * (double)R2 * 1.00001) return;
-        bi = 0;
-        nbr = 8 * r;
       }
-      int dx, dy;
-      ring_bin(r, bi, dx, dy);
-      bi++;
-      int xx = bx + dx, yy = by + dy;
-      if (xx < 0 || yy < 0 || xx >= a.nbx || yy >= a.nby) continue;
-      uint32_t key = morton((uint32_t)xx, (uint32_t)yy);
-      s = gld(a.bin_start, (int64_t)key);
-      se = gld(a.bin_start, (int64_t)key + 1);
     }
   }
 
