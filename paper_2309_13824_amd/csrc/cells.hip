@@ -1006,7 +1006,11 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       if (lane < n) {
         jin = con(lane == 0 ? n - 1 : lane - 1);
         jout = con(lane);
-        if (jin >= 0 && jout >= 0) {
+        bool test = jin >= 0 && jout >= 0;
+        if constexpr (MODE == MODE_CVD) {  // only the triangles p owns are emitted
+          if (test) test = pid < gld(a.id, jin) && pid < gld(a.id, jout);
+        }
+        if (test) {
           int e = inside_octagon(lane, jin, jout);
           if (!why && e) e = inside_octagon(lane, jout, jin);
           if (!why && e) {
@@ -1226,11 +1230,16 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     if constexpr (MODE == MODE_CELLS) {
       write_cell();
     } else {
-      // ---- decisions: triangles at the VV vertices, validity
+      // ---- decisions: triangles at the VV vertices, validity.  A CVD step
+      // emits only the triangles p owns (smallest id), so it tests only
+      // those; extraction needs validity at every vertex (adjacency rows).
       uint32_t exists = 0, valid = 0;
       for (int j = 0; j < n; j++) {
         int jin = con(j == 0 ? n - 1 : j - 1), jout = con(j);
         if (jin < 0 || jout < 0) continue;
+        if constexpr (MODE == MODE_CVD) {
+          if (!(pid < gld(a.id, jin) && pid < gld(a.id, jout))) continue;
+        }
         int e = inside_octagon(j, jin, jout);
         if (why) return false;
         if (e) e = inside_octagon(j, jout, jin);
