@@ -127,6 +127,25 @@ typedef struct {
   int32_t test2_mode;      /* 0: one midpoint inside -> Test 3; 1: invalid  */
 } trime_params;
 
+/* Control block of an adaptive run (trime_step_adaptive), kept on the
+   device with the statistics.  Iterations are numbered from 0 within the
+   run. */
+enum { TRIME_STOP_NONE = 0, TRIME_STOP_QUALITY = 1, TRIME_STOP_MOVEMENT = 2 };
+typedef struct {
+  int32_t method;      /* method of the next iteration (TRIME_METHOD_*)      */
+  int32_t stopped;     /* 1 once a termination test held                    */
+  int32_t iters;       /* iterations run (the stopping one included)        */
+  int32_t switch_iter; /* iteration whose statistics switched DistMesh to CVD, -1 */
+  int32_t stop_iter;   /* iteration whose statistics ended the run, -1      */
+  int32_t reason;      /* TRIME_STOP_*                                      */
+  int32_t moving;      /* an inner point moved >= fac_end*h in the iteration */
+  int32_t have_prev;   /* prev holds the statistics of the previous iteration */
+  int32_t gate[8];     /* per-iteration kernel gates (internal)             */
+  double prev[3];      /* M_1/2(alpha), M_1/2(beta), max alpha: previous    */
+  double last[3];      /* the same, iteration just run                      */
+  double rel[3];       /* their relative changes (-1 when not defined)      */
+} trime_adapt_ctl;
+
 /* Device-side counters and statistics of a state (read with trime_stats_read). */
 typedef struct {
   int64_t fp64_replays;    /* points recomputed in FP64 after an uncertain FP32 decision */
@@ -151,6 +170,7 @@ typedef struct {
      last load: neighbours tested against the search range, vertex margins
      evaluated, polygon cuts, quadrature leaf triangles (Sec. 4.2 II) */
   int64_t work_candidates, work_margins, work_cuts, work_leaves;
+  trime_adapt_ctl adapt;   /* the last adaptive run                           */
 } trime_stats;
 
 /* Per-point arrays of a state are kept in "slot" order: the order of the
@@ -316,6 +336,41 @@ trime_status trime_step_dm(trime_state *st, int32_t n_iter, int32_t fresh,
 trime_status trime_step_cvd(trime_state *st, int32_t n_iter, void *stream);
 /* A fixed schedule of DistMesh and CVD segments (Sec. 2.4, 4.2 III). */
 trime_status trime_step_hybrid(trime_state *st, const trime_schedule *sch, void *stream);
+
+/* ---- adaptive runs ---------------------------------------------------------
+   Termination on mesh quality or small movement (Sec. 6, thresholds in
+   Table 8) and the quality-driven switch of hybrid meshing from DistMesh to
+   CVD (Sec. 4.2, hybrid meshing).  Each iteration measures the mesh it works
+   on: the valid triangles of its triangulation (DistMesh keeps the last one
+   until a point has moved more than fac_retria*h, Alg. 1) at the positions
+   the iteration starts from: M_1/2(alpha), M_1/2(beta) (Eq. 10-11) and max
+   alpha.  After the update, with r the relative change of each against the
+   previous iteration:
+   - mode TRIME_ADAPT_HYBRID, DistMesh phase: the next iterations are CVD
+     when r(M_1/2 alpha) < t_switch;
+   - otherwise the run stops when r(M_1/2 alpha) < t_quality, r(M_1/2 beta)
+     < t_quality and r(max alpha) < t_amax (TRIME_STOP_QUALITY), else when
+     no inner point (category at the start of the iteration) moved by
+     fac_end*h or more, h of the cell it started in (TRIME_STOP_MOVEMENT).
+   The first iteration has no previous statistics: only the movement test can
+   end it.  DistMesh iterations run in flag mode and triangulate on the first
+   iteration of the run.
+   All decisions are taken on the device: the call enqueues max_iter
+   iterations whose kernels check the control block (in stats->adapt) and do
+   nothing once the run has stopped, apart from carrying the positions over,
+   so it makes no host reads and can be captured in a HIP graph.  Read the
+   outcome with trime_stats_read.  Errors: TRIME_EINVAL for a null or unbound
+   state, a null cfg, an unknown mode, max_iter < 0 or a negative or NaN
+   threshold. */
+enum { TRIME_ADAPT_DM = 0, TRIME_ADAPT_CVD = 1, TRIME_ADAPT_HYBRID = 2 };
+typedef struct {
+  int32_t mode;        /* TRIME_ADAPT_*                                      */
+  int32_t max_iter;    /* iterations enqueued                                */
+  double t_quality;    /* T_end_quality (Table 8: 0.001)                     */
+  double t_amax;       /* T_end_alpha_max (Table 8: 0.005)                   */
+  double t_switch;     /* T_switch_quality (Table 8: 0.0015)                 */
+} trime_adaptive;
+trime_status trime_step_adaptive(trime_state *st, const trime_adaptive *cfg, void *stream);
 
 /* Mesh quality of the state's valid triangles (Eq. 10-11) into stats. */
 trime_status trime_quality(trime_state *st, void *stream);

@@ -478,3 +478,91 @@ def run(grid: OracleGrid, x, y, schedule, params=None, nthreads=1, retriangulate
             x, y, cat, dprev = xn, yn, cn, dn
     final = triangulate(grid, x, y, nthreads, prm)
     return x, y, cat, final, info
+
+
+STOP_QUALITY, STOP_MOVEMENT = 1, 2
+
+
+def cell_h(grid: OracleGrid, x, y) -> np.ndarray:
+    """h of the grid cell holding each point (Sec. 3.7): the cell index is
+    floor((x - x0) / dx) with the division taken as a product by 1/dx,
+    clamped to the grid."""
+    fx = np.floor((np.asarray(x) - grid.x0) * (1.0 / grid.dx)).astype(np.int64)
+    fy = np.floor((np.asarray(y) - grid.y0) * (1.0 / grid.dy)).astype(np.int64)
+    fx = np.clip(fx, 0, grid.nx - 2)
+    fy = np.clip(fy, 0, grid.ny - 2)
+    return grid.hcell[fy * (grid.nx - 1) + fx].astype(np.float64)
+
+
+def run_adaptive(grid: OracleGrid, x, y, mode, max_iter, t_quality=0.001, t_amax=0.005, t_switch=0.0015,
+                 params=None, nthreads=1):
+    """Adaptive run: termination tests and the DistMesh -> CVD switch.
+
+    mode is "dm", "cvd" or "hybrid" (DistMesh first, then CVD).  Every
+    iteration measures the mesh it works on: the triangles of its
+    triangulation (DistMesh reuses the last one until a point has moved more
+    than fac_retria*h, Alg. 1) at the positions the iteration starts from,
+    giving M_1/2(alpha), M_1/2(beta) (Eq. 10-11) and max alpha over the valid
+    triangles.  After the iteration's update, with r the relative change of
+    each of the three against the previous iteration:
+
+    - hybrid, DistMesh phase: switch to CVD for the next iteration when
+      r(M_1/2 alpha) < t_switch (Sec. 4.2, hybrid meshing; Table 8);
+    - otherwise stop when r(M_1/2 alpha) < t_quality, r(M_1/2 beta) <
+      t_quality and r(max alpha) < t_amax (Sec. 6, the quality criteria),
+      else when no inner point (category of the start position) moved by
+      fac_end*h or more, h of the cell it started in (Sec. 6 and Sec. 3.7,
+      T_end_mvmt).
+
+    The first iteration has no previous statistics, so only the movement test
+    can end it.  Returns the final positions and categories and a dict with
+    the iterations run, the iteration that switched and the one that stopped
+    (-1 when none), the stop reason (STOP_QUALITY / STOP_MOVEMENT, 0) and the
+    per-iteration history.
+    """
+    prm = params or default_params()
+    x = np.array(x, np.float64)
+    y = np.array(y, np.float64)
+    cat = initial_categories(grid, x, y, prm)
+    dprev = np.full(len(x), -1.0)
+    hybrid = mode == "hybrid"
+    method = "cvd" if mode == "cvd" else "dm"
+    mesh, retri, xl, yl = None, True, None, None
+    prev, switch_iter, stop_iter, reason, hist = None, -1, -1, 0, []
+    for it in range(max_iter):
+        ran = method
+        if method == "dm":
+            if retri or mesh is None:
+                mesh = triangulate(grid, x, y, nthreads, prm)
+                xl, yl = x.copy(), y.copy()
+            q = quality(x, y, mesh.tri, mesh.valid)
+            xn, yn, cn, moved, _, _ = dm_step(grid, x, y, cat, mesh, xl, yl, prm)
+            retri = moved > 0
+            dn = np.sqrt((xn - x) * (xn - x) + (yn - y) * (yn - y))
+        else:
+            mesh = triangulate(grid, x, y, nthreads, prm)
+            q = quality(x, y, mesh.tri, mesh.valid)
+            xn, yn, cn, dn, _, _ = cvd_step(grid, x, y, cat, dprev, nthreads, prm)
+        cur = (q["half_mean_alpha"], q["half_mean_beta"], q["max_alpha"])
+        step = np.sqrt((xn - x) * (xn - x) + (yn - y) * (yn - y))
+        moving = bool(np.any((cat == CAT_INNER) & (step >= prm.fac_end * cell_h(grid, x, y))))
+        rel = None
+        if prev is not None and q["ntri"] > 0 and min(prev) > 0:
+            rel = tuple(abs(c - p) / p for c, p in zip(cur, prev))
+        stop = False
+        if hybrid and method == "dm":
+            if rel is not None and rel[0] < t_switch:
+                method = "cvd"
+                switch_iter = it
+        elif rel is not None and rel[0] < t_quality and rel[1] < t_quality and rel[2] < t_amax:
+            stop, reason = True, STOP_QUALITY
+        elif not moving:
+            stop, reason = True, STOP_MOVEMENT
+        hist.append({"method": ran, "quality": cur, "rel": rel, "moving": moving})
+        prev = cur if q["ntri"] > 0 else None
+        x, y, cat, dprev = xn, yn, cn, dn
+        if stop:
+            stop_iter = it
+            break
+    return x, y, cat, {"iters": len(hist), "switch_iter": switch_iter, "stop_iter": stop_iter,
+                       "reason": reason, "history": hist}

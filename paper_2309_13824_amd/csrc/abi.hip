@@ -487,6 +487,42 @@ trime_status trime_step_hybrid(trime_state *st, const trime_schedule *sch, void 
   return TRIME_OK;
 }
 
+trime_status trime_step_adaptive(trime_state *st, const trime_adaptive *cfg, void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  if (!cfg) return fail(TRIME_EINVAL, "trime_step_adaptive: null configuration");
+  if (cfg->mode != TRIME_ADAPT_DM && cfg->mode != TRIME_ADAPT_CVD && cfg->mode != TRIME_ADAPT_HYBRID)
+    return fail(TRIME_EINVAL, "trime_step_adaptive: unknown mode");
+  if (cfg->max_iter < 0) return fail(TRIME_EINVAL, "trime_step_adaptive: negative iteration count");
+  if (!(cfg->t_quality >= 0.0) || !(cfg->t_amax >= 0.0) || !(cfg->t_switch >= 0.0))
+    return fail(TRIME_EINVAL, "trime_step_adaptive: thresholds must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  const int hybrid = cfg->mode == TRIME_ADAPT_HYBRID;
+  launch_adapt_init(make_args(st), cfg->mode == TRIME_ADAPT_CVD ? TRIME_METHOD_CVD : TRIME_METHOD_DM, s);
+  for (int it = 0; it < cfg->max_iter; it++) {
+    launch_adapt_pre(make_args(st), s);
+    // every group of kernels runs only when its gate is raised; the buffer
+    // swaps are the same whatever the gates say
+    bin_points(st, s, adapt_gate(st, G_BIN));
+    extract(st, s, adapt_gate(st, G_DMTRI));  // DistMesh, re-triangulating
+    KArgs a = make_args(st);
+    a.cond = adapt_gate(st, G_DMQ);  // DistMesh on the last triangulation: its quality now
+    launch_quality(a, s);
+    a.cond = adapt_gate(st, G_CVD);
+    launch_stats_reset(a, 0, s);
+    launch_cells(a, MODE_CVD, st->grid.dtype_bytes, s);
+    launch_finish_extract(a, s);
+    a.cond = adapt_gate(st, G_DM);
+    launch_dm(a, st->grid.dtype_bytes, s);
+    a.cond = nullptr;
+    launch_adapt_end(a, hybrid, cfg->t_quality, cfg->t_amax, cfg->t_switch, s);
+    st->cur_pos ^= 1;
+    e = check_hip("trime_step_adaptive");
+    if (e) return e;
+  }
+  return TRIME_OK;
+}
+
 trime_status trime_quality(trime_state *st, void *stream) {
   trime_status e = bound_ok(st);
   if (e) return e;

@@ -15,6 +15,7 @@ namespace trime {
 constexpr int DM_BLOCK = 256;
 
 template <class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_sums(KArgs a) {
+  if (cond_off(a)) return;
   __shared__ double s1[DM_BLOCK / 64], s2[DM_BLOCK / 64];
   int64_t k = (int64_t)blockIdx.x * DM_BLOCK + threadIdx.x;
   double l2 = 0.0, m2 = 0.0;
@@ -53,6 +54,7 @@ template <class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_sums(KArgs a
 }
 
 __global__ __launch_bounds__(256) void k_dm_final(KArgs a, int nparts) {
+  if (cond_off(a)) return;
   __shared__ double s1[256], s2[256];
   double A = 0, B = 0;
   for (int q = threadIdx.x; q < nparts; q += 256) {
@@ -125,6 +127,7 @@ TRIME_D bool dm_point(const KArgs &a, int64_t k, int &moved, TreatCount &tc) {
 }
 
 template <class T, class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_force(KArgs a) {
+  if (cond_off(a)) return;
   int64_t k = (int64_t)blockIdx.x * DM_BLOCK + threadIdx.x;
   int moved = 0, replay = 0;
   TreatCount tc;
@@ -153,6 +156,7 @@ template <class T, class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_for
 }
 
 template <class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_force_replay(KArgs a) {
+  if (cond_off(a)) return;
   int nq = a.counters[CNT_QUEUE];
   for (int w = blockIdx.x * DM_BLOCK + threadIdx.x; w < nq; w += gridDim.x * DM_BLOCK) {
     int64_t k = a.queue[w];
@@ -166,6 +170,7 @@ template <class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_force_replay
 }
 
 __global__ void k_dm_flag(KArgs a) {
+  if (cond_off(a)) return;
   a.stats->retri_flag = a.stats->moved > 0 ? 1 : 0;
   a.stats->iterations++;
 }
@@ -177,6 +182,7 @@ __global__ void k_set_flag(KArgs a) { a.stats->retri_flag = 1; }
 void launch_set_flag(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, s, a); }
 
 __global__ void k_dm_begin(KArgs a) {
+  if (cond_off(a)) return;
   a.stats->moved = 0;
   a.counters[CNT_QUEUE] = 0;
 }
@@ -297,6 +303,7 @@ void launch_export_adj(const KArgs &a, int32_t *deg_o, int32_t *col_o, hipStream
 
 // Quality of the stored valid triangles with the current positions.
 __global__ __launch_bounds__(256) void k_quality(KArgs a) {
+  if (cond_off(a)) return;
   __shared__ int hist[40];
   for (int b = threadIdx.x; b < 40; b += 256) hist[b] = 0;
   __syncthreads();

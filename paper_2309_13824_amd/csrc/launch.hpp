@@ -57,6 +57,15 @@ void launch_quality(const KArgs &a, hipStream_t s);
 void launch_stats_reset(const KArgs &a, int full, hipStream_t s);
 void launch_finish_extract(const KArgs &a, hipStream_t s);
 void launch_set_flag(const KArgs &a, hipStream_t s);
+
+// adaptive runs (adapt.hip): the gates of the control block, one per group
+// of kernels of an iteration
+enum { G_BIN = 0, G_DMTRI = 1, G_DMQ = 2, G_CVD = 3, G_DM = 4, G_COPY = 5, G_RUN = 6 };
+void launch_adapt_init(const KArgs &a, int method, hipStream_t s);
+void launch_adapt_pre(const KArgs &a, hipStream_t s);
+void launch_adapt_end(const KArgs &a, int hybrid, double t_quality, double t_amax, double t_switch,
+                      hipStream_t s);
+const int32_t *adapt_gate(const trime_state *st, int g);
 int64_t grid_partials(int nx, int ny);
 void launch_grid_build(const GridPrims &g, int dtype_bytes, void *sdf, void *mu, uint8_t *cat,
                        float *hcell, trime_grid_scalars *scal, double *part, hipStream_t s);

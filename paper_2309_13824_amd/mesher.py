@@ -128,6 +128,12 @@ class Mesher:
     def step_hybrid(self, schedule):
         T.step_hybrid(self.state, schedule)
 
+    def step_adaptive(self, mode, max_iter, t_quality=0.001, t_amax=0.005, t_switch=0.0015):
+        """Adaptive run (termination tests, hybrid switch); returns the
+        control block: iterations run, switch and stop iterations, reason."""
+        T.step_adaptive(self.state, mode, max_iter, t_quality, t_amax, t_switch)
+        return self.stats_raw().as_dict()["adapt"]
+
     def quality(self):
         T.quality(self.state)
 

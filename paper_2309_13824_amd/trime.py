@@ -63,6 +63,13 @@ class Params(C.Structure):
                 ("trace_max_steps", C.c_int32), ("trace_bisect", C.c_int32), ("test2_mode", C.c_int32)]
 
 
+class AdaptCtl(C.Structure):
+    _fields_ = [("method", C.c_int32), ("stopped", C.c_int32), ("iters", C.c_int32), ("switch_iter", C.c_int32),
+                ("stop_iter", C.c_int32), ("reason", C.c_int32), ("moving", C.c_int32), ("have_prev", C.c_int32),
+                ("gate", C.c_int32 * 8), ("prev", C.c_double * 3), ("last", C.c_double * 3),
+                ("rel", C.c_double * 3)]
+
+
 class Stats(C.Structure):
     _fields_ = [("fp64_replays", C.c_int64), ("exact_points", C.c_int64), ("exact_calls", C.c_int64),
                 ("sos_calls", C.c_int64), ("overflow_points", C.c_int64), ("newton_fail", C.c_int64),
@@ -73,10 +80,14 @@ class Stats(C.Structure):
                 ("fac_mu", C.c_double), ("sum_sqrt_alpha", C.c_double), ("sum_sqrt_beta", C.c_double),
                 ("sum_q", C.c_double), ("max_alpha", C.c_double), ("nq", C.c_int64),
                 ("hist_beta", C.c_int64 * 40), ("work_candidates", C.c_int64), ("work_margins", C.c_int64),
-                ("work_cuts", C.c_int64), ("work_leaves", C.c_int64)]
+                ("work_cuts", C.c_int64), ("work_leaves", C.c_int64), ("adapt", AdaptCtl)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "hist_beta"}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("hist_beta", "adapt")}
+        a = self.adapt
+        d["adapt"] = {"method": a.method, "stopped": a.stopped, "iters": a.iters, "switch_iter": a.switch_iter,
+                      "stop_iter": a.stop_iter, "reason": a.reason, "last": tuple(a.last[:]),
+                      "rel": tuple(a.rel[:])}
         d["hist_beta"] = np.array(self.hist_beta[:], np.int64)
         nq = max(self.nq, 1)
         d["half_mean_alpha"] = (self.sum_sqrt_alpha / nq) ** 2
@@ -109,6 +120,15 @@ class State(C.Structure):
                 ("ev_cells", C.c_void_p * 2)]
 
 
+ADAPT_DM, ADAPT_CVD, ADAPT_HYBRID = 0, 1, 2
+STOP_NONE, STOP_QUALITY, STOP_MOVEMENT = 0, 1, 2
+
+
+class Adaptive(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("max_iter", C.c_int32), ("t_quality", C.c_double), ("t_amax", C.c_double),
+                ("t_switch", C.c_double)]
+
+
 class Schedule(C.Structure):
     _fields_ = [("nseg", C.c_int32), ("method", C.POINTER(C.c_int32)), ("iters", C.POINTER(C.c_int32))]
 
@@ -122,7 +142,8 @@ EXPORTED = ["trime_last_error", "trime_version", "trime_default_params", "trime_
             "trime_export_triangles", "trime_export_adjacency", "trime_bin_points", "trime_voronoi_cells",
             "trime_delaunay_extract", "trime_step_dm", "trime_step_cvd", "trime_step_hybrid",
             "trime_quality", "trime_stats_read", "trime_stats_check", "trime_autotune_workspace_bytes",
-            "trime_autotune", "trime_batch_graph_create", "trime_graph_launch", "trime_graph_destroy"]
+            "trime_autotune", "trime_batch_graph_create", "trime_graph_launch", "trime_graph_destroy",
+            "trime_step_adaptive"]
 
 _lib = None
 
@@ -246,6 +267,13 @@ def step_hybrid(state, schedule, stream=None):
     its = (C.c_int32 * len(schedule))(*[int(k) for _, k in schedule])
     sch = Schedule(len(schedule), meth, its)
     _check(lib().trime_step_hybrid(C.byref(state), C.byref(sch), _stream(stream)))
+
+
+def step_adaptive(state, mode, max_iter, t_quality=0.001, t_amax=0.005, t_switch=0.0015, stream=None):
+    """mode: "dm", "cvd" or "hybrid"; the outcome is in the stats (adapt)."""
+    m = {"dm": ADAPT_DM, "cvd": ADAPT_CVD, "hybrid": ADAPT_HYBRID}[mode]
+    cfg = Adaptive(m, int(max_iter), float(t_quality), float(t_amax), float(t_switch))
+    _check(lib().trime_step_adaptive(C.byref(state), C.byref(cfg), _stream(stream)))
 
 
 def quality(state, stream=None):

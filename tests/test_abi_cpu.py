@@ -83,6 +83,29 @@ def test_schedule_validation(T):
     assert L.trime_step_hybrid(C.byref(st), None, None) == 1
 
 
+def test_adaptive_configuration_rejected_on_host(T):
+    """Unbound state, null configuration, unknown mode, negative budget and
+    negative or NaN thresholds return TRIME_EINVAL before anything is
+    launched (the state below only looks bound: none of its pointers is ever
+    dereferenced on these paths)."""
+    L = T.lib(require_gpu=False)
+    st = T.State()
+    good = T.Adaptive(T.ADAPT_HYBRID, 10, 0.001, 0.005, 0.0015)
+    assert L.trime_step_adaptive(C.byref(st), C.byref(good), None) == 1
+    st.n = 10
+    st.grid = T.Grid(16, 16, 0.0, 0.0, 0.1, 0.1, 8)
+    st.sdf = st.mu = st.cat_grid = st.hcell = st.scal = 256
+    st.stats = 512
+    st.pos[0].x = 768
+    assert L.trime_step_adaptive(C.byref(st), None, None) == 1
+    for bad in (T.Adaptive(7, 10, 0.001, 0.005, 0.0015), T.Adaptive(T.ADAPT_DM, -1, 0.001, 0.005, 0.0015),
+                T.Adaptive(T.ADAPT_CVD, 10, -0.001, 0.005, 0.0015),
+                T.Adaptive(T.ADAPT_CVD, 10, 0.001, float("nan"), 0.0015),
+                T.Adaptive(T.ADAPT_HYBRID, 10, 0.001, 0.005, -1.0)):
+        assert L.trime_step_adaptive(C.byref(st), C.byref(bad), None) == 1
+        assert b"trime_step_adaptive" in L.trime_last_error()
+
+
 def test_stats_check_codes(T):
     L = T.lib(require_gpu=False)
     s = T.Stats()

@@ -1,0 +1,124 @@
+"""Adaptive runs on the GPU through the C ABI against the oracle's run of the
+same rule: termination on mesh quality or small movement (Sec. 6, Table 8)
+and the quality-driven switch of hybrid meshing (Sec. 4.2), decided on the
+device."""
+import numpy as np
+import pytest
+
+from paper_2309_13824_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+TQ, TA, TS = 0.001, 0.005, 0.0015  # Table 8
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2309_13824_amd import trime
+    trime.lib()
+    return trime
+
+
+def mesher(wl, prec, grid=None, **kw):
+    from paper_2309_13824_amd.mesher import Mesher
+    m = Mesher(wl, precision=prec, grid=grid, **kw)
+    m.load()
+    return m
+
+
+def h_of(og, x, y):
+    fx = np.floor((x - og.x0) * (1.0 / og.dx)).astype(int)
+    fy = np.floor((y - og.y0) * (1.0 / og.dy)).astype(int)
+    return og.hcell[fy * (og.nx - 1) + fx].astype(np.float64)
+
+
+def workload(name):
+    return I.disk() if name == "disk" else I.annulus(n=4000, grid_n=256)
+
+
+def decision_margin(info, mode):
+    """Smallest relative distance of a compared change to its threshold over
+    the oracle's run (a tiny one would make the decision depend on rounding)."""
+    m = np.inf
+    phase_dm = mode == "hybrid"
+    for k, h in enumerate(info["history"]):
+        if h["rel"] is None:
+            continue
+        if phase_dm:
+            m = min(m, abs(h["rel"][0] - TS) / TS)
+            if k == info["switch_iter"]:
+                phase_dm = False
+        else:
+            m = min(m, abs(h["rel"][0] - TQ) / TQ, abs(h["rel"][1] - TQ) / TQ, abs(h["rel"][2] - TA) / TA)
+    return m
+
+
+@pytest.mark.parametrize("name,mode", [("disk", "hybrid"), ("disk", "dm"), ("annulus", "cvd"),
+                                       ("annulus", "hybrid")])
+def test_adaptive_run_matches_oracle(orc, T, name, mode):
+    """FP64: the same iteration switches and the same one stops, for the same
+    reason, and the final points agree to FP64 rounding."""
+    wl = workload(name)
+    og = orc.build_grid(wl)
+    x, y, cat, info = orc.run_adaptive(og, wl.x, wl.y, mode, 200, TQ, TA, TS, nthreads=8)
+    assert info["stop_iter"] >= 0
+    assert decision_margin(info, mode) > 1e-6
+    m = mesher(wl, FP64, grid=og)
+    ad = m.step_adaptive(mode, 200, TQ, TA, TS)
+    print(name, mode, "oracle", {k: v for k, v in info.items() if k != "history"}, "gpu", ad, flush=True)
+    assert ad["iters"] == info["iters"]
+    assert ad["switch_iter"] == info["switch_iter"]
+    assert ad["stop_iter"] == info["stop_iter"] and ad["reason"] == info["reason"]
+    want = info["history"][-1]["quality"]
+    assert np.allclose(ad["last"], want, rtol=1e-9, atol=0), (ad["last"], want)
+    gx, gy, gc = m.points()
+    err = np.hypot(gx - x, gy - y) / h_of(og, x, y)
+    assert err.max() <= 1e-9, err.max()
+    assert np.array_equal(gc, cat)
+    assert m.stats_raw().error == 0
+
+
+def test_adaptive_run_in_fp32_stops_with_oracle_quality(orc, T):
+    """FP32 + FP64 replay: the run stops inside the budget, and the quality
+    it stops at is within 1% of the oracle's (trajectories of the two
+    precisions separate, so the iterations themselves are not compared)."""
+    wl = workload("annulus")
+    og = orc.build_grid(wl)
+    _, _, _, info = orc.run_adaptive(og, wl.x, wl.y, "hybrid", 200, TQ, TA, TS, nthreads=8)
+    m = mesher(wl, FP32, grid=og)
+    ad = m.step_adaptive("hybrid", 200, TQ, TA, TS)
+    assert ad["stop_iter"] >= 0 and ad["reason"] in (1, 2)
+    want = info["history"][-1]["quality"]
+    assert abs(ad["last"][0] - want[0]) <= 0.01 * want[0]
+    assert abs(ad["last"][1] - want[1]) <= 0.01 * want[1]
+
+
+def test_adaptive_run_replays_in_a_graph(orc, T):
+    """The run makes no host reads: captured in a HIP graph and replayed
+    (the points reloaded between replays, eager work on the side), every
+    replay equals the eager run bit for bit, outcome included."""
+    import torch
+    wl = workload("annulus")
+    og = orc.build_grid(wl)
+    eager = mesher(wl, FP32, grid=og)
+    want_ad = eager.step_adaptive("hybrid", 40, 0.004, 0.05, 0.01)
+    want = eager.points()
+    m = mesher(wl, FP32, grid=og)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        T.step_adaptive(m.state, "hybrid", 40, 0.004, 0.05, 0.01, stream=s)
+    # 40 iterations: the host-side buffer parity is back where it started
+    for r in range(3):
+        m.load()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        x, y, c = m.points()
+        assert np.array_equal(x, want[0]) and np.array_equal(y, want[1]), r
+        assert np.array_equal(c, want[2]), r
+        ad = m.stats_raw().as_dict()["adapt"]
+        assert (ad["iters"], ad["switch_iter"], ad["stop_iter"], ad["reason"]) == \
+            (want_ad["iters"], want_ad["switch_iter"], want_ad["stop_iter"], want_ad["reason"]), r
