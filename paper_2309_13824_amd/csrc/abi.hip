@@ -11,6 +11,10 @@
 
 using namespace trime;
 
+namespace trime {
+thread_local std::vector<LaunchRec> *g_launch_log = nullptr;
+}
+
 static thread_local char g_err[512] = "";
 
 static trime_status fail(trime_status st, const char *msg) {

@@ -18,19 +18,31 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     p[i] = v;
 }
 
-__global__ void k_fill_cond(KArgs a, int32_t *p, int64_t n) {
-  if (cond_off(a)) return;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0;
-}
+// Zeroes the bin fill counts (grid-stride).
+struct FillCond {
+  struct Args {
+    KArgs a;
+    int32_t *p;
+    int64_t n;
+  };
+  static constexpr int BLOCK = 256;
+  TRIME_D static void run(const Args &A, Blk b) {
+    if (cond_off(A.a)) return;
+    for (int64_t i = (int64_t)b.id * BLOCK + threadIdx.x; i < A.n; i += (int64_t)b.n * BLOCK) A.p[i] = 0;
+  }
+};
 
 // Keys and ranks within the bins.  The points arrive in the previous slot
 // order, so runs of equal keys fill a wavefront: the first lane of each run
 // takes the run's ranks with one atomic and hands them out.
-__global__ void k_bin_keys(KArgs a) {
+struct BinKeys {
+  using Args = KArgs;
+  static constexpr int BLOCK = 256;
+  TRIME_D static void run(const KArgs &a, Blk blk);
+};
+TRIME_D void BinKeys::run(const KArgs &a, Blk blk) {
   if (cond_off(a)) return;
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t k = (int64_t)blk.id * BLOCK + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const bool valid = k < a.n;
   int key = -1;
@@ -81,12 +93,27 @@ __device__ __forceinline__ int block_excl_scan(int v, int *smem, int &total) {
   return before;
 }
 
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tiles(const int32_t *in, int32_t *out,
-                                                            int64_t n, int32_t *tile_sums,
-                                                            const int32_t *cond) {
+// The three passes of an exclusive scan share one argument set.
+struct ScanArgs {
+  const int32_t *in;
+  int32_t *out;
+  int64_t n, nt;
+  int32_t *sums;  // nt + 1 tile sums
+  const int32_t *cond;
+};
+
+struct ScanTiles {
+  using Args = ScanArgs;
+  static constexpr int BLOCK = SCAN_BLOCK;
+  TRIME_D static void run(const ScanArgs &A, Blk blk);
+};
+TRIME_D void ScanTiles::run(const ScanArgs &A, Blk blk) {
   __shared__ int smem[SCAN_BLOCK / 64];
-  if (cond && *cond == 0) return;
-  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  if (A.cond && gld(A.cond, 0) == 0) return;
+  const int32_t *in = A.in;
+  int32_t *out = A.out;
+  const int64_t n = A.n;
+  int64_t base = (int64_t)blk.id * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   int v[SCAN_ITEMS];
   int s = 0;
 #pragma unroll
@@ -101,13 +128,20 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tiles(const int32_t *in, in
     if (base + q < n) out[base + q] = before;
     before += v[q];
   }
-  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+  if (threadIdx.x == 0) A.sums[blk.id] = total;
 }
 
 // Single block: exclusive scan of the tile sums (any count), total at [nt].
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_sums(int32_t *sums, int64_t nt, const int32_t *cond) {
+struct ScanSums {
+  using Args = ScanArgs;
+  static constexpr int BLOCK = SCAN_BLOCK;
+  TRIME_D static void run(const ScanArgs &A, Blk blk);
+};
+TRIME_D void ScanSums::run(const ScanArgs &A, Blk) {
   __shared__ int smem[SCAN_BLOCK / 64];
-  if (cond && *cond == 0) return;
+  if (A.cond && gld(A.cond, 0) == 0) return;
+  int32_t *sums = A.sums;
+  const int64_t nt = A.nt;
   int carry = 0;
   for (int64_t base = 0; base < nt; base += SCAN_BLOCK) {
     int64_t i = base + threadIdx.x;
@@ -120,17 +154,19 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_sums(int32_t *sums, int64_t
   if (threadIdx.x == 0) sums[nt] = carry;
 }
 
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_add(int32_t *out, int64_t n,
-                                                          const int32_t *sums, int64_t nt,
-                                                          const int32_t *cond) {
-  if (cond && *cond == 0) return;
-  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-  int add = sums[blockIdx.x];
+struct ScanAdd {
+  using Args = ScanArgs;
+  static constexpr int BLOCK = SCAN_BLOCK;
+  TRIME_D static void run(const ScanArgs &A, Blk blk) {
+    if (A.cond && gld(A.cond, 0) == 0) return;
+    int64_t base = (int64_t)blk.id * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int add = A.sums[blk.id];
 #pragma unroll
-  for (int q = 0; q < SCAN_ITEMS; q++)
-    if (base + q < n) out[base + q] += add;
-  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[nt];
-}
+    for (int q = 0; q < SCAN_ITEMS; q++)
+      if (base + q < A.n) A.out[base + q] += add;
+    if (blk.id == 0 && threadIdx.x == 0) A.out[A.n] = A.sums[A.nt];
+  }
+};
 
 // Exclusive scan of in[0..n) into out[0..n], out[n] = total; skipped when
 // cond is set and *cond == 0.
@@ -138,36 +174,49 @@ void scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStrea
               const int32_t *cond) {
   int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
   if (nt == 0) nt = 1;
-  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(SCAN_BLOCK), 0, s, in, out, n, tmp, cond);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BLOCK), 0, s, tmp, nt, cond);
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(SCAN_BLOCK), 0, s, out, n, tmp, nt, cond);
+  ScanArgs A{in, out, n, nt, tmp, cond};
+  launch<ScanTiles>(A, (uint32_t)nt, s);
+  launch<ScanSums>(A, 1, s);
+  launch<ScanAdd>(A, (uint32_t)nt, s);
 }
 
 size_t scan_tmp_ints(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) + 2; }
 
-__global__ void k_bin_scatter(KArgs a) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.n || cond_off(a)) return;
-  a.perm[a.bin_start[a.key[k]] + a.rank[k]] = (int)k;
-}
+struct BinScatter {
+  using Args = KArgs;
+  static constexpr int BLOCK = 256;
+  TRIME_D static void run(const KArgs &a, Blk blk) {
+    int64_t k = (int64_t)blk.id * BLOCK + threadIdx.x;
+    if (k >= a.n || cond_off(a)) return;
+    a.perm[a.bin_start[a.key[k]] + a.rank[k]] = (int)k;
+  }
+};
 
 // One thread per bin: order its entries by their previous slot (insertion
 // sort), so the new slot order is (key, previous slot): deterministic,
 // whatever order the atomics took.
-__global__ void k_bin_sort(KArgs a, int64_t nkeys) {
-  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nkeys || cond_off(a)) return;
-  int s0 = a.bin_start[b], s1 = a.bin_start[b + 1];
-  for (int s = s0 + 1; s < s1; s++) {
-    int v = a.perm[s];
-    int t = s;
-    while (t > s0 && a.perm[t - 1] > v) {
-      a.perm[t] = a.perm[t - 1];
-      t--;
+struct BinSort {
+  struct Args {
+    KArgs a;
+    int64_t nkeys;
+  };
+  static constexpr int BLOCK = 256;
+  TRIME_D static void run(const Args &A, Blk blk) {
+    const KArgs &a = A.a;
+    int64_t b = (int64_t)blk.id * BLOCK + threadIdx.x;
+    if (b >= A.nkeys || cond_off(a)) return;
+    int s0 = a.bin_start[b], s1 = a.bin_start[b + 1];
+    for (int s = s0 + 1; s < s1; s++) {
+      int v = a.perm[s];
+      int t = s;
+      while (t > s0 && a.perm[t - 1] > v) {
+        a.perm[t] = a.perm[t - 1];
+        t--;
+      }
+      a.perm[t] = v;
     }
-    a.perm[t] = v;
   }
-}
+};
 
 // Gather every per-point array into the new slot order (writes the other
 // buffer set); the positions of the last triangulation become the current
@@ -175,8 +224,18 @@ __global__ void k_bin_sort(KArgs a, int64_t nkeys) {
 // conditional binning without work copies every array in place order
 // instead (the buffer sets still swap), keeping the last-triangulation
 // positions and spans.
-__global__ void k_bin_gather(KArgs a, GatherArgs g) {
-  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+struct BinGather {
+  struct Args {
+    KArgs a;
+    GatherArgs g;
+  };
+  static constexpr int BLOCK = 256;
+  TRIME_D static void run(const Args &A, Blk blk);
+};
+TRIME_D void BinGather::run(const Args &A, Blk blk) {
+  const KArgs &a = A.a;
+  const GatherArgs &g = A.g;
+  int64_t s = (int64_t)blk.id * BLOCK + threadIdx.x;
   if (s >= a.n) return;
   if (cond_off(a)) {
     g.xo[s] = g.x[s];
@@ -206,35 +265,50 @@ __global__ void k_bin_gather(KArgs a, GatherArgs g) {
 // the most bins), then all others, each group in slot order.  Heavy points
 // then share wavefronts and start first instead of holding back 64-point
 // wavefronts of light ones.
-__global__ void k_order_flags(KArgs a, const uint8_t *cat) {
-  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.n || cond_off(a)) return;
-  a.key[s] = cat[s] == TRIME_CAT_BOUNDARY ? 1 : 0;
-}
+struct OrderFlags {
+  struct Args {
+    KArgs a;
+    const uint8_t *cat;
+  };
+  static constexpr int BLOCK = 256;
+  TRIME_D static void run(const Args &A, Blk blk) {
+    const KArgs &a = A.a;
+    int64_t s = (int64_t)blk.id * BLOCK + threadIdx.x;
+    if (s >= a.n || cond_off(a)) return;
+    a.key[s] = A.cat[s] == TRIME_CAT_BOUNDARY ? 1 : 0;
+  }
+};
 
-__global__ void k_order_scatter(KArgs a) {
-  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.n || cond_off(a)) return;
-  int before = a.perm[s];  // heavy slots before s
-  int heavy = a.perm[a.n];
-  if (s == 0) a.counters[CNT_HEAVY] = heavy;
-  int64_t w = a.key[s] ? before : heavy + (s - before);
-  a.order[w] = (int)s;
-}
+struct OrderScatter {
+  using Args = KArgs;
+  static constexpr int BLOCK = 256;
+  TRIME_D static void run(const KArgs &a, Blk blk) {
+    int64_t s = (int64_t)blk.id * BLOCK + threadIdx.x;
+    if (s >= a.n || cond_off(a)) return;
+    int before = a.perm[s];  // heavy slots before s
+    int heavy = a.perm[a.n];
+    if (s == 0) a.counters[CNT_HEAVY] = heavy;
+    int64_t w = a.key[s] ? before : heavy + (s - before);
+    a.order[w] = (int)s;
+  }
+};
 
 void launch_bin(const KArgs &a, const GatherArgs &g, int64_t nkeys, int32_t *scan_tmp,
                 hipStream_t s) {
   const int B = 256;
-  int nb = (int)((a.n + B - 1) / B);
-  hipLaunchKernelGGL(k_fill_cond, dim3(1024), dim3(256), 0, s, a, a.bin_fill, nkeys);
-  if (nb) hipLaunchKernelGGL(k_bin_keys, dim3(nb), dim3(B), 0, s, a);
+  const uint32_t nb = (uint32_t)((a.n + B - 1) / B);
+  // the fill is grid-stride: a grid that grows with the bin count, at most 1024
+  const int64_t nf0 = (nkeys + 4 * B - 1) / (4 * B);
+  const uint32_t nf = (uint32_t)(nf0 < 1024 ? nf0 : 1024);
+  launch<FillCond>(FillCond::Args{a, a.bin_fill, nkeys}, nf, s);
+  launch<BinKeys>(a, nb, s);
   scan_i32(a.bin_fill, a.bin_start, nkeys, scan_tmp, s, a.cond);
-  if (nb) hipLaunchKernelGGL(k_bin_scatter, dim3(nb), dim3(B), 0, s, a);
-  hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((nkeys + B - 1) / B)), dim3(B), 0, s, a, nkeys);
-  if (nb) hipLaunchKernelGGL(k_bin_gather, dim3(nb), dim3(B), 0, s, a, g);
-  if (nb) hipLaunchKernelGGL(k_order_flags, dim3(nb), dim3(B), 0, s, a, (const uint8_t *)g.cato);
+  launch<BinScatter>(a, nb, s);
+  launch<BinSort>(BinSort::Args{a, nkeys}, (uint32_t)((nkeys + B - 1) / B), s);
+  launch<BinGather>(BinGather::Args{a, g}, nb, s);
+  launch<OrderFlags>(OrderFlags::Args{a, (const uint8_t *)g.cato}, nb, s);
   scan_i32(a.key, a.perm, a.n, scan_tmp, s, a.cond);
-  if (nb) hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(B), 0, s, a);
+  launch<OrderScatter>(a, nb, s);
 }
 
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {

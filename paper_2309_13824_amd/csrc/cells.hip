@@ -1438,106 +1438,120 @@ TRIME_D void push(const KArgs &a, int which, int64_t k, int why) {
 // Fast kernel: one point per lane, slots in the processing order.  Points it
 // cannot finish (an undecided decision, a polygon beyond its capacity, the
 // grid box within reach) go to the FP64 replay queue.
-template <class T, class G, int MODE, int VMAX, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_cells(KArgs a) {
-  if (cond_off(a)) return;
-  __shared__ VRec<T> P[VMAX][BLOCK];
-  __shared__ int hist[40];
-  zero_hist<BLOCK>(hist);
-  LaneStats st;
-  int64_t w = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (w < a.n && TRIME_HEAVY_WAVE && w < gld(a.counters, (int64_t)CNT_HEAVY)) {
-    // points on the boundary (first in the order) scan the most bins: one
-    // wavefront per point loads their candidates 64 at a time
-    int64_t k = gld(a.order, w);
-    push(a, 1, k, WHY_HEAVY);
-  } else if (w < a.n) {
-    int64_t k = gld(a.order, w);
-    Lane<T, G, MODE, false, VMAX, BLOCK> L(a, P, threadIdx.x, k);
-    if (!L.run(st, hist)) {
-      push(a, 1, k, L.why);
-      st.replays++;
-      if (L.why == WHY_POLY) st.overflow++;
+template <class T, class G, int MODE, int VMAX, int B> struct Cells {
+  using Args = KArgs;
+  static constexpr int BLOCK = B;
+  TRIME_D static void run(const KArgs &a, Blk blk) {
+    if (cond_off(a)) return;
+    __shared__ VRec<T> P[VMAX][B];
+    __shared__ int hist[40];
+    zero_hist<B>(hist);
+    LaneStats st;
+    int64_t w = (int64_t)blk.id * B + threadIdx.x;
+    if (w < a.n && TRIME_HEAVY_WAVE && w < gld(a.counters, (int64_t)CNT_HEAVY)) {
+      // points on the boundary (first in the order) scan the most bins: one
+      // wavefront per point loads their candidates 64 at a time
+      int64_t k = gld(a.order, w);
+      push(a, 1, k, WHY_HEAVY);
+    } else if (w < a.n) {
+      int64_t k = gld(a.order, w);
+      Lane<T, G, MODE, false, VMAX, B> L(a, P, threadIdx.x, k);
+      if (!L.run(st, hist)) {
+        push(a, 1, k, L.why);
+        st.replays++;
+        if (L.why == WHY_POLY) st.overflow++;
+      }
     }
+    flush_stats<B>(a, st, hist);
   }
-  flush_stats<BLOCK>(a, st, hist);
-}
+};
 
 // The passes after the fast kernel, in one launch so that they overlap:
-//  - blocks [0, WAVE_GRID): FP64 replay of the queue, one wavefront per point
+//  - blocks [0, wgrid): FP64 replay of the queue, one wavefront per point
 //    (grid-stride): the ring scan, the tests, triangles and quadrature are
 //    shared by the 64 lanes.  Points FP64 cannot decide go on to the exact
 //    queue.
-//  - blocks [WAVE_GRID, WAVE_GRID + CENTROID_GRID) (CVD): the deferred FP32
-//    centroids, one lane per point: FP64 vertices from the stored
-//    constraints, FP64 CVD target and treatment.  The cells and triangles of
-//    these points were committed by the fast kernel.
-template <class G, int MODE, int VMAX, int WGRID>
-__global__ __launch_bounds__(64) void k_cells_post(KArgs a) {
-  if (cond_off(a)) return;
-  constexpr int V = CQ_STRIDE - 1;
-  __shared__ VRec<double> P[VMAX][1];
-  __shared__ VRec<double> PC[V][64];
-  __shared__ int hist[40];
-  __shared__ int sh_s0[64], sh_incl[64];
-  __shared__ double sh_ro[8];
-  zero_hist<64>(hist);
-  LaneStats st;
-  const int lane = threadIdx.x;
-  if ((int)blockIdx.x < WGRID) {
-    int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE);
-    for (int64_t w = blockIdx.x; w < nq; w += WGRID) {
-      int64_t k = gld(a.queue, w);
-      Lane<double, G, MODE, false, VMAX, 1> L(a, P, 0, k);
-      bool ok = L.begin();
-      if (ok) {
-        L.scan_wave(lane, sh_s0, sh_incl, sh_ro);
-        ok = !L.why;
+//  - the blocks after them (CVD): the deferred FP32 centroids, one lane per
+//    point: FP64 vertices from the stored constraints, FP64 CVD target and
+//    treatment.  The cells and triangles of these points were committed by
+//    the fast kernel.
+template <class G, int MODE, int VMAX> struct CellsPost {
+  struct Args {
+    KArgs a;
+    int32_t wgrid;
+  };
+  static constexpr int BLOCK = 64;
+  TRIME_D static void run(const Args &A, Blk blk) {
+    const KArgs &a = A.a;
+    if (cond_off(a)) return;
+    constexpr int V = CQ_STRIDE - 1;
+    __shared__ VRec<double> P[VMAX][1];
+    __shared__ VRec<double> PC[V][64];
+    __shared__ int hist[40];
+    __shared__ int sh_s0[64], sh_incl[64];
+    __shared__ double sh_ro[8];
+    zero_hist<64>(hist);
+    LaneStats st;
+    const int lane = threadIdx.x;
+    const int64_t wg = A.wgrid;
+    if ((int64_t)blk.id < wg) {
+      int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE);
+      for (int64_t w = blk.id; w < nq; w += wg) {
+        int64_t k = gld(a.queue, w);
+        Lane<double, G, MODE, false, VMAX, 1> L(a, P, 0, k);
+        bool ok = L.begin();
+        if (ok) {
+          L.scan_wave(lane, sh_s0, sh_incl, sh_ro);
+          ok = !L.why;
+        }
+        if (ok) ok = L.finish_wave(lane, st, hist);
+        if (!ok && lane == 0) push(a, 2, k, L.why);
+        __syncthreads();
       }
-      if (ok) ok = L.finish_wave(lane, st, hist);
-      if (!ok && lane == 0) push(a, 2, k, L.why);
-      __syncthreads();
+    } else if constexpr (MODE == MODE_CVD) {
+      const int64_t cb = (int64_t)blk.id - wg, cg = (int64_t)blk.n - wg;
+      int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE3);
+      for (int64_t w = cb * 64 + lane; w < nq; w += cg * 64) {
+        int64_t k = gld(a.queue3, w);
+        Lane<double, G, MODE_CVD, false, V, 64> L(a, PC, lane, k);
+        L.centroid_replay(st, w * CQ_STRIDE);
+      }
     }
-  } else if constexpr (MODE == MODE_CVD) {
-    const int64_t cb = (int64_t)blockIdx.x - WGRID, cg = (int64_t)gridDim.x - WGRID;
-    int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE3);
-    for (int64_t w = cb * 64 + lane; w < nq; w += cg * 64) {
-      int64_t k = gld(a.queue3, w);
-      Lane<double, G, MODE_CVD, false, V, 64> L(a, PC, lane, k);
-      L.centroid_replay(st, w * CQ_STRIDE);
-    }
+    flush_stats<64>(a, st, hist);
   }
-  flush_stats<64>(a, st, hist);
-}
+};
 
 // Exact replay of the second queue.
-template <class G, int MODE, int VMAX, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_cells_exact(KArgs a) {
-  if (cond_off(a)) return;
-  __shared__ VRec<double> P[VMAX][BLOCK];
-  __shared__ int hist[40];
-  zero_hist<BLOCK>(hist);
-  LaneStats st;
-  int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE2);
-  for (int64_t w = (int64_t)blockIdx.x * BLOCK + threadIdx.x; w < nq; w += (int64_t)gridDim.x * BLOCK) {
-    int64_t k = gld(a.queue2, w);
-    Lane<double, G, MODE, true, VMAX, BLOCK> L(a, P, threadIdx.x, k);
-    if (!L.run(st, hist)) {  // beyond the polygon capacity, or off the grid: keep the point
-      st.overflow++;
-      atomicOr(&a.counters[CNT_ERR], ERR_POLY_CAP);
-      if constexpr (MODE == MODE_CVD) {
-        gst(a.xn, k, gld(a.x, k));
-        gst(a.yn, k, gld(a.y, k));
-        gst(a.catn, k, gld(a.cat, k));
-        gst(a.dprevn, k, 0.0);
+template <class G, int MODE, int VMAX, int B> struct CellsExact {
+  using Args = KArgs;
+  static constexpr int BLOCK = B;
+  TRIME_D static void run(const KArgs &a, Blk blk) {
+    if (cond_off(a)) return;
+    __shared__ VRec<double> P[VMAX][B];
+    __shared__ int hist[40];
+    zero_hist<B>(hist);
+    LaneStats st;
+    int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE2);
+    for (int64_t w = (int64_t)blk.id * B + threadIdx.x; w < nq; w += (int64_t)blk.n * B) {
+      int64_t k = gld(a.queue2, w);
+      Lane<double, G, MODE, true, VMAX, B> L(a, P, threadIdx.x, k);
+      if (!L.run(st, hist)) {  // beyond the polygon capacity, or off the grid: keep the point
+        st.overflow++;
+        atomicOr(&a.counters[CNT_ERR], ERR_POLY_CAP);
+        if constexpr (MODE == MODE_CVD) {
+          gst(a.xn, k, gld(a.x, k));
+          gst(a.yn, k, gld(a.y, k));
+          gst(a.catn, k, gld(a.cat, k));
+          gst(a.dprevn, k, 0.0);
+        }
+        if constexpr (MODE == MODE_EXTRACT) gst(a.deg, k, 0);
+        if constexpr (MODE != MODE_CELLS) gst(a.tri_n, k, 0);
+        if constexpr (MODE == MODE_CELLS) gst(a.cell_n, (int64_t)gld(a.id, k), -1);
       }
-      if constexpr (MODE == MODE_EXTRACT) gst(a.deg, k, 0);
-      if constexpr (MODE != MODE_CELLS) gst(a.tri_n, k, 0);
-      if constexpr (MODE == MODE_CELLS) gst(a.cell_n, (int64_t)gld(a.id, k), -1);
     }
+    flush_stats<B>(a, st, hist);
   }
-  flush_stats<BLOCK>(a, st, hist);
-}
+};
 
 // ------------------------------------------------------------ launchers --
 constexpr int FAST_BLOCK = 128;
@@ -1552,14 +1566,21 @@ constexpr int WAVE_GRID = TRIME_HEAVY_WAVE ? 4096 : 1024;
 constexpr int CENTROID_GRID = 256;
 static_assert(FAST_VMAX < CQ_STRIDE, "a deferred cell must fit its queue entry");
 
+static int64_t clamp64(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// The queue passes get grids that grow with the point count (their queues
+// hold a small fraction of the points), up to the sizes that fill the chip.
 template <class T, class G, int MODE> static void launch_mode(const KArgs &a, hipStream_t s) {
-  int nb = (int)((a.n + FAST_BLOCK - 1) / FAST_BLOCK);
-  if (a.ev0) (void)hipEventRecord((hipEvent_t)a.ev0, s);
-  if (nb > 0) hipLaunchKernelGGL((k_cells<T, G, MODE, FAST_VMAX, FAST_BLOCK>), dim3(nb), dim3(FAST_BLOCK), 0, s, a);
-  if (a.ev1) (void)hipEventRecord((hipEvent_t)a.ev1, s);
-  const int post = WAVE_GRID + (MODE == MODE_CVD && sizeof(T) == 4 ? CENTROID_GRID : 0);
-  hipLaunchKernelGGL((k_cells_post<G, MODE, WAVE_VMAX, WAVE_GRID>), dim3(post), dim3(64), 0, s, a);
-  hipLaunchKernelGGL((k_cells_exact<G, MODE, REPLAY_VMAX, REPLAY_BLOCK>), dim3(64), dim3(REPLAY_BLOCK), 0, s, a);
+  const uint32_t nb = (uint32_t)((a.n + FAST_BLOCK - 1) / FAST_BLOCK);
+  const bool rec = g_launch_log != nullptr;
+  if (a.ev0 && !rec) (void)hipEventRecord((hipEvent_t)a.ev0, s);
+  launch<Cells<T, G, MODE, FAST_VMAX, FAST_BLOCK>>(a, nb, s);
+  if (a.ev1 && !rec) (void)hipEventRecord((hipEvent_t)a.ev1, s);
+  const int wgrid = (int)clamp64(a.n / 512, 8, WAVE_GRID);
+  const int cgrid = (MODE == MODE_CVD && sizeof(T) == 4) ? (int)clamp64(a.n / 2048, 4, CENTROID_GRID) : 0;
+  using Post = CellsPost<G, MODE, WAVE_VMAX>;
+  launch<Post>(typename Post::Args{a, wgrid}, (uint32_t)(wgrid + cgrid), s);
+  launch<CellsExact<G, MODE, REPLAY_VMAX, REPLAY_BLOCK>>(a, (uint32_t)clamp64(a.n / 8192, 2, 64), s);
 }
 
 template <class G> static void launch_g(const KArgs &a, int mode, hipStream_t s) {

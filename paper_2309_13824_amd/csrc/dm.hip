@@ -14,10 +14,15 @@ namespace trime {
 
 constexpr int DM_BLOCK = 256;
 
-template <class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_sums(KArgs a) {
+template <class G> struct DmSums {
+  using Args = KArgs;
+  static constexpr int BLOCK = DM_BLOCK;
+  TRIME_D static void run(const KArgs &a, Blk blk);
+};
+template <class G> TRIME_D void DmSums<G>::run(const KArgs &a, Blk blk) {
   if (cond_off(a)) return;
   __shared__ double s1[DM_BLOCK / 64], s2[DM_BLOCK / 64];
-  int64_t k = (int64_t)blockIdx.x * DM_BLOCK + threadIdx.x;
+  int64_t k = (int64_t)blk.id * DM_BLOCK + threadIdx.x;
   double l2 = 0.0, m2 = 0.0;
   if (k < a.n) {
     double px = a.x[k], py = a.y[k];
@@ -48,12 +53,22 @@ template <class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_sums(KArgs a
       A += s1[q];
       B += s2[q];
     }
-    a.partials[2 * blockIdx.x] = A;
-    a.partials[2 * blockIdx.x + 1] = B;
+    a.partials[2 * blk.id] = A;
+    a.partials[2 * blk.id + 1] = B;
   }
 }
 
-__global__ __launch_bounds__(256) void k_dm_final(KArgs a, int nparts) {
+struct DmFinal {
+  struct Args {
+    KArgs a;
+    int32_t nparts;
+  };
+  static constexpr int BLOCK = 256;
+  TRIME_D static void run(const Args &A_, Blk blk);
+};
+TRIME_D void DmFinal::run(const Args &A_, Blk) {
+  const KArgs &a = A_.a;
+  const int nparts = A_.nparts;
   if (cond_off(a)) return;
   __shared__ double s1[256], s2[256];
   double A = 0, B = 0;
@@ -126,9 +141,14 @@ TRIME_D bool dm_point(const KArgs &a, int64_t k, int &moved, TreatCount &tc) {
   return true;
 }
 
-template <class T, class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_force(KArgs a) {
+template <class T, class G> struct DmForce {
+  using Args = KArgs;
+  static constexpr int BLOCK = DM_BLOCK;
+  TRIME_D static void run(const KArgs &a, Blk blk);
+};
+template <class T, class G> TRIME_D void DmForce<T, G>::run(const KArgs &a, Blk blk) {
   if (cond_off(a)) return;
-  int64_t k = (int64_t)blockIdx.x * DM_BLOCK + threadIdx.x;
+  int64_t k = (int64_t)blk.id * DM_BLOCK + threadIdx.x;
   int moved = 0, replay = 0;
   TreatCount tc;
   if (k < a.n) {
@@ -155,10 +175,15 @@ template <class T, class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_for
   }
 }
 
-template <class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_force_replay(KArgs a) {
+template <class G> struct DmForceReplay {
+  using Args = KArgs;
+  static constexpr int BLOCK = DM_BLOCK;
+  TRIME_D static void run(const KArgs &a, Blk blk);
+};
+template <class G> TRIME_D void DmForceReplay<G>::run(const KArgs &a, Blk blk) {
   if (cond_off(a)) return;
   int nq = a.counters[CNT_QUEUE];
-  for (int w = blockIdx.x * DM_BLOCK + threadIdx.x; w < nq; w += gridDim.x * DM_BLOCK) {
+  for (int w = blk.id * DM_BLOCK + threadIdx.x; w < nq; w += blk.n * DM_BLOCK) {
     int64_t k = a.queue[w];
     int moved = 0;
     TreatCount tc;
@@ -169,35 +194,51 @@ template <class G> __global__ __launch_bounds__(DM_BLOCK) void k_dm_force_replay
   }
 }
 
-__global__ void k_dm_flag(KArgs a) {
-  if (cond_off(a)) return;
-  a.stats->retri_flag = a.stats->moved > 0 ? 1 : 0;
-  a.stats->iterations++;
-}
+struct DmFlag {
+  using Args = KArgs;
+  static constexpr int BLOCK = 64;
+  TRIME_D static void run(const KArgs &a, Blk) {
+    if (cond_off(a) || threadIdx.x != 0) return;
+    a.stats->retri_flag = a.stats->moved > 0 ? 1 : 0;
+    a.stats->iterations++;
+  }
+};
 
 // Sets the re-triangulation flag (the first iteration of a segment, or
 // every iteration when asked to).
-__global__ void k_set_flag(KArgs a) { a.stats->retri_flag = 1; }
+struct SetFlag {
+  using Args = KArgs;
+  static constexpr int BLOCK = 64;
+  TRIME_D static void run(const KArgs &a, Blk) {
+    if (threadIdx.x == 0) a.stats->retri_flag = 1;
+  }
+};
 
-void launch_set_flag(const KArgs &a, hipStream_t s) { hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, s, a); }
+void launch_set_flag(const KArgs &a, hipStream_t s) { launch<SetFlag>(a, 1, s); }
 
-__global__ void k_dm_begin(KArgs a) {
-  if (cond_off(a)) return;
-  a.stats->moved = 0;
-  a.counters[CNT_QUEUE] = 0;
-}
+struct DmBegin {
+  using Args = KArgs;
+  static constexpr int BLOCK = 64;
+  TRIME_D static void run(const KArgs &a, Blk) {
+    if (cond_off(a) || threadIdx.x != 0) return;
+    a.stats->moved = 0;
+    a.counters[CNT_QUEUE] = 0;
+  }
+};
 
 template <class G> static void launch_dm_g(const KArgs &a, hipStream_t s) {
-  int nb = (int)((a.n + DM_BLOCK - 1) / DM_BLOCK);
-  hipLaunchKernelGGL(k_dm_begin, dim3(1), dim3(1), 0, s, a);
-  hipLaunchKernelGGL(k_dm_sums<G>, dim3(nb), dim3(DM_BLOCK), 0, s, a);
-  hipLaunchKernelGGL(k_dm_final, dim3(1), dim3(256), 0, s, a, nb);
+  const uint32_t nb = (uint32_t)((a.n + DM_BLOCK - 1) / DM_BLOCK);
+  launch<DmBegin>(a, 1, s);
+  launch<DmSums<G>>(a, nb, s);
+  launch<DmFinal>(DmFinal::Args{a, (int32_t)nb}, 1, s);
   if (a.precision == TRIME_FP32)
-    hipLaunchKernelGGL((k_dm_force<float, G>), dim3(nb), dim3(DM_BLOCK), 0, s, a);
+    launch<DmForce<float, G>>(a, nb, s);
   else
-    hipLaunchKernelGGL((k_dm_force<double, G>), dim3(nb), dim3(DM_BLOCK), 0, s, a);
-  hipLaunchKernelGGL(k_dm_force_replay<G>, dim3(64), dim3(DM_BLOCK), 0, s, a);
-  hipLaunchKernelGGL(k_dm_flag, dim3(1), dim3(1), 0, s, a);
+    launch<DmForce<double, G>>(a, nb, s);
+  // the replay queue holds the few points an FP32 decision left open
+  const int64_t nr = a.n / 16384;
+  launch<DmForceReplay<G>>(a, (uint32_t)(nr < 2 ? 2 : (nr > 64 ? 64 : nr)), s);
+  launch<DmFlag>(a, 1, s);
 }
 
 void launch_dm(const KArgs &a, int grid_bytes, hipStream_t s) {
@@ -352,7 +393,17 @@ __global__ __launch_bounds__(256) void k_quality(KArgs a) {
 }
 
 // Clears the quality part of the stats (before an extraction / quality pass).
-__global__ void k_stats_reset_quality(KArgs a, int full) {
+struct StatsReset {
+  struct Args {
+    KArgs a;
+    int32_t full;
+  };
+  static constexpr int BLOCK = 64;
+  TRIME_D static void run(const Args &A, Blk);
+};
+TRIME_D void StatsReset::run(const Args &A, Blk) {
+  const KArgs &a = A.a;
+  const int full = A.full;
   if (cond_off(a)) return;
   trime_stats *S = a.stats;
   int t = threadIdx.x;
@@ -393,26 +444,28 @@ __global__ void k_stats_reset_quality(KArgs a, int full) {
 }
 
 void launch_stats_reset(const KArgs &a, int full, hipStream_t s) {
-  hipLaunchKernelGGL(k_stats_reset_quality, dim3(1), dim3(64), 0, s, a, full);
+  launch<StatsReset>(StatsReset::Args{a, full}, 1, s);
 }
 
 void launch_quality(const KArgs &a, hipStream_t s) {
   int nb = (int)((a.n + 255) / 256);
-  hipLaunchKernelGGL(k_stats_reset_quality, dim3(1), dim3(64), 0, s, a, 0);
+  launch<StatsReset>(StatsReset::Args{a, 0}, 1, s);
   if (nb) hipLaunchKernelGGL(k_quality, dim3(nb), dim3(256), 0, s, a);
 }
 
 // Copies the error bits of the counters into the stats and counts an
 // extraction.
-__global__ void k_finish_extract(KArgs a) {
-  if (cond_off(a)) return;
-  a.stats->error |= a.counters[CNT_ERR];
-  a.stats->triangulations++;
-  a.counters[CNT_QUEUE] = 0;
-}
+struct FinishExtract {
+  using Args = KArgs;
+  static constexpr int BLOCK = 64;
+  TRIME_D static void run(const KArgs &a, Blk) {
+    if (cond_off(a) || threadIdx.x != 0) return;
+    a.stats->error |= a.counters[CNT_ERR];
+    a.stats->triangulations++;
+    a.counters[CNT_QUEUE] = 0;
+  }
+};
 
-void launch_finish_extract(const KArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish_extract, dim3(1), dim3(1), 0, s, a);
-}
+void launch_finish_extract(const KArgs &a, hipStream_t s) { launch<FinishExtract>(a, 1, s); }
 
 }  // namespace trime

@@ -1,8 +1,71 @@
 // Launch-side declarations shared by the kernel files and the ABI.
 #pragma once
+#include <vector>
+
 #include "trime_dev.hpp"
 
 namespace trime {
+
+// ---- one kernel for one shape, or for a whole batch of shapes --------------
+// A kernel of the iteration loop is a functor F: F::Args its arguments,
+// F::BLOCK its block size, F::run(args, blk) its body, written against the
+// block coordinates blk instead of blockIdx / gridDim.  k_one runs it for one
+// shape; k_many runs it for every shape of a batch in one launch: first[s] is
+// the first block of shape s (first[ns] the grid size) and tab[s] its
+// arguments, so each block finds its shape and runs the same body on that
+// shape's buffers as if it were launched alone.
+struct Blk {
+  uint32_t id, n;  // block index and block count within the shape's grid
+};
+
+// The shape of block blk: the s with first[s] <= blk < first[s + 1] (shapes
+// with no blocks are never returned).
+TRIME_D int shape_of(const uint32_t *first, int ns, uint32_t blk) {
+  int lo = 0, hi = ns;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (gld(first, mid) <= blk)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <class F> __global__ __launch_bounds__(F::BLOCK) void k_one(typename F::Args a) {
+  F::run(a, Blk{blockIdx.x, gridDim.x});
+}
+
+template <class F>
+__global__ __launch_bounds__(F::BLOCK) void k_many(const typename F::Args *__restrict__ tab,
+                                                   const uint32_t *__restrict__ first, int ns) {
+  const int s = shape_of(first, ns, blockIdx.x);
+  const uint32_t f0 = gld(first, s), f1 = gld(first, s + 1);
+  F::run(tab[s], Blk{blockIdx.x - f0, f1 - f0});
+}
+
+// A launch as recorded for a batch: the batched kernel, the grid of one
+// shape, and that shape's argument bytes.
+struct LaunchRec {
+  const void *many;
+  uint32_t grid, block;
+  std::vector<unsigned char> args;
+};
+// When set (on the calling host thread), launches are recorded, not issued.
+extern thread_local std::vector<LaunchRec> *g_launch_log;
+
+template <class F> void launch(const typename F::Args &a, uint32_t grid, hipStream_t s) {
+  if (g_launch_log) {
+    LaunchRec r;
+    r.many = (const void *)&k_many<F>;
+    r.grid = grid;
+    r.block = F::BLOCK;
+    r.args.assign((const unsigned char *)&a, (const unsigned char *)&a + sizeof a);
+    g_launch_log->push_back(std::move(r));
+    return;
+  }
+  if (grid) hipLaunchKernelGGL((k_one<F>), dim3(grid), dim3(F::BLOCK), 0, s, a);
+}
 
 enum { MODE_CELLS = 0, MODE_EXTRACT = 1, MODE_CVD = 2 };
 
