@@ -398,6 +398,33 @@ trime_status trime_batch_graph_create(trime_state *const *states, int32_t nstate
 trime_status trime_graph_launch(trime_graph *g, void *stream);
 trime_status trime_graph_destroy(trime_graph *g);
 
+/* ---- batches of shapes, one launch per kernel --------------------------------
+   The batched launch of many shapes: trime_batch_create records one period
+   of the chosen method (two iterations, after which every buffer swap is
+   back where it started) for every state without launching anything, and
+   merges the records kernel by kernel.  trime_batch_run then issues each
+   kernel of an iteration once for all shapes: each block finds its shape in
+   a table of per-shape arguments (binary search over the per-shape block
+   offsets) and runs the same code on that shape's buffers.  Each shape's
+   results equal running it alone with trime_step_dm (flag mode, fresh = 0)
+   or trime_step_cvd; its statistics stay in its own state.
+   - states: bound and loaded, no timing events, all with the same precision
+     and grid dtype (they must record the same sequence of kernels); they
+     must stay bound to the same workspaces while the batch exists, and
+     their buffer parity must be the one they had at creation when the batch
+     runs (runs of an even number of iterations keep it).
+   - Ownership: the library allocates the argument tables in device memory
+     at creation (synchronising) and frees them in trime_batch_destroy.
+   - trime_batch_run enqueues n_iter (even) iterations on the stream; it
+     makes no host reads and can be captured in a HIP graph.
+   Errors: TRIME_EINVAL for bad arguments or states whose kernel sequences
+   differ; TRIME_EHIP for a failed allocation or copy. */
+typedef struct trime_batch trime_batch;
+trime_status trime_batch_create(trime_state *const *states, int32_t nstates, int32_t method, trime_batch **out);
+trime_status trime_batch_run(trime_batch *b, int32_t n_iter, void *stream);
+trime_status trime_batch_destroy(trime_batch *b);
+
+
 /* ---- autotuner (tuning only: no result depends on it) ----------------------
    The bin size sets how many neighbours a cell scans and how far; the cells
    do not depend on it (every cut decision is exact and the centroid sums run

@@ -659,6 +659,127 @@ trime_status trime_graph_launch(trime_graph *g, void *stream) {
   return TRIME_OK;
 }
 
+// ---- one launch per kernel for a batch of shapes ----
+struct BatchLaunch {
+  const void *fn;       // k_many<F>
+  uint32_t total, block;
+  const void *tab;      // per-shape arguments (device)
+  const uint32_t *first;  // per-shape first block, ns + 1 (device)
+};
+
+struct trime_batch {
+  int32_t ns = 0;
+  std::vector<BatchLaunch> launches;
+  void *mem = nullptr;  // one device allocation for every table
+};
+
+trime_status trime_batch_destroy(trime_batch *b) {
+  if (!b) return TRIME_OK;
+  if (b->mem) (void)hipFree(b->mem);
+  delete b;
+  return TRIME_OK;
+}
+
+trime_status trime_batch_create(trime_state *const *states, int32_t nstates, int32_t method, trime_batch **out) {
+  if (!states || nstates <= 0 || !out) return fail(TRIME_EINVAL, "trime_batch_create: bad argument");
+  if (method != TRIME_METHOD_DM && method != TRIME_METHOD_CVD)
+    return fail(TRIME_EINVAL, "trime_batch_create: bad method");
+  *out = nullptr;
+  for (int k = 0; k < nstates; k++) {
+    trime_status e = bound_ok(states[k]);
+    if (e) return e;
+    if (states[k]->ev_cells[0] || states[k]->ev_cells[1])
+      return fail(TRIME_EINVAL, "trime_batch_create: a state requests timing events");
+  }
+  // record one period (two iterations) of every state; nothing is launched
+  std::vector<std::vector<LaunchRec>> logs(nstates);
+  for (int k = 0; k < nstates; k++) {
+    g_launch_log = &logs[k];
+    trime_status e = method == TRIME_METHOD_DM ? trime_step_dm(states[k], 2, 0, 0, nullptr)
+                                               : trime_step_cvd(states[k], 2, nullptr);
+    g_launch_log = nullptr;
+    if (e) return e;
+  }
+  const size_t m = logs[0].size();
+  for (int k = 1; k < nstates; k++) {
+    if (logs[k].size() != m) return fail(TRIME_EINVAL, "trime_batch_create: the states' kernel sequences differ");
+    for (size_t i = 0; i < m; i++)
+      if (logs[k][i].many != logs[0][i].many || logs[k][i].block != logs[0][i].block ||
+          logs[k][i].args.size() != logs[0][i].args.size())
+        return fail(TRIME_EINVAL, "trime_batch_create: the states' kernel sequences differ");
+  }
+  // layout: per launch, the argument table then the block offsets, each
+  // 256-byte aligned, in one device allocation
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  std::vector<size_t> off_tab(m), off_first(m);
+  size_t bytes = 0;
+  for (size_t i = 0; i < m; i++) {
+    off_tab[i] = bytes;
+    bytes += up(logs[0][i].args.size() * (size_t)nstates);
+    off_first[i] = bytes;
+    bytes += up(sizeof(uint32_t) * ((size_t)nstates + 1));
+  }
+  std::vector<unsigned char> host(bytes, 0);
+  trime_batch *b = new (std::nothrow) trime_batch;
+  if (!b) return fail(TRIME_EINVAL, "trime_batch_create: out of host memory");
+  b->ns = nstates;
+  for (size_t i = 0; i < m; i++) {
+    const size_t asz = logs[0][i].args.size();
+    uint32_t *first = (uint32_t *)&host[off_first[i]];
+    uint64_t tot = 0;
+    for (int k = 0; k < nstates; k++) {
+      memcpy(&host[off_tab[i] + asz * (size_t)k], logs[k][i].args.data(), asz);
+      first[k] = (uint32_t)tot;
+      tot += logs[k][i].grid;
+    }
+    if (tot > 0x7fffffffull) {
+      trime_batch_destroy(b);
+      return fail(TRIME_EINVAL, "trime_batch_create: batched grid too large");
+    }
+    first[nstates] = (uint32_t)tot;
+    BatchLaunch L;
+    L.fn = logs[0][i].many;
+    L.total = (uint32_t)tot;
+    L.block = logs[0][i].block;
+    L.tab = nullptr;
+    L.first = nullptr;
+    b->launches.push_back(L);
+  }
+  if (hipMalloc(&b->mem, bytes ? bytes : 256) != hipSuccess) {
+    b->mem = nullptr;
+    trime_batch_destroy(b);
+    return fail(TRIME_EHIP, "trime_batch_create: device allocation");
+  }
+  if (bytes && hipMemcpy(b->mem, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    trime_batch_destroy(b);
+    return fail(TRIME_EHIP, "trime_batch_create: copy of the argument tables");
+  }
+  for (size_t i = 0; i < m; i++) {
+    b->launches[i].tab = (const unsigned char *)b->mem + off_tab[i];
+    b->launches[i].first = (const uint32_t *)((const unsigned char *)b->mem + off_first[i]);
+  }
+  *out = b;
+  return TRIME_OK;
+}
+
+trime_status trime_batch_run(trime_batch *b, int32_t n_iter, void *stream) {
+  if (!b) return fail(TRIME_EINVAL, "trime_batch_run: null batch");
+  if (n_iter < 0 || (n_iter & 1)) return fail(TRIME_EINVAL, "trime_batch_run: n_iter must be even and >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  for (int it = 0; it < n_iter; it += 2) {
+    for (const BatchLaunch &L : b->launches) {
+      if (!L.total) continue;
+      const void *tab = L.tab;
+      const uint32_t *first = L.first;
+      int ns = b->ns;
+      void *args[3] = {(void *)&tab, (void *)&first, (void *)&ns};
+      if (hipLaunchKernel(L.fn, dim3(L.total), dim3(L.block), args, 0, s) != hipSuccess)
+        return fail(TRIME_EHIP, "trime_batch_run: launch");
+    }
+  }
+  return check_hip("trime_batch_run");
+}
+
 trime_status trime_autotune_workspace_bytes(const trime_state *st_in, const double *dens, int32_t nd,
                                             size_t *bytes) {
   if (!st_in || !dens || nd <= 0 || !bytes) return fail(TRIME_EINVAL, "trime_autotune_workspace_bytes: bad argument");

@@ -187,24 +187,35 @@ class Mesher:
 
 
 class Batch:
-    """Many shapes meshed by one graph launch per n_iter iterations
-    (trime_batch_graph_create); the Meshers stay usable one by one."""
+    """Many shapes meshed together; the Meshers stay usable one by one.
 
-    def __init__(self, meshers, method="dm", n_iter=2, nstreams=8):
+    kind "kernels" (trime_batch_create): every kernel of an iteration is
+    launched once for all shapes; kind "graph" (trime_batch_graph_create):
+    the shapes' own launches in one graph over nstreams streams."""
+
+    def __init__(self, meshers, method="dm", n_iter=2, nstreams=8, kind="graph"):
         import torch
         self.torch = torch
         self.meshers = list(meshers)
         self.n_iter = n_iter
+        self.kind = kind
         self.stream = torch.cuda.Stream()
         torch.cuda.synchronize()
         meth = T.METHOD_DM if method == "dm" else T.METHOD_CVD
-        self.graph = T.batch_graph_create([m.state for m in self.meshers], meth, n_iter, nstreams, self.stream)
+        self.graph = self.batch = None
+        if kind == "kernels":
+            self.batch = T.batch_create([m.state for m in self.meshers], meth)
+        else:
+            self.graph = T.batch_graph_create([m.state for m in self.meshers], meth, n_iter, nstreams, self.stream)
         torch.cuda.synchronize()
 
     def run(self, iters):
         """iters iterations of every shape (a multiple of n_iter)."""
         if iters % self.n_iter:
             raise ValueError("iters must be a multiple of %d" % self.n_iter)
+        if self.batch is not None:
+            T.batch_run(self.batch, iters, self.stream)
+            return
         for _ in range(iters // self.n_iter):
             T.graph_launch(self.graph, self.stream)
 
@@ -213,6 +224,10 @@ class Batch:
             self.torch.cuda.synchronize()
             T.graph_destroy(self.graph)
             self.graph = None
+        if self.batch is not None:
+            self.torch.cuda.synchronize()
+            T.batch_destroy(self.batch)
+            self.batch = None
 
     def __del__(self):
         try:

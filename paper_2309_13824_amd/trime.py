@@ -143,7 +143,7 @@ EXPORTED = ["trime_last_error", "trime_version", "trime_default_params", "trime_
             "trime_delaunay_extract", "trime_step_dm", "trime_step_cvd", "trime_step_hybrid",
             "trime_quality", "trime_stats_read", "trime_stats_check", "trime_autotune_workspace_bytes",
             "trime_autotune", "trime_batch_graph_create", "trime_graph_launch", "trime_graph_destroy",
-            "trime_step_adaptive"]
+            "trime_step_adaptive", "trime_batch_create", "trime_batch_run", "trime_batch_destroy"]
 
 _lib = None
 
@@ -318,6 +318,23 @@ def batch_graph_create(states, method, n_iter, nstreams, stream):
     _check(lib().trime_batch_graph_create(arr, len(states), int(method), int(n_iter), int(nstreams), C.byref(g),
                                           _stream(stream)))
     return g
+
+
+def batch_create(states, method):
+    """A batch running every kernel of an iteration once for all states
+    (method METHOD_DM or METHOD_CVD); synchronises (uploads its tables)."""
+    arr = (C.POINTER(State) * len(states))(*[C.pointer(s) for s in states])
+    b = C.c_void_p()
+    _check(lib().trime_batch_create(arr, len(states), int(method), C.byref(b)))
+    return b
+
+
+def batch_run(b, n_iter, stream=None):
+    _check(lib().trime_batch_run(b, int(n_iter), _stream(stream)))
+
+
+def batch_destroy(b):
+    _check(lib().trime_batch_destroy(b))
 
 
 def graph_launch(g, stream=None):

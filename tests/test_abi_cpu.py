@@ -106,6 +106,18 @@ def test_adaptive_configuration_rejected_on_host(T):
         assert b"trime_step_adaptive" in L.trime_last_error()
 
 
+def test_batch_arguments_rejected_on_host(T):
+    L = T.lib(require_gpu=False)
+    out = C.c_void_p()
+    assert L.trime_batch_create(None, 1, 0, C.byref(out)) == 1
+    st = T.State()
+    arr = (C.POINTER(T.State) * 1)(C.pointer(st))
+    assert L.trime_batch_create(arr, 1, 0, C.byref(out)) == 1  # unbound state
+    assert L.trime_batch_create(arr, 1, 5, C.byref(out)) == 1  # bad method
+    assert L.trime_batch_run(None, 2, None) == 1
+    assert L.trime_batch_destroy(None) == 0
+
+
 def test_stats_check_codes(T):
     L = T.lib(require_gpu=False)
     s = T.Stats()

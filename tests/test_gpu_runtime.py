@@ -172,10 +172,13 @@ def test_star_polygon_dm_matches_oracle(orc, T):
     assert np.array_equal(gc, cat)
 
 
+@pytest.mark.parametrize("kind", ["graph", "kernels"])
 @pytest.mark.parametrize("method", ["dm", "cvd"])
-def test_batch_graph_matches_per_shape_runs(orc, T, method):
-    """Shapes of uneven size in one graph launch give, shape by shape, the
-    results of running each shape alone."""
+def test_batch_matches_per_shape_runs(orc, T, method, kind):
+    """Shapes of uneven size run as one batch (kind "graph": the shapes'
+    launches in one graph over several streams; kind "kernels": one launch
+    per kernel for all shapes) give, shape by shape, the results of running
+    each shape alone."""
     from paper_2309_13824_amd.mesher import Batch
     wls = I.stars(count=6, grid_n=256, n_range=(3.0, 3.6))
     grids = [orc.build_grid(w) for w in wls]
@@ -188,10 +191,41 @@ def test_batch_graph_matches_per_shape_runs(orc, T, method):
             m.step_cvd(4)
         alone.append(m.points())
     ms = [mesher(w, FP32, grid=g) for w, g in zip(wls, grids)]
-    b = Batch(ms, method=method, n_iter=2, nstreams=3)
+    b = Batch(ms, method=method, n_iter=2, nstreams=3, kind=kind)
     b.run(4)
     import torch
     torch.cuda.synchronize()
+    for k, m in enumerate(ms):
+        x, y, c = m.points()
+        assert np.array_equal(x, alone[k][0]) and np.array_equal(y, alone[k][1]), k
+        assert np.array_equal(c, alone[k][2]), k
+    b.close()
+
+
+def test_kernel_batch_replays_in_a_graph(orc, T):
+    """The batched launches make no host reads: captured in a HIP graph and
+    replayed twice (two iterations each), they equal four iterations of each
+    shape alone."""
+    import torch
+    from paper_2309_13824_amd.mesher import Batch
+    wls = I.stars(count=5, grid_n=256, n_range=(3.0, 3.5), seed=1105)
+    grids = [orc.build_grid(w) for w in wls]
+    alone = []
+    for w, g in zip(wls, grids):
+        m = mesher(w, FP32, grid=g)
+        m.step_dm(4, fresh=False)
+        alone.append(m.points())
+    ms = [mesher(w, FP32, grid=g) for w, g in zip(wls, grids)]
+    b = Batch(ms, method="dm", n_iter=2, kind="kernels")
+    s = b.stream
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        T.batch_run(b.batch, 2, s)
+    for r in range(2):
+        g.replay()
+        torch.cuda.synchronize()
+        ms[0].stats_raw()  # eager work between replays
     for k, m in enumerate(ms):
         x, y, c = m.points()
         assert np.array_equal(x, alone[k][0]) and np.array_equal(y, alone[k][1]), k
