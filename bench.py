@@ -86,6 +86,8 @@ def parse():
                          "(DistMesh), batched in one graph vs per-shape launches; disk, annulus, "
                          "ellipses: their fixed schedules, one JSON line each")
     ap.add_argument("--shapes", type=int, default=512)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="stars: time only the batch with one launch per kernel (no per-shape or graph runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -220,9 +222,10 @@ def stars_run(args, log):
         def per_shape():
             for m in ms:
                 T.step_dm(m.state, iters, fresh=False)
-        per_ms = timed(per_shape)
-        out["per_shape_" + name] = total * iters / (per_ms * 1e-3)
-        log("  %s per-shape launches: %.1f ms for %d iterations" % (name, per_ms, iters))
+        if not args.batch_only:
+            per_ms = timed(per_shape)
+            out["per_shape_" + name] = total * iters / (per_ms * 1e-3)
+            log("  %s per-shape launches: %.1f ms for %d iterations" % (name, per_ms, iters))
         for m in ms:
             m.load()
         t = time.perf_counter()
@@ -237,7 +240,7 @@ def stars_run(args, log):
         out["batched_" + name] = total * iters / (bat_ms * 1e-3)
         out["batched_ms_" + name] = bat_ms
         log("  %s batched kernels: %.1f ms for %d iterations" % (name, bat_ms, iters))
-        if prec == T.FP32:
+        if prec == T.FP32 and not args.batch_only:
             for m in ms:
                 m.load()
             t = time.perf_counter()
@@ -262,12 +265,14 @@ def stars_run(args, log):
                                "log-uniform point counts in [1e3, 1e5], %d points in total, 60 DistMesh "
                                "iterations" % (len(wls), total), "shapes": len(wls), "total_points": total,
                    "seed": 1005},
-        "batched_fp64": out["batched_fp64"], "graph_fp32": out["graph_fp32"],
-        "per_shape_fp32": out["per_shape_fp32"], "per_shape_fp64": out["per_shape_fp64"],
-        "batched_over_per_shape_fp32": out["batched_fp32"] / out["per_shape_fp32"],
-        "batched_fp32_over_per_shape_fp64": out["batched_fp32"] / out["per_shape_fp64"],
+        "batched_fp64": out["batched_fp64"],
         "batched_fp32_over_batched_fp64": out["batched_fp32"] / out["batched_fp64"],
     }
+    if not args.batch_only:
+        line.update({"graph_fp32": out["graph_fp32"], "per_shape_fp32": out["per_shape_fp32"],
+                     "per_shape_fp64": out["per_shape_fp64"],
+                     "batched_over_per_shape_fp32": out["batched_fp32"] / out["per_shape_fp32"],
+                     "batched_fp32_over_per_shape_fp64": out["batched_fp32"] / out["per_shape_fp64"]})
     print(json.dumps(line), flush=True)
 
 
