@@ -283,6 +283,34 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
                                vx, vy, E);
   }
 
+  // A new polygon vertex, between the edges of constraints c1 and c2 (r the
+  // row of c3 == c2 or c1, already at hand).  The FP32 mode builds it in
+  // FP64 from the FP64 rows and rounds it: an FP32 intersection of two
+  // bisectors at angle t carries an error of ~20u h / sin t, which the cells
+  // would pass on to their centroids; the rounded FP64 vertex is within
+  // u|v| of the true one.  The bound E then covers that rounding plus the
+  // FP32 cut test's own (6u|v|).  MI355X issues FP64 FMA at the FP32 rate.
+  TRIME_D bool new_vertex(int c1, int c2, const Row<T> &r1, const Row<T> &r2, T &vx, T &vy, float &E) const {
+    if constexpr (sizeof(T) == 4) {
+      double dx, dy;
+      float E64;
+      if (!make_vertex<double>(row_of<double>(a, c1, px, py, S, D), row_of<double>(a, c2, px, py, S, D), dx, dy,
+                               E64)) {
+        vx = 0;
+        vy = 0;
+        E = INFINITY;
+        return false;
+      }
+      vx = (T)dx;
+      vy = (T)dy;
+      const double vmax = fmax(fabs(dx), fabs(dy));
+      E = (float)(((double)E64 + 7.0 * (double)U<float>::v * vmax) * 1.00001);
+      return true;
+    } else {
+      return make_vertex<T>(r1, r2, vx, vy, E);
+    }
+  }
+
   // The octagon test of vertex j against wall w of the point q at (qxd, qyd)
   // in FP64, from the FP64 vertex: +1 outside, -1 inside, 0 undecided.
   TRIME_D int oct_margin64(int j, double qxd, double qyd, float Sq, float Dq, int w) const {
@@ -419,8 +447,8 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     int cout = con(k1);
     T x1, y1, x2, y2;
     float e1, e2;
-    bool ok1 = make_vertex<T>(row_of<T>(a, cin, px, py, S, D), r3, x1, y1, e1);
-    bool ok2 = make_vertex<T>(r3, row_of<T>(a, cout, px, py, S, D), x2, y2, e2);
+    bool ok1 = new_vertex(cin, c3, row_of<T>(a, cin, px, py, S, D), r3, x1, y1, e1);
+    bool ok2 = new_vertex(c3, cout, r3, row_of<T>(a, cout, px, py, S, D), x2, y2, e2);
     if (!ok1 || !ok2) {
       why = WHY_VERTEX;
       return;
@@ -495,8 +523,8 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     int cout = con(k1);
     T x1, y1, x2, y2;
     float e1, e2;
-    bool ok1 = make_vertex<T>(row_of<T>(a, cin, px, py, S, D), r3, x1, y1, e1);
-    bool ok2 = make_vertex<T>(r3, row_of<T>(a, cout, px, py, S, D), x2, y2, e2);
+    bool ok1 = new_vertex(cin, c3, row_of<T>(a, cin, px, py, S, D), r3, x1, y1, e1);
+    bool ok2 = new_vertex(c3, cout, r3, row_of<T>(a, cout, px, py, S, D), x2, y2, e2);
     if constexpr (!EXACT) {
       if (!ok1 || !ok2) {
         why = WHY_VERTEX;
@@ -718,9 +746,13 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   // either way.
   static constexpr int QK = 3;
 
+  // The leaf geometry and weights are in V; the sums are FP64 in both
+  // precisions: an FP32 sum over the hundreds of leaves of a large boundary
+  // cell (up to the octagon, 5h) would move its centroid by more than the
+  // 1e-5 h the FP32 mode allows.
   template <class V, class GetV>
   TRIME_D void level_centroid(int L, V fxf, V fyf, int64_t cx0, int64_t cy0, GetV &getv, V &cx, V &cy) {
-    V sw = 0, swx = 0, swy = 0;
+    double sw = 0, swx = 0, swy = 0;
     const V idx = (V)a.inv_dx, idy = (V)a.inv_dy;
     const G *mu = (const G *)a.mu;
     const int64_t nxc = a.nx - 2, nyc = a.ny - 2;
@@ -747,10 +779,10 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
         last = n0;
       }
       V m = (m00 * ((V)1 - tx) + m10 * tx) * ((V)1 - ty) + (m01 * ((V)1 - tx) + m11 * tx) * ty;
-      V w = A * recip<V>(m * m);
+      const double w = (double)(A * recip<V>(m * m));
       sw += w;
-      swx += w * gx;
-      swy += w * gy;
+      swx += w * (double)gx;
+      swy += w * (double)gy;
     };
     const int D = L - 1;
     if constexpr (BLOCK == 1) {
@@ -783,9 +815,9 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       swx = __shfl(swx, 0);
       swy = __shfl(swy, 0);
       wk.leaves += n << D;
-      V inv = (V)1 / sw;
-      cx = swx * inv;
-      cy = swy * inv;
+      const double inv = 1.0 / sw;
+      cx = (V)(swx * inv);
+      cy = (V)(swy * inv);
       return;
     }
     V vx0, vy0, ax, ay;
@@ -819,16 +851,17 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       ay = by;
     }
     wk.leaves += n << D;
-    V inv = (V)1 / sw;
-    cx = swx * inv;
-    cy = swy * inv;
+    const double inv = 1.0 / sw;
+    cx = (V)(swx * inv);
+    cy = (V)(swy * inv);
   }
 
   // The adaptive level loop of the CVD target (Sec. 4.2 II) in V arithmetic.
   // BAND (FP32): false when a level decision lies within the error bound of
   // the two centroids compared; the caller then redoes it in FP64.
   template <class V, bool BAND, class GetV>
-  TRIME_D bool cvd_levels(double h, double dp, GetV &getv, double &xnew, double &ynew, int &cap_hit) {
+  TRIME_D bool cvd_levels(double h, double dp, GetV &getv, double &xnew, double &ynew, int &cap_hit,
+                          V vtx_err = 0) {
     const V u = U<V>::v;
     V A = 0;
     {
@@ -862,9 +895,10 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       V ex_ = c0x - c1x, ey_ = c0y - c1y;
       V d2 = ex_ * ex_ + ey_ * ey_;
       if constexpr (BAND) {
-        // centroid error: vertices and weights (~32u R) plus the sums
-        // (u R per leaf term), for both levels compared
-        V err1 = ((V)32 + (V)2 * (V)(n << (L - 1))) * u * R;
+        // centroid error: the vertices' own error bounds, vertices and
+        // weights (~32u R) plus the sums (u R per leaf term), for both
+        // levels compared
+        V err1 = (V)2 * vtx_err + ((V)32 + (V)2 * (V)(n << (L - 1))) * u * R;
         V dd = err0 + err1;
         V lo = fmax(E - dd, (V)0), hi = E + dd;
         if (d2 >= lo * lo && d2 <= hi * hi) return false;
@@ -895,7 +929,27 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       y = v.y;
     };
     constexpr bool band = !EXACT && sizeof(T) == 4;
-    if (!cvd_levels<T, band>(h, dp, getT, xnew, ynew, cap_hit)) why = WHY_LEVEL;
+    T emax = 0;
+    if constexpr (band) {
+      // the centroid moves by up to a few times the largest vertex error.
+      // The vertices are rounded FP64 intersections: e is 7u|v| (rounding
+      // and the cut test's allowance) plus the FP64 bound, which only a
+      // nearly singular pair of rows makes large; such cells take the FP64
+      // centroid pass (1e-6 h of excess keeps the centroid well inside the
+      // 1e-5 h of the FP32 mode)
+      const T u = U<T>::v;
+      T excess = 0;
+      for (int j = 0; j < n; j++) {
+        VRec<T> v = P[j][tid];
+        emax = fmax(emax, (T)v.e);
+        excess = fmax(excess, (T)v.e - (T)7.0001 * u * fmax(fabs(v.x), fabs(v.y)));
+      }
+      if ((double)excess > 1e-6 * h) {
+        why = WHY_PREC;
+        return;
+      }
+    }
+    if (!cvd_levels<T, band>(h, dp, getT, xnew, ynew, cap_hit, emax)) why = WHY_LEVEL;
   }
 
   // CVD target (Sec. 4.2 II) and treatment (Sec. 4.3) of p; false when an

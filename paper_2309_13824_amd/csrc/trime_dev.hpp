@@ -87,7 +87,7 @@ constexpr int CQ_STRIDE = 16;
 enum { ERR_TRI_CAP = 1, ERR_DEG_CAP = 2, ERR_POLY_CAP = 4, ERR_EXACT_CAP = 8, ERR_QUEUE = 16 };
 // why a point left the fast path
 enum { WHY_PRED = 1, WHY_VERTEX = 2, WHY_POLY = 3, WHY_AND = 4, WHY_LEVEL = 5, WHY_TREAT = 6,
-       WHY_BOX = 7, WHY_HEAVY = 8 };
+       WHY_BOX = 7, WHY_HEAVY = 8, WHY_PREC = 9 };
 
 // ---------------------------------------------------------------- grid ----
 

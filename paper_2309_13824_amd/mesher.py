@@ -177,7 +177,7 @@ class Mesher:
         return T.stats_read(self.state)
 
     REASONS = {1: "predicate", 2: "vertex", 3: "polygon", 4: "and_test", 5: "cvd_level", 6: "treatment",
-               7: "box", 8: "heavy"}
+               7: "box", 8: "heavy", 9: "vertex_error"}
 
     def replay_reasons(self) -> dict:
         """Points sent from the fast kernels to a replay, by reason (since load)."""
