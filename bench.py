@@ -83,8 +83,9 @@ def parse():
                          "empty for the default 3.3")
     ap.add_argument("--workload", default="holes20", choices=["holes20", "stars", "disk", "annulus", "ellipses"],
                     help="holes20: the headline CVD run; stars: the batch of 512 star polygons "
-                         "(DistMesh), batched in one graph vs per-shape launches; disk, annulus, "
-                         "ellipses: their fixed schedules, one JSON line each")
+                         "(DistMesh), one launch per kernel for all shapes, against a graph of per-shape "
+                         "launches and per-shape launches; disk, annulus, ellipses: their fixed schedules, "
+                         "one JSON line each")
     ap.add_argument("--shapes", type=int, default=512)
     ap.add_argument("--batch-only", action="store_true",
                     help="stars: time only the batch with one launch per kernel (no per-shape or graph runs)")
@@ -160,10 +161,13 @@ def gpu_run(wl, precision, steps, warmup, log, tune=()):
 CPU_ITERS = 3
 
 
-def cpu_baseline(wl, threads, log):
+def cpu_baseline(wl, threads, log, bin_density=0.0):
     """The oracle as it stands: the first CPU_ITERS CVD iterations from the
     seeded start (triangulation with validity and quality, centroids,
-    treatment) over every point, on the host cores; setup not timed."""
+    treatment) over every point, on the host cores; setup not timed.  Its
+    first iteration also gives the position error of one GPU CVD step in
+    each precision (the oracle's grid uploaded, so both sides see the same
+    inputs), in units of the local h, over every point."""
     from oracle import oracle as orc
     t = time.perf_counter()
     og = orc.build_grid(wl)
@@ -172,6 +176,7 @@ def cpu_baseline(wl, threads, log):
     dprev = np.full(wl.n, -1.0)
     log("  cpu oracle setup (grid, categories) %.1f s" % (time.perf_counter() - t))
     secs = 0.0
+    first = None
     for it in range(CPU_ITERS):
         t = time.perf_counter()
         mesh = orc.triangulate(og, x, y, nthreads=threads)
@@ -179,8 +184,37 @@ def cpu_baseline(wl, threads, log):
         x, y, cats, dprev, _, _ = orc.cvd_step(og, x, y, cats, dprev, nthreads=threads)
         dt = time.perf_counter() - t
         secs += dt
+        if it == 0:
+            first = (x, y, cats)
         log("  cpu oracle iteration %d: %.2f s on %d threads" % (it + 1, dt, threads))
-    return secs
+    return secs, position_error(wl, og, first, bin_density, log)
+
+
+def position_error(wl, og, ref, bin_density, log):
+    """Max and mean |p_gpu - p_oracle| / h after one CVD step from the seeded
+    start, FP32 + FP64 replay and plain FP64; categories compared too."""
+    import torch
+    from paper_2309_13824_amd import trime as T
+    from paper_2309_13824_amd.mesher import Mesher
+    xr, yr, cr = ref
+    fx = np.floor((xr - og.x0) * (1.0 / og.dx)).astype(int)
+    fy = np.floor((yr - og.y0) * (1.0 / og.dy)).astype(int)
+    h = og.hcell[fy * (og.nx - 1) + fx].astype(np.float64)
+    out = {}
+    for prec, name in ((T.FP32, "fp32"), (T.FP64, "fp64")):
+        m = Mesher(wl, precision=prec, grid=og, bin_density=bin_density)
+        m.load()
+        m.step_cvd(1)
+        gx, gy, gc = m.points()
+        err = np.hypot(gx - xr, gy - yr) / h
+        out[name] = {"max_h": float(err.max()), "mean_h": float(err.mean()),
+                     "categories_equal": bool(np.array_equal(gc, cr))}
+        log("  %s position error against the oracle after one CVD step: max %.3g h, mean %.3g h"
+            % (name, err.max(), err.mean()))
+        del m
+        torch.cuda.empty_cache()
+    out["what"] = "one CVD step from the seeded start, every point, |p - p_oracle| / h"
+    return out
 
 
 def stars_run(args, log):
@@ -385,10 +419,11 @@ def main():
 
     threads = args.cpu_threads or min(16, os.cpu_count() or 1)
     cpu = None
+    perr = None
     if not args.no_cpu_baseline:
         del m32
         torch.cuda.empty_cache()
-        secs = cpu_baseline(wl, threads, log)
+        secs, perr = cpu_baseline(wl, threads, log, dens32)
         cpu = {"value": wl.n * CPU_ITERS / secs, "unit": "point-iterations/s", "cores": threads, "kind": "oracle",
                "sample": "the first %d CVD iterations from the seeded start (cells, triangles with Tests 1-3 "
                          "and quality, centroids, treatment) over all %d points of the holes20 workload, "
@@ -424,6 +459,7 @@ def main():
                    "n_points": wl.n, "grid": args.grid, "method": "cvd",
                    "precision": "fp32 + fp64 replay", "seed": wl.seed, "bin_density": dens32},
         "roofline": roof, "cpu_baseline": cpu, "fp64": fp64,
+        "position_error": perr,
         "fp64_replays_per_step": st32["fp64_replays"] / max(args.steps, 1),
         "quality": {k: st32[k] for k in ("half_mean_alpha", "half_mean_beta", "min_q", "mean_q", "nvalid")},
     })
