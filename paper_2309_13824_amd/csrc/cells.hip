@@ -247,6 +247,7 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   T R2;
   ExactCount ec;
   Work wk;
+  double cqx = 0, cqy = 0;  // FP64 offset of the candidate being clipped
 
   TRIME_D Lane(const KArgs &a_, VRec<T> (&P_)[VMAX][BLOCK], int tid_, int64_t k_)
       : a(a_), P(P_), tid(tid_), k(k_), n(0), why(0), R2(0) {}
@@ -290,12 +291,22 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   // would pass on to their centroids; the rounded FP64 vertex is within
   // u|v| of the true one.  The bound E then covers that rounding plus the
   // FP32 cut test's own (6u|v|).  MI355X issues FP64 FMA at the FP32 rate.
-  TRIME_D bool new_vertex(int c1, int c2, const Row<T> &r1, const Row<T> &r2, T &vx, T &vy, float &E) const {
+  TRIME_D Row<double> row64(int c, int c3) const {
+    if (c == c3 && c3 >= 0) {  // the candidate: its FP64 offset is at hand
+      Row<double> r;
+      r.nx = cqx;
+      r.ny = cqy;
+      r.s = (cqx * cqx + cqy * cqy) * 0.5;
+      return r;
+    }
+    return row_of<double>(a, c, px, py, S, D);
+  }
+  TRIME_D bool new_vertex(int c1, int c2, const Row<T> &r1, const Row<T> &r2, T &vx, T &vy, float &E,
+                          int c3) const {
     if constexpr (sizeof(T) == 4) {
       double dx, dy;
       float E64;
-      if (!make_vertex<double>(row_of<double>(a, c1, px, py, S, D), row_of<double>(a, c2, px, py, S, D), dx, dy,
-                               E64)) {
+      if (!make_vertex<double>(row64(c1, c3), row64(c2, c3), dx, dy, E64)) {
         vx = 0;
         vy = 0;
         E = INFINITY;
@@ -447,8 +458,8 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     int cout = con(k1);
     T x1, y1, x2, y2;
     float e1, e2;
-    bool ok1 = new_vertex(cin, c3, row_of<T>(a, cin, px, py, S, D), r3, x1, y1, e1);
-    bool ok2 = new_vertex(c3, cout, r3, row_of<T>(a, cout, px, py, S, D), x2, y2, e2);
+    bool ok1 = new_vertex(cin, c3, row_of<T>(a, cin, px, py, S, D), r3, x1, y1, e1, c3);
+    bool ok2 = new_vertex(c3, cout, r3, row_of<T>(a, cout, px, py, S, D), x2, y2, e2, c3);
     if (!ok1 || !ok2) {
       why = WHY_VERTEX;
       return;
@@ -523,8 +534,8 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     int cout = con(k1);
     T x1, y1, x2, y2;
     float e1, e2;
-    bool ok1 = new_vertex(cin, c3, row_of<T>(a, cin, px, py, S, D), r3, x1, y1, e1);
-    bool ok2 = new_vertex(c3, cout, r3, row_of<T>(a, cout, px, py, S, D), x2, y2, e2);
+    bool ok1 = new_vertex(cin, c3, row_of<T>(a, cin, px, py, S, D), r3, x1, y1, e1, c3);
+    bool ok2 = new_vertex(c3, cout, r3, row_of<T>(a, cout, px, py, S, D), x2, y2, e2, c3);
     if constexpr (!EXACT) {
       if (!ok1 || !ok2) {
         why = WHY_VERTEX;
@@ -654,6 +665,8 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
           T sq = r3.nx * r3.nx + r3.ny * r3.ny;
           r3.s = sq * (T)0.5;
           if (!(sq * ((T)1 - (T)8 * u) > (T)4 * R2)) {
+            cqx = qx - px;
+            cqy = qy - py;
             clip(r3, s);
             if (why || n == 0) return;
           }
