@@ -274,6 +274,14 @@ def stars_run(args, log):
         out["batched_" + name] = total * iters / (bat_ms * 1e-3)
         out["batched_ms_" + name] = bat_ms
         log("  %s batched kernels: %.1f ms for %d iterations" % (name, bat_ms, iters))
+        if prec == T.FP32:  # whole-iteration HBM roofline of the timed batch run
+            nbytes = 0
+            for m in ms:
+                tri = m.stats_raw().triangulations
+                nbytes += m.n * (tri * ITER_BYTES["dm_tri"] + (iters - tri) * ITER_BYTES["dm"])
+            bw = nbytes / (bat_ms * 1e-3)
+            out["hbm"] = {"bound": "hbm", "achieved": bw / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                          "frac": bw / PEAK_HBM, "algorithmic_bytes": nbytes, "kernel": "whole iteration"}
         if prec == T.FP32 and not args.batch_only:
             for m in ms:
                 m.load()
@@ -301,13 +309,81 @@ def stars_run(args, log):
                    "seed": 1005},
         "batched_fp64": out["batched_fp64"],
         "batched_fp32_over_batched_fp64": out["batched_fp32"] / out["batched_fp64"],
+        "whole_iteration_hbm": out["hbm"],
     }
+    if not args.no_cpu_baseline:
+        # the oracle beside it: the first DistMesh iteration of 8 of the shapes
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        secs, errs, npts = 0.0, [], 0
+        for w in wls[:8]:
+            s_, e_ = oracle_first_step(w, "dm", (T.FP32, T.FP64), threads, lambda _: None)
+            secs += s_
+            npts += w.n
+            errs.append(e_)
+        line["cpu_baseline"] = {"value": npts / secs, "unit": "point-iterations/s", "cores": threads,
+                                "kind": "oracle", "sample": "the first DistMesh iteration of the first 8 "
+                                "shapes (%d points), FP64 with exact predicates" % npts}
+        line["position_error"] = {
+            "what": "one DistMesh step from the seeded start, every point of the first 8 shapes, "
+                    "|p - p_oracle| / h",
+            "fp32": {"max_h": max(e["fp32"]["max_h"] for e in errs),
+                     "categories_equal": all(e["fp32"]["categories_equal"] for e in errs)},
+            "fp64": {"max_h": max(e["fp64"]["max_h"] for e in errs),
+                     "categories_equal": all(e["fp64"]["categories_equal"] for e in errs)}}
+        log("  cpu oracle: first DistMesh iteration of 8 shapes (%d points) %.2f s; fp32 max error %.3g h"
+            % (npts, secs, line["position_error"]["fp32"]["max_h"]))
     if not args.batch_only:
         line.update({"graph_fp32": out["graph_fp32"], "per_shape_fp32": out["per_shape_fp32"],
                      "per_shape_fp64": out["per_shape_fp64"],
                      "batched_over_per_shape_fp32": out["batched_fp32"] / out["per_shape_fp32"],
                      "batched_fp32_over_per_shape_fp64": out["batched_fp32"] / out["per_shape_fp64"]})
     print(json.dumps(line), flush=True)
+
+
+# Algorithmic HBM bytes per point-iteration of a whole iteration (every
+# kernel), counting each position, grid node and connectivity entry once per
+# pass: binning 2 x 49 + 12, the cells with triangles and statistics 156
+# (the fused kernel's figure above), the DistMesh force step over a sorted
+# row (6 neighbours x 4 + 6 mu samples x 16 + own state 50 = 170) and the
+# re-triangulation test's last-triangulation positions 16.
+ITER_BYTES = {"cvd": 110 + 156, "dm_tri": 110 + 156 + 170 + 16, "dm": 170 + 16}
+
+
+def oracle_first_step(wl, method, precs, threads, log):
+    """The oracle's first iteration of `method` from the seeded start over
+    every point (timed), and the GPU's first iteration in each precision on
+    the oracle's grid against it: max and mean |p - p_oracle| / h."""
+    from oracle import oracle as orc
+    from paper_2309_13824_amd import trime as T
+    from paper_2309_13824_amd.mesher import Mesher
+    og = orc.build_grid(wl)
+    cats = orc.initial_categories(og, wl.x, wl.y)
+    t = time.perf_counter()
+    mesh = orc.triangulate(og, wl.x, wl.y, nthreads=threads)
+    orc.quality(wl.x, wl.y, mesh.tri, mesh.valid)
+    if method == "cvd":
+        xr, yr, cr, _, _, _ = orc.cvd_step(og, wl.x, wl.y, cats, np.full(wl.n, -1.0), nthreads=threads)
+    else:
+        xr, yr, cr, _, _, _ = orc.dm_step(og, wl.x, wl.y, cats, mesh)
+    secs = time.perf_counter() - t
+    fx = np.floor((xr - og.x0) * (1.0 / og.dx)).astype(int)
+    fy = np.floor((yr - og.y0) * (1.0 / og.dy)).astype(int)
+    h = og.hcell[fy * (og.nx - 1) + fx].astype(np.float64)
+    err = {"what": "one %s step from the seeded start, every point, |p - p_oracle| / h" % method}
+    for prec in precs:
+        name = "fp32" if prec == T.FP32 else "fp64"
+        m = Mesher(wl, precision=prec, grid=og)
+        m.load()
+        if method == "cvd":
+            m.step_cvd(1)
+        else:
+            m.step_dm(1)
+        gx, gy, gc = m.points()
+        e = np.hypot(gx - xr, gy - yr) / h
+        err[name] = {"max_h": float(e.max()), "mean_h": float(e.mean()), "categories_equal": bool(np.array_equal(gc, cr))}
+        log("  %s position error against the oracle after one %s step: max %.3g h, mean %.3g h"
+            % (name, method, e.max(), e.mean()))
+    return secs, err
 
 
 def schedule_run(args, log):
@@ -351,18 +427,28 @@ def schedule_run(args, log):
             ms_ = a.elapsed_time(b)
             st = m.stats()
             key = "%s %s" % (pname, "+".join("%d %s" % (k, meth) for meth, k in sch))
+            n_cvd = sum(k for meth, k in sch if meth == "cvd")
+            n_dm = iters - n_cvd
+            n_dm_tri = min(max(st["triangulations"] - n_cvd, 0), n_dm)
+            nbytes = wl.n * (n_cvd * ITER_BYTES["cvd"] + n_dm_tri * ITER_BYTES["dm_tri"]
+                             + (n_dm - n_dm_tri) * ITER_BYTES["dm"])
+            bw = nbytes / (ms_ * 1e-3)
             res[key] = {"value": wl.n * iters / (ms_ * 1e-3), "ms_per_step": ms_ / iters, "wall_s": wall,
                         "triangulations": st["triangulations"], "fp64_replays": st["fp64_replays"],
-                        "bin_density": dens, "mean_q": st["mean_q"], "min_q": st["min_q"]}
+                        "bin_density": dens, "mean_q": st["mean_q"], "min_q": st["min_q"],
+                        "whole_iteration_hbm": {"bound": "hbm", "achieved": bw / 1e9, "peak": PEAK_HBM / 1e9,
+                                                "unit": "GB/s", "frac": bw / PEAK_HBM,
+                                                "algorithmic_bytes": nbytes}}
             log("  %s: %.1f ms for %d iterations (%d triangulations), mean q %.4f" % (
                 key, ms_, iters, st["triangulations"], st["mean_q"]))
         del m
         torch.cuda.empty_cache()
     first = res[next(iter(res))]
     cpu = None
+    perr = None
+    threads = args.cpu_threads or min(16, os.cpu_count() or 1)
     if which == "disk" and not args.no_cpu_baseline:
         from oracle import oracle as orc
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         og = orc.build_grid(wl)
         t = time.perf_counter()
         orc.run(og, wl.x, wl.y, wl.schedule, nthreads=threads)
@@ -371,13 +457,20 @@ def schedule_run(args, log):
                "sample": "the full 50-iteration DistMesh run of the disk workload (2000 points), FP64 with "
                          "exact predicates"}
         log("  cpu oracle: full run %.2f s on %d threads" % (secs, threads))
+        _, perr = oracle_first_step(wl, "dm", precs, threads, log)
+    elif which == "annulus" and not args.no_cpu_baseline:
+        secs, perr = oracle_first_step(wl, wl.schedule[0][0], precs, threads, log)
+        cpu = {"value": wl.n / secs, "unit": "point-iterations/s", "cores": threads, "kind": "oracle",
+               "sample": "the first %s iteration (triangulation with quality, then the step) from the seeded "
+                         "start over all %d points, FP64 with exact predicates" % (wl.schedule[0][0], wl.n)}
+        log("  cpu oracle: first iteration %.2f s on %d threads" % (secs, threads))
     line = {"metric": "point-iterations/s, %s workload" % wl.name, "value": first["value"],
             "unit": "point-iterations/s", "n_gpus": 1, "steps": sum(k for _, k in wl.schedule), "warmup": 2,
             "ms_per_step": first["ms_per_step"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64" if which == "disk" else "f32", "data": "synthetic",
             "config": {"workload": "%s, %d points, %d^2 grid, schedule %s" % (
                 wl.name, wl.n, wl.grid.nx, wl.schedule), "seed": wl.seed},
-            "runs": res, "cpu_baseline": cpu}
+            "runs": res, "cpu_baseline": cpu, "position_error": perr}
     print(json.dumps(line), flush=True)
 
 
