@@ -55,7 +55,7 @@ BYTES_PER_POINT = 37 + 25 + 30 + 64
 # HBM traffic of one launch of the fused kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (first two CVD iterations, scaled by a 1 GiB copy: FETCH x 2.0,
 # WRITE x 1.0), valid for the kernel sources with this digest only.
-TRAFFIC = {"sha1": "94564b8d5c0d0f3ce6fbdba3a914e8ff69c8cd7c", "bytes_per_launch": 500098152.7}
+TRAFFIC = {"sha1": "44e328e87e41981bc42c2edb57cdb7703fe80e19", "bytes_per_launch": 494359861.4}
 KERNEL_SOURCES = ["cells.hip", "trime_dev.hpp", "geom_dev.hpp", "exact_dev.hpp", "launch.hpp"]
 
 
