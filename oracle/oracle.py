@@ -9,6 +9,7 @@ does.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -565,4 +566,120 @@ def run_adaptive(grid: OracleGrid, x, y, mode, max_iter, t_quality=0.001, t_amax
             stop_iter = it
             break
     return x, y, cat, {"iters": len(hist), "switch_iter": switch_iter, "stop_iter": stop_iter,
+                       "reason": reason, "history": hist}
+
+
+def scaled_grid(grid: OracleGrid, h_scale: float) -> OracleGrid:
+    """The grid with every h scaled for the current point count (Sec. 3.7:
+    when points are added, the geometric quantities are scaled by
+    sqrt(N_old / N_current)): h_cell = fl32(h_cell * h_scale), h_avg too."""
+    hc = (grid.hcell.astype(np.float64) * h_scale).astype(np.float32)
+    return OracleGrid(grid.nx, grid.ny, grid.x0, grid.y0, grid.dx, grid.dy, grid.sdf, grid.mu, grid.cat, hc,
+                      grid.h_avg * h_scale, grid.H)
+
+
+def added_points(grid: OracleGrid, x, y, mesh: Mesh, n_add: int, params=None):
+    """Point addition (Sec. 3.6): the n_add valid triangles with the largest
+    ratio of circumradius to the local desired edge length h (the h of the
+    grid cell holding the triangle's centroid) give one new point each, at
+    their centroids.  Ties in the ratio go to the smaller (owner id, second
+    id) of the triangle (the owner is its smallest id, first in CCW order).
+    The new points are returned in the order of (owner id, second id) of
+    their triangles: they get the ids n, n + 1, ...  The circumradius is
+    sqrt(|ab|^2 |bc|^2 |ca|^2) / (2 |(b - a) x (c - a)|) and the centroid
+    ((x_a + x_b) + x_c) / 3, in FP64."""
+    tri = mesh.tri[mesh.valid.astype(bool)].astype(np.int64)
+    xa, ya, xb, yb, xc, yc = x[tri[:, 0]], y[tri[:, 0]], x[tri[:, 1]], y[tri[:, 1]], x[tri[:, 2]], y[tri[:, 2]]
+    d1x, d1y, d2x, d2y = xb - xa, yb - ya, xc - xa, yc - ya
+    cross = d1x * d2y - d1y * d2x
+    la2 = d1x * d1x + d1y * d1y
+    lb2 = (xc - xb) * (xc - xb) + (yc - yb) * (yc - yb)
+    lc2 = d2x * d2x + d2y * d2y
+    R = np.sqrt(la2 * lb2 * lc2) / (2.0 * np.abs(cross))
+    gx = ((xa + xb) + xc) / 3.0
+    gy = ((ya + yb) + yc) / 3.0
+    ratio = R / cell_h(grid, gx, gy)
+    order = np.lexsort((tri[:, 1], tri[:, 0], -ratio))
+    sel = order[:n_add]
+    sel = sel[np.lexsort((tri[sel, 1], tri[sel, 0]))]
+    return gx[sel], gy[sel]
+
+
+def run_growing(grid: OracleGrid, x_all, y_all, mode, max_iter, n_init, t_add=0.002, fac_add=0.6,
+                t_quality=0.001, t_amax=0.005, t_switch=0.0015, params=None, nthreads=1):
+    """Adaptive run with point addition (Sec. 3.6): it starts from the first
+    n_init points; while fewer than N_total = len(x_all) points are in the
+    mesh, an iteration whose relative changes of M_1/2(alpha) and
+    M_1/2(beta) are both below t_add adds min(floor(fac_add N_current),
+    N_total - N_current) points (added_points), and the switch and
+    termination tests (run_adaptive) wait until all points are in.  The
+    geometric quantities follow the current count: h scaled by
+    sqrt(N_total / N_current) (the grid is built for N_total).  After an
+    addition the next iteration has no previous statistics, DistMesh
+    re-triangulates, and the new points start with d_prev = -1 and the
+    category of their position.  Returns the final points and categories
+    and a dict with the iterations at which points were added (and the
+    counts), the switch and stop iterations, the reason and the history."""
+    prm = params or default_params()
+    n_total = len(x_all)
+    n = int(n_init)
+    x = np.array(x_all[:n], np.float64)
+    y = np.array(y_all[:n], np.float64)
+    gcur = scaled_grid(grid, math.sqrt(n_total / n))
+    cat = initial_categories(gcur, x, y, prm)
+    dprev = np.full(n, -1.0)
+    hybrid = mode == "hybrid"
+    method = "cvd" if mode == "cvd" else "dm"
+    mesh, retri, xl, yl = None, True, None, None
+    prev, switch_iter, stop_iter, reason, hist, adds = None, -1, -1, 0, [], []
+    for it in range(max_iter):
+        ran = method
+        if method == "dm":
+            if retri or mesh is None:
+                mesh = triangulate(gcur, x, y, nthreads, prm)
+                xl, yl = x.copy(), y.copy()
+            q = quality(x, y, mesh.tri, mesh.valid)
+            xn, yn, cn, moved, _, _ = dm_step(gcur, x, y, cat, mesh, xl, yl, prm)
+            retri = moved > 0
+            dn = np.sqrt((xn - x) * (xn - x) + (yn - y) * (yn - y))
+        else:
+            mesh = triangulate(gcur, x, y, nthreads, prm)
+            q = quality(x, y, mesh.tri, mesh.valid)
+            xn, yn, cn, dn, _, _ = cvd_step(gcur, x, y, cat, dprev, nthreads, prm)
+        cur = (q["half_mean_alpha"], q["half_mean_beta"], q["max_alpha"])
+        step = np.sqrt((xn - x) * (xn - x) + (yn - y) * (yn - y))
+        moving = bool(np.any((cat == CAT_INNER) & (step >= prm.fac_end * cell_h(gcur, x, y))))
+        rel = None
+        if prev is not None and q["ntri"] > 0 and min(prev) > 0:
+            rel = tuple(abs(c - p) / p for c, p in zip(cur, prev))
+        stop, add = False, 0
+        if n < n_total:
+            if rel is not None and rel[0] < t_add and rel[1] < t_add:
+                add = min(int(math.floor(fac_add * n)), n_total - n)
+        elif hybrid and method == "dm":
+            if rel is not None and rel[0] < t_switch:
+                method = "cvd"
+                switch_iter = it
+        elif rel is not None and rel[0] < t_quality and rel[1] < t_quality and rel[2] < t_amax:
+            stop, reason = True, STOP_QUALITY
+        elif not moving:
+            stop, reason = True, STOP_MOVEMENT
+        hist.append({"method": ran, "n": n, "quality": cur, "rel": rel, "moving": moving})
+        prev = cur if q["ntri"] > 0 else None
+        x, y, cat, dprev = xn, yn, cn, dn
+        if add > 0:
+            # the mesh of this iteration at the updated positions picks the triangles
+            gx, gy = added_points(gcur, x, y, mesh, add, prm)
+            n += add
+            gcur = scaled_grid(grid, math.sqrt(n_total / n))
+            x = np.concatenate([x, gx])
+            y = np.concatenate([y, gy])
+            cat = np.concatenate([cat, initial_categories(gcur, gx, gy, prm)])
+            dprev = np.concatenate([dprev, np.full(add, -1.0)])
+            adds.append((it, add))
+            prev, retri = None, True
+        if stop:
+            stop_iter = it
+            break
+    return x, y, cat, {"iters": len(hist), "adds": adds, "switch_iter": switch_iter, "stop_iter": stop_iter,
                        "reason": reason, "history": hist}
