@@ -140,6 +140,8 @@ typedef struct {
   int32_t reason;      /* TRIME_STOP_*                                      */
   int32_t moving;      /* an inner point moved >= fac_end*h in the iteration */
   int32_t have_prev;   /* prev holds the statistics of the previous iteration */
+  int32_t growing;     /* points are still to be added (trime_run_growing)  */
+  int32_t add_request; /* the iteration just run asks for new points        */
   int32_t gate[8];     /* per-iteration kernel gates (internal)             */
   double prev[3];      /* M_1/2(alpha), M_1/2(beta), max alpha: previous    */
   double last[3];      /* the same, iteration just run                      */
@@ -238,6 +240,13 @@ typedef struct {
   /* optional hipEvent_t pair (caller-owned, may be null): recorded just
      before and after the fused cell kernel of each extraction / CVD step */
   void *ev_cells[2];
+  /* -- point addition (Sec. 3.6) -- */
+  int64_t n_cap;           /* caller: capacity for added points (0 -> n); the
+                              workspace is laid out for n_cap points       */
+  double h_scale;          /* every h of the grid times this (0 -> 1): a grid
+                              built for N points used with n points takes
+                              sqrt(N / n) (Sec. 3.7)                        */
+  int64_t nkeys_cap;       /* bin keys the workspace holds (set by bind)    */
 } trime_state;
 
 /* A fixed hybrid schedule: segments (method, iterations) run in order. */
@@ -371,6 +380,50 @@ typedef struct {
   double t_switch;     /* T_switch_quality (Table 8: 0.0015)                 */
 } trime_adaptive;
 trime_status trime_step_adaptive(trime_state *st, const trime_adaptive *cfg, void *stream);
+
+/* ---- point addition (Sec. 3.6) ---------------------------------------------
+   trime_add_points appends n_add points to a state: the centroids of the
+   n_add valid triangles of the stored triangulation (as the last extraction,
+   DistMesh triangulation or CVD step left it) with the largest ratio of
+   circumradius to the local desired edge length h, at the current positions:
+   h of the grid cell holding the centroid (clamped to the grid), with the
+   state's h_scale.  Ties in the ratio go to the smaller (owner id, second id)
+   of the triangle (owner: its smallest id, first in CCW order), so the
+   selection is unique.  The circumradius is
+   sqrt(|ab|^2 |bc|^2 |ca|^2) / (2 |(b - a) x (c - a)|), the centroid
+   ((x_a + x_b) + x_c) / 3, in FP64.  The new points take the ids n, n + 1,
+   ... in the order of (owner id, second id) of their triangles, d_prev = -1,
+   and the category (Sec. 3.5) and octagon span of their position under
+   h_scale_after, which becomes the state's h_scale (0: h_scale unchanged).
+   Afterwards the adjacency is stale and the next DistMesh iteration of an
+   adaptive run re-triangulates (stats->retri_flag = 1, have_prev = 0).  The
+   call synchronises the stream.  Errors: TRIME_EINVAL for n_add < 0,
+   n + n_add > n_cap, more points than valid triangles or a negative or
+   non-finite h_scale_after; TRIME_ECAPACITY when the valid triangles
+   outnumber the key buffer (max_deg n_cap / 4 keys, 4 n_cap for max_deg 16). */
+trime_status trime_add_points(trime_state *st, int64_t n_add, double h_scale_after, void *stream);
+
+/* An adaptive run with point addition (Sec. 3.6): the state starts with its
+   current n points (fac_init N_total of them in the paper), loaded with
+   h_scale = sqrt(n_total / n) (the grid is built for n_total points), and
+   grows to n_total <= n_cap.  While n < n_total an iteration whose relative
+   changes of M_1/2(alpha) and M_1/2(beta) are both below t_add adds
+   min(floor(fac_add n), n_total - n) points with trime_add_points, h_scale
+   becoming sqrt(n_total / n) for the new n; the switch and the termination
+   tests of trime_step_adaptive apply once all points are in.  The run reads
+   the control block after every iteration (synchronising; not for graph
+   capture) and returns once the run has stopped or after max_iter
+   iterations; read the outcome with trime_stats_read.  Errors: as
+   trime_step_adaptive and trime_add_points, and TRIME_EINVAL for n_total
+   outside [n, n_cap], a negative t_add, fac_add <= 0 or an h_scale other
+   than sqrt(n_total / n). */
+typedef struct {
+  trime_adaptive base;  /* mode, max_iter and the Table 8 thresholds      */
+  int64_t n_total;      /* N_total                                        */
+  double t_add;         /* T_add_quality (Table 8: 0.002)                 */
+  double fac_add;       /* fac_add (Table 8: 0.6)                         */
+} trime_growing;
+trime_status trime_run_growing(trime_state *st, const trime_growing *cfg, void *stream);
 
 /* Mesh quality of the state's valid triangles (Eq. 10-11) into stats. */
 trime_status trime_quality(trime_state *st, void *stream);

@@ -172,6 +172,23 @@ static trime_status bin_geometry(trime_state *st, void *stream) {
   return TRIME_OK;
 }
 
+// The bin keys of the capacity n_cap (more points, smaller bins, more keys).
+static trime_status cap_geometry(trime_state *st) {
+  st->nkeys_cap = st->nkeys;
+  if (st->n_cap > st->n) {
+    trime_state t = *st;
+    t.n = st->n_cap;
+    trime_status e = bin_geometry(&t, nullptr);  // area_sel is known by now
+    if (e) return e;
+    st->nkeys_cap = t.nkeys > st->nkeys ? t.nkeys : st->nkeys;
+  }
+  return TRIME_OK;
+}
+
+// The int32 queue: the FP64 replay, exact and deferred-centroid queues
+// (3 (n + 1) + CQ_STRIDE n), and room for the point-addition selection.
+static int64_t queue_ints(int64_t n) { return 3 * (n + 1) + (int64_t)CQ_STRIDE * n + 512; }
+
 struct Layout {
   size_t off = 0;
   char *base;
@@ -183,8 +200,11 @@ struct Layout {
   }
 };
 
+// Sizes follow the capacity n_cap (points that trime_add_points may add)
+// and the bin keys of that many points.
 static void layout(trime_state *st, Layout &L) {
-  int64_t n = st->n;
+  const int64_t n = st->n_cap > st->n ? st->n_cap : st->n;
+  const int64_t nkeys = st->nkeys_cap > st->nkeys ? st->nkeys_cap : st->nkeys;
   int64_t md = defaults_deg(st);
   for (int b = 0; b < 2; b++) {
     st->pos[b].x = L.take<double>(n);
@@ -205,12 +225,12 @@ static void layout(trime_state *st, Layout &L) {
   st->key = L.take<int32_t>(n);
   st->rank = L.take<int32_t>(n);
   st->order = L.take<int32_t>(n);
-  st->bin_start = L.take<int32_t>(st->nkeys + 1);
-  st->bin_fill = L.take<int32_t>(st->nkeys);
-  int64_t scan_n = st->nkeys > n ? st->nkeys : n;
+  st->bin_start = L.take<int32_t>(nkeys + 1);
+  st->bin_fill = L.take<int32_t>(nkeys);
+  int64_t scan_n = nkeys > n ? nkeys : n;
   st->scan_tmp = L.take<int32_t>(scan_tmp_ints(scan_n) + 1);
   // FP64 replay queue, exact queue, deferred-centroid queue and its cells
-  st->queue = L.take<int32_t>(3 * (n + 1) + (size_t)CQ_STRIDE * n);
+  st->queue = L.take<int32_t>(queue_ints(n));
   st->counters = L.take<int32_t>(CNT_NCOUNTERS);
   int64_t np = dm_partials(n);
   st->partials = L.take<double>(2 * (np > 1 ? np : 1));
@@ -219,6 +239,9 @@ static void layout(trime_state *st, Layout &L) {
 
 static trime_status state_ok(const trime_state *st) {
   if (!st || st->n <= 0 || st->n > (int64_t)1 << 30) return fail(TRIME_EINVAL, "state: bad n");
+  if (st->n_cap != 0 && (st->n_cap < st->n || st->n_cap > (int64_t)1 << 30))
+    return fail(TRIME_EINVAL, "state: n_cap must be 0 or in [n, 2^30]");
+  if (!(st->h_scale >= 0.0) || !isfinite(st->h_scale)) return fail(TRIME_EINVAL, "state: bad h_scale");
   if (st->precision != TRIME_FP64 && st->precision != TRIME_FP32)
     return fail(TRIME_EINVAL, "state: bad precision");
   if (!grid_ok(&st->grid)) return fail(TRIME_EINVAL, "state: bad grid");
@@ -235,6 +258,8 @@ trime_status trime_state_workspace_bytes(const trime_state *st_in, size_t *bytes
   trime_state st = *st_in;
   e = bin_geometry(&st, 0);
   if (e) return e;
+  e = cap_geometry(&st);
+  if (e) return e;
   Layout L;
   L.base = nullptr;
   layout(&st, L);
@@ -248,6 +273,8 @@ trime_status trime_state_bind(trime_state *st, void *d_ws, size_t bytes, void *s
   if (!d_ws) return fail(TRIME_EINVAL, "trime_state_bind: null workspace");
   if (((uintptr_t)d_ws) & 255) return fail(TRIME_EINVAL, "trime_state_bind: workspace not 256-aligned");
   e = bin_geometry(st, stream);
+  if (e) return e;
+  e = cap_geometry(st);
   if (e) return e;
   Layout probe;
   probe.base = nullptr;
@@ -328,6 +355,7 @@ static KArgs make_args(const trime_state *st) {
   a.partials = st->partials;
   a.stats = st->stats;
   a.prm = st->params;
+  a.h_scale = st->h_scale > 0 ? st->h_scale : 1.0;
   a.precision = st->precision;
   a.ev0 = st->ev_cells[0];
   a.ev1 = st->ev_cells[1];
@@ -491,38 +519,151 @@ trime_status trime_step_hybrid(trime_state *st, const trime_schedule *sch, void 
   return TRIME_OK;
 }
 
+static trime_status adapt_cfg_ok(const trime_adaptive *cfg, const char *who) {
+  static thread_local char msg[128];
+  const char *why = nullptr;
+  if (!cfg)
+    why = "null configuration";
+  else if (cfg->mode != TRIME_ADAPT_DM && cfg->mode != TRIME_ADAPT_CVD && cfg->mode != TRIME_ADAPT_HYBRID)
+    why = "unknown mode";
+  else if (cfg->max_iter < 0)
+    why = "negative iteration count";
+  else if (!(cfg->t_quality >= 0.0) || !(cfg->t_amax >= 0.0) || !(cfg->t_switch >= 0.0))
+    why = "thresholds must be >= 0";
+  if (!why) return TRIME_OK;
+  snprintf(msg, sizeof msg, "%s: %s", who, why);
+  return fail(TRIME_EINVAL, msg);
+}
+
+// One iteration of an adaptive run: every group of kernels runs only when
+// its gate is raised; the buffer swaps are the same whatever the gates say.
+static void adapt_iteration(trime_state *st, const trime_adaptive *cfg, double t_add, hipStream_t s) {
+  launch_adapt_pre(make_args(st), s);
+  bin_points(st, s, adapt_gate(st, G_BIN));
+  extract(st, s, adapt_gate(st, G_DMTRI));  // DistMesh, re-triangulating
+  KArgs a = make_args(st);
+  a.cond = adapt_gate(st, G_DMQ);  // DistMesh on the last triangulation: its quality now
+  launch_quality(a, s);
+  a.cond = adapt_gate(st, G_CVD);
+  launch_stats_reset(a, 0, s);
+  launch_cells(a, MODE_CVD, st->grid.dtype_bytes, s);
+  launch_finish_extract(a, s);
+  a.cond = adapt_gate(st, G_DM);
+  launch_dm(a, st->grid.dtype_bytes, s);
+  a.cond = nullptr;
+  launch_adapt_end(a, cfg->mode == TRIME_ADAPT_HYBRID, cfg->t_quality, cfg->t_amax, cfg->t_switch, t_add, s);
+  st->cur_pos ^= 1;
+}
+
 trime_status trime_step_adaptive(trime_state *st, const trime_adaptive *cfg, void *stream) {
   trime_status e = bound_ok(st);
   if (e) return e;
-  if (!cfg) return fail(TRIME_EINVAL, "trime_step_adaptive: null configuration");
-  if (cfg->mode != TRIME_ADAPT_DM && cfg->mode != TRIME_ADAPT_CVD && cfg->mode != TRIME_ADAPT_HYBRID)
-    return fail(TRIME_EINVAL, "trime_step_adaptive: unknown mode");
-  if (cfg->max_iter < 0) return fail(TRIME_EINVAL, "trime_step_adaptive: negative iteration count");
-  if (!(cfg->t_quality >= 0.0) || !(cfg->t_amax >= 0.0) || !(cfg->t_switch >= 0.0))
-    return fail(TRIME_EINVAL, "trime_step_adaptive: thresholds must be >= 0");
+  e = adapt_cfg_ok(cfg, "trime_step_adaptive");
+  if (e) return e;
   hipStream_t s = (hipStream_t)stream;
-  const int hybrid = cfg->mode == TRIME_ADAPT_HYBRID;
   launch_adapt_init(make_args(st), cfg->mode == TRIME_ADAPT_CVD ? TRIME_METHOD_CVD : TRIME_METHOD_DM, s);
   for (int it = 0; it < cfg->max_iter; it++) {
-    launch_adapt_pre(make_args(st), s);
-    // every group of kernels runs only when its gate is raised; the buffer
-    // swaps are the same whatever the gates say
-    bin_points(st, s, adapt_gate(st, G_BIN));
-    extract(st, s, adapt_gate(st, G_DMTRI));  // DistMesh, re-triangulating
-    KArgs a = make_args(st);
-    a.cond = adapt_gate(st, G_DMQ);  // DistMesh on the last triangulation: its quality now
-    launch_quality(a, s);
-    a.cond = adapt_gate(st, G_CVD);
-    launch_stats_reset(a, 0, s);
-    launch_cells(a, MODE_CVD, st->grid.dtype_bytes, s);
-    launch_finish_extract(a, s);
-    a.cond = adapt_gate(st, G_DM);
-    launch_dm(a, st->grid.dtype_bytes, s);
-    a.cond = nullptr;
-    launch_adapt_end(a, hybrid, cfg->t_quality, cfg->t_amax, cfg->t_switch, s);
-    st->cur_pos ^= 1;
+    adapt_iteration(st, cfg, -1.0, s);
     e = check_hip("trime_step_adaptive");
     if (e) return e;
+  }
+  return TRIME_OK;
+}
+
+// ------------------------------------------------------ point addition --
+//
+// Scratch: the int32 queue holds the valid-triangle count per slot and its
+// scan, the selected count per owner id and its scan, then the selection
+// state; the selection keys overwrite the adjacency (rebuilt by the next
+// triangulation, which an addition always forces).
+
+static trime_status add_points(trime_state *st, int64_t n_add, double h_after, int growing, hipStream_t s) {
+  const int64_t n = st->n;
+  const int64_t cap = st->n_cap > n ? st->n_cap : n;
+  if (n_add < 0 || n + n_add > cap) return fail(TRIME_EINVAL, "trime_add_points: n + n_add exceeds n_cap");
+  KArgs a = make_args(st);
+  int32_t *cnt = st->queue, *off = cnt + (n + 1), *cnt_id = off + (n + 1), *base = cnt_id + (n + 1);
+  void *sel = (void *)(st->queue + ((4 * (n + 1) + 63) & ~(int64_t)63));
+  const int64_t sel_end = ((4 * (n + 1) + 63) & ~(int64_t)63) + (int64_t)((grow_sel_bytes() + 3) / 4);
+  if (sel_end > queue_ints(cap)) return fail(TRIME_ECAPACITY, "trime_add_points: selection scratch too small");
+  if (n_add > 0) {
+    launch_grow_count(a, cnt, s);
+    scan_i32(cnt, off, n, st->scan_tmp, s);
+    int32_t nk = 0;
+    TRY_HIP(hipMemcpyAsync(&nk, off + n, sizeof nk, hipMemcpyDeviceToHost, s), "read triangle count");
+    TRY_HIP(hipStreamSynchronize(s), "read triangle count (sync)");
+    if (n_add > nk) return fail(TRIME_EINVAL, "trime_add_points: more points than valid triangles");
+    const int64_t key_cap = (int64_t)defaults_deg(st) * cap * 4 / (int64_t)grow_key_bytes();
+    if (nk > key_cap) return fail(TRIME_ECAPACITY, "trime_add_points: too many triangles for the key buffer");
+    launch_grow_select(a, off, st->adj, nk, sel, n_add, s);
+    launch_grow_mark(a, sel, cnt_id, s);
+    scan_i32(cnt_id, base, n, st->scan_tmp, s);
+    if (h_after > 0) st->h_scale = h_after;
+    KArgs b = make_args(st);  // new points: categories and spans at the new h
+    const trime_posbuf &P = st->pos[st->cur_pos];
+    const trime_ordbuf &O = st->ord[st->cur_ord];
+    launch_grow_write(b, a.h_scale, st->grid.dtype_bytes, sel, base, P.x, P.y, P.dprev, P.cat, O.id, O.span, O.xl,
+                      O.yl, s);
+    st->n = n + n_add;
+    trime_status e = bin_geometry(st, s);
+    if (e) return e;
+    if (st->nkeys > (st->nkeys_cap > 0 ? st->nkeys_cap : st->nkeys))
+      return fail(TRIME_ECAPACITY, "trime_add_points: bin keys beyond the workspace");
+  }
+  launch_grow_state(make_args(st), growing, n_add > 0, s);
+  TRY_HIP(hipStreamSynchronize(s), "trime_add_points (sync)");
+  return check_hip("trime_add_points");
+}
+
+trime_status trime_add_points(trime_state *st, int64_t n_add, double h_scale_after, void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  if (!(h_scale_after >= 0.0) || !isfinite(h_scale_after))
+    return fail(TRIME_EINVAL, "trime_add_points: bad h_scale_after");
+  if (n_add < 0 || n_add > (st->n_cap > st->n ? st->n_cap : st->n) - st->n)
+    return fail(TRIME_EINVAL, "trime_add_points: n_add must be in [0, n_cap - n]");
+  hipStream_t s = (hipStream_t)stream;
+  trime_adapt_ctl c;
+  TRY_HIP(hipMemcpyAsync(&c, &st->stats->adapt, sizeof c, hipMemcpyDeviceToHost, s), "read control block");
+  TRY_HIP(hipStreamSynchronize(s), "read control block (sync)");
+  return add_points(st, n_add, h_scale_after, c.growing, s);
+}
+
+trime_status trime_run_growing(trime_state *st, const trime_growing *cfg, void *stream) {
+  trime_status e = bound_ok(st);
+  if (e) return e;
+  if (!cfg) return fail(TRIME_EINVAL, "trime_run_growing: null configuration");
+  e = adapt_cfg_ok(&cfg->base, "trime_run_growing");
+  if (e) return e;
+  const int64_t cap = st->n_cap > st->n ? st->n_cap : st->n;
+  if (cfg->n_total < st->n || cfg->n_total > cap)
+    return fail(TRIME_EINVAL, "trime_run_growing: n_total must be in [n, n_cap]");
+  if (!(cfg->t_add >= 0.0) || !(cfg->fac_add > 0.0) || !isfinite(cfg->fac_add))
+    return fail(TRIME_EINVAL, "trime_run_growing: t_add must be >= 0 and fac_add > 0");
+  const double h0 = sqrt((double)cfg->n_total / (double)st->n);
+  const double hs = st->h_scale > 0 ? st->h_scale : 1.0;
+  if (fabs(hs - h0) > 1e-15 * h0)
+    return fail(TRIME_EINVAL, "trime_run_growing: the state's h_scale must be sqrt(n_total / n)");
+  hipStream_t s = (hipStream_t)stream;
+  const trime_adaptive *base = &cfg->base;
+  launch_adapt_init(make_args(st), base->mode == TRIME_ADAPT_CVD ? TRIME_METHOD_CVD : TRIME_METHOD_DM, s);
+  launch_grow_state(make_args(st), st->n < cfg->n_total, 0, s);
+  for (int it = 0; it < base->max_iter; it++) {
+    adapt_iteration(st, base, cfg->t_add, s);
+    trime_adapt_ctl c;
+    TRY_HIP(hipMemcpyAsync(&c, &st->stats->adapt, sizeof c, hipMemcpyDeviceToHost, s), "read control block");
+    TRY_HIP(hipStreamSynchronize(s), "read control block (sync)");
+    e = check_hip("trime_run_growing");
+    if (e) return e;
+    if (c.stopped) break;
+    if (c.add_request) {
+      int64_t n_add = (int64_t)floor(cfg->fac_add * (double)st->n);
+      if (n_add > cfg->n_total - st->n) n_add = cfg->n_total - st->n;
+      if (n_add <= 0) continue;
+      const int64_t n_new = st->n + n_add;
+      e = add_points(st, n_add, sqrt((double)cfg->n_total / (double)n_new), n_new < cfg->n_total, s);
+      if (e) return e;
+    }
   }
   return TRIME_OK;
 }

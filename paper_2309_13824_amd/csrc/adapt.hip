@@ -22,6 +22,8 @@ __global__ void k_adapt_init(KArgs a, int method) {
   c->reason = TRIME_STOP_NONE;
   c->moving = 0;
   c->have_prev = 0;
+  c->growing = 0;
+  c->add_request = 0;
   for (int g = 0; g < 8; g++) c->gate[g] = 0;
   for (int q = 0; q < 3; q++) {
     c->prev[q] = 0.0;
@@ -77,8 +79,10 @@ __global__ __launch_bounds__(256) void k_adapt_copy(KArgs a) {
   a.catn[k] = a.cat[k];
 }
 
-// The decisions after iteration c->iters (one thread).
-__global__ void k_adapt_post(KArgs a, int hybrid, double t_quality, double t_amax, double t_switch) {
+// The decisions after iteration c->iters (one thread).  While points are
+// still to be added (Sec. 3.6) the only decision is whether to add them:
+// both half-mean changes below t_add; switch and termination wait.
+__global__ void k_adapt_post(KArgs a, int hybrid, double t_quality, double t_amax, double t_switch, double t_add) {
   trime_adapt_ctl *c = &a.stats->adapt;
   if (c->stopped) return;
   const trime_stats *S = a.stats;
@@ -96,7 +100,10 @@ __global__ void k_adapt_post(KArgs a, int hybrid, double t_quality, double t_ama
     c->last[q] = cur[q];
     c->rel[q] = rel_ok ? fabs(cur[q] - c->prev[q]) / c->prev[q] : -1.0;
   }
-  if (hybrid && c->method == TRIME_METHOD_DM) {
+  c->add_request = 0;
+  if (c->growing) {
+    if (rel_ok && c->rel[0] < t_add && c->rel[1] < t_add) c->add_request = 1;
+  } else if (hybrid && c->method == TRIME_METHOD_DM) {
     if (rel_ok && c->rel[0] < t_switch) {
       c->method = TRIME_METHOD_CVD;
       c->switch_iter = it;
@@ -125,7 +132,7 @@ void launch_adapt_pre(const KArgs &a, hipStream_t s) {
 const int32_t *adapt_gate(const trime_state *st, int g) { return &st->stats->adapt.gate[g]; }
 
 void launch_adapt_end(const KArgs &a, int hybrid, double t_quality, double t_amax, double t_switch,
-                      hipStream_t s) {
+                      double t_add, hipStream_t s) {
   int nb = (int)((a.n + 255) / 256);
   if (nb) {
     KArgs c = a;
@@ -134,7 +141,7 @@ void launch_adapt_end(const KArgs &a, int hybrid, double t_quality, double t_ama
     c.cond = &a.stats->adapt.gate[G_RUN];
     hipLaunchKernelGGL(k_adapt_move, dim3(nb), dim3(256), 0, s, c);
   }
-  hipLaunchKernelGGL(k_adapt_post, dim3(1), dim3(1), 0, s, a, hybrid, t_quality, t_amax, t_switch);
+  hipLaunchKernelGGL(k_adapt_post, dim3(1), dim3(1), 0, s, a, hybrid, t_quality, t_amax, t_switch, t_add);
 }
 
 }  // namespace trime

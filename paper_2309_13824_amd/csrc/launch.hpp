@@ -126,9 +126,24 @@ void launch_set_flag(const KArgs &a, hipStream_t s);
 enum { G_BIN = 0, G_DMTRI = 1, G_DMQ = 2, G_CVD = 3, G_DM = 4, G_COPY = 5, G_RUN = 6 };
 void launch_adapt_init(const KArgs &a, int method, hipStream_t s);
 void launch_adapt_pre(const KArgs &a, hipStream_t s);
+// t_add < 0: no point addition (the request is never raised)
 void launch_adapt_end(const KArgs &a, int hybrid, double t_quality, double t_amax, double t_switch,
-                      hipStream_t s);
+                      double t_add, hipStream_t s);
 const int32_t *adapt_gate(const trime_state *st, int g);
+
+// point addition (grow.hip); the selection keys and state live in the
+// caller's scratch (grow_key_bytes / grow_sel_bytes each)
+void launch_grow_count(const KArgs &a, int32_t *cnt, hipStream_t s);
+void launch_grow_select(const KArgs &a, const int32_t *off, void *keys, int64_t nk, void *sel, int64_t n_add,
+                        hipStream_t s);
+void launch_grow_mark(const KArgs &a, const void *sel, int32_t *cnt_id, hipStream_t s);
+// a: the state after the addition's h scale; h_sel: the selection's
+void launch_grow_write(const KArgs &a, double h_sel, int grid_bytes, const void *sel, const int32_t *base, double *x,
+                       double *y, double *dprev, uint8_t *cat, int32_t *id, float *span, double *xl, double *yl,
+                       hipStream_t s);
+void launch_grow_state(const KArgs &a, int growing, int added, hipStream_t s);
+size_t grow_key_bytes();
+size_t grow_sel_bytes();
 int64_t grid_partials(int nx, int ny);
 void launch_grid_build(const GridPrims &g, int dtype_bytes, void *sdf, void *mu, uint8_t *cat,
                        float *hcell, trime_grid_scalars *scal, double *part, hipStream_t s);

@@ -74,6 +74,9 @@ struct KArgs {
   // When set, the binning and extraction kernels work only if *cond != 0
   // (the re-triangulation flag of a DistMesh step, read on the device).
   const int32_t *cond;
+  // every h of the grid times this (the grid built for more points than are
+  // in the mesh, Sec. 3.7)
+  double h_scale;
 };
 
 // Whether a conditional launch has work (uniform over the grid).
@@ -120,9 +123,13 @@ TRIME_D double bilinear(const KArgs &a, const void *f, int64_t cell, double tx, 
 }
 
 TRIME_D uint8_t cell_cat(const KArgs &a, int64_t cell) { return gld(a.cgrid, cell); }
-TRIME_D float cell_h(const KArgs &a, int64_t cell) { return gld(a.hcell, cell); }
+// h of a cell, scaled for the current point count (fl32(h * h_scale))
+TRIME_D float cell_h(const KArgs &a, int64_t cell) {
+  const float h = gld(a.hcell, cell);
+  return a.h_scale == 1.0 ? h : (float)((double)h * a.h_scale);
+}
 TRIME_D double h_avg(const KArgs &a) {
-  return gld((const double *)a.scal, 1);  // trime_grid_scalars.h_avg
+  return gld((const double *)a.scal, 1) * a.h_scale;  // trime_grid_scalars.h_avg
 }
 
 // geps of a cell (Sec. 3.7): fac_geps * min(h_cell, h_avg).

@@ -3,6 +3,7 @@ calls the C ABI (paper_2309_13824_amd.trime) for every step."""
 from __future__ import annotations
 
 import ctypes as C
+import math
 
 import numpy as np
 
@@ -32,10 +33,13 @@ class Mesher:
     """Grid + state of one workload on the current HIP device."""
 
     def __init__(self, wl, precision=T.FP64, max_deg=16, params=None, bin_density=0.0, device="cuda",
-                 grid=None):
+                 grid=None, n_init=None):
         """grid: None builds the geometry grid on the GPU (trime_sdf_grid_build);
         otherwise an object with sdf, mu, cat, hcell (node / cell arrays), H and
-        h_avg whose arrays are uploaded as the grid (a grid built elsewhere)."""
+        h_avg whose arrays are uploaded as the grid (a grid built elsewhere).
+        n_init: the state starts with the first n_init of the workload's
+        points and has room for all of them (point addition, run_growing);
+        the grid is built for all, h scaled by sqrt(N / n_init)."""
         import torch
         T.lib()
         self.torch = torch
@@ -64,7 +68,10 @@ class Mesher:
             area = float(np.count_nonzero(grid.cat)) * g.dx * g.dy  # bin sizing only
             self.scal = torch.tensor([grid.H, grid.h_avg, area, 0.0], dtype=torch.float64, device=self.dev)
         st = T.State()
-        st.n = wl.n
+        n0 = wl.n if n_init is None else int(n_init)
+        st.n = n0
+        st.n_cap = wl.n
+        st.h_scale = math.sqrt(wl.n / n0) if n0 < wl.n else 0.0
         st.precision = precision
         st.max_deg = max_deg
         st.bin_density = bin_density
@@ -76,13 +83,13 @@ class Mesher:
         nbytes = T.state_workspace_bytes(st)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.dev)
         T.state_bind(st, self.ws)
-        self.n = wl.n
+        self.n = n0
 
     # ---------------------------------------------------------------- input
     def load(self, x=None, y=None):
         torch = self.torch
-        x = self.wl.x if x is None else x
-        y = self.wl.y if y is None else y
+        x = self.wl.x[:self.n] if x is None else x
+        y = self.wl.y[:self.n] if y is None else y
         self.x_in = torch.as_tensor(np.ascontiguousarray(x, np.float64), device=self.dev)
         self.y_in = torch.as_tensor(np.ascontiguousarray(y, np.float64), device=self.dev)
         T.state_load(self.state, self.x_in, self.y_in)
@@ -133,6 +140,18 @@ class Mesher:
         control block: iterations run, switch and stop iterations, reason."""
         T.step_adaptive(self.state, mode, max_iter, t_quality, t_amax, t_switch)
         return self.stats_raw().as_dict()["adapt"]
+
+    def run_growing(self, mode, max_iter, t_add=0.002, fac_add=0.6, t_quality=0.001, t_amax=0.005,
+                    t_switch=0.0015):
+        """Adaptive run with point addition up to all of the workload's
+        points (Sec. 3.6); returns the control block like step_adaptive."""
+        T.run_growing(self.state, mode, max_iter, self.wl.n, t_add, fac_add, t_quality, t_amax, t_switch)
+        self.n = int(self.state.n)
+        return self.stats_raw().as_dict()["adapt"]
+
+    def add_points(self, n_add, h_scale_after=0.0):
+        T.add_points(self.state, n_add, h_scale_after)
+        self.n = int(self.state.n)
 
     def quality(self):
         T.quality(self.state)

@@ -66,7 +66,7 @@ class Params(C.Structure):
 class AdaptCtl(C.Structure):
     _fields_ = [("method", C.c_int32), ("stopped", C.c_int32), ("iters", C.c_int32), ("switch_iter", C.c_int32),
                 ("stop_iter", C.c_int32), ("reason", C.c_int32), ("moving", C.c_int32), ("have_prev", C.c_int32),
-                ("gate", C.c_int32 * 8), ("prev", C.c_double * 3), ("last", C.c_double * 3),
+                ("growing", C.c_int32), ("add_request", C.c_int32), ("gate", C.c_int32 * 8), ("prev", C.c_double * 3), ("last", C.c_double * 3),
                 ("rel", C.c_double * 3)]
 
 
@@ -86,7 +86,8 @@ class Stats(C.Structure):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("hist_beta", "adapt")}
         a = self.adapt
         d["adapt"] = {"method": a.method, "stopped": a.stopped, "iters": a.iters, "switch_iter": a.switch_iter,
-                      "stop_iter": a.stop_iter, "reason": a.reason, "last": tuple(a.last[:]),
+                      "stop_iter": a.stop_iter, "reason": a.reason, "growing": a.growing,
+                      "last": tuple(a.last[:]),
                       "rel": tuple(a.rel[:])}
         d["hist_beta"] = np.array(self.hist_beta[:], np.int64)
         nq = max(self.nq, 1)
@@ -117,7 +118,8 @@ class State(C.Structure):
                 ("counters", C.c_void_p), ("partials", C.c_void_p), ("stats", C.c_void_p),
                 ("nbx", C.c_int32), ("nby", C.c_int32), ("lbits", C.c_int32), ("bx0", C.c_double),
                 ("by0", C.c_double), ("bw", C.c_double), ("area_sel", C.c_double), ("nkeys", C.c_int64),
-                ("ev_cells", C.c_void_p * 2)]
+                ("ev_cells", C.c_void_p * 2), ("n_cap", C.c_int64), ("h_scale", C.c_double),
+                ("nkeys_cap", C.c_int64)]
 
 
 ADAPT_DM, ADAPT_CVD, ADAPT_HYBRID = 0, 1, 2
@@ -127,6 +129,10 @@ STOP_NONE, STOP_QUALITY, STOP_MOVEMENT = 0, 1, 2
 class Adaptive(C.Structure):
     _fields_ = [("mode", C.c_int32), ("max_iter", C.c_int32), ("t_quality", C.c_double), ("t_amax", C.c_double),
                 ("t_switch", C.c_double)]
+
+
+class Growing(C.Structure):
+    _fields_ = [("base", Adaptive), ("n_total", C.c_int64), ("t_add", C.c_double), ("fac_add", C.c_double)]
 
 
 class Schedule(C.Structure):
@@ -143,7 +149,8 @@ EXPORTED = ["trime_last_error", "trime_version", "trime_default_params", "trime_
             "trime_delaunay_extract", "trime_step_dm", "trime_step_cvd", "trime_step_hybrid",
             "trime_quality", "trime_stats_read", "trime_stats_check", "trime_autotune_workspace_bytes",
             "trime_autotune", "trime_batch_graph_create", "trime_graph_launch", "trime_graph_destroy",
-            "trime_step_adaptive", "trime_batch_create", "trime_batch_run", "trime_batch_destroy"]
+            "trime_step_adaptive", "trime_batch_create", "trime_batch_run", "trime_batch_destroy",
+            "trime_add_points", "trime_run_growing"]
 
 _lib = None
 
@@ -188,6 +195,12 @@ def lib(require_gpu: bool = True):
                                                C.POINTER(vp), vp]
         L.trime_graph_launch.argtypes = [vp, vp]
         L.trime_graph_destroy.argtypes = [vp]
+        L.trime_step_adaptive.argtypes = [st, C.POINTER(Adaptive), vp]
+        L.trime_batch_create.argtypes = [C.POINTER(st), C.c_int32, C.c_int32, C.POINTER(vp)]
+        L.trime_batch_run.argtypes = [vp, C.c_int32, vp]
+        L.trime_batch_destroy.argtypes = [vp]
+        L.trime_add_points.argtypes = [st, C.c_int64, C.c_double, vp]
+        L.trime_run_growing.argtypes = [st, C.POINTER(Growing), vp]
         for f in EXPORTED:
             if f not in ("trime_last_error", "trime_version", "trime_default_params"):
                 getattr(L, f).restype = C.c_int
@@ -274,6 +287,23 @@ def step_adaptive(state, mode, max_iter, t_quality=0.001, t_amax=0.005, t_switch
     m = {"dm": ADAPT_DM, "cvd": ADAPT_CVD, "hybrid": ADAPT_HYBRID}[mode]
     cfg = Adaptive(m, int(max_iter), float(t_quality), float(t_amax), float(t_switch))
     _check(lib().trime_step_adaptive(C.byref(state), C.byref(cfg), _stream(stream)))
+
+
+def add_points(state, n_add, h_scale_after=0.0, stream=None):
+    """Appends the centroids of the n_add valid triangles with the largest
+    circumradius / h (synchronises); h_scale_after > 0 becomes the state's
+    h scale (the new points' categories and spans use it)."""
+    _check(lib().trime_add_points(C.byref(state), int(n_add), float(h_scale_after), _stream(stream)))
+
+
+def run_growing(state, mode, max_iter, n_total, t_add=0.002, fac_add=0.6, t_quality=0.001, t_amax=0.005,
+                t_switch=0.0015, stream=None):
+    """Adaptive run with point addition up to n_total points (the state
+    loaded with h_scale = sqrt(n_total / n)); the outcome is in the stats."""
+    m = {"dm": ADAPT_DM, "cvd": ADAPT_CVD, "hybrid": ADAPT_HYBRID}[mode]
+    cfg = Growing(Adaptive(m, int(max_iter), float(t_quality), float(t_amax), float(t_switch)), int(n_total),
+                  float(t_add), float(fac_add))
+    _check(lib().trime_run_growing(C.byref(state), C.byref(cfg), _stream(stream)))
 
 
 def quality(state, stream=None):

@@ -1,6 +1,7 @@
 """The C ABI without a GPU: the library loads, exports every function the
 header declares, and rejects bad arguments on the host before any launch."""
 import ctypes as C
+import math
 import os
 import re
 
@@ -106,6 +107,39 @@ def test_adaptive_configuration_rejected_on_host(T):
         assert b"trime_step_adaptive" in L.trime_last_error()
 
 
+def test_growing_configuration_rejected_on_host(T):
+    """Point addition and growing runs: a capacity below n, n_add outside
+    [0, n_cap - n], a bad h scale, n_total outside [n, n_cap], a negative
+    t_add, fac_add <= 0 and an h_scale other than sqrt(n_total / n) return
+    TRIME_EINVAL on the host (the state only looks bound, as above)."""
+    L = T.lib(require_gpu=False)
+    st = T.State()
+    st.n = 10
+    st.grid = T.Grid(16, 16, 0.0, 0.0, 0.1, 0.1, 8)
+    st.sdf = st.mu = st.cat_grid = st.hcell = st.scal = 256
+    st.stats = 512
+    st.pos[0].x = 768
+    st.n_cap = 5
+    assert L.trime_add_points(C.byref(st), 1, 0.0, None) == 1
+    assert b"n_cap" in L.trime_last_error()
+    st.n_cap = 20
+    for n_add, hs in ((-1, 0.0), (11, 0.0), (1, -1.0), (1, float("inf"))):
+        assert L.trime_add_points(C.byref(st), n_add, hs, None) == 1
+        assert b"trime_add_points" in L.trime_last_error()
+    base = T.Adaptive(T.ADAPT_HYBRID, 10, 0.001, 0.005, 0.0015)
+    assert L.trime_run_growing(C.byref(st), None, None) == 1
+    st.h_scale = math.sqrt(2.0)
+    for n_total, t_add, fac in ((9, 0.002, 0.6), (21, 0.002, 0.6), (20, -0.1, 0.6), (20, 0.002, 0.0),
+                                (20, float("nan"), 0.6)):
+        assert L.trime_run_growing(C.byref(st), C.byref(T.Growing(base, n_total, t_add, fac)), None) == 1
+        assert b"trime_run_growing" in L.trime_last_error()
+    bad_mode = T.Adaptive(9, 10, 0.001, 0.005, 0.0015)
+    assert L.trime_run_growing(C.byref(st), C.byref(T.Growing(bad_mode, 20, 0.002, 0.6)), None) == 1
+    st.h_scale = 1.5  # not sqrt(20 / 10)
+    assert L.trime_run_growing(C.byref(st), C.byref(T.Growing(base, 20, 0.002, 0.6)), None) == 1
+    assert b"h_scale" in L.trime_last_error()
+
+
 def test_batch_arguments_rejected_on_host(T):
     L = T.lib(require_gpu=False)
     out = C.c_void_p()
@@ -137,8 +171,9 @@ def test_struct_sizes_match_header(T):
 #include <stdio.h>
 #include "trime.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(trime_prim), sizeof(trime_sizing), sizeof(trime_grid),
-         sizeof(trime_params), sizeof(trime_stats), sizeof(trime_state), sizeof(trime_grid_scalars));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(trime_prim), sizeof(trime_sizing), sizeof(trime_grid),
+         sizeof(trime_params), sizeof(trime_stats), sizeof(trime_state), sizeof(trime_grid_scalars),
+         sizeof(trime_adaptive), sizeof(trime_growing));
   return 0;
 }
 '''
@@ -150,4 +185,5 @@ int main(void) {
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     sizes = [int(v) for v in out]
     assert sizes == [C.sizeof(T.Prim), C.sizeof(T.Sizing), C.sizeof(T.Grid), C.sizeof(T.Params),
-                     C.sizeof(T.Stats), C.sizeof(T.State), C.sizeof(T.GridScalars)]
+                     C.sizeof(T.Stats), C.sizeof(T.State), C.sizeof(T.GridScalars), C.sizeof(T.Adaptive),
+                     C.sizeof(T.Growing)]

@@ -1,0 +1,150 @@
+"""Point addition (Sec. 3.6) on the GPU through the C ABI against the
+oracle: the selected triangles and the new points of one addition, and
+whole growing runs (additions, then the switch and termination tests of the
+adaptive run)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2309_13824_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+TQ, TA, TS, TADD = 0.001, 0.005, 0.0015, 0.002  # Table 8
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2309_13824_amd import trime
+    trime.lib()
+    return trime
+
+
+def mesher(wl, prec, og, n_init):
+    from paper_2309_13824_amd.mesher import Mesher
+    m = Mesher(wl, precision=prec, grid=og, n_init=n_init)
+    m.load()
+    return m
+
+
+def workload(name):
+    return I.disk() if name == "disk" else I.annulus(n=4000, grid_n=256)
+
+
+def h_of(og, x, y):
+    fx = np.floor((x - og.x0) * (1.0 / og.dx)).astype(int)
+    fy = np.floor((y - og.y0) * (1.0 / og.dy)).astype(int)
+    return og.hcell[fy * (og.nx - 1) + fx].astype(np.float64)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("name,n_init,n_add", [("disk", 1200, 300), ("annulus", 2500, 1000), ("disk", 1200, 1)])
+def test_added_points_match_oracle(orc, T, name, n_init, n_add, prec):
+    """From the triangulation of the first n_init points: the new points,
+    their ids and categories equal the oracle's bit for bit (the selection
+    and the centroids are FP64 in both precisions), the old points are
+    untouched and the count is n_init + n_add."""
+    wl = I.disk() if name == "disk" else I.annulus(n=4000, grid_n=256)
+    og = orc.build_grid(wl)
+    hs0, hs1 = math.sqrt(wl.n / n_init), math.sqrt(wl.n / (n_init + n_add))
+    g0, g1 = orc.scaled_grid(og, hs0), orc.scaled_grid(og, hs1)
+    x0, y0 = wl.x[:n_init], wl.y[:n_init]
+    mesh = orc.triangulate(g0, x0, y0, 8)
+    gx, gy = orc.added_points(g0, x0, y0, mesh, n_add)
+    m = mesher(wl, prec, og, n_init)
+    m.bin()
+    m.extract()
+    tri, valid = m.triangles()
+    assert len(tri) == len(mesh.tri) and int(valid.sum()) == int(mesh.valid.sum())
+    c0 = m.points()[2]
+    m.add_points(n_add, hs1)
+    assert m.n == n_init + n_add and m.state.n == n_init + n_add and m.state.h_scale == hs1
+    x, y, c = m.points()
+    assert np.array_equal(x[:n_init], x0) and np.array_equal(y[:n_init], y0) and np.array_equal(c[:n_init], c0)
+    assert np.array_equal(x[n_init:], gx) and np.array_equal(y[n_init:], gy)
+    assert np.array_equal(c[n_init:], orc.initial_categories(g1, gx, gy))
+    assert m.stats_raw().error == 0
+
+
+def test_add_points_edge_cases(orc, T):
+    """n_add = 0 changes nothing; more points than valid triangles and more
+    than the capacity are refused, the state unchanged."""
+    wl = I.disk()
+    og = orc.build_grid(wl)
+    m = mesher(wl, FP64, og, 12)
+    m.bin()
+    m.extract()
+    before = m.points()
+    m.add_points(0)
+    assert m.n == 12
+    with pytest.raises(T.TrimeError):
+        m.add_points(500)  # a dozen points have far fewer triangles
+    with pytest.raises(T.TrimeError):
+        m.add_points(wl.n)  # beyond n_cap - n
+    assert m.n == 12 and m.state.n == 12
+    after = m.points()
+    assert all(np.array_equal(a, b) for a, b in zip(before, after))
+
+
+def decision_margin(info, mode):
+    """Smallest relative distance of a compared change to its threshold over
+    the oracle's run (additions while growing, then switch or termination)."""
+    m = np.inf
+    phase_dm = mode == "hybrid"
+    adds = {it for it, _ in info["adds"]}
+    last_add = max(adds) if adds else -1
+    n_total = info["history"][-1]["n"]
+    for k, h in enumerate(info["history"]):
+        if h["rel"] is None:
+            continue
+        if h["n"] < n_total or k <= last_add:
+            m = min(m, abs(h["rel"][0] - TADD) / TADD, abs(h["rel"][1] - TADD) / TADD)
+        elif phase_dm:
+            m = min(m, abs(h["rel"][0] - TS) / TS)
+            if k == info["switch_iter"]:
+                phase_dm = False
+        else:
+            m = min(m, abs(h["rel"][0] - TQ) / TQ, abs(h["rel"][1] - TQ) / TQ, abs(h["rel"][2] - TA) / TA)
+    return m
+
+
+@pytest.mark.parametrize("name,mode,n_init,max_iter", [("disk", "hybrid", 800, 200), ("disk", "dm", 800, 90),
+                                                       ("annulus", "cvd", 1600, 200)])
+def test_growing_run_matches_oracle(orc, T, name, mode, n_init, max_iter):
+    """FP64: the run grows to all points, switches and stops (DistMesh alone
+    does not stop inside its budget) at the oracle's iterations for the
+    oracle's reason, and the final points agree to FP64 rounding."""
+    wl = workload(name)
+    og = orc.build_grid(wl)
+    x, y, cat, info = orc.run_growing(og, wl.x, wl.y, mode, max_iter, n_init, TADD, 0.6, TQ, TA, TS, nthreads=8)
+    assert (info["stop_iter"] >= 0 or mode == "dm") and len(info["adds"]) >= 1
+    assert decision_margin(info, mode) > 1e-6
+    m = mesher(wl, FP64, og, n_init)
+    ad = m.run_growing(mode, max_iter, TADD, 0.6, TQ, TA, TS)
+    print(name, mode, "oracle", {k: v for k, v in info.items() if k != "history"}, "gpu", ad, flush=True)
+    assert m.n == wl.n and ad["growing"] == 0
+    assert ad["iters"] == info["iters"]
+    assert ad["switch_iter"] == info["switch_iter"]
+    assert ad["stop_iter"] == info["stop_iter"] and ad["reason"] == info["reason"]
+    assert np.allclose(ad["last"], info["history"][-1]["quality"], rtol=1e-9, atol=0)
+    gx, gy, gc = m.points()
+    err = np.hypot(gx - x, gy - y) / h_of(og, x, y)
+    assert err.max() <= 1e-9, err.max()
+    assert np.array_equal(gc, cat)
+    assert m.stats_raw().error == 0
+
+
+def test_growing_run_in_fp32_reaches_oracle_quality(orc, T):
+    """FP32 + FP64 replay: all points are added, the run stops inside the
+    budget, at a quality within 1% of the oracle's."""
+    wl = workload("annulus")
+    og = orc.build_grid(wl)
+    _, _, _, info = orc.run_growing(og, wl.x, wl.y, "hybrid", 200, 1600, nthreads=8)
+    m = mesher(wl, FP32, og, 1600)
+    ad = m.run_growing("hybrid", 200)
+    assert m.n == wl.n and ad["stop_iter"] >= 0 and ad["reason"] in (1, 2)
+    want = info["history"][-1]["quality"]
+    assert abs(ad["last"][0] - want[0]) <= 0.01 * want[0]
+    assert abs(ad["last"][1] - want[1]) <= 0.01 * want[1]
