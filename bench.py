@@ -55,7 +55,9 @@ BYTES_PER_POINT = 37 + 25 + 30 + 64
 # HBM traffic of one launch of the fused kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (first two CVD iterations, scaled by a 1 GiB copy: FETCH x 2.0,
 # WRITE x 1.0), valid for the kernel sources with this digest only.
-TRAFFIC = {"sha1": "44e328e87e41981bc42c2edb57cdb7703fe80e19", "bytes_per_launch": 494359861.4}
+TRAFFIC = {"sha1": "bb994ff4127e36b8f024bd4b6c53583344a1ffd2", "bytes_per_launch": 494254617.9}
+# CVD iterations from the seeded points before the autotuner's timing
+TUNE_FROM = 10
 KERNEL_SOURCES = ["cells.hip", "trime_dev.hpp", "geom_dev.hpp", "exact_dev.hpp", "launch.hpp"]
 
 
@@ -117,7 +119,12 @@ def gpu_run(wl, precision, steps, warmup, log, tune=()):
     m = Mesher(wl, precision=precision)
     density = 3.3
     if tune:
-        density, ms = m.autotune(tune, n_iter=3)
+        # tuned on the positions after a few iterations: the seeded points'
+        # first iterations scan differently from the rest of the run
+        m.load()
+        m.step_cvd(TUNE_FROM)
+        px, py, _ = m.points()
+        density, ms = m.autotune(tune, n_iter=4, x=px, y=py)
         log("  autotune (%s): %s -> %.2f points per bin" % (
             "fp32" if precision == T.FP32 else "fp64",
             ", ".join("%.2f: %.3f ms" % (d, t) for d, t in sorted(ms.items())), density))
