@@ -100,6 +100,8 @@ def lib():
                                      C.c_int32, C.c_int64, dp, dp, u8p, fp, dp, dp]
         L.orc_sdf_eval.argtypes = [C.POINTER(Prim), C.c_int32, dp, C.c_double, C.c_double]
         L.orc_sdf_eval.restype = C.c_double
+        L.orc_segments_sdf.argtypes = [dp, C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_int32)]
+        L.orc_segments_sdf.restype = C.c_double
         L.orc_grid_init.argtypes = [C.POINTER(Grid), C.c_int32, C.c_int32, C.c_double, C.c_double,
                                     C.c_double, C.c_double, dp, dp, u8p, fp, C.c_double]
         L.orc_cells_all.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int64, dp, dp, i32p, i32p,
@@ -227,6 +229,16 @@ def grid_from_arrays(spec, sdf, mu, cat, hcell, h_avg) -> OracleGrid:
 def sdf_eval(wl, x, y) -> float:
     prims, sz, poly, keep = _geometry(wl)
     return lib().orc_sdf_eval(prims, len(wl.prims), _p(poly, C.c_double), float(x), float(y))
+
+
+def segments_sdf(verts, x, y):
+    """Signed distance of (x, y) to the closed clockwise loop through verts
+    ((m, 2) array), and the index of the nearest segment (Sec. 3.2; the rule
+    is stated with orc_segments_sdf in orc.h)."""
+    v = np.ascontiguousarray(np.asarray(verts, np.float64).reshape(-1))
+    k = C.c_int32(-1)
+    d = lib().orc_segments_sdf(_p(v, C.c_double), len(v) // 2, float(x), float(y), C.byref(k))
+    return d, k.value
 
 
 def cells(grid: OracleGrid, x, y, cap=64, all_pairs=False, nthreads=1, params=None):

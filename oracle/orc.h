@@ -25,15 +25,30 @@ extern "C" {
 
 /* ---- geometry (Sec. 3.1: analytic SDF and set operations) ---------------- */
 enum { ORC_OP_INIT = 0, ORC_OP_UNION = 1, ORC_OP_DIFF = 2, ORC_OP_INTERSECT = 3 };
-enum { ORC_PRIM_DISK = 0, ORC_PRIM_BOX = 1, ORC_PRIM_ELLIPSE = 2, ORC_PRIM_POLYGON = 3 };
+enum { ORC_PRIM_DISK = 0, ORC_PRIM_BOX = 1, ORC_PRIM_ELLIPSE = 2, ORC_PRIM_POLYGON = 3, ORC_PRIM_SEGMENTS = 4 };
 
 typedef struct {
   int32_t op, kind;
   /* DISK: cx, cy, r.  BOX: x0, y0, x1, y1.  ELLIPSE: cx, cy, a, b, phi.
-     POLYGON: vertices in poly[voff .. voff+nv) as (x, y) pairs, any winding. */
+     POLYGON: vertices in poly[voff .. voff+nv) as (x, y) pairs, any winding.
+     SEGMENTS: a closed clockwise loop of line segments through poly[voff ..
+     voff+nv) (Sec. 3.2): distance to the nearest segment, sign from its
+     inward normal (orc_segments_sdf). */
   double p[6];
   int32_t voff, nv;
 } orc_prim;
+
+/* Signed distance to a closed clockwise loop of nv >= 3 segments, segment k
+   from v_k to v_(k+1 mod nv) (Sec. 3.2).  The magnitude is the distance to
+   the nearest segment (the closest point p* = a + t (b - a), t clamped to
+   [0, 1]); equal distances go to the lower segment index.  The inward
+   normal of a segment is its direction turned clockwise by 90 degrees (the
+   interior lies to the right of a clockwise loop), unit length; when p* is
+   an end point the normal is the mean of the unit normals of the two
+   segments that meet there.  The sign is negative (inside) when
+   (p - p*) . n > 0, else positive.  Brute force over every segment.  If
+   seg_out is not null it receives the nearest segment's index. */
+double orc_segments_sdf(const double *v, int32_t nv, double x, double y, int32_t *seg_out);
 
 /* ---- sizing field (Sec. 3.3-3.4, Eq. 9) ---------------------------------- */
 enum {

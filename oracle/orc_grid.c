@@ -103,6 +103,55 @@ static double ellipse_sdf(const double *p, double x, double y) {
   return inside < 0 ? -d : d;
 }
 
+/* Unit inward normal of the segment a -> b of a clockwise loop: the
+   direction (ex, ey) turned clockwise, (ey, -ex) / |e|. */
+static void seg_normal(double ax, double ay, double bx, double by, double *nx, double *ny) {
+  double ex = bx - ax, ey = by - ay;
+  double L = sqrt(ex * ex + ey * ey);
+  *nx = L > 0 ? ey / L : 0.0;
+  *ny = L > 0 ? -ex / L : 0.0;
+}
+
+double orc_segments_sdf(const double *v, int32_t nv, double x, double y, int32_t *seg_out) {
+  double best = INFINITY, bt = 0.0;
+  int32_t kb = -1;
+  for (int32_t k = 0; k < nv; k++) {
+    int32_t k1 = k + 1 == nv ? 0 : k + 1;
+    double ax = v[2 * k], ay = v[2 * k + 1], bx = v[2 * k1], by = v[2 * k1 + 1];
+    double ex = bx - ax, ey = by - ay, wx = x - ax, wy = y - ay;
+    double L2 = ex * ex + ey * ey;
+    double t = L2 > 0 ? (wx * ex + wy * ey) / L2 : 0.0;
+    if (t < 0) t = 0;
+    if (t > 1) t = 1;
+    double qx = wx - t * ex, qy = wy - t * ey;
+    double d = sqrt(qx * qx + qy * qy);
+    if (d < best) { /* strict: equal distances keep the lower index */
+      best = d;
+      bt = t;
+      kb = k;
+    }
+  }
+  if (seg_out) *seg_out = kb;
+  int32_t k1 = kb + 1 == nv ? 0 : kb + 1;
+  double ax = v[2 * kb], ay = v[2 * kb + 1], bx = v[2 * k1], by = v[2 * k1 + 1];
+  double nx, ny;
+  seg_normal(ax, ay, bx, by, &nx, &ny);
+  double px = ax + bt * (bx - ax), py = ay + bt * (by - ay);
+  if (bt == 0.0 || bt == 1.0) {
+    /* an end point: the mean of the normals of the two segments there */
+    int32_t ko = bt == 0.0 ? (kb == 0 ? nv - 1 : kb - 1) : k1;
+    int32_t ko1 = ko + 1 == nv ? 0 : ko + 1;
+    double mx, my;
+    seg_normal(v[2 * ko], v[2 * ko + 1], v[2 * ko1], v[2 * ko1 + 1], &mx, &my);
+    nx = 0.5 * (nx + mx);
+    ny = 0.5 * (ny + my);
+    px = bt == 0.0 ? ax : bx;
+    py = bt == 0.0 ? ay : by;
+  }
+  double dot = (x - px) * nx + (y - py) * ny;
+  return dot > 0 ? -best : best;
+}
+
 static double prim_sdf(const orc_prim *pr, const double *poly, double x, double y) {
   switch (pr->kind) {
     case ORC_PRIM_DISK: {
@@ -136,6 +185,8 @@ static double prim_sdf(const orc_prim *pr, const double *poly, double x, double 
       }
       return inside ? -d : d;
     }
+    case ORC_PRIM_SEGMENTS:
+      return orc_segments_sdf(poly + 2 * (size_t)pr->voff, pr->nv, x, y, NULL);
   }
   return INFINITY;
 }
@@ -188,6 +239,7 @@ int orc_grid_build(const orc_prim *prims, int32_t nprims, const double *poly,
                    double dx, double dy, int32_t dtype_bytes, int64_t n_total, double *sdf,
                    double *mu, uint8_t *cat, float *hcell, double *h_avg, double *H_out) {
   if (nx < 2 || ny < 2 || n_total <= 0 || !(dx > 0) || !(dy > 0)) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
   for (int j = 0; j < ny; j++)
     for (int i = 0; i < nx; i++) {
       double x = x0 + i * dx, y = y0 + j * dy;

@@ -31,7 +31,7 @@ import numpy as np
 
 # CSG operations and primitive kinds (shared numbering of the input format)
 OP_INIT, OP_UNION, OP_DIFF, OP_INTERSECT = 0, 1, 2, 3
-PRIM_DISK, PRIM_BOX, PRIM_ELLIPSE, PRIM_POLYGON = 0, 1, 2, 3
+PRIM_DISK, PRIM_BOX, PRIM_ELLIPSE, PRIM_POLYGON, PRIM_SEGMENTS = 0, 1, 2, 3, 4
 SZ_UNIFORM, SZ_ABS_SDF, SZ_GAUSS_RHO, SZ_HOLE_RAMP = 0, 1, 2, 3
 
 
@@ -81,7 +81,7 @@ class Workload:
         verts, offs = [], []
         off = 0
         for p in self.prims:
-            if p.kind == PRIM_POLYGON:
+            if p.kind in (PRIM_POLYGON, PRIM_SEGMENTS):
                 offs.append((off, len(p.poly)))
                 verts.append(np.asarray(p.poly, dtype=np.float64))
                 off += len(p.poly)
@@ -306,6 +306,37 @@ def annulus(n: int = 100000, seed: int = 1002, grid_n: int = 1024) -> Workload:
     wl = Workload("annulus", prims, Sizing(SZ_ABS_SDF, 1.0, 2.0),
                   centred_grid(grid_n, 5, span_log2, 0.0, 4), n, [("cvd", 30), ("dm", 70)], seed)
     wl.x, wl.y = sample_points(wl, np.random.default_rng(ss[2]), (-1, -1, 1, 1))
+    return wl
+
+
+def coast_loop(m: int = 4096, seed: int = 1006) -> np.ndarray:
+    """A closed clockwise loop of m segments around (0.5, 0.5): radius
+    r(theta) = 0.3 (1 + sum_k a_k cos(k theta + phi_k)), k = 2..48, with
+    a_k = 0.22 k^-1.2 u_k, u_k ~ U[-1, 1] and phi_k ~ U[0, 2 pi), clipped to
+    [0.12, 0.46]: a coastline-like shape with narrow bays and sharp turns,
+    standing in for the paper's line-segment inputs (Sec. 3.2).  Vertices at
+    decreasing angles 2 pi (m - j) / m (clockwise)."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(3)[0])
+    k = np.arange(2, 49)
+    amp = 0.22 * k ** -1.2 * rng.uniform(-1, 1, len(k))
+    ph = rng.uniform(0, 2 * np.pi, len(k))
+    th = 2 * np.pi * (m - np.arange(m)) / m
+    r = 0.3 * (1.0 + (amp[None, :] * np.cos(k[None, :] * th[:, None] + ph[None, :])).sum(1))
+    r = np.clip(r, 0.12, 0.46)
+    return np.ascontiguousarray(np.stack([0.5 + r * np.cos(th), 0.5 + r * np.sin(th)], 1), np.float64)
+
+
+def coast(n: int = 100000, segments: int = 4096, seed: int = 1006, grid_n: int = 1024, iters: int = 50) -> Workload:
+    """Line-segment input (Sec. 3.2): the coast_loop shape minus a disk of
+    radius 0.05 at (0.5, 0.5), uniform sizing, on a grid over [0, 1]^2 (with
+    a margin); CVD iterations."""
+    ss = np.random.SeedSequence(seed).spawn(3)
+    loop = coast_loop(segments, seed)
+    prims = [Prim(OP_INIT, PRIM_SEGMENTS, (), loop), Prim(OP_DIFF, PRIM_DISK, (0.5, 0.5, 0.05))]
+    log2n = int(round(math.log2(grid_n)))
+    grid = centred_grid(grid_n, 17, log2n + 4, 0.5, 8)
+    wl = Workload("coast", prims, Sizing(SZ_UNIFORM), grid, n, [("cvd", iters)], seed)
+    wl.x, wl.y = sample_points(wl, np.random.default_rng(ss[2]), (0, 0, 1, 1))
     return wl
 
 
