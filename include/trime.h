@@ -24,8 +24,10 @@
  *    trime_state_workspace_bytes(); the library keeps no pointer after a
  *    call returns, allocates no device memory in any call except
  *    trime_sdf_grid_build (setup: one temporary buffer for the primitive
- *    list), and never synchronises except in trime_state_bind (setup: reads
- *    the grid scalars), trime_stats_read and trime_autotune (tuning).
+ *    list, and the candidate lists of SEGMENTS primitives), and never
+ *    synchronises except in trime_state_bind (setup: reads the grid
+ *    scalars), trime_sdf_grid_build with SEGMENTS primitives, trime_stats_read,
+ *    trime_autotune (tuning), trime_add_points and trime_run_growing.
  *  - Streams: `stream` is a hipStream_t (passed as void*); 0 is the null
  *    stream.  All work is enqueued on it in order.
  *  - Layouts: structure of arrays.  Positions are float64 x[n], y[n] in both
@@ -63,11 +65,23 @@ enum { TRIME_CAT_OUTER = 0, TRIME_CAT_INNER = 1, TRIME_CAT_BOUNDARY = 2 };
 
 /* ---- geometry and sizing input (Sec. 3.1, 3.3, Eq. 9) -------------------- */
 enum { TRIME_OP_INIT = 0, TRIME_OP_UNION = 1, TRIME_OP_DIFF = 2, TRIME_OP_INTERSECT = 3 };
-enum { TRIME_PRIM_DISK = 0, TRIME_PRIM_BOX = 1, TRIME_PRIM_ELLIPSE = 2, TRIME_PRIM_POLYGON = 3 };
+enum { TRIME_PRIM_DISK = 0, TRIME_PRIM_BOX = 1, TRIME_PRIM_ELLIPSE = 2, TRIME_PRIM_POLYGON = 3,
+       TRIME_PRIM_SEGMENTS = 4 };
 
 /* One analytic primitive of the constructive geometry.  Parameters p:
    DISK (cx, cy, r); BOX (x0, y0, x1, y1); ELLIPSE (cx, cy, a, b, phi);
-   POLYGON: vertices poly[voff .. voff+nv) of trime_geometry.poly.  The running
+   POLYGON: vertices poly[voff .. voff+nv) of trime_geometry.poly (distance
+   to the nearest edge, inside by crossing number).
+   SEGMENTS: line-segment input (Sec. 3.2), a closed clockwise loop of the
+   nv >= 3 segments poly[voff + k] -> poly[voff + (k + 1) mod nv].  The
+   distance is to the nearest segment (equal distances: the lower index), at
+   the closest point p* = a + t (b - a), t clamped to [0, 1].  The inward
+   normal n is the segment's direction turned clockwise by 90 degrees (unit
+   length), or at an end point the mean of the two segments' unit normals;
+   the value is negative (inside) when (p - p*) . n > 0.  The grid build
+   finds each node's nearest segment in per-cell candidate lists that it
+   builds first (device memory it allocates and frees, and one stream
+   synchronisation per level of the list hierarchy).  The running
    sdf s is combined with the primitive's t by op: INIT s = t, UNION min(s, t),
    DIFF max(s, -t), INTERSECT max(s, t) (Sec. 3.1 set operations). */
 typedef struct {

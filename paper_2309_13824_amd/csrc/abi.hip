@@ -79,9 +79,10 @@ trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing 
     return fail(TRIME_EINVAL, "trime_sdf_grid_build: the first primitive must be INIT");
   for (int k = 0; k < geo->nprims; k++) {
     const trime_prim &p = geo->prims[k];
-    if (p.op < 0 || p.op > 3 || p.kind < 0 || p.kind > 3)
+    if (p.op < 0 || p.op > 3 || p.kind < 0 || p.kind > TRIME_PRIM_SEGMENTS)
       return fail(TRIME_EINVAL, "trime_sdf_grid_build: bad primitive op/kind");
-    if (p.kind == TRIME_PRIM_POLYGON && (p.nv < 3 || p.voff < 0 || p.voff + p.nv > geo->npoly || !geo->poly))
+    if ((p.kind == TRIME_PRIM_POLYGON || p.kind == TRIME_PRIM_SEGMENTS) &&
+        (p.nv < 3 || p.voff < 0 || p.voff + p.nv > geo->npoly || !geo->poly))
       return fail(TRIME_EINVAL, "trime_sdf_grid_build: bad polygon range");
     if ((p.kind == TRIME_PRIM_DISK && !(p.p[2] > 0)) ||
         (p.kind == TRIME_PRIM_ELLIPSE && !(p.p[2] > 0 && p.p[3] > 0)))
@@ -98,14 +99,16 @@ trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing 
         return fail(TRIME_EINVAL, "trime_sdf_grid_build: hole index out of range");
   }
   hipStream_t s = (hipStream_t)stream;
-  // one temporary device buffer: prims | poly | cent | holes | partials
+  // one temporary device buffer: prims | poly | cent | holes | partials |
+  // segment candidate trees (their lists are allocated while they are built)
   size_t b_prims = sizeof(trime_prim) * (size_t)geo->nprims;
+  size_t b_segs = sizeof(SegTree) * (size_t)geo->nprims;
   size_t b_poly = sizeof(double) * 2 * (size_t)(geo->npoly > 0 ? geo->npoly : 0);
   size_t b_cent = sizeof(double) * 2 * (size_t)(sz->kind == TRIME_SZ_GAUSS_RHO ? sz->ncent : 0);
   size_t b_holes = sizeof(int32_t) * (size_t)(sz->kind == TRIME_SZ_HOLE_RAMP ? sz->nholes : 0);
   size_t b_part = sizeof(double) * 2 * (size_t)grid_partials(grid->nx, grid->ny);
   auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-  size_t total = al(b_prims) + al(b_poly) + al(b_cent) + al(b_holes) + al(b_part);
+  size_t total = al(b_prims) + al(b_poly) + al(b_cent) + al(b_holes) + al(b_part) + al(b_segs);
   char *buf = nullptr;
   TRY_HIP(hipMallocAsync((void **)&buf, total, s), "trime_sdf_grid_build: hipMallocAsync");
   char *q = buf;
@@ -113,15 +116,49 @@ trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing 
   double *d_poly = (double *)q; q += al(b_poly);
   double *d_cent = (double *)q; q += al(b_cent);
   int32_t *d_holes = (int32_t *)q; q += al(b_holes);
-  double *d_part = (double *)q;
+  double *d_part = (double *)q; q += al(b_part);
+  SegTree *d_segs = (SegTree *)q;
   TRY_HIP(hipMemcpyAsync(d_prims, geo->prims, b_prims, hipMemcpyHostToDevice, s), "copy prims");
   if (b_poly) TRY_HIP(hipMemcpyAsync(d_poly, geo->poly, b_poly, hipMemcpyHostToDevice, s), "copy poly");
   if (b_cent) TRY_HIP(hipMemcpyAsync(d_cent, sz->cent, b_cent, hipMemcpyHostToDevice, s), "copy cent");
   if (b_holes) TRY_HIP(hipMemcpyAsync(d_holes, sz->holes, b_holes, hipMemcpyHostToDevice, s), "copy holes");
+  // segment loops: the candidate hierarchy over the grid's box and the loop's
+  std::vector<SegTree> trees((size_t)geo->nprims);
+  memset(trees.data(), 0, sizeof(SegTree) * trees.size());
+  std::vector<void *> allocs;
+  bool any_seg = false;
+  const char *seg_err = nullptr;
+  for (int k = 0; k < geo->nprims && !seg_err; k++) {
+    const trime_prim &p = geo->prims[k];
+    if (p.kind != TRIME_PRIM_SEGMENTS) continue;
+    any_seg = true;
+    double bx0 = grid->x0, by0 = grid->y0;
+    double bx1 = grid->x0 + (grid->nx - 1) * grid->dx, by1 = grid->y0 + (grid->ny - 1) * grid->dy;
+    for (int i = 0; i < p.nv; i++) {
+      const double *v = geo->poly + 2 * (size_t)(p.voff + i);
+      bx0 = fmin(bx0, v[0]);
+      by0 = fmin(by0, v[1]);
+      bx1 = fmax(bx1, v[0]);
+      by1 = fmax(by1, v[1]);
+    }
+    seg_err = seg_tree_build(d_poly + 2 * (size_t)p.voff, p.nv, bx0, by0, bx1, by1,
+                             8.0 * fmax(grid->dx, grid->dy), &trees[k], allocs, s);
+  }
+  if (!seg_err && any_seg &&
+      (hipMemcpyAsync(d_segs, trees.data(), b_segs, hipMemcpyHostToDevice, s) != hipSuccess ||
+       hipStreamSynchronize(s) != hipSuccess))
+    seg_err = "copy segment trees";
+  if (seg_err) {
+    for (void *a : allocs) (void)hipFreeAsync(a, s);
+    (void)hipFreeAsync(buf, s);
+    (void)hipGetLastError();
+    return fail(TRIME_EINVAL, seg_err);
+  }
   GridPrims g;
   g.nprims = geo->nprims;
   g.prims = d_prims;
   g.poly = d_poly;
+  g.segs = d_segs;
   g.sz = *sz;
   g.cent = d_cent;
   g.holes = d_holes;
@@ -134,6 +171,7 @@ trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing 
   g.n_total = n_total;
   launch_grid_build(g, grid->dtype_bytes, d_sdf, d_mu, d_cat, d_hcell, d_scal, d_part, s);
   trime_status st = check_hip("trime_sdf_grid_build: launch");
+  for (void *a : allocs) (void)hipFreeAsync(a, s);
   (void)hipFreeAsync(buf, s);
   return st;
 }

@@ -10,7 +10,7 @@
 // One thread per node.  A primitive whose distance bound cannot change the
 // running value (a hole far from the node) is skipped, so hundreds of holes
 // cost a few flops each.
-#include "launch.hpp"
+#include "segsdf_dev.hpp"
 
 namespace trime {
 
@@ -50,7 +50,10 @@ TRIME_D double ellipse_q1(double e0, double e1, double y0, double y1) {
   return fabs(y0 - e0);
 }
 
-TRIME_D double prim_sdf(const trime_prim &pr, const double *poly, double x, double y) {
+// Signed distance of primitive k of the geometry.
+TRIME_D double prim_sdf(const GridPrims &g, int k, double x, double y) {
+  const trime_prim &pr = g.prims[k];
+  const double *poly = g.poly;
   switch (pr.kind) {
     case TRIME_PRIM_DISK: {
       double dx = x - pr.p[0], dy = y - pr.p[1];
@@ -72,6 +75,8 @@ TRIME_D double prim_sdf(const trime_prim &pr, const double *poly, double x, doub
       double d = a >= b ? ellipse_q1(a, b, u, v) : ellipse_q1(b, a, v, u);
       return in < 0 ? -d : d;
     }
+    case TRIME_PRIM_SEGMENTS:
+      return segments_sdf(g.segs[k], x, y);
     default: {  // polygon: segment distance, crossing-number sign
       const double *v = poly + 2 * (int64_t)pr.voff;
       int nv = pr.nv;
@@ -125,7 +130,7 @@ TRIME_D double csg_sdf(const GridPrims &g, double x, double y) {
         if (pr.op == TRIME_OP_UNION && dist >= s) continue;
       }
     }
-    double t = prim_sdf(pr, g.poly, x, y);
+    double t = prim_sdf(g, k, x, y);
     switch (pr.op) {
       case TRIME_OP_INIT: s = t; break;
       case TRIME_OP_UNION: s = fmin(s, t); break;
@@ -157,7 +162,7 @@ TRIME_D double sizing_mu(const GridPrims &g, double x, double y, double sdf) {
           double lb = sqrt((x - cx) * (x - cx) + (y - cy) * (y - cy)) - R;
           if (lb > dh) continue;
         }
-        dh = fmin(dh, fabs(prim_sdf(pr, g.poly, x, y)));
+        dh = fmin(dh, fabs(prim_sdf(g, g.holes[k], x, y)));
       }
       double r = fmin(dh / g.sz.a1, 1.0);
       return 1.0 + (g.sz.a0 - 1.0) * r;

@@ -91,10 +91,22 @@ struct LoadArgs {
 };
 
 // Geometry for the grid build (device copies of the primitive lists).
+// Candidate lists of a segment loop (segsdf.hip): the finest cell grid of
+// its hierarchy over a box; cell c lists, in ascending order, every segment
+// that can be the nearest one for a point of the cell.
+struct SegTree {
+  const double *v;  // device vertices of the loop
+  int nv;
+  int nx, ny;
+  double x0, y0, cw, ch;
+  const int32_t *start, *cand;
+};
+
 struct GridPrims {
   int nprims;
   const trime_prim *prims;
   const double *poly;
+  const SegTree *segs;  // per primitive (device); used by SEGMENTS only
   trime_sizing sz;  // cent / holes point into device memory
   const double *cent;
   const int32_t *holes;
@@ -145,6 +157,8 @@ void launch_grow_state(const KArgs &a, int growing, int added, hipStream_t s);
 size_t grow_key_bytes();
 size_t grow_sel_bytes();
 int64_t grid_partials(int nx, int ny);
+const char *seg_tree_build(const double *d_v, int nv, double bx0, double by0, double bx1, double by1,
+                           double target, SegTree *T, std::vector<void *> &allocs, hipStream_t s);
 void launch_grid_build(const GridPrims &g, int dtype_bytes, void *sdf, void *mu, uint8_t *cat,
                        float *hcell, trime_grid_scalars *scal, double *part, hipStream_t s);
 
