@@ -18,7 +18,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liborc.so")
-SOURCES = ["orc_exact.c", "orc_grid.c", "orc_mesh.c", "orc_step.c"]
+SOURCES = ["orc_exact.c", "orc_grid.c", "orc_mesh.c", "orc_sizing.c", "orc_step.c"]
 
 CAT_OUTER, CAT_INNER, CAT_BOUNDARY = 0, 1, 2
 
@@ -47,7 +47,7 @@ class Prim(C.Structure):
 class Sizing(C.Structure):
     _fields_ = [("kind", C.c_int32), ("a0", C.c_double), ("a1", C.c_double), ("s2", C.c_double),
                 ("ncent", C.c_int32), ("cent", C.POINTER(C.c_double)), ("nholes", C.c_int32),
-                ("holes", C.POINTER(C.c_int32))]
+                ("holes", C.POINTER(C.c_int32)), ("lfs", C.POINTER(C.c_double))]
 
 
 class Grid(C.Structure):
@@ -102,6 +102,15 @@ def lib():
         L.orc_sdf_eval.restype = C.c_double
         L.orc_segments_sdf.argtypes = [dp, C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_int32)]
         L.orc_segments_sdf.restype = C.c_double
+        L.orc_boundary_points.argtypes = [C.POINTER(Prim), C.c_int32, dp, C.c_double, dp, C.c_int64]
+        L.orc_boundary_points.restype = C.c_int64
+        L.orc_medial_points.argtypes = [dp, C.c_int64, dp, dp, C.c_int64]
+        L.orc_medial_points.restype = C.c_int64
+        L.orc_trim_medial.argtypes = [dp, C.c_int64, C.c_double, C.c_int32, C.POINTER(C.c_uint8)]
+        L.orc_trim_medial.restype = C.c_int64
+        L.orc_lfs.argtypes = [dp, C.c_int64, dp, C.c_int64, C.POINTER(C.c_uint8), dp]
+        L.orc_auto_mu.argtypes = [dp, dp, C.c_int64, C.c_double, C.c_double, C.c_double]
+        L.orc_auto_mu.restype = C.c_double
         L.orc_grid_init.argtypes = [C.POINTER(Grid), C.c_int32, C.c_int32, C.c_double, C.c_double,
                                     C.c_double, C.c_double, dp, dp, u8p, fp, C.c_double]
         L.orc_cells_all.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_int64, dp, dp, i32p, i32p,
@@ -199,9 +208,55 @@ def _geometry(wl):
     return prims, sz, poly, keep
 
 
+@dataclass
+class AutoSizing:
+    """The automatic sizing field's ingredients (Sec. 3.3, Eq. 8)."""
+    s: np.ndarray       # (ns, 2) boundary points
+    medial: np.ndarray  # (nm, 2) medial-axis approximating points
+    keep: np.ndarray    # (nm,) kept by the trimming
+    lfs: np.ndarray     # (ns,) local feature size of each boundary point
+    d_s: float
+    r_nei: float
+
+
+def auto_sizing(wl) -> AutoSizing:
+    """Boundary points of the workload's segment loops (App. A) at
+    d_s = fac_s min(dx, dy) (fac_s = sizing.a1), medial-axis points from
+    their Voronoi cells clipped to the grid's box grown by its size on every
+    side, trimming with r_nei = fac_nei n_thres d_s, and lfs (orc.h states
+    each step)."""
+    g = wl.grid
+    sz = wl.sizing
+    prims, _, poly, keep_ = _geometry(wl)
+    d_s = sz.a1 * min(g.dx, g.dy)
+    n = lib().orc_boundary_points(prims, len(wl.prims), _p(poly, C.c_double), d_s, None, 0)
+    s = np.empty((n, 2), np.float64)
+    lib().orc_boundary_points(prims, len(wl.prims), _p(poly, C.c_double), d_s, _p(s, C.c_double), n)
+    W, H = (g.nx - 1) * g.dx, (g.ny - 1) * g.dy
+    box = np.array([g.x0 - W, g.y0 - H, g.x0 + 2 * W, g.y0 + 2 * H], np.float64)
+    m = np.empty((2 * n, 2), np.float64)
+    nm = lib().orc_medial_points(_p(s, C.c_double), n, _p(box, C.c_double), _p(m, C.c_double), 2 * n)
+    m = np.ascontiguousarray(m[:nm])
+    r_nei = sz.fac_nei * sz.n_thres * d_s
+    keep = np.zeros(nm, np.uint8)
+    lib().orc_trim_medial(_p(m, C.c_double), nm, r_nei, sz.n_thres, _p(keep, C.c_uint8))
+    lfs = np.empty(n, np.float64)
+    lib().orc_lfs(_p(s, C.c_double), n, _p(m, C.c_double), nm, _p(keep, C.c_uint8), _p(lfs, C.c_double))
+    return AutoSizing(s, m, keep, lfs, d_s, r_nei)
+
+
 def build_grid(wl) -> OracleGrid:
     g = wl.grid
     prims, sz, poly, keep = _geometry(wl)
+    if wl.sizing.kind == 4:  # automatic: mu from the boundary points and lfs
+        au = auto_sizing(wl)
+        s_pts = np.ascontiguousarray(au.s.reshape(-1))
+        lfs = np.ascontiguousarray(au.lfs)
+        keep = keep + (s_pts, lfs)
+        sz.ncent = len(au.s)
+        sz.cent = _p(s_pts, C.c_double)
+        sz.lfs = _p(lfs, C.c_double)
+        sz.a0 = wl.sizing.a0
     nn = g.nx * g.ny
     sdf = np.empty(nn, np.float64)
     mu = np.empty(nn, np.float64)

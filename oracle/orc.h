@@ -55,8 +55,10 @@ enum {
   ORC_SZ_UNIFORM = 0,     /* mu = 1                                          */
   ORC_SZ_ABS_SDF = 1,     /* mu = a0 + a1*|sdf(x)|                           */
   ORC_SZ_GAUSS_RHO = 2,   /* rho = a0 + a1*sum_k exp(-|x-c_k|^2/s2); mu = rho^-1/2 */
-  ORC_SZ_HOLE_RAMP = 3    /* mu = 1 + (a0-1)*min(d_H(x)/a1, 1), d_H = distance to
+  ORC_SZ_HOLE_RAMP = 3,   /* mu = 1 + (a0-1)*min(d_H(x)/a1, 1), d_H = distance to
                              the nearest primitive listed in holes[]           */
+  ORC_SZ_AUTO = 4         /* automatic (Eq. 8): mu = min_s K |s - x| + lfs(s),
+                             K = a0, s the ncent points of cent, lfs given    */
 };
 typedef struct {
   int32_t kind;
@@ -65,7 +67,29 @@ typedef struct {
   const double *cent;     /* ncent (x, y) pairs                               */
   int32_t nholes;
   const int32_t *holes;   /* indices into the primitive list                   */
+  const double *lfs;      /* AUTO: lfs of each of the ncent points             */
 } orc_sizing;
+
+/* ---- automatic sizing (Sec. 3.3, Eq. 8; App. A) -------------------------- */
+/* Boundary points of the SEGMENTS loops, in primitive and vertex order:
+   every vertex, then on a segment of length L > d_s the floor(L / d_s)
+   points splitting it evenly (spacing below d_s).  Returns the count (the
+   first cap points are written). */
+int64_t orc_boundary_points(const orc_prim *prims, int32_t nprims, const double *poly, double d_s, double *out,
+                            int64_t cap);
+/* Medial-axis approximating points: for each point s, its Voronoi cell among
+   all points (every other point's bisector, in index order, clipping the box
+   [box0, box2] x [box1, box3]); v1 = the farthest cell vertex, added unless
+   it lies on the box (it then stands for a vertex at infinity); v2 = the
+   farthest cell vertex not on the box with (v2 - s) . (v1 - s) < 0, added if
+   there is one.  Returns the count (first cap points written). */
+int64_t orc_medial_points(const double *s, int64_t ns, const double box[4], double *out, int64_t cap);
+/* keep[i] = at least n_thres other medial points within r_nei of point i. */
+int64_t orc_trim_medial(const double *m, int64_t nm, double r_nei, int32_t n_thres, uint8_t *keep);
+/* lfs(s) = distance to the nearest kept medial point (inf when none). */
+void orc_lfs(const double *s, int64_t ns, const double *m, int64_t nm, const uint8_t *keep, double *lfs);
+/* mu(x, y) = min over s of K |s - (x, y)| + lfs(s) (Eq. 8). */
+double orc_auto_mu(const double *s, const double *lfs, int64_t ns, double K, double x, double y);
 
 /* ---- the geometry grid (Sec. 3.2, Sec. 3.7) ------------------------------ */
 enum { ORC_CAT_OUTER = 0, ORC_CAT_INNER = 1, ORC_CAT_BOUNDARY = 2 };

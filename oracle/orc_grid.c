@@ -209,6 +209,8 @@ double orc_sdf_eval(const orc_prim *prims, int32_t nprims, const double *poly, d
 static double sizing_mu(const orc_sizing *sz, const orc_prim *prims, const double *poly,
                         double x, double y, double sdf) {
   switch (sz->kind) {
+    case ORC_SZ_AUTO:
+      return orc_auto_mu(sz->cent, sz->lfs, sz->ncent, sz->a0, x, y);
     case ORC_SZ_UNIFORM: return 1.0;
     case ORC_SZ_ABS_SDF: return sz->a0 + sz->a1 * fabs(sdf);
     case ORC_SZ_GAUSS_RHO: {

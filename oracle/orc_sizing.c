@@ -1,0 +1,169 @@
+/* Automatic sizing field (Sec. 3.3, Eq. 8), oracle side: boundary points
+   of segment loops (App. A), medial-axis approximating points from the
+   Voronoi cells of the boundary points, their trimming, the local feature
+   size lfs(s) and mu(x) = min over s of K |s - x| + lfs(s).  Brute force
+   throughout: every Voronoi cell is clipped by every other point's
+   bisector, every count and minimum runs over all points.  Test
+   infrastructure only. */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "orc.h"
+
+int64_t orc_boundary_points(const orc_prim *prims, int32_t nprims, const double *poly, double d_s, double *out,
+                            int64_t cap) {
+  int64_t n = 0;
+  for (int32_t q = 0; q < nprims; q++) {
+    if (prims[q].kind != ORC_PRIM_SEGMENTS) continue;
+    const double *v = poly + 2 * (size_t)prims[q].voff;
+    int32_t nv = prims[q].nv;
+    for (int32_t k = 0; k < nv; k++) {
+      int32_t k1 = k + 1 == nv ? 0 : k + 1;
+      double ax = v[2 * k], ay = v[2 * k + 1], bx = v[2 * k1], by = v[2 * k1 + 1];
+      double L = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
+      /* the vertex, then floor(L / d_s) evenly spaced points inside a
+         segment longer than d_s: spacing L / (floor(L / d_s) + 1) < d_s */
+      int64_t pieces = L > d_s ? (int64_t)floor(L / d_s) + 1 : 1;
+      for (int64_t i = 0; i < pieces; i++) {
+        if (n < cap) {
+          double t = (double)i / (double)pieces;
+          out[2 * n] = ax + t * (bx - ax);
+          out[2 * n + 1] = ay + t * (by - ay);
+        }
+        n++;
+      }
+    }
+  }
+  return n;
+}
+
+/* Voronoi cell of point i among s[0..ns), clipped to the box: a convex
+   polygon (x, y) with, per edge k (from vertex k to k+1), the index of the
+   point whose bisector carries it, or -1 for a box edge.  Points equal to
+   s_i are skipped.  Returns the vertex count. */
+#define ORC_VMAX 256
+static int voronoi_cell(const double *s, int64_t ns, int64_t i, const double box[4], double *px, double *py,
+                        int64_t *pe) {
+  int n = 4;
+  px[0] = box[0]; py[0] = box[1]; pe[0] = -1;
+  px[1] = box[2]; py[1] = box[1]; pe[1] = -1;
+  px[2] = box[2]; py[2] = box[3]; pe[2] = -1;
+  px[3] = box[0]; py[3] = box[3]; pe[3] = -1;
+  double qx[ORC_VMAX], qy[ORC_VMAX], val[ORC_VMAX];
+  int64_t qe[ORC_VMAX];
+  const double sx = s[2 * i], sy = s[2 * i + 1];
+  for (int64_t j = 0; j < ns; j++) {
+    if (j == i) continue;
+    const double tx = s[2 * j], ty = s[2 * j + 1];
+    if (tx == sx && ty == sy) continue;
+    /* inside the cell: (x - m) . (t - s) <= 0, m the midpoint */
+    const double nx = tx - sx, ny = ty - sy, mx = 0.5 * (sx + tx), my = 0.5 * (sy + ty);
+    int out = 0;
+    for (int k = 0; k < n; k++) {
+      val[k] = (px[k] - mx) * nx + (py[k] - my) * ny;
+      out |= val[k] > 0;
+    }
+    if (!out) continue;
+    int m = 0;
+    for (int k = 0; k < n; k++) {
+      int k1 = k + 1 == n ? 0 : k + 1;
+      if (val[k] <= 0) {
+        qx[m] = px[k]; qy[m] = py[k]; qe[m] = pe[k]; m++;
+      }
+      if ((val[k] <= 0) != (val[k1] <= 0)) {
+        /* the edge k crosses the bisector: the crossing starts the next
+           piece of edge k (entering) or the bisector edge (leaving) */
+        double t = val[k] / (val[k] - val[k1]);
+        qx[m] = px[k] + t * (px[k1] - px[k]);
+        qy[m] = py[k] + t * (py[k1] - py[k]);
+        qe[m] = val[k] <= 0 ? j : pe[k];
+        m++;
+      }
+      if (m >= ORC_VMAX - 2) return -1;
+    }
+    n = m;
+    memcpy(px, qx, sizeof(double) * n);
+    memcpy(py, qy, sizeof(double) * n);
+    memcpy(pe, qe, sizeof(int64_t) * n);
+  }
+  return n;
+}
+
+int64_t orc_medial_points(const double *s, int64_t ns, const double box[4], double *out, int64_t cap) {
+  int64_t nm = 0;
+  double px[ORC_VMAX], py[ORC_VMAX];
+  int64_t pe[ORC_VMAX];
+  for (int64_t i = 0; i < ns; i++) {
+    int n = voronoi_cell(s, ns, i, box, px, py, pe);
+    if (n < 3) continue;
+    const double sx = s[2 * i], sy = s[2 * i + 1];
+    /* v1: the farthest vertex; a vertex with a box edge on either side
+       stands for infinity and is never a medial point */
+    int b1 = -1;
+    double d1 = -1.0;
+    for (int k = 0; k < n; k++) {
+      double d = (px[k] - sx) * (px[k] - sx) + (py[k] - sy) * (py[k] - sy);
+      if (d > d1) { d1 = d; b1 = k; }
+    }
+    const double ux = px[b1] - sx, uy = py[b1] - sy;
+    int real1 = pe[b1] >= 0 && pe[b1 == 0 ? n - 1 : b1 - 1] >= 0;
+    if (real1) {
+      if (nm < cap) { out[2 * nm] = px[b1]; out[2 * nm + 1] = py[b1]; }
+      nm++;
+    }
+    /* v2: the farthest real vertex in the open half plane (v - s) . u < 0 */
+    int b2 = -1;
+    double d2 = -1.0;
+    for (int k = 0; k < n; k++) {
+      int real = pe[k] >= 0 && pe[k == 0 ? n - 1 : k - 1] >= 0;
+      if (!real || (px[k] - sx) * ux + (py[k] - sy) * uy >= 0) continue;
+      double d = (px[k] - sx) * (px[k] - sx) + (py[k] - sy) * (py[k] - sy);
+      if (d > d2) { d2 = d; b2 = k; }
+    }
+    if (b2 >= 0) {
+      if (nm < cap) { out[2 * nm] = px[b2]; out[2 * nm + 1] = py[b2]; }
+      nm++;
+    }
+  }
+  return nm;
+}
+
+int64_t orc_trim_medial(const double *m, int64_t nm, double r_nei, int32_t n_thres, uint8_t *keep) {
+  int64_t kept = 0;
+  const double r2 = r_nei * r_nei;
+  for (int64_t i = 0; i < nm; i++) {
+    int64_t c = 0;
+    for (int64_t j = 0; j < nm; j++) {
+      if (j == i) continue;
+      double dx = m[2 * j] - m[2 * i], dy = m[2 * j + 1] - m[2 * i + 1];
+      c += dx * dx + dy * dy <= r2;
+    }
+    keep[i] = c >= n_thres;
+    kept += keep[i];
+  }
+  return kept;
+}
+
+void orc_lfs(const double *s, int64_t ns, const double *m, int64_t nm, const uint8_t *keep, double *lfs) {
+  for (int64_t i = 0; i < ns; i++) {
+    double best = INFINITY;
+    for (int64_t j = 0; j < nm; j++) {
+      if (!keep[j]) continue;
+      double dx = m[2 * j] - s[2 * i], dy = m[2 * j + 1] - s[2 * i + 1];
+      double d = sqrt(dx * dx + dy * dy);
+      if (d < best) best = d;
+    }
+    lfs[i] = best;
+  }
+}
+
+double orc_auto_mu(const double *s, const double *lfs, int64_t ns, double K, double x, double y) {
+  double best = INFINITY;
+  for (int64_t i = 0; i < ns; i++) {
+    double dx = x - s[2 * i], dy = y - s[2 * i + 1];
+    double f = K * sqrt(dx * dx + dy * dy) + lfs[i];
+    if (f < best) best = f;
+  }
+  return best;
+}

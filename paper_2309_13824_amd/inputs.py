@@ -32,7 +32,7 @@ import numpy as np
 # CSG operations and primitive kinds (shared numbering of the input format)
 OP_INIT, OP_UNION, OP_DIFF, OP_INTERSECT = 0, 1, 2, 3
 PRIM_DISK, PRIM_BOX, PRIM_ELLIPSE, PRIM_POLYGON, PRIM_SEGMENTS = 0, 1, 2, 3, 4
-SZ_UNIFORM, SZ_ABS_SDF, SZ_GAUSS_RHO, SZ_HOLE_RAMP = 0, 1, 2, 3
+SZ_UNIFORM, SZ_ABS_SDF, SZ_GAUSS_RHO, SZ_HOLE_RAMP, SZ_AUTO = 0, 1, 2, 3, 4
 
 
 @dataclass
@@ -51,6 +51,10 @@ class Sizing:
     s2: float = 1.0
     cent: np.ndarray = field(default_factory=lambda: np.zeros((0, 2)))
     holes: list = field(default_factory=list)
+    # automatic sizing (Eq. 8): K = a0, d_s = a1 min(dx, dy), and the medial
+    # point trimming's n_thres and fac_nei
+    n_thres: int = 3
+    fac_nei: float = 2.0
 
 
 @dataclass
@@ -205,7 +209,8 @@ def _inside(wl: Workload, x: np.ndarray, y: np.ndarray) -> np.ndarray:
 def _weight(wl: Workload, x: np.ndarray, y: np.ndarray) -> np.ndarray:
     """Sampling weight proportional to the target point density."""
     sz = wl.sizing
-    if sz.kind == SZ_UNIFORM:
+    if sz.kind in (SZ_UNIFORM, SZ_AUTO):
+        # automatic sizing is computed by the method itself: uniform start
         return np.ones_like(x)
     if sz.kind == SZ_GAUSS_RHO:
         acc = np.zeros_like(x)
