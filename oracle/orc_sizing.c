@@ -90,48 +90,75 @@ static int voronoi_cell(const double *s, int64_t ns, int64_t i, const double box
   return n;
 }
 
-int64_t orc_medial_points(const double *s, int64_t ns, const double box[4], double *out, int64_t cap) {
-  int64_t nm = 0;
+/* The poles of point i (v1 then v2) into out[0..4), returns a 2-bit mask
+   of the poles found. */
+static int poles(const double *s, int64_t ns, int64_t i, const double box[4], double *out) {
   double px[ORC_VMAX], py[ORC_VMAX];
   int64_t pe[ORC_VMAX];
-  for (int64_t i = 0; i < ns; i++) {
-    int n = voronoi_cell(s, ns, i, box, px, py, pe);
-    if (n < 3) continue;
-    const double sx = s[2 * i], sy = s[2 * i + 1];
-    /* v1: the farthest vertex; a vertex with a box edge on either side
-       stands for infinity and is never a medial point */
-    int b1 = -1;
-    double d1 = -1.0;
-    for (int k = 0; k < n; k++) {
-      double d = (px[k] - sx) * (px[k] - sx) + (py[k] - sy) * (py[k] - sy);
-      if (d > d1) { d1 = d; b1 = k; }
-    }
-    const double ux = px[b1] - sx, uy = py[b1] - sy;
-    int real1 = pe[b1] >= 0 && pe[b1 == 0 ? n - 1 : b1 - 1] >= 0;
-    if (real1) {
-      if (nm < cap) { out[2 * nm] = px[b1]; out[2 * nm + 1] = py[b1]; }
-      nm++;
-    }
-    /* v2: the farthest real vertex in the open half plane (v - s) . u < 0 */
-    int b2 = -1;
-    double d2 = -1.0;
-    for (int k = 0; k < n; k++) {
-      int real = pe[k] >= 0 && pe[k == 0 ? n - 1 : k - 1] >= 0;
-      if (!real || (px[k] - sx) * ux + (py[k] - sy) * uy >= 0) continue;
-      double d = (px[k] - sx) * (px[k] - sx) + (py[k] - sy) * (py[k] - sy);
-      if (d > d2) { d2 = d; b2 = k; }
-    }
-    if (b2 >= 0) {
-      if (nm < cap) { out[2 * nm] = px[b2]; out[2 * nm + 1] = py[b2]; }
-      nm++;
-    }
+  int n = voronoi_cell(s, ns, i, box, px, py, pe);
+  if (n < 3) return 0;
+  const double sx = s[2 * i], sy = s[2 * i + 1];
+  int found = 0;
+  /* v1: the farthest vertex; a vertex with a box edge on either side
+     stands for infinity and is never a medial point */
+  int b1 = -1;
+  double d1 = -1.0;
+  for (int k = 0; k < n; k++) {
+    double d = (px[k] - sx) * (px[k] - sx) + (py[k] - sy) * (py[k] - sy);
+    if (d > d1) { d1 = d; b1 = k; }
   }
+  const double ux = px[b1] - sx, uy = py[b1] - sy;
+  if (pe[b1] >= 0 && pe[b1 == 0 ? n - 1 : b1 - 1] >= 0) {
+    out[0] = px[b1];
+    out[1] = py[b1];
+    found |= 1;
+  }
+  /* v2: the farthest real vertex in the open half plane (v - s) . u < 0 */
+  int b2 = -1;
+  double d2 = -1.0;
+  for (int k = 0; k < n; k++) {
+    int real = pe[k] >= 0 && pe[k == 0 ? n - 1 : k - 1] >= 0;
+    if (!real || (px[k] - sx) * ux + (py[k] - sy) * uy >= 0) continue;
+    double d = (px[k] - sx) * (px[k] - sx) + (py[k] - sy) * (py[k] - sy);
+    if (d > d2) { d2 = d; b2 = k; }
+  }
+  if (b2 >= 0) {
+    out[2] = px[b2];
+    out[3] = py[b2];
+    found |= 2;
+  }
+  return found;
+}
+
+int64_t orc_medial_points(const double *s, int64_t ns, const double box[4], double *out, int64_t cap) {
+  double *tmp = (double *)malloc(sizeof(double) * 4 * (size_t)(ns > 0 ? ns : 1));
+  unsigned char *mask = (unsigned char *)malloc((size_t)(ns > 0 ? ns : 1));
+  if (!tmp || !mask) {
+    free(tmp);
+    free(mask);
+    return -1;
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < ns; i++) mask[i] = (unsigned char)poles(s, ns, i, box, tmp + 4 * i);
+  int64_t nm = 0;
+  for (int64_t i = 0; i < ns; i++)
+    for (int q = 0; q < 2; q++) {
+      if (!(mask[i] >> q & 1)) continue;
+      if (nm < cap) {
+        out[2 * nm] = tmp[4 * i + 2 * q];
+        out[2 * nm + 1] = tmp[4 * i + 2 * q + 1];
+      }
+      nm++;
+    }
+  free(tmp);
+  free(mask);
   return nm;
 }
 
 int64_t orc_trim_medial(const double *m, int64_t nm, double r_nei, int32_t n_thres, uint8_t *keep) {
   int64_t kept = 0;
   const double r2 = r_nei * r_nei;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : kept)
   for (int64_t i = 0; i < nm; i++) {
     int64_t c = 0;
     for (int64_t j = 0; j < nm; j++) {
@@ -146,6 +173,7 @@ int64_t orc_trim_medial(const double *m, int64_t nm, double r_nei, int32_t n_thr
 }
 
 void orc_lfs(const double *s, int64_t ns, const double *m, int64_t nm, const uint8_t *keep, double *lfs) {
+#pragma omp parallel for schedule(dynamic, 64)
   for (int64_t i = 0; i < ns; i++) {
     double best = INFINITY;
     for (int64_t j = 0; j < nm; j++) {
