@@ -24,10 +24,12 @@
  *    trime_state_workspace_bytes(); the library keeps no pointer after a
  *    call returns, allocates no device memory in any call except
  *    trime_sdf_grid_build (setup: one temporary buffer for the primitive
- *    list, and the candidate lists of SEGMENTS primitives), and never
- *    synchronises except in trime_state_bind (setup: reads the grid
- *    scalars), trime_sdf_grid_build with SEGMENTS primitives, trime_stats_read,
- *    trime_autotune (tuning), trime_add_points and trime_run_growing.
+ *    list, the candidate lists of SEGMENTS primitives and of automatic
+ *    sizing) and trime_auto_sizing (its scratch), and never synchronises
+ *    except in trime_state_bind (setup: reads the grid scalars),
+ *    trime_sdf_grid_build with SEGMENTS primitives or automatic sizing,
+ *    trime_auto_sizing, trime_stats_read, trime_autotune (tuning),
+ *    trime_add_points and trime_run_growing.
  *  - Streams: `stream` is a hipStream_t (passed as void*); 0 is the null
  *    stream.  All work is enqueued on it in order.
  *  - Layouts: structure of arrays.  Positions are float64 x[n], y[n] in both
@@ -101,8 +103,11 @@ enum {
   TRIME_SZ_UNIFORM = 0,   /* mu = 1                                          */
   TRIME_SZ_ABS_SDF = 1,   /* mu = a0 + a1 |sdf|                              */
   TRIME_SZ_GAUSS_RHO = 2, /* rho = a0 + a1 sum_k exp(-|x - c_k|^2 / s2), mu = rho^-1/2 */
-  TRIME_SZ_HOLE_RAMP = 3  /* mu = 1 + (a0 - 1) min(d_H / a1, 1), d_H = distance to
+  TRIME_SZ_HOLE_RAMP = 3, /* mu = 1 + (a0 - 1) min(d_H / a1, 1), d_H = distance to
                              the nearest primitive listed in holes              */
+  TRIME_SZ_AUTO = 4       /* automatic (Sec. 3.3, Eq. 8): mu(x) = min over the
+                             boundary points s of K |x - s| + lfs(s), K = a0;
+                             see trime_auto_sizing                             */
 };
 typedef struct {
   int32_t kind;
@@ -111,6 +116,8 @@ typedef struct {
   const double *cent;   /* host, ncent (x, y) pairs                         */
   int32_t nholes;
   const int32_t *holes; /* host, indices into the primitive list            */
+  int32_t n_thres;      /* AUTO: medial points need this many neighbours (0 -> 3) */
+  double fac_nei;       /* AUTO: neighbour radius fac_nei n_thres d_s (0 -> 2)   */
 } trime_sizing;
 
 /* Vertex-centred node grid: node (i, j) at (x0 + i dx, y0 + j dy).  Node
@@ -438,6 +445,35 @@ typedef struct {
   double fac_add;       /* fac_add (Table 8: 0.6)                         */
 } trime_growing;
 trime_status trime_run_growing(trime_state *st, const trime_growing *cfg, void *stream);
+
+/* ---- automatic sizing (Sec. 3.3, Eq. 8; App. A) ----------------------------
+   The steps of TRIME_SZ_AUTO, which trime_sdf_grid_build runs before its
+   node pass (mu at the nodes, h from it as for every sizing):
+   - boundary points S of the SEGMENTS loops, in primitive and vertex order:
+     each vertex, then on a segment of length L > d_s the floor(L / d_s)
+     points that split it evenly (spacing below d_s), d_s = a1 min(dx, dy)
+     (fac_s in App. A; the trimming of S to spacing d_s is not done);
+   - medial-axis approximating points: the Voronoi cell of each s among S,
+     clipped to the grid's box grown by its width and height on every side;
+     v1 = its farthest vertex, kept unless a box edge meets it (then it
+     stands for a vertex at infinity), v2 = its farthest vertex without a box
+     edge in the open half plane (v - s) . (v1 - s) < 0, if any; in the order
+     of S, v1 before v2;
+   - trimming: a medial point is kept when at least n_thres other medial
+     points lie within r_nei = fac_nei n_thres d_s;
+   - lfs(s) = the distance to the nearest kept medial point;
+   - mu(x) = min over s of K |x - s| + lfs(s), K = a0, at the grid nodes.
+   trime_auto_sizing runs the first four on the device and returns S
+   (d_pts, s_cap points), the medial points (d_medial, m_cap points) with
+   their keep flags, and lfs (d_lfs, s_cap entries); *ns_out and *nm_out
+   receive the counts.  Synchronises the stream; allocates and frees device
+   scratch.  Errors: TRIME_EINVAL for a geometry without SEGMENTS loops, a
+   sizing kind other than AUTO, a1 <= 0, a0 < 0, a Voronoi cell of more than
+   62 vertices or no kept medial point; TRIME_ECAPACITY when s_cap < |S| or
+   m_cap < 2 |S| (the counts known so far are written). */
+trime_status trime_auto_sizing(const trime_geometry *geo, const trime_sizing *sz, const trime_grid *grid,
+                               double *d_pts, int64_t s_cap, int64_t *ns_out, double *d_medial, uint8_t *d_keep,
+                               int64_t m_cap, int64_t *nm_out, double *d_lfs, void *stream);
 
 /* Mesh quality of the state's valid triangles (Eq. 10-11) into stats. */
 trime_status trime_quality(trime_state *st, void *stream);

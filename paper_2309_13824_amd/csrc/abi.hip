@@ -69,6 +69,105 @@ static bool grid_ok(const trime_grid *g) {
          (g->dtype_bytes == 4 || g->dtype_bytes == 8) && isfinite(g->x0) && isfinite(g->y0);
 }
 
+// ------------------------------------------------------ automatic sizing --
+
+static trime_status auto_ok(const trime_geometry *geo, const trime_sizing *sz, const char *who) {
+  static thread_local char msg[160];
+  const char *why = nullptr;
+  bool any = false;
+  for (int k = 0; geo && k < geo->nprims; k++) any = any || geo->prims[k].kind == TRIME_PRIM_SEGMENTS;
+  if (!sz || sz->kind != TRIME_SZ_AUTO)
+    why = "the sizing kind is not AUTO";
+  else if (!any)
+    why = "automatic sizing needs SEGMENTS loops";
+  else if (!(sz->a1 > 0) || !(sz->a0 >= 0) || !isfinite(sz->a0) || !isfinite(sz->a1))
+    why = "automatic sizing needs a0 = K >= 0 and a1 = fac_s > 0";
+  else if (sz->n_thres < 0 || !(sz->fac_nei >= 0))
+    why = "automatic sizing: negative n_thres or fac_nei";
+  if (!why) return TRIME_OK;
+  snprintf(msg, sizeof msg, "%s: %s", who, why);
+  return fail(TRIME_EINVAL, msg);
+}
+
+// Boundary points of the SEGMENTS loops (App. A, segment input): each vertex,
+// then floor(L / d_s) points splitting a segment of length L > d_s evenly.
+static std::vector<double> boundary_points(const trime_geometry *geo, double d_s) {
+  std::vector<double> out;
+  for (int q = 0; q < geo->nprims; q++) {
+    const trime_prim &p = geo->prims[q];
+    if (p.kind != TRIME_PRIM_SEGMENTS) continue;
+    const double *v = geo->poly + 2 * (size_t)p.voff;
+    for (int k = 0; k < p.nv; k++) {
+      const int k1 = k + 1 == p.nv ? 0 : k + 1;
+      const double ax = v[2 * k], ay = v[2 * k + 1], bx = v[2 * k1], by = v[2 * k1 + 1];
+      const double L = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
+      const int64_t pieces = L > d_s ? (int64_t)floor(L / d_s) + 1 : 1;
+      for (int64_t i = 0; i < pieces; i++) {
+        const double t = (double)i / (double)pieces;
+        out.push_back(ax + t * (bx - ax));
+        out.push_back(ay + t * (by - ay));
+      }
+    }
+  }
+  return out;
+}
+
+struct AutoSetup {
+  double d_s, r_nei, box[4], gbox[4];
+  int n_thres;
+};
+
+static AutoSetup auto_setup(const trime_sizing *sz, const trime_grid *grid) {
+  AutoSetup a;
+  a.d_s = sz->a1 * fmin(grid->dx, grid->dy);
+  a.n_thres = sz->n_thres > 0 ? sz->n_thres : 3;
+  const double fac_nei = sz->fac_nei > 0 ? sz->fac_nei : 2.0;
+  a.r_nei = fac_nei * a.n_thres * a.d_s;
+  const double W = (grid->nx - 1) * grid->dx, H = (grid->ny - 1) * grid->dy;
+  a.gbox[0] = grid->x0;
+  a.gbox[1] = grid->y0;
+  a.gbox[2] = grid->x0 + W;
+  a.gbox[3] = grid->y0 + H;
+  a.box[0] = grid->x0 - W;
+  a.box[1] = grid->y0 - H;
+  a.box[2] = grid->x0 + 2 * W;
+  a.box[3] = grid->y0 + 2 * H;
+  return a;
+}
+
+trime_status trime_auto_sizing(const trime_geometry *geo, const trime_sizing *sz, const trime_grid *grid,
+                               double *d_pts, int64_t s_cap, int64_t *ns_out, double *d_medial, uint8_t *d_keep,
+                               int64_t m_cap, int64_t *nm_out, double *d_lfs, void *stream) {
+  if (!geo || !grid_ok(grid) || !ns_out || !nm_out || !d_pts || !d_medial || !d_keep || !d_lfs ||
+      geo->nprims <= 0 || !geo->prims)
+    return fail(TRIME_EINVAL, "trime_auto_sizing: null or invalid argument");
+  for (int k = 0; k < geo->nprims; k++) {
+    const trime_prim &p = geo->prims[k];
+    if (p.kind == TRIME_PRIM_SEGMENTS && (p.nv < 3 || p.voff < 0 || p.voff + p.nv > geo->npoly || !geo->poly))
+      return fail(TRIME_EINVAL, "trime_auto_sizing: bad polygon range");
+  }
+  trime_status e = auto_ok(geo, sz, "trime_auto_sizing");
+  if (e) return e;
+  const AutoSetup A = auto_setup(sz, grid);
+  std::vector<double> S = boundary_points(geo, A.d_s);
+  const int64_t ns = (int64_t)S.size() / 2;
+  *ns_out = ns;
+  *nm_out = -1;
+  if (s_cap < ns || m_cap < 2 * ns) return fail(TRIME_ECAPACITY, "trime_auto_sizing: output buffers too small");
+  if (ns >= ((int64_t)1 << 30)) return fail(TRIME_EUNSUPPORTED, "trime_auto_sizing: too many boundary points");
+  hipStream_t s = (hipStream_t)stream;
+  TRY_HIP(hipMemcpyAsync(d_pts, S.data(), sizeof(double) * S.size(), hipMemcpyHostToDevice, s), "copy points");
+  std::vector<void *> allocs;
+  int64_t nm = 0;
+  const char *err = auto_sizing_build(d_pts, ns, A.box, A.gbox, A.r_nei, A.n_thres, sz->a0, 0.0, d_medial, d_keep,
+                                      d_lfs, &nm, nullptr, allocs, s);
+  for (void *a : allocs) (void)hipFreeAsync(a, s);
+  TRY_HIP(hipStreamSynchronize(s), "trime_auto_sizing (sync)");
+  if (err) return fail(TRIME_EINVAL, err);
+  *nm_out = nm;
+  return check_hip("trime_auto_sizing");
+}
+
 trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing *sz,
                                   const trime_grid *grid, int64_t n_total, void *d_sdf, void *d_mu,
                                   uint8_t *d_cat, float *d_hcell, trime_grid_scalars *d_scal,
@@ -88,7 +187,11 @@ trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing 
         (p.kind == TRIME_PRIM_ELLIPSE && !(p.p[2] > 0 && p.p[3] > 0)))
       return fail(TRIME_EINVAL, "trime_sdf_grid_build: nonpositive radius");
   }
-  if (sz->kind < 0 || sz->kind > 3) return fail(TRIME_EINVAL, "trime_sdf_grid_build: bad sizing kind");
+  if (sz->kind < 0 || sz->kind > TRIME_SZ_AUTO) return fail(TRIME_EINVAL, "trime_sdf_grid_build: bad sizing kind");
+  if (sz->kind == TRIME_SZ_AUTO) {
+    trime_status e = auto_ok(geo, sz, "trime_sdf_grid_build");
+    if (e) return e;
+  }
   if (sz->kind == TRIME_SZ_GAUSS_RHO && (sz->ncent < 0 || (sz->ncent > 0 && !sz->cent) || !(sz->s2 > 0)))
     return fail(TRIME_EINVAL, "trime_sdf_grid_build: bad density centres");
   if (sz->kind == TRIME_SZ_HOLE_RAMP) {
@@ -148,6 +251,32 @@ trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing 
       (hipMemcpyAsync(d_segs, trees.data(), b_segs, hipMemcpyHostToDevice, s) != hipSuccess ||
        hipStreamSynchronize(s) != hipSuccess))
     seg_err = "copy segment trees";
+  LfsField auto_field;
+  memset(&auto_field, 0, sizeof auto_field);
+  std::vector<double> S;
+  if (!seg_err && sz->kind == TRIME_SZ_AUTO) {
+    const AutoSetup A = auto_setup(sz, grid);
+    S = boundary_points(geo, A.d_s);
+    const int64_t ns = (int64_t)S.size() / 2;
+    double *d_S = nullptr, *d_med = nullptr, *d_lfs = nullptr;
+    uint8_t *d_keep = nullptr;
+    if (ns >= ((int64_t)1 << 30) ||
+        hipMallocAsync((void **)&d_S, sizeof(double) * S.size(), s) != hipSuccess ||
+        hipMallocAsync((void **)&d_med, sizeof(double) * 4 * (size_t)ns, s) != hipSuccess ||
+        hipMallocAsync((void **)&d_keep, 2 * (size_t)ns, s) != hipSuccess ||
+        hipMallocAsync((void **)&d_lfs, sizeof(double) * (size_t)ns, s) != hipSuccess) {
+      seg_err = "automatic sizing: allocation";
+    } else {
+      for (void *a : {(void *)d_S, (void *)d_med, (void *)d_keep, (void *)d_lfs}) allocs.push_back(a);
+      int64_t nm = 0;
+      if (hipMemcpyAsync(d_S, S.data(), sizeof(double) * S.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        seg_err = "automatic sizing: copy the boundary points";
+      else
+        seg_err = auto_sizing_build(d_S, ns, A.box, A.gbox, A.r_nei, A.n_thres, sz->a0,
+                                    8.0 * fmax(grid->dx, grid->dy), d_med, d_keep, d_lfs, &nm, &auto_field, allocs,
+                                    s);
+    }
+  }
   if (seg_err) {
     for (void *a : allocs) (void)hipFreeAsync(a, s);
     (void)hipFreeAsync(buf, s);
@@ -159,6 +288,7 @@ trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing 
   g.prims = d_prims;
   g.poly = d_poly;
   g.segs = d_segs;
+  g.auto_mu = auto_field;
   g.sz = *sz;
   g.cent = d_cent;
   g.holes = d_holes;

@@ -143,6 +143,7 @@ TRIME_D double csg_sdf(const GridPrims &g, double x, double y) {
 
 TRIME_D double sizing_mu(const GridPrims &g, double x, double y, double sdf) {
   switch (g.sz.kind) {
+    case TRIME_SZ_AUTO: return auto_mu(g.auto_mu, x, y);
     case TRIME_SZ_UNIFORM: return 1.0;
     case TRIME_SZ_ABS_SDF: return g.sz.a0 + g.sz.a1 * fabs(sdf);
     case TRIME_SZ_GAUSS_RHO: {

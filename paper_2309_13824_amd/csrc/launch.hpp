@@ -91,15 +91,29 @@ struct LoadArgs {
 };
 
 // Geometry for the grid build (device copies of the primitive lists).
-// Candidate lists of a segment loop (segsdf.hip): the finest cell grid of
-// its hierarchy over a box; cell c lists, in ascending order, every segment
-// that can be the nearest one for a point of the cell.
-struct SegTree {
-  const double *v;  // device vertices of the loop
-  int nv;
+// Candidate lists over a cell grid (segsdf.hip): cell c lists, in ascending
+// order, every item that can give the minimum of a Lipschitz function
+// family for some point of the cell.
+struct CandGrid {
   int nx, ny;
   double x0, y0, cw, ch;
   const int32_t *start, *cand;
+};
+
+// A closed segment loop and its candidate lists (the nearest segment).
+struct SegTree {
+  const double *v;  // device vertices of the loop
+  int nv;
+  CandGrid g;
+};
+
+// Automatic sizing (Eq. 8): boundary points s with lfs(s), and candidate
+// lists for min over s of K |x - s| + lfs(s).
+struct LfsField {
+  const double *s, *lfs;
+  int64_t ns;
+  double K;
+  CandGrid g;
 };
 
 struct GridPrims {
@@ -107,6 +121,7 @@ struct GridPrims {
   const trime_prim *prims;
   const double *poly;
   const SegTree *segs;  // per primitive (device); used by SEGMENTS only
+  LfsField auto_mu;     // automatic sizing
   trime_sizing sz;  // cent / holes point into device memory
   const double *cent;
   const int32_t *holes;
@@ -159,6 +174,14 @@ size_t grow_sel_bytes();
 int64_t grid_partials(int nx, int ny);
 const char *seg_tree_build(const double *d_v, int nv, double bx0, double by0, double bx1, double by1,
                            double target, SegTree *T, std::vector<void *> &allocs, hipStream_t s);
+// automatic sizing (sizing.hip): medial points of the ns device boundary
+// points from their Voronoi cells clipped to box (written to medial, room
+// for 2 ns points, compacted in order; count to *nm_host), their keep
+// flags, lfs, and (F not null) the candidate lists of the field over gbox
+const char *auto_sizing_build(const double *d_s, int64_t ns, const double box[4], const double gbox[4],
+                              double r_nei, int n_thres, double K, double target, double *medial, uint8_t *keep,
+                              double *lfs, int64_t *nm_host, LfsField *F, std::vector<void *> &allocs,
+                              hipStream_t s);
 void launch_grid_build(const GridPrims &g, int dtype_bytes, void *sdf, void *mu, uint8_t *cat,
                        float *hcell, trime_grid_scalars *scal, double *part, hipStream_t s);
 

@@ -1,4 +1,5 @@
-// Signed distance to a closed clockwise loop of line segments (Sec. 3.2).
+// Candidate lists over cell grids, for the nearest segment of a clockwise
+// segment loop (Sec. 3.2) and for the automatic sizing field (Eq. 8).
 //
 // The magnitude at a node is the distance to the nearest segment (equal
 // distances go to the lower segment index); the sign comes from the inward
@@ -23,16 +24,15 @@ namespace trime {
 
 // ------------------------------------------------------ candidate build --
 
-struct SegLevelArgs {
-  const double *v;
-  int nv;
+template <class M> struct LevelArgs {
+  M metric;
   // parent grid: F x F children per parent cell, the same origin
   int pnx;
   const int32_t *pstart, *pcand;
   int F, cnx, cny;
   double x0, y0, cw, ch;
-  int32_t *cnt;                 // count pass: per child cell
-  const int32_t *cstart;        // fill pass
+  int32_t *cnt;           // count pass: per child cell
+  const int32_t *cstart;  // fill pass
   int32_t *ccand;
 };
 
@@ -50,9 +50,11 @@ __device__ double block_min(double v, double *sh) {
   return r;
 }
 
-// Nearest distance at the child's centre over the parent's list, and the
-// filter bound; the child's parent range in [ps, pe).
-__device__ double child_bound(const SegLevelArgs &A, int64_t c, double &cx, double &cy, int32_t &ps, int32_t &pe,
+// The minimum at the child's centre over the parent's list, and the filter
+// bound: an item that gives the minimum somewhere within r of the centre has
+// a value there at most the minimum plus slack(r); the factor covers rounding.
+template <class M>
+__device__ double child_bound(const LevelArgs<M> &A, int64_t c, double &cx, double &cy, int32_t &ps, int32_t &pe,
                               double *sh) {
   const int ci = (int)(c % A.cnx), cj = (int)(c / A.cnx);
   const int64_t p = (int64_t)(cj / A.F) * A.pnx + ci / A.F;
@@ -60,19 +62,14 @@ __device__ double child_bound(const SegLevelArgs &A, int64_t c, double &cx, doub
   pe = A.pstart[p + 1];
   cx = A.x0 + ((double)ci + 0.5) * A.cw;
   cy = A.y0 + ((double)cj + 0.5) * A.ch;
-  double dmin = INFINITY;
-  for (int32_t i = ps + threadIdx.x; i < pe; i += SB) {
-    double t;
-    dmin = fmin(dmin, seg_dist_t(A.v, A.nv, A.pcand[i], cx, cy, t));
-  }
-  dmin = block_min(dmin, sh);
-  // a segment nearest to some point within r of the centre lies within
-  // dmin + 2r of the centre; the factor covers rounding of the distances
+  double vmin = INFINITY;
+  for (int32_t i = ps + threadIdx.x; i < pe; i += SB) vmin = fmin(vmin, A.metric.value(A.pcand[i], cx, cy));
+  vmin = block_min(vmin, sh);
   const double r = 0.5 * sqrt(A.cw * A.cw + A.ch * A.ch);
-  return (dmin + 2.0 * r) * (1.0 + 1e-9);
+  return (vmin + A.metric.slack(r)) * (1.0 + 1e-9);
 }
 
-__global__ __launch_bounds__(SB) void k_seg_count(SegLevelArgs A) {
+template <class M> __global__ __launch_bounds__(SB) void k_cand_count(LevelArgs<M> A) {
   __shared__ double sh[SB];
   __shared__ int cnt_sh;
   const int64_t c = blockIdx.x;
@@ -82,17 +79,14 @@ __global__ __launch_bounds__(SB) void k_seg_count(SegLevelArgs A) {
   if (threadIdx.x == 0) cnt_sh = 0;
   __syncthreads();
   int n = 0;
-  for (int32_t i = ps + threadIdx.x; i < pe; i += SB) {
-    double t;
-    n += seg_dist_t(A.v, A.nv, A.pcand[i], cx, cy, t) <= bound ? 1 : 0;
-  }
+  for (int32_t i = ps + threadIdx.x; i < pe; i += SB) n += A.metric.value(A.pcand[i], cx, cy) <= bound ? 1 : 0;
   if (n) atomicAdd(&cnt_sh, n);
   __syncthreads();
   if (threadIdx.x == 0) A.cnt[c] = cnt_sh;
 }
 
-// The kept candidates in the parent's order (ascending segment index).
-__global__ __launch_bounds__(SB) void k_seg_fill(SegLevelArgs A) {
+// The kept candidates in the parent's order (ascending).
+template <class M> __global__ __launch_bounds__(SB) void k_cand_fill(LevelArgs<M> A) {
   __shared__ double sh[SB];
   __shared__ int wsum[SB / 64];
   const int64_t c = blockIdx.x;
@@ -104,8 +98,7 @@ __global__ __launch_bounds__(SB) void k_seg_fill(SegLevelArgs A) {
   const int32_t end = A.cstart[c + 1];  // the count pass kept as many
   for (int32_t base = ps; base < pe; base += SB) {
     const int32_t i = base + threadIdx.x;
-    double t;
-    const bool keep = i < pe && seg_dist_t(A.v, A.nv, A.pcand[i], cx, cy, t) <= bound;
+    const bool keep = i < pe && A.metric.value(A.pcand[i], cx, cy) <= bound;
     const uint64_t m = __ballot(keep);
     if (lane == 0) wsum[w] = __popcll(m);
     __syncthreads();
@@ -121,7 +114,7 @@ __global__ __launch_bounds__(SB) void k_seg_fill(SegLevelArgs A) {
   }
 }
 
-__global__ void k_seg_iota(int32_t *p, int n, int32_t *start) {
+__global__ void k_cand_iota(int32_t *p, int n, int32_t *start) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = i;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     start[0] = 0;
@@ -129,30 +122,30 @@ __global__ void k_seg_iota(int32_t *p, int n, int32_t *start) {
   }
 }
 
-// Builds the candidate hierarchy of one loop (device vertices d_v) over the
-// box [bx0, bx1] x [by0, by1], down to cells of about `target` on a side.
-// Allocations go to `allocs` (freed by the caller after the grid build).
-const char *seg_tree_build(const double *d_v, int nv, double bx0, double by0, double bx1, double by1,
-                           double target, SegTree *T, std::vector<void *> &allocs, hipStream_t s) {
+// Builds the candidate hierarchy of n items over the box [bx0, bx1] x
+// [by0, by1]: up to three levels of 8 x 8 refinement, down to cells of about
+// `target` on a side.  Allocations go to `allocs` (freed by the caller).
+template <class M>
+static const char *cand_build(const M &metric, int n, double bx0, double by0, double bx1, double by1, double target,
+                              CandGrid *G, std::vector<void *> &allocs, hipStream_t s) {
   const int F = 8;
   const double W = bx1 - bx0, H = by1 - by0;
   int levels = 1;
   while (levels < 3 && fmax(W, H) / pow((double)F, levels) > target) levels++;
   int32_t *start = nullptr, *cand = nullptr;
-  if (hipMallocAsync((void **)&start, 2 * sizeof(int32_t), s) != hipSuccess) return "segment lattice: allocation";
+  if (hipMallocAsync((void **)&start, 2 * sizeof(int32_t), s) != hipSuccess) return "candidate lists: allocation";
   allocs.push_back(start);
-  if (hipMallocAsync((void **)&cand, sizeof(int32_t) * (size_t)nv, s) != hipSuccess)
-    return "segment lattice: allocation";
+  if (hipMallocAsync((void **)&cand, sizeof(int32_t) * (size_t)(n > 0 ? n : 1), s) != hipSuccess)
+    return "candidate lists: allocation";
   allocs.push_back(cand);
-  hipLaunchKernelGGL(k_seg_iota, dim3((nv + 255) / 256 < 1024 ? (nv + 255) / 256 : 1024), dim3(256), 0, s, cand, nv,
-                     start);
+  const int ib = (n + 255) / 256;
+  hipLaunchKernelGGL(k_cand_iota, dim3(ib < 1 ? 1 : (ib > 1024 ? 1024 : ib)), dim3(256), 0, s, cand, n, start);
   int pnx = 1;
   for (int l = 1; l <= levels; l++) {
     const int cnx = pnx * F;
     const int64_t nc = (int64_t)cnx * cnx;
-    SegLevelArgs A;
-    A.v = d_v;
-    A.nv = nv;
+    LevelArgs<M> A;
+    A.metric = metric;
     A.pnx = pnx;
     A.pstart = start;
     A.pcand = cand;
@@ -163,47 +156,60 @@ const char *seg_tree_build(const double *d_v, int nv, double bx0, double by0, do
     A.y0 = by0;
     A.cw = W / cnx;
     A.ch = H / cnx;
-    int32_t *cnt = nullptr, *cstart = nullptr;
+    int32_t *cnt = nullptr, *cstart = nullptr, *tmp = nullptr;
     if (hipMallocAsync((void **)&cnt, sizeof(int32_t) * (size_t)nc, s) != hipSuccess ||
-        hipMallocAsync((void **)&cstart, sizeof(int32_t) * (size_t)(nc + 1), s) != hipSuccess)
-      return "segment lattice: allocation";
+        hipMallocAsync((void **)&cstart, sizeof(int32_t) * (size_t)(nc + 1), s) != hipSuccess ||
+        hipMallocAsync((void **)&tmp, sizeof(int32_t) * (scan_tmp_ints(nc) + 1), s) != hipSuccess)
+      return "candidate lists: allocation";
     allocs.push_back(cnt);
     allocs.push_back(cstart);
-    int32_t *tmp = nullptr;
-    if (hipMallocAsync((void **)&tmp, sizeof(int32_t) * (scan_tmp_ints(nc) + 1), s) != hipSuccess)
-      return "segment lattice: allocation";
     allocs.push_back(tmp);
     A.cnt = cnt;
     A.cstart = cstart;
     A.ccand = nullptr;
-    hipLaunchKernelGGL(k_seg_count, dim3((unsigned)nc), dim3(SB), 0, s, A);
+    hipLaunchKernelGGL(k_cand_count<M>, dim3((unsigned)nc), dim3(SB), 0, s, A);
     scan_i32(cnt, cstart, nc, tmp, s);
     int32_t total = 0;
     if (hipMemcpyAsync(&total, cstart + nc, sizeof total, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
-      return "segment lattice: read candidate count";
-    if (total < 0) return "segment lattice: more than 2^31 candidates";
+      return "candidate lists: read the candidate count";
+    if (total < 0) return "candidate lists: more than 2^31 candidates";
     int32_t *ccand = nullptr;
     if (hipMallocAsync((void **)&ccand, sizeof(int32_t) * (size_t)(total > 0 ? total : 1), s) != hipSuccess)
-      return "segment lattice: allocation";
+      return "candidate lists: allocation";
     allocs.push_back(ccand);
     A.ccand = ccand;
-    hipLaunchKernelGGL(k_seg_fill, dim3((unsigned)nc), dim3(SB), 0, s, A);
+    hipLaunchKernelGGL(k_cand_fill<M>, dim3((unsigned)nc), dim3(SB), 0, s, A);
     start = cstart;
     cand = ccand;
     pnx = cnx;
   }
+  G->nx = pnx;
+  G->ny = pnx;
+  G->x0 = bx0;
+  G->y0 = by0;
+  G->cw = W / pnx;
+  G->ch = H / pnx;
+  G->start = start;
+  G->cand = cand;
+  return nullptr;
+}
+
+const char *seg_tree_build(const double *d_v, int nv, double bx0, double by0, double bx1, double by1,
+                           double target, SegTree *T, std::vector<void *> &allocs, hipStream_t s) {
   T->v = d_v;
   T->nv = nv;
-  T->nx = pnx;
-  T->ny = pnx;
-  T->x0 = bx0;
-  T->y0 = by0;
-  T->cw = W / pnx;
-  T->ch = H / pnx;
-  T->start = start;
-  T->cand = cand;
-  return nullptr;
+  return cand_build(SegMetric{d_v, nv}, nv, bx0, by0, bx1, by1, target, &T->g, allocs, s);
+}
+
+const char *lfs_field_build(const double *d_s, const double *d_lfs, int64_t ns, double K, double bx0, double by0,
+                            double bx1, double by1, double target, LfsField *F, std::vector<void *> &allocs,
+                            hipStream_t s) {
+  F->s = d_s;
+  F->lfs = d_lfs;
+  F->ns = ns;
+  F->K = K;
+  return cand_build(LfsMetric{d_s, d_lfs, K}, (int)ns, bx0, by0, bx1, by1, target, &F->g, allocs, s);
 }
 
 }  // namespace trime

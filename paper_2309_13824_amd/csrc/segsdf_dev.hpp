@@ -47,20 +47,53 @@ TRIME_D double seg_signed(const double *v, int nv, int kb, double bt, double bes
   return dot > 0 ? -best : best;
 }
 
-TRIME_D int64_t seg_cell(const SegTree &T, double x, double y) {
-  double fx = floor((x - T.x0) / T.cw), fy = floor((y - T.y0) / T.ch);
-  fx = fmin(fmax(fx, 0.0), (double)(T.nx - 1));
-  fy = fmin(fmax(fy, 0.0), (double)(T.ny - 1));
-  return (int64_t)fy * T.nx + (int64_t)fx;
+TRIME_D int64_t cand_cell(const CandGrid &G, double x, double y) {
+  double fx = floor((x - G.x0) / G.cw), fy = floor((y - G.y0) / G.ch);
+  fx = fmin(fmax(fx, 0.0), (double)(G.nx - 1));
+  fy = fmin(fmax(fy, 0.0), (double)(G.ny - 1));
+  return (int64_t)fy * G.nx + (int64_t)fx;
+}
+
+// The function families the candidate lists are built for: value(k, x, y)
+// is L-Lipschitz in (x, y) for every item k, slack(r) = 2 L r.
+struct SegMetric {
+  const double *v;
+  int nv;
+  TRIME_D double value(int k, double x, double y) const {
+    double t;
+    return seg_dist_t(v, nv, k, x, y, t);
+  }
+  TRIME_D double slack(double r) const { return 2.0 * r; }
+};
+
+// K |x - s_k| + lfs(s_k), in the operation order of Eq. 8's reference.
+struct LfsMetric {
+  const double *s, *lfs;
+  double K;
+  TRIME_D double value(int k, double x, double y) const {
+    const double dx = x - s[2 * k], dy = y - s[2 * k + 1];
+    return K * sqrt(dx * dx + dy * dy) + lfs[k];
+  }
+  TRIME_D double slack(double r) const { return 2.0 * K * r; }
+};
+
+// mu at (x, y): the minimum over the cell's candidates (order-free).
+TRIME_D double auto_mu(const LfsField &F, double x, double y) {
+  const int64_t c = cand_cell(F.g, x, y);
+  const LfsMetric M{F.s, F.lfs, F.K};
+  double best = INFINITY;
+  const int32_t e = F.g.start[c + 1];
+  for (int32_t i = F.g.start[c]; i < e; i++) best = fmin(best, M.value(F.g.cand[i], x, y));
+  return best;
 }
 
 TRIME_D double segments_sdf(const SegTree &T, double x, double y) {
-  const int64_t c = seg_cell(T, x, y);
-  const int32_t e = T.start[c + 1];
+  const int64_t c = cand_cell(T.g, x, y);
+  const int32_t e = T.g.start[c + 1];
   double best = INFINITY, bt = 0.0;
   int kb = -1;
-  for (int32_t i = T.start[c]; i < e; i++) {
-    const int k = T.cand[i];  // ascending: strict < keeps the lowest index
+  for (int32_t i = T.g.start[c]; i < e; i++) {
+    const int k = T.g.cand[i];  // ascending: strict < keeps the lowest index
     double t;
     const double d = seg_dist_t(T.v, T.nv, k, x, y, t);
     if (d < best) {

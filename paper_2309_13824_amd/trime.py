@@ -43,7 +43,7 @@ class Geometry(C.Structure):
 class Sizing(C.Structure):
     _fields_ = [("kind", C.c_int32), ("a0", C.c_double), ("a1", C.c_double), ("s2", C.c_double),
                 ("ncent", C.c_int32), ("cent", C.POINTER(C.c_double)), ("nholes", C.c_int32),
-                ("holes", C.POINTER(C.c_int32))]
+                ("holes", C.POINTER(C.c_int32)), ("n_thres", C.c_int32), ("fac_nei", C.c_double)]
 
 
 class Grid(C.Structure):
@@ -150,7 +150,7 @@ EXPORTED = ["trime_last_error", "trime_version", "trime_default_params", "trime_
             "trime_quality", "trime_stats_read", "trime_stats_check", "trime_autotune_workspace_bytes",
             "trime_autotune", "trime_batch_graph_create", "trime_graph_launch", "trime_graph_destroy",
             "trime_step_adaptive", "trime_batch_create", "trime_batch_run", "trime_batch_destroy",
-            "trime_add_points", "trime_run_growing"]
+            "trime_add_points", "trime_run_growing", "trime_auto_sizing"]
 
 _lib = None
 
@@ -201,6 +201,9 @@ def lib(require_gpu: bool = True):
         L.trime_batch_destroy.argtypes = [vp]
         L.trime_add_points.argtypes = [st, C.c_int64, C.c_double, vp]
         L.trime_run_growing.argtypes = [st, C.POINTER(Growing), vp]
+        i64p = C.POINTER(C.c_int64)
+        L.trime_auto_sizing.argtypes = [C.POINTER(Geometry), C.POINTER(Sizing), C.POINTER(Grid), vp, C.c_int64, i64p,
+                                        vp, vp, C.c_int64, i64p, vp, vp]
         for f in EXPORTED:
             if f not in ("trime_last_error", "trime_version", "trime_default_params"):
                 getattr(L, f).restype = C.c_int
@@ -304,6 +307,16 @@ def run_growing(state, mode, max_iter, n_total, t_add=0.002, fac_add=0.6, t_qual
     cfg = Growing(Adaptive(m, int(max_iter), float(t_quality), float(t_amax), float(t_switch)), int(n_total),
                   float(t_add), float(fac_add))
     _check(lib().trime_run_growing(C.byref(state), C.byref(cfg), _stream(stream)))
+
+
+def auto_sizing(geo, sz, grid, pts, medial, keep, lfs, stream=None):
+    """Boundary points, medial points with keep flags and lfs of the
+    automatic sizing field into device tensors; returns (ns, nm)."""
+    ns, nm = C.c_int64(0), C.c_int64(0)
+    _check(lib().trime_auto_sizing(C.byref(geo), C.byref(sz), C.byref(grid), _ptr(pts), pts.numel() // 2,
+                                   C.byref(ns), _ptr(medial), _ptr(keep), medial.numel() // 2, C.byref(nm), _ptr(lfs),
+                                   _stream(stream)))
+    return ns.value, nm.value
 
 
 def quality(state, stream=None):

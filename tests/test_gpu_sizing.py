@@ -1,0 +1,119 @@
+"""Automatic sizing (Sec. 3.3, Eq. 8) on the GPU through the C ABI against
+the oracle: boundary points, medial-axis points, their trimming and lfs bit
+for bit, and the mu field of the grid build at every node."""
+import ctypes as C
+import math
+import time
+
+import numpy as np
+import pytest
+
+from paper_2309_13824_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+FP64 = 0
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2309_13824_amd import trime
+    trime.lib()
+    return trime
+
+
+def loop_workload(verts, grid_n=128, K=0.1, fac_s=0.5, n=2000):
+    prims = [I.Prim(I.OP_INIT, I.PRIM_SEGMENTS, (), np.asarray(verts, np.float64))]
+    grid = I.centred_grid(grid_n, 17, int(round(math.log2(grid_n))) + 4, 0.5, 8)
+    wl = I.Workload("loop", prims, I.Sizing(I.SZ_AUTO, K, fac_s), grid, n, [], 0)
+    wl.x, wl.y = I.sample_points(wl, np.random.default_rng(1), (0, 0, 1, 1))
+    return wl
+
+
+def circle(m, r=0.4):
+    th = 0.1 - 2 * np.pi * np.arange(m) / m
+    return np.stack([0.5 + r * np.cos(th), 0.5 + r * np.sin(th)], 1)
+
+
+CASES = {
+    "circle96": lambda: loop_workload(circle(96), K=0.1, fac_s=1.1 * 2 * 0.4 * math.sin(math.pi / 96)
+                                      / (17 * 2.0 ** -11)),
+    "square": lambda: loop_workload(np.array([[0.2, 0.2], [0.2, 0.8], [0.8, 0.8], [0.8, 0.2]])),
+    "coast300": lambda: loop_workload(I.coast_loop(300), K=0.2),
+    "coast2000": lambda: loop_workload(I.coast_loop(2000), grid_n=512, K=0.05),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_auto_sizing_steps_match_oracle(orc, T, name):
+    """The boundary points, the medial points (in order), their keep flags
+    and lfs equal the oracle's bit for bit."""
+    import torch
+    from paper_2309_13824_amd.mesher import _geometry
+    wl = CASES[name]()
+    au = orc.auto_sizing(wl)
+    geo, sz, keep_alive = _geometry(wl)
+    g = wl.grid
+    grid = T.Grid(g.nx, g.ny, g.x0, g.y0, g.dx, g.dy, g.dtype_bytes)
+    ns = len(au.s)
+    pts = torch.empty(2 * ns, dtype=torch.float64, device="cuda")
+    med = torch.empty(4 * ns, dtype=torch.float64, device="cuda")
+    keep = torch.empty(2 * ns, dtype=torch.uint8, device="cuda")
+    lfs = torch.empty(ns, dtype=torch.float64, device="cuda")
+    gns, gnm = T.auto_sizing(geo, sz, grid, pts, med, keep, lfs)
+    print("%s: %d boundary points, %d medial points (%d kept)" % (name, gns, gnm, int(au.keep.sum())), flush=True)
+    assert gns == ns and gnm == len(au.medial)
+    assert np.array_equal(pts.cpu().numpy().reshape(-1, 2), au.s)
+    assert np.array_equal(med[:2 * gnm].cpu().numpy().reshape(-1, 2), au.medial)
+    assert np.array_equal(keep[:gnm].cpu().numpy(), au.keep)
+    assert np.array_equal(lfs.cpu().numpy(), au.lfs)
+
+
+@pytest.mark.parametrize("name", ["circle96", "coast300", "coast2000"])
+def test_auto_sizing_grid_matches_oracle(orc, T, name):
+    """The grid built with automatic sizing: mu at every node equals the
+    oracle's brute-force minimum over all boundary points, bit for bit; the
+    categories, H and h_avg follow."""
+    import torch
+    from paper_2309_13824_amd.mesher import Mesher
+    wl = CASES[name]()
+    og = orc.build_grid(wl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m = Mesher(wl, precision=FP64)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    sdf, mu, cat, hcell, scal = m.grid_arrays()
+    print("%s: GPU grid build with automatic sizing %.1f ms (with the Mesher setup), %d^2 nodes" %
+          (name, secs * 1e3, wl.grid.nx), flush=True)
+    assert np.array_equal(sdf, og.sdf)
+    assert np.array_equal(mu, og.mu)
+    assert np.array_equal(cat, og.cat)
+    assert scal[0] == pytest.approx(og.H, rel=1e-13)
+    assert scal[1] == pytest.approx(og.h_avg, rel=1e-12)
+
+
+def test_auto_sizing_full_grid_on_sampled_nodes(orc, T):
+    """The coast loop of 4096 segments on a 4096^2 grid: mu at 2,000 seeded
+    nodes equals the oracle's pointwise field."""
+    import torch
+    from paper_2309_13824_amd.mesher import Mesher
+    wl = loop_workload(I.coast_loop(4096), grid_n=4096, K=0.05, n=2000)
+    au = orc.auto_sizing(wl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m = Mesher(wl, precision=FP64)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    print("coast 4096 segments, 4096^2 grid: %d boundary points, GPU grid build with automatic sizing %.1f ms "
+          "(with the Mesher setup)" % (len(au.s), secs * 1e3), flush=True)
+    mu = m.mu.double().cpu().numpy()
+    g = wl.grid
+    s_pts = np.ascontiguousarray(au.s.reshape(-1))
+    lfs = np.ascontiguousarray(au.lfs)
+    dp = C.POINTER(C.c_double)
+    for k in np.random.default_rng(9).integers(0, g.nx * g.ny, 2000):
+        i, j = int(k % g.nx), int(k // g.nx)
+        x, y = g.x0 + i * g.dx, g.y0 + j * g.dy
+        want = orc.lib().orc_auto_mu(s_pts.ctypes.data_as(dp), lfs.ctypes.data_as(dp), len(au.s), 0.05, x, y)
+        assert mu[k] == want, (i, j)
