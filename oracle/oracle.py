@@ -104,6 +104,8 @@ def lib():
         L.orc_segments_sdf.restype = C.c_double
         L.orc_boundary_points.argtypes = [C.POINTER(Prim), C.c_int32, dp, C.c_double, dp, C.c_int64]
         L.orc_boundary_points.restype = C.c_int64
+        L.orc_trim_boundary.argtypes = [C.POINTER(Prim), C.c_int32, dp, C.c_double, C.c_double, dp, C.c_int64]
+        L.orc_trim_boundary.restype = C.c_int64
         L.orc_medial_points.argtypes = [dp, C.c_int64, dp, dp, C.c_int64]
         L.orc_medial_points.restype = C.c_int64
         L.orc_trim_medial.argtypes = [dp, C.c_int64, C.c_double, C.c_int32, C.POINTER(C.c_uint8)]
@@ -219,9 +221,10 @@ class AutoSizing:
     r_nei: float
 
 
-def auto_sizing(wl) -> AutoSizing:
+def auto_sizing(wl, trim=True) -> AutoSizing:
     """Boundary points of the workload's segment loops (App. A) at
-    d_s = fac_s min(dx, dy) (fac_s = sizing.a1), medial-axis points from
+    d_s = fac_s min(dx, dy) (fac_s = sizing.a1), trimmed (trim=True) with
+    geps = fac_geps min(dx, dy), medial-axis points from
     their Voronoi cells clipped to the grid's box grown by its size on every
     side, trimming with r_nei = fac_nei n_thres d_s, and lfs (orc.h states
     each step)."""
@@ -232,6 +235,10 @@ def auto_sizing(wl) -> AutoSizing:
     n = lib().orc_boundary_points(prims, len(wl.prims), _p(poly, C.c_double), d_s, None, 0)
     s = np.empty((n, 2), np.float64)
     lib().orc_boundary_points(prims, len(wl.prims), _p(poly, C.c_double), d_s, _p(s, C.c_double), n)
+    if trim:
+        geps = sz.fac_geps * min(g.dx, g.dy)
+        n = lib().orc_trim_boundary(prims, len(wl.prims), _p(poly, C.c_double), d_s, geps, _p(s, C.c_double), n)
+        s = np.ascontiguousarray(s[:n])
     W, H = (g.nx - 1) * g.dx, (g.ny - 1) * g.dy
     box = np.array([g.x0 - W, g.y0 - H, g.x0 + 2 * W, g.y0 + 2 * H], np.float64)
     m = np.empty((2 * n, 2), np.float64)

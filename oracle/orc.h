@@ -77,6 +77,16 @@ typedef struct {
    first cap points are written). */
 int64_t orc_boundary_points(const orc_prim *prims, int32_t nprims, const double *poly, double d_s, double *out,
                             int64_t cap);
+/* App. A trimming of boundary points, in place: sweeps over the points in
+   index order until one changes nothing.  Point i (not removed, not done)
+   takes its closest other remaining point p* whose midpoint m with it lies
+   on the boundary (distance to the nearest segment of the SEGMENTS loops at
+   most geps), the nearest first, ties to the lower index.  With none, or p*
+   at least d_s away, point i is done; otherwise p* is removed and point i
+   moves to m.  Returns the count of the remaining points, compacted in
+   order. */
+int64_t orc_trim_boundary(const orc_prim *prims, int32_t nprims, const double *poly, double d_s, double geps,
+                          double *pts, int64_t n);
 /* Medial-axis approximating points: for each point s, its Voronoi cell among
    all points (every other point's bisector, in index order, clipping the box
    [box0, box2] x [box1, box3]); v1 = the farthest cell vertex, added unless

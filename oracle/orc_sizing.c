@@ -195,3 +195,75 @@ double orc_auto_mu(const double *s, const double *lfs, int64_t ns, double K, dou
   }
   return best;
 }
+
+/* |sdf| of the segment loops at (x, y): the distance to the nearest segment
+   of any SEGMENTS loop. */
+static double loops_dist(const orc_prim *prims, int32_t nprims, const double *poly, double x, double y) {
+  double d = INFINITY;
+  for (int32_t q = 0; q < nprims; q++) {
+    if (prims[q].kind != ORC_PRIM_SEGMENTS) continue;
+    double t = fabs(orc_segments_sdf(poly + 2 * (size_t)prims[q].voff, prims[q].nv, x, y, NULL));
+    if (t < d) d = t;
+  }
+  return d;
+}
+
+int64_t orc_trim_boundary(const orc_prim *prims, int32_t nprims, const double *poly, double d_s, double geps,
+                          double *pts, int64_t n) {
+  unsigned char *gone = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+  unsigned char *done = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+  unsigned char *bad = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+  double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  if (!gone || !done || !bad || !d) {
+    free(gone); free(done); free(bad); free(d);
+    return -1;
+  }
+  int changed = 1;
+  while (changed) {
+    changed = 0;
+    for (int64_t i = 0; i < n; i++) {
+      if (gone[i] || done[i]) continue;
+      const double xi = pts[2 * i], yi = pts[2 * i + 1];
+#pragma omp parallel for schedule(static)
+      for (int64_t j = 0; j < n; j++) {
+        double dx = pts[2 * j] - xi, dy = pts[2 * j + 1] - yi;
+        d[j] = sqrt(dx * dx + dy * dy);
+        bad[j] = (unsigned char)(gone[j] || j == i);
+      }
+      /* the closest point whose midpoint with p_i is on the boundary: the
+         nearest (ties: lower index), then the next nearest, ... */
+      int64_t bj = -1;
+      double mx = 0, my = 0;
+      for (;;) {
+        int64_t c = -1;
+        for (int64_t j = 0; j < n; j++)
+          if (!bad[j] && (c < 0 || d[j] < d[c])) c = j;
+        if (c < 0) break;
+        mx = 0.5 * (xi + pts[2 * c]);
+        my = 0.5 * (yi + pts[2 * c + 1]);
+        if (loops_dist(prims, nprims, poly, mx, my) <= geps) {
+          bj = c;
+          break;
+        }
+        bad[c] = 1;
+      }
+      if (bj < 0 || d[bj] >= d_s) {
+        done[i] = 1;
+        continue;
+      }
+      gone[bj] = 1;
+      pts[2 * i] = mx;
+      pts[2 * i + 1] = my;
+      changed = 1;
+    }
+  }
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; i++)
+    if (!gone[i]) {
+      pts[2 * m] = pts[2 * i];
+      pts[2 * m + 1] = pts[2 * i + 1];
+      m++;
+    }
+  free(gone); free(done); free(bad); free(d);
+  return m;
+}

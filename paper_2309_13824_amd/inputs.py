@@ -55,6 +55,7 @@ class Sizing:
     # point trimming's n_thres and fac_nei
     n_thres: int = 3
     fac_nei: float = 2.0
+    fac_geps: float = 0.01  # boundary tolerance of the boundary-point trimming
 
 
 @dataclass

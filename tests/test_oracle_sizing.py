@@ -27,7 +27,7 @@ def test_boundary_points_split_long_segments_evenly(orc):
     segment longer than d_s: all on the loop, spacing below d_s."""
     sq = np.array([[0.2, 0.2], [0.2, 0.8], [0.8, 0.8], [0.8, 0.2]])
     wl = loop_workload(sq, fac_s=0.5)
-    au = orc.auto_sizing(wl)
+    au = orc.auto_sizing(wl, trim=False)
     per_side = math.floor(0.6 / au.d_s) + 1
     assert len(au.s) == 4 * per_side
     for k in range(4):
@@ -49,7 +49,7 @@ def test_circle_poles_meet_at_the_centre(orc):
     verts = circle(96, R)
     chord = 2 * R * math.sin(math.pi / 96)
     wl = loop_workload(verts, grid_n=128, K=K, fac_s=1.1 * chord / (17 * 2.0 ** -(7 + 4)))
-    au = orc.auto_sizing(wl)
+    au = orc.auto_sizing(wl, trim=False)
     assert len(au.s) == 96 and au.d_s > chord
     assert len(au.medial) == 96
     assert np.allclose(au.medial, [0.5, 0.5], rtol=0, atol=1e-12)
@@ -69,18 +69,20 @@ def dist_to_segment(p, a, b):
 
 
 def test_square_medial_axis_is_its_diagonals(orc):
-    """A square: every kept medial point lies on a diagonal (its medial
-    axis), and lfs of a boundary point is its distance to the diagonals
-    within the boundary spacing d_s."""
+    """A square: with evenly split sides (no trimming) every kept medial
+    point lies on a diagonal (its medial axis) and lfs of a boundary point
+    is its distance to the diagonals within the spacing d_s; after trimming
+    (uneven spacing) both hold within d_s and 2 d_s."""
     sq = np.array([[0.2, 0.2], [0.2, 0.8], [0.8, 0.8], [0.8, 0.2]])
-    au = orc.auto_sizing(loop_workload(sq))
-    m = au.medial[au.keep.astype(bool)]
-    assert len(m) > 0
-    off = np.minimum(np.abs((m[:, 0] - 0.5) - (m[:, 1] - 0.5)), np.abs((m[:, 0] - 0.5) + (m[:, 1] - 0.5)))
-    assert off.max() <= 1e-12
-    ref = np.minimum(dist_to_segment(au.s, np.array([0.2, 0.2]), np.array([0.8, 0.8])),
-                     dist_to_segment(au.s, np.array([0.2, 0.8]), np.array([0.8, 0.2])))
-    assert np.max(np.abs(au.lfs - ref)) < au.d_s
+    for trimmed, tol_axis, tol_lfs in ((False, 1e-12, 1.0), (True, 1.0, 2.0)):
+        au = orc.auto_sizing(loop_workload(sq), trim=trimmed)
+        m = au.medial[au.keep.astype(bool)]
+        assert len(m) > 0
+        off = np.minimum(np.abs((m[:, 0] - 0.5) - (m[:, 1] - 0.5)), np.abs((m[:, 0] - 0.5) + (m[:, 1] - 0.5)))
+        assert off.max() <= (tol_axis if not trimmed else tol_axis * au.d_s)
+        ref = np.minimum(dist_to_segment(au.s, np.array([0.2, 0.2]), np.array([0.8, 0.8])),
+                         dist_to_segment(au.s, np.array([0.2, 0.8]), np.array([0.8, 0.2])))
+        assert np.max(np.abs(au.lfs - ref)) < tol_lfs * au.d_s
 
 
 def test_trimming_drops_isolated_points(orc):
@@ -131,3 +133,44 @@ def test_grid_mu_is_the_field_at_the_nodes(orc):
             x, y = g.x0 + i * g.dx, g.y0 + j * g.dy
             want = orc.lib().orc_auto_mu(s_pts.ctypes.data_as(dp), lfs.ctypes.data_as(dp), len(au.s), 0.15, x, y)
             assert og.mu[j * g.nx + i] == want
+
+
+def trim(orc, prims_wl, pts, d_s, geps):
+    from oracle.oracle import _geometry, _p
+    prims, _, poly, keep = _geometry(prims_wl)
+    p = np.ascontiguousarray(np.asarray(pts, np.float64).reshape(-1))
+    n = orc.lib().orc_trim_boundary(prims, len(prims_wl.prims), _p(poly, C.c_double), d_s, geps,
+                                    p.ctypes.data_as(C.POINTER(C.c_double)), len(p) // 2)
+    return p[:2 * n].reshape(-1, 2)
+
+
+def test_trimming_by_hand():
+    """Four points 0.3 d_s apart on the bottom side of a large square (the
+    rest far away): sweep 1 merges 0 with 1 (to 0.15) and 2 with 3 (to 0.75),
+    sweep 2 merges them (to 0.45), sweep 3 changes nothing."""
+    from oracle import oracle as orc
+    sq = np.array([[0.0, 0.0], [0.0, 8.0], [8.0, 8.0], [8.0, 0.0]])
+    wl = loop_workload(sq)
+    d_s = 0.125
+    pts = [[4 + 0.3 * d_s * k, 0.0] for k in range(4)]
+    out = trim(orc, wl, pts, d_s, 1e-9)
+    assert out.shape == (1, 2)
+    assert out[0, 0] == pytest.approx(4 + 0.45 * d_s, rel=1e-15) and out[0, 1] == 0.0
+
+
+def test_trimmed_points_keep_a_valid_spacing_of_d_s(orc):
+    """After trimming, no two remaining points closer than d_s have their
+    midpoint on the boundary, and every point stays within geps of it."""
+    for verts in (np.array([[0.2, 0.2], [0.2, 0.8], [0.8, 0.8], [0.8, 0.2]]), I.coast_loop(400)):
+        wl = loop_workload(verts, fac_s=0.5)
+        au = orc.auto_sizing(wl)
+        raw = orc.auto_sizing(wl, trim=False)
+        assert len(au.s) < len(raw.s)
+        geps = 0.01 * min(wl.grid.dx, wl.grid.dy)
+        dist = lambda x, y: abs(orc.segments_sdf(verts, x, y)[0])  # noqa: E731
+        s = au.s
+        for i in range(len(s)):
+            assert dist(*s[i]) <= geps
+            d = np.hypot(s[:, 0] - s[i, 0], s[:, 1] - s[i, 1])
+            for j in np.nonzero((d < au.d_s) & (np.arange(len(s)) != i))[0]:
+                assert dist(*(0.5 * (s[i] + s[j]))) > geps, (i, j)
