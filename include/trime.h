@@ -118,6 +118,8 @@ typedef struct {
   const int32_t *holes; /* host, indices into the primitive list            */
   int32_t n_thres;      /* AUTO: medial points need this many neighbours (0 -> 3) */
   double fac_nei;       /* AUTO: neighbour radius fac_nei n_thres d_s (0 -> 2)   */
+  double fac_geps;      /* AUTO: on-boundary tolerance of the boundary-point
+                           trimming, fac_geps min(dx, dy) (0 -> 0.01)         */
 } trime_sizing;
 
 /* Vertex-centred node grid: node (i, j) at (x0 + i dx, y0 + j dy).  Node
@@ -452,7 +454,13 @@ trime_status trime_run_growing(trime_state *st, const trime_growing *cfg, void *
    - boundary points S of the SEGMENTS loops, in primitive and vertex order:
      each vertex, then on a segment of length L > d_s the floor(L / d_s)
      points that split it evenly (spacing below d_s), d_s = a1 min(dx, dy)
-     (fac_s in App. A; the trimming of S to spacing d_s is not done);
+     (fac_s in App. A);
+   - their trimming (App. A): sweeps over S in index order until one changes
+     nothing; a point (not removed, not done) takes its closest remaining
+     point p* whose midpoint m with it lies within geps = fac_geps
+     min(dx, dy) of a segment of the loops (the nearest first, ties to the
+     lower index); with none, or p* at least d_s away, the point is done,
+     otherwise p* is removed and the point moves to m (serial, on the host);
    - medial-axis approximating points: the Voronoi cell of each s among S,
      clipped to the grid's box grown by its width and height on every side;
      v1 = its farthest vertex, kept unless a box edge meets it (then it

@@ -82,44 +82,22 @@ static trime_status auto_ok(const trime_geometry *geo, const trime_sizing *sz, c
     why = "automatic sizing needs SEGMENTS loops";
   else if (!(sz->a1 > 0) || !(sz->a0 >= 0) || !isfinite(sz->a0) || !isfinite(sz->a1))
     why = "automatic sizing needs a0 = K >= 0 and a1 = fac_s > 0";
-  else if (sz->n_thres < 0 || !(sz->fac_nei >= 0))
+  else if (sz->n_thres < 0 || !(sz->fac_nei >= 0) || !(sz->fac_geps >= 0))
     why = "automatic sizing: negative n_thres or fac_nei";
   if (!why) return TRIME_OK;
   snprintf(msg, sizeof msg, "%s: %s", who, why);
   return fail(TRIME_EINVAL, msg);
 }
 
-// Boundary points of the SEGMENTS loops (App. A, segment input): each vertex,
-// then floor(L / d_s) points splitting a segment of length L > d_s evenly.
-static std::vector<double> boundary_points(const trime_geometry *geo, double d_s) {
-  std::vector<double> out;
-  for (int q = 0; q < geo->nprims; q++) {
-    const trime_prim &p = geo->prims[q];
-    if (p.kind != TRIME_PRIM_SEGMENTS) continue;
-    const double *v = geo->poly + 2 * (size_t)p.voff;
-    for (int k = 0; k < p.nv; k++) {
-      const int k1 = k + 1 == p.nv ? 0 : k + 1;
-      const double ax = v[2 * k], ay = v[2 * k + 1], bx = v[2 * k1], by = v[2 * k1 + 1];
-      const double L = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
-      const int64_t pieces = L > d_s ? (int64_t)floor(L / d_s) + 1 : 1;
-      for (int64_t i = 0; i < pieces; i++) {
-        const double t = (double)i / (double)pieces;
-        out.push_back(ax + t * (bx - ax));
-        out.push_back(ay + t * (by - ay));
-      }
-    }
-  }
-  return out;
-}
-
 struct AutoSetup {
-  double d_s, r_nei, box[4], gbox[4];
+  double d_s, geps, r_nei, box[4], gbox[4];
   int n_thres;
 };
 
 static AutoSetup auto_setup(const trime_sizing *sz, const trime_grid *grid) {
   AutoSetup a;
   a.d_s = sz->a1 * fmin(grid->dx, grid->dy);
+  a.geps = (sz->fac_geps > 0 ? sz->fac_geps : 0.01) * fmin(grid->dx, grid->dy);
   a.n_thres = sz->n_thres > 0 ? sz->n_thres : 3;
   const double fac_nei = sz->fac_nei > 0 ? sz->fac_nei : 2.0;
   a.r_nei = fac_nei * a.n_thres * a.d_s;
@@ -149,7 +127,7 @@ trime_status trime_auto_sizing(const trime_geometry *geo, const trime_sizing *sz
   trime_status e = auto_ok(geo, sz, "trime_auto_sizing");
   if (e) return e;
   const AutoSetup A = auto_setup(sz, grid);
-  std::vector<double> S = boundary_points(geo, A.d_s);
+  std::vector<double> S = trim_boundary(geo, A.d_s, A.geps, boundary_points(geo, A.d_s));
   const int64_t ns = (int64_t)S.size() / 2;
   *ns_out = ns;
   *nm_out = -1;
@@ -256,7 +234,7 @@ trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing 
   std::vector<double> S;
   if (!seg_err && sz->kind == TRIME_SZ_AUTO) {
     const AutoSetup A = auto_setup(sz, grid);
-    S = boundary_points(geo, A.d_s);
+    S = trim_boundary(geo, A.d_s, A.geps, boundary_points(geo, A.d_s));
     const int64_t ns = (int64_t)S.size() / 2;
     double *d_S = nullptr, *d_med = nullptr, *d_lfs = nullptr;
     uint8_t *d_keep = nullptr;

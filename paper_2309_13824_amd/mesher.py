@@ -25,7 +25,7 @@ def _geometry(wl):
     cent = np.ascontiguousarray(np.asarray(s.cent, np.float64).reshape(-1))
     holes = np.ascontiguousarray(np.asarray(s.holes, np.int32))
     sz = T.Sizing(s.kind, s.a0, s.a1, s.s2, len(cent) // 2, cent.ctypes.data_as(C.POINTER(C.c_double)),
-                  len(holes), holes.ctypes.data_as(C.POINTER(C.c_int32)), s.n_thres, s.fac_nei)
+                  len(holes), holes.ctypes.data_as(C.POINTER(C.c_int32)), s.n_thres, s.fac_nei, s.fac_geps)
     return geo, sz, (prims, poly, cent, holes)
 
 

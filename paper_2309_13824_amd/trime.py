@@ -43,7 +43,8 @@ class Geometry(C.Structure):
 class Sizing(C.Structure):
     _fields_ = [("kind", C.c_int32), ("a0", C.c_double), ("a1", C.c_double), ("s2", C.c_double),
                 ("ncent", C.c_int32), ("cent", C.POINTER(C.c_double)), ("nholes", C.c_int32),
-                ("holes", C.POINTER(C.c_int32)), ("n_thres", C.c_int32), ("fac_nei", C.c_double)]
+                ("holes", C.POINTER(C.c_int32)), ("n_thres", C.c_int32), ("fac_nei", C.c_double),
+                ("fac_geps", C.c_double)]
 
 
 class Grid(C.Structure):

@@ -105,7 +105,7 @@ def test_auto_sizing_full_grid_on_sampled_nodes(orc, T):
     m = Mesher(wl, precision=FP64)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
-    print("coast 4096 segments, 4096^2 grid: %d boundary points, GPU grid build with automatic sizing %.1f ms "
+    print("coast 4096 segments, 4096^2 grid: %d trimmed boundary points, GPU grid build with automatic sizing %.1f ms "
           "(with the Mesher setup)" % (len(au.s), secs * 1e3), flush=True)
     mu = m.mu.double().cpu().numpy()
     g = wl.grid
