@@ -55,7 +55,7 @@ BYTES_PER_POINT = 37 + 25 + 30 + 64
 # HBM traffic of one launch of the fused kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (first two CVD iterations, scaled by a 1 GiB copy: FETCH x 2.0,
 # WRITE x 1.0), valid for the kernel sources with this digest only.
-TRAFFIC = {"sha1": "bb994ff4127e36b8f024bd4b6c53583344a1ffd2", "bytes_per_launch": 494254617.9}
+TRAFFIC = {"sha1": "c33eca4940fbd74a1094f8d46d57331b1a7ed4e5", "bytes_per_launch": 494486400.5}
 # CVD iterations from the seeded points before the autotuner's timing
 TUNE_FROM = 10
 KERNEL_SOURCES = ["cells.hip", "trime_dev.hpp", "geom_dev.hpp", "exact_dev.hpp", "launch.hpp"]
@@ -83,11 +83,12 @@ def parse():
     ap.add_argument("--tune", type=str, default="1.0,1.4,2.0,2.8",
                     help="bin densities (points per bin) the autotuner tries before the timed run; "
                          "empty for the default 3.3")
-    ap.add_argument("--workload", default="holes20", choices=["holes20", "stars", "disk", "annulus", "ellipses"],
+    ap.add_argument("--workload", default="holes20",
+                    choices=["holes20", "stars", "disk", "annulus", "ellipses", "coast"],
                     help="holes20: the headline CVD run; stars: the batch of 512 star polygons "
                          "(DistMesh), one launch per kernel for all shapes, against a graph of per-shape "
-                         "launches and per-shape launches; disk, annulus, ellipses: their fixed schedules, "
-                         "one JSON line each")
+                         "launches and per-shape launches; disk, annulus, ellipses, coast (segment input): "
+                         "their fixed schedules, one JSON line each")
     ap.add_argument("--shapes", type=int, default=512)
     ap.add_argument("--batch-only", action="store_true",
                     help="stars: time only the batch with one launch per kernel (no per-shape or graph runs)")
@@ -393,19 +394,50 @@ def oracle_first_step(wl, method, precs, threads, log):
     return secs, err
 
 
+def grid_build_times(wl, log):
+    """Geometry grid of a segment-input workload, built on the GPU from its
+    loop (Sec. 3.2): with the workload's sizing, and with the automatic
+    sizing field (Eq. 8, K = 0.05) on the same loop; the median of three
+    builds each, Mesher setup (workspace allocation) included."""
+    import copy
+
+    import torch
+    from paper_2309_13824_amd import inputs as I
+    from paper_2309_13824_amd.mesher import Mesher
+    out = {}
+    auto = copy.copy(wl)
+    auto.sizing = I.Sizing(I.SZ_AUTO, 0.05, 0.5)
+    for name, w in (("segments_%d_uniform" % len(wl.prims[0].poly), wl),
+                    ("segments_%d_auto_sizing" % len(wl.prims[0].poly), auto)):
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m = Mesher(w)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+            del m
+        out[name] = sorted(ts)[1]
+        log("  grid build %s on %d^2 nodes: %.1f ms" % (name, wl.grid.nx, out[name]))
+    return out
+
+
 def schedule_run(args, log):
     """disk (DistMesh, FP64, CPU oracle timed beside it), annulus (30 CVD then
     70 DistMesh as configured, and the paper's order 70 DistMesh then 30
-    CVD; FP32 + FP64 replay vs FP64) or ellipses (70 DistMesh then 30 CVD,
-    10^7 points, autotuned bin size, FP32 + FP64 replay)."""
+    CVD; FP32 + FP64 replay vs FP64), ellipses (70 DistMesh then 30 CVD,
+    10^7 points, autotuned bin size, FP32 + FP64 replay) or coast (a
+    4096-segment loop minus a disk, 10^5 points, 50 CVD; also the time of
+    its grid build from segments, with and without automatic sizing)."""
     import torch
     from paper_2309_13824_amd import inputs as I
     from paper_2309_13824_amd import trime as T
     from paper_2309_13824_amd.mesher import Mesher
     which = args.workload
     t = time.perf_counter()
-    wl = {"disk": I.disk, "annulus": I.annulus, "ellipses": I.ellipses}[which]()
+    wl = {"disk": I.disk, "annulus": I.annulus, "ellipses": I.ellipses, "coast": I.coast}[which]()
     log("workload %s: %d points (%.1f s to sample)" % (wl.name, wl.n, time.perf_counter() - t))
+    builds = grid_build_times(wl, log) if which == "coast" else None
     schedules = [wl.schedule]
     if which == "annulus":
         schedules.append([("dm", 70), ("cvd", 30)])
@@ -465,7 +497,7 @@ def schedule_run(args, log):
                          "exact predicates"}
         log("  cpu oracle: full run %.2f s on %d threads" % (secs, threads))
         _, perr = oracle_first_step(wl, "dm", precs, threads, log)
-    elif which == "annulus" and not args.no_cpu_baseline:
+    elif which in ("annulus", "coast") and not args.no_cpu_baseline:
         secs, perr = oracle_first_step(wl, wl.schedule[0][0], precs, threads, log)
         cpu = {"value": wl.n / secs, "unit": "point-iterations/s", "cores": threads, "kind": "oracle",
                "sample": "the first %s iteration (triangulation with quality, then the step) from the seeded "
@@ -478,6 +510,8 @@ def schedule_run(args, log):
             "config": {"workload": "%s, %d points, %d^2 grid, schedule %s" % (
                 wl.name, wl.n, wl.grid.nx, wl.schedule), "seed": wl.seed},
             "runs": res, "cpu_baseline": cpu, "position_error": perr}
+    if builds:
+        line["grid_build_ms"] = builds
     print(json.dumps(line), flush=True)
 
 
@@ -494,7 +528,7 @@ def main():
     if args.workload == "stars":
         stars_run(args, log)
         return
-    if args.workload in ("disk", "annulus", "ellipses"):
+    if args.workload in ("disk", "annulus", "ellipses", "coast"):
         schedule_run(args, log)
         return
     import torch
