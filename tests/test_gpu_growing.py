@@ -148,3 +148,19 @@ def test_growing_run_in_fp32_reaches_oracle_quality(orc, T):
     want = info["history"][-1]["quality"]
     assert abs(ad["last"][0] - want[0]) <= 0.01 * want[0]
     assert abs(ad["last"][1] - want[1]) <= 0.01 * want[1]
+
+
+def test_growing_from_all_points_is_the_adaptive_run(orc, T):
+    """n_init = N: nothing to add, and the growing run reaches the same
+    iterations, outcome and points as the adaptive run, bit for bit."""
+    wl = workload("disk")
+    og = orc.build_grid(wl)
+    a = mesher(wl, FP64, og, None)
+    want = a.step_adaptive("hybrid", 200, TQ, TA, TS)
+    g = mesher(wl, FP64, og, wl.n)
+    got = g.run_growing("hybrid", 200, TADD, 0.6, TQ, TA, TS)
+    assert (got["iters"], got["switch_iter"], got["stop_iter"], got["reason"]) == \
+        (want["iters"], want["switch_iter"], want["stop_iter"], want["reason"])
+    ax, ay, ac = a.points()
+    gx, gy, gc = g.points()
+    assert np.array_equal(ax, gx) and np.array_equal(ay, gy) and np.array_equal(ac, gc)

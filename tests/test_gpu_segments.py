@@ -91,3 +91,28 @@ def test_cvd_step_on_a_segment_grid_matches_oracle(orc, T):
     assert err.max() <= 1e-12, err.max()
     assert np.array_equal(c, cr)
     assert m.stats_raw().error == 0
+
+
+def two_loops(n=8000, grid_n=256):
+    """A 500-segment coast loop minus a clockwise square hole given as a
+    second loop (two SEGMENTS primitives), and a repeated vertex (a
+    zero-length segment) in the outer loop."""
+    outer = I.coast_loop(500)
+    outer = np.insert(outer, 7, outer[7], axis=0)  # segment 7 has length zero
+    hole = np.array([[0.45, 0.45], [0.45, 0.55], [0.55, 0.55], [0.55, 0.45]])
+    prims = [I.Prim(I.OP_INIT, I.PRIM_SEGMENTS, (), outer), I.Prim(I.OP_DIFF, I.PRIM_SEGMENTS, (), hole)]
+    grid = I.centred_grid(grid_n, 17, int(round(np.log2(grid_n))) + 4, 0.5, 8)
+    wl = I.Workload("two_loops", prims, I.Sizing(I.SZ_UNIFORM), grid, n, [("cvd", 10)], 7)
+    wl.x, wl.y = I.sample_points(wl, np.random.default_rng(7), (0, 0, 1, 1))
+    return wl
+
+
+def test_two_loops_and_a_zero_length_segment_match_oracle(orc, T):
+    """Two segment loops combined by difference, one with a zero-length
+    segment: every node equals the oracle's, bit for bit."""
+    wl = two_loops()
+    og = orc.build_grid(wl)
+    m, _ = gpu_grid(wl)
+    sdf, mu, cat, hcell, scal = m.grid_arrays()
+    assert np.array_equal(sdf, og.sdf)
+    assert np.array_equal(cat, og.cat)

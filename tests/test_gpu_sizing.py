@@ -41,7 +41,17 @@ CASES = {
     "square": lambda: loop_workload(np.array([[0.2, 0.2], [0.2, 0.8], [0.8, 0.8], [0.8, 0.2]])),
     "coast300": lambda: loop_workload(I.coast_loop(300), K=0.2),
     "coast2000": lambda: loop_workload(I.coast_loop(2000), grid_n=512, K=0.05),
+    "coast_hole": lambda: with_hole(loop_workload(I.coast_loop(300), K=0.1)),
 }
+
+
+def with_hole(wl):
+    """A second loop, a clockwise square hole, taken away by difference: its
+    boundary points, medial axis and lfs join the outer loop's."""
+    hole = np.array([[0.45, 0.45], [0.45, 0.55], [0.55, 0.55], [0.55, 0.45]])
+    wl.prims.append(I.Prim(I.OP_DIFF, I.PRIM_SEGMENTS, (), hole))
+    wl.x, wl.y = I.sample_points(wl, np.random.default_rng(1), (0, 0, 1, 1))
+    return wl
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -69,7 +79,7 @@ def test_auto_sizing_steps_match_oracle(orc, T, name):
     assert np.array_equal(lfs.cpu().numpy(), au.lfs)
 
 
-@pytest.mark.parametrize("name", ["circle96", "coast300", "coast2000"])
+@pytest.mark.parametrize("name", ["circle96", "coast300", "coast2000", "coast_hole"])
 def test_auto_sizing_grid_matches_oracle(orc, T, name):
     """The grid built with automatic sizing: mu at every node equals the
     oracle's brute-force minimum over all boundary points, bit for bit; the
