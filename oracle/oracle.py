@@ -102,7 +102,7 @@ def lib():
         L.orc_sdf_eval.restype = C.c_double
         L.orc_segments_sdf.argtypes = [dp, C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_int32)]
         L.orc_segments_sdf.restype = C.c_double
-        L.orc_boundary_points.argtypes = [C.POINTER(Prim), C.c_int32, dp, C.c_double, dp, C.c_int64]
+        L.orc_boundary_points.argtypes = [C.POINTER(Prim), C.c_int32, dp, C.c_double, C.c_double, dp, C.c_int64]
         L.orc_boundary_points.restype = C.c_int64
         L.orc_trim_boundary.argtypes = [C.POINTER(Prim), C.c_int32, dp, C.c_double, C.c_double, dp, C.c_int64]
         L.orc_trim_boundary.restype = C.c_int64
@@ -222,7 +222,8 @@ class AutoSizing:
 
 
 def auto_sizing(wl, trim=True) -> AutoSizing:
-    """Boundary points of the workload's segment loops (App. A) at
+    """Boundary points of the workload's geometry (App. A; every primitive's
+    boundary sampled, the points on the whole boundary kept) at
     d_s = fac_s min(dx, dy) (fac_s = sizing.a1), trimmed (trim=True) with
     geps = fac_geps min(dx, dy), medial-axis points from
     their Voronoi cells clipped to the grid's box grown by its size on every
@@ -232,11 +233,11 @@ def auto_sizing(wl, trim=True) -> AutoSizing:
     sz = wl.sizing
     prims, _, poly, keep_ = _geometry(wl)
     d_s = sz.a1 * min(g.dx, g.dy)
-    n = lib().orc_boundary_points(prims, len(wl.prims), _p(poly, C.c_double), d_s, None, 0)
+    geps = sz.fac_geps * min(g.dx, g.dy)
+    n = lib().orc_boundary_points(prims, len(wl.prims), _p(poly, C.c_double), d_s, geps, None, 0)
     s = np.empty((n, 2), np.float64)
-    lib().orc_boundary_points(prims, len(wl.prims), _p(poly, C.c_double), d_s, _p(s, C.c_double), n)
+    lib().orc_boundary_points(prims, len(wl.prims), _p(poly, C.c_double), d_s, geps, _p(s, C.c_double), n)
     if trim:
-        geps = sz.fac_geps * min(g.dx, g.dy)
         n = lib().orc_trim_boundary(prims, len(wl.prims), _p(poly, C.c_double), d_s, geps, _p(s, C.c_double), n)
         s = np.ascontiguousarray(s[:n])
     W, H = (g.nx - 1) * g.dx, (g.ny - 1) * g.dy

@@ -71,12 +71,18 @@ typedef struct {
 } orc_sizing;
 
 /* ---- automatic sizing (Sec. 3.3, Eq. 8; App. A) -------------------------- */
-/* Boundary points of the SEGMENTS loops, in primitive and vertex order:
-   every vertex, then on a segment of length L > d_s the floor(L / d_s)
-   points splitting it evenly (spacing below d_s).  Returns the count (the
-   first cap points are written). */
-int64_t orc_boundary_points(const orc_prim *prims, int32_t nprims, const double *poly, double d_s, double *out,
-                            int64_t cap);
+/* Boundary points (App. A), in primitive order: a disk or an ellipse at
+   m = max(3, floor(2 pi r / d_s) + 1) equal steps of its angle parameter
+   (r the larger semi-axis), (r cos t, r sin t) about its centre (an
+   ellipse's (a cos t, b sin t) turned by phi); a box as the clockwise loop
+   (x0,y0) (x0,y1) (x1,y1) (x1,y0), a polygon or a segment loop through its
+   vertices: every vertex, then floor(L / d_s) points splitting each segment
+   of length L > d_s evenly.  A point is kept when the geometry's signed
+   distance there is at most geps in magnitude (the parts of each boundary
+   that bound the whole geometry).  Returns the count (the first cap points
+   are written). */
+int64_t orc_boundary_points(const orc_prim *prims, int32_t nprims, const double *poly, double d_s, double geps,
+                            double *out, int64_t cap);
 /* App. A trimming of boundary points, in place: sweeps over the points in
    index order until one changes nothing.  Point i (not removed, not done)
    takes its closest other remaining point p* whose midpoint m with it lies

@@ -11,29 +11,82 @@
 
 #include "orc.h"
 
-int64_t orc_boundary_points(const orc_prim *prims, int32_t nprims, const double *poly, double d_s, double *out,
-                            int64_t cap) {
+/* The vertices of a closed loop, then floor(L / d_s) points splitting each
+   segment of length L > d_s evenly (spacing below d_s); returns the new
+   count (writes below cap only). */
+static int64_t loop_points(const double *v, int32_t nv, double d_s, double *out, int64_t n, int64_t cap) {
+  for (int32_t k = 0; k < nv; k++) {
+    int32_t k1 = k + 1 == nv ? 0 : k + 1;
+    double ax = v[2 * k], ay = v[2 * k + 1], bx = v[2 * k1], by = v[2 * k1 + 1];
+    double L = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
+    int64_t pieces = L > d_s ? (int64_t)floor(L / d_s) + 1 : 1;
+    for (int64_t i = 0; i < pieces; i++) {
+      if (n < cap) {
+        double t = (double)i / (double)pieces;
+        out[2 * n] = ax + t * (bx - ax);
+        out[2 * n + 1] = ay + t * (by - ay);
+      }
+      n++;
+    }
+  }
+  return n;
+}
+
+#define ORC_TWO_PI 6.283185307179586
+
+int64_t orc_boundary_points(const orc_prim *prims, int32_t nprims, const double *poly, double d_s, double geps,
+                            double *out, int64_t cap) {
   int64_t n = 0;
   for (int32_t q = 0; q < nprims; q++) {
-    if (prims[q].kind != ORC_PRIM_SEGMENTS) continue;
-    const double *v = poly + 2 * (size_t)prims[q].voff;
-    int32_t nv = prims[q].nv;
-    for (int32_t k = 0; k < nv; k++) {
-      int32_t k1 = k + 1 == nv ? 0 : k + 1;
-      double ax = v[2 * k], ay = v[2 * k + 1], bx = v[2 * k1], by = v[2 * k1 + 1];
-      double L = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
-      /* the vertex, then floor(L / d_s) evenly spaced points inside a
-         segment longer than d_s: spacing L / (floor(L / d_s) + 1) < d_s */
-      int64_t pieces = L > d_s ? (int64_t)floor(L / d_s) + 1 : 1;
-      for (int64_t i = 0; i < pieces; i++) {
-        if (n < cap) {
-          double t = (double)i / (double)pieces;
-          out[2 * n] = ax + t * (bx - ax);
-          out[2 * n + 1] = ay + t * (by - ay);
+    const orc_prim *p = &prims[q];
+    /* sample this primitive's boundary into a scratch list */
+    int64_t m = 0;
+    double *raw = NULL;
+    if (p->kind == ORC_PRIM_DISK || p->kind == ORC_PRIM_ELLIPSE) {
+      double rmax = p->kind == ORC_PRIM_DISK ? p->p[2] : fmax(p->p[2], p->p[3]);
+      m = (int64_t)floor(ORC_TWO_PI * rmax / d_s) + 1;
+      if (m < 3) m = 3;
+      raw = (double *)malloc(sizeof(double) * 2 * (size_t)m);
+      double c = p->kind == ORC_PRIM_ELLIPSE ? cos(p->p[4]) : 1.0, sn = p->kind == ORC_PRIM_ELLIPSE ? sin(p->p[4]) : 0.0;
+      for (int64_t k = 0; k < m; k++) {
+        double th = ORC_TWO_PI * (double)k / (double)m;
+        if (p->kind == ORC_PRIM_DISK) {
+          raw[2 * k] = p->p[0] + p->p[2] * cos(th);
+          raw[2 * k + 1] = p->p[1] + p->p[2] * sin(th);
+        } else {
+          double u = p->p[2] * cos(th), w = p->p[3] * sin(th);
+          raw[2 * k] = p->p[0] + (c * u - sn * w);
+          raw[2 * k + 1] = p->p[1] + (sn * u + c * w);
         }
-        n++;
       }
+    } else {
+      double box[8];
+      const double *v;
+      int32_t nv;
+      if (p->kind == ORC_PRIM_BOX) {
+        /* the clockwise loop (x0,y0) (x0,y1) (x1,y1) (x1,y0) */
+        box[0] = p->p[0]; box[1] = p->p[1]; box[2] = p->p[0]; box[3] = p->p[3];
+        box[4] = p->p[2]; box[5] = p->p[3]; box[6] = p->p[2]; box[7] = p->p[1];
+        v = box;
+        nv = 4;
+      } else {
+        v = poly + 2 * (size_t)p->voff;
+        nv = p->nv;
+      }
+      m = loop_points(v, nv, d_s, NULL, 0, 0);
+      raw = (double *)malloc(sizeof(double) * 2 * (size_t)(m > 0 ? m : 1));
+      loop_points(v, nv, d_s, raw, 0, m);
     }
+    /* keep the points on the boundary of the whole geometry */
+    for (int64_t k = 0; k < m; k++) {
+      if (fabs(orc_sdf_eval(prims, nprims, poly, raw[2 * k], raw[2 * k + 1])) > geps) continue;
+      if (n < cap) {
+        out[2 * n] = raw[2 * k];
+        out[2 * n + 1] = raw[2 * k + 1];
+      }
+      n++;
+    }
+    free(raw);
   }
   return n;
 }
@@ -196,18 +249,6 @@ double orc_auto_mu(const double *s, const double *lfs, int64_t ns, double K, dou
   return best;
 }
 
-/* |sdf| of the segment loops at (x, y): the distance to the nearest segment
-   of any SEGMENTS loop. */
-static double loops_dist(const orc_prim *prims, int32_t nprims, const double *poly, double x, double y) {
-  double d = INFINITY;
-  for (int32_t q = 0; q < nprims; q++) {
-    if (prims[q].kind != ORC_PRIM_SEGMENTS) continue;
-    double t = fabs(orc_segments_sdf(poly + 2 * (size_t)prims[q].voff, prims[q].nv, x, y, NULL));
-    if (t < d) d = t;
-  }
-  return d;
-}
-
 int64_t orc_trim_boundary(const orc_prim *prims, int32_t nprims, const double *poly, double d_s, double geps,
                           double *pts, int64_t n) {
   unsigned char *gone = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
@@ -241,7 +282,7 @@ int64_t orc_trim_boundary(const orc_prim *prims, int32_t nprims, const double *p
         if (c < 0) break;
         mx = 0.5 * (xi + pts[2 * c]);
         my = 0.5 * (yi + pts[2 * c + 1]);
-        if (loops_dist(prims, nprims, poly, mx, my) <= geps) {
+        if (fabs(orc_sdf_eval(prims, nprims, poly, mx, my)) <= geps) {
           bj = c;
           break;
         }

@@ -174,3 +174,29 @@ def test_trimmed_points_keep_a_valid_spacing_of_d_s(orc):
             d = np.hypot(s[:, 0] - s[i, 0], s[:, 1] - s[i, 1])
             for j in np.nonzero((d < au.d_s) & (np.arange(len(s)) != i))[0]:
                 assert dist(*(0.5 * (s[i] + s[j]))) > geps, (i, j)
+
+
+def test_boundary_points_of_a_constructive_geometry(orc):
+    """A box minus a disk inside it and minus a disk across its edge: the
+    inner disk keeps every sample, the crossing disk only the samples inside
+    the box (about the share of its circle there), the box loses its samples
+    inside the crossing disk, and every kept point has |sdf| <= geps."""
+    prims = [I.Prim(I.OP_INIT, I.PRIM_BOX, (0.2, 0.2, 0.8, 0.8)),
+             I.Prim(I.OP_DIFF, I.PRIM_DISK, (0.4, 0.5, 0.1)),
+             I.Prim(I.OP_DIFF, I.PRIM_DISK, (0.8, 0.5, 0.1))]
+    grid = I.centred_grid(128, 17, 11, 0.5, 8)
+    wl = I.Workload("csg", prims, I.Sizing(I.SZ_AUTO, 0.1, 0.5), grid, 1000, [], 0)
+    au = orc.auto_sizing(wl, trim=False)
+    s = au.s
+    geps = 0.01 * grid.dx
+    for x, y in s:
+        assert abs(orc.sdf_eval(wl, x, y)) <= geps
+    r_in = np.hypot(s[:, 0] - 0.4, s[:, 1] - 0.5)
+    r_x = np.hypot(s[:, 0] - 0.8, s[:, 1] - 0.5)
+    m_disk = math.floor(2 * math.pi * 0.1 / au.d_s) + 1
+    assert np.count_nonzero(np.abs(r_in - 0.1) < 1e-12) == m_disk
+    on_x = np.abs(r_x - 0.1) < 1e-12
+    assert abs(np.count_nonzero(on_x) - m_disk / 2) <= 2
+    assert np.all(s[on_x, 0] <= 0.8 + 1e-12)
+    on_box_right = (np.abs(s[:, 0] - 0.8) < 1e-12) & ~on_x
+    assert np.all(np.abs(s[on_box_right, 1] - 0.5) >= 0.1 - 1e-12)
