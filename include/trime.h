@@ -451,22 +451,27 @@ trime_status trime_run_growing(trime_state *st, const trime_growing *cfg, void *
 /* ---- automatic sizing (Sec. 3.3, Eq. 8; App. A) ----------------------------
    The steps of TRIME_SZ_AUTO, which trime_sdf_grid_build runs before its
    node pass (mu at the nodes, h from it as for every sizing):
-   - boundary points S of the SEGMENTS loops, in primitive and vertex order:
-     each vertex, then on a segment of length L > d_s the floor(L / d_s)
-     points that split it evenly (spacing below d_s), d_s = a1 min(dx, dy)
-     (fac_s in App. A);
+   - boundary points S (App. A), in primitive order, d_s = a1 min(dx, dy)
+     (fac_s in App. A): a disk or an ellipse at m = max(3, floor(2 pi r /
+     d_s) + 1) equal steps of its angle parameter (r its larger semi-axis);
+     a box as the clockwise loop (x0,y0) (x0,y1) (x1,y1) (x1,y0), a polygon
+     or a segment loop through its vertices: each vertex, then on a segment
+     of length L > d_s the floor(L / d_s) points that split it evenly; of
+     these, the points where the geometry's signed distance is within
+     geps = fac_geps min(dx, dy) (the parts that bound the whole shape);
    - their trimming (App. A): sweeps over S in index order until one changes
      nothing; a point (not removed, not done) takes its closest remaining
-     point p* whose midpoint m with it lies within geps = fac_geps
-     min(dx, dy) of a segment of the loops (the nearest first, ties to the
-     lower index); with none, or p* at least d_s away, the point is done,
+     point p* whose midpoint m with it lies on the boundary (the geometry's
+     signed distance within geps; the nearest first, ties to the lower
+     index); with none, or p* at least d_s away, the point is done,
      otherwise p* is removed and the point moves to m (serial, on the host);
    - medial-axis approximating points: the Voronoi cell of each s among S,
      clipped to the grid's box grown by its width and height on every side;
      v1 = its farthest vertex, kept unless a box edge meets it (then it
      stands for a vertex at infinity), v2 = its farthest vertex without a box
      edge in the open half plane (v - s) . (v1 - s) < 0, if any; in the order
-     of S, v1 before v2;
+     of S, v1 before v2 (a cell that reaches 254 vertices while it is
+     clipped gives none);
    - trimming: a medial point is kept when at least n_thres other medial
      points lie within r_nei = fac_nei n_thres d_s;
    - lfs(s) = the distance to the nearest kept medial point;
@@ -475,9 +480,8 @@ trime_status trime_run_growing(trime_state *st, const trime_growing *cfg, void *
    (d_pts, s_cap points), the medial points (d_medial, m_cap points) with
    their keep flags, and lfs (d_lfs, s_cap entries); *ns_out and *nm_out
    receive the counts.  Synchronises the stream; allocates and frees device
-   scratch.  Errors: TRIME_EINVAL for a geometry without SEGMENTS loops, a
-   sizing kind other than AUTO, a1 <= 0, a0 < 0, a Voronoi cell of more than
-   62 vertices or no kept medial point; TRIME_ECAPACITY when s_cap < |S| or
+   scratch.  Errors: TRIME_EINVAL for a bad primitive, a sizing kind other
+   than AUTO, a1 <= 0, a0 < 0 or no kept medial point; TRIME_ECAPACITY when s_cap < |S| or
    m_cap < 2 |S| (the counts known so far are written). */
 trime_status trime_auto_sizing(const trime_geometry *geo, const trime_sizing *sz, const trime_grid *grid,
                                double *d_pts, int64_t s_cap, int64_t *ns_out, double *d_medial, uint8_t *d_keep,

@@ -74,12 +74,8 @@ static bool grid_ok(const trime_grid *g) {
 static trime_status auto_ok(const trime_geometry *geo, const trime_sizing *sz, const char *who) {
   static thread_local char msg[160];
   const char *why = nullptr;
-  bool any = false;
-  for (int k = 0; geo && k < geo->nprims; k++) any = any || geo->prims[k].kind == TRIME_PRIM_SEGMENTS;
   if (!sz || sz->kind != TRIME_SZ_AUTO)
     why = "the sizing kind is not AUTO";
-  else if (!any)
-    why = "automatic sizing needs SEGMENTS loops";
   else if (!(sz->a1 > 0) || !(sz->a0 >= 0) || !isfinite(sz->a0) || !isfinite(sz->a1))
     why = "automatic sizing needs a0 = K >= 0 and a1 = fac_s > 0";
   else if (sz->n_thres < 0 || !(sz->fac_nei >= 0) || !(sz->fac_geps >= 0))
@@ -121,13 +117,16 @@ trime_status trime_auto_sizing(const trime_geometry *geo, const trime_sizing *sz
     return fail(TRIME_EINVAL, "trime_auto_sizing: null or invalid argument");
   for (int k = 0; k < geo->nprims; k++) {
     const trime_prim &p = geo->prims[k];
-    if (p.kind == TRIME_PRIM_SEGMENTS && (p.nv < 3 || p.voff < 0 || p.voff + p.nv > geo->npoly || !geo->poly))
+    if ((p.kind == TRIME_PRIM_SEGMENTS || p.kind == TRIME_PRIM_POLYGON) &&
+        (p.nv < 3 || p.voff < 0 || p.voff + p.nv > geo->npoly || !geo->poly))
       return fail(TRIME_EINVAL, "trime_auto_sizing: bad polygon range");
+    if (p.kind < 0 || p.kind > TRIME_PRIM_SEGMENTS || p.op < 0 || p.op > 3)
+      return fail(TRIME_EINVAL, "trime_auto_sizing: bad primitive op/kind");
   }
   trime_status e = auto_ok(geo, sz, "trime_auto_sizing");
   if (e) return e;
   const AutoSetup A = auto_setup(sz, grid);
-  std::vector<double> S = trim_boundary(geo, A.d_s, A.geps, boundary_points(geo, A.d_s));
+  std::vector<double> S = trim_boundary(geo, A.d_s, A.geps, boundary_points(geo, A.d_s, A.geps));
   const int64_t ns = (int64_t)S.size() / 2;
   *ns_out = ns;
   *nm_out = -1;
@@ -234,7 +233,7 @@ trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing 
   std::vector<double> S;
   if (!seg_err && sz->kind == TRIME_SZ_AUTO) {
     const AutoSetup A = auto_setup(sz, grid);
-    S = trim_boundary(geo, A.d_s, A.geps, boundary_points(geo, A.d_s));
+    S = trim_boundary(geo, A.d_s, A.geps, boundary_points(geo, A.d_s, A.geps));
     const int64_t ns = (int64_t)S.size() / 2;
     double *d_S = nullptr, *d_med = nullptr, *d_lfs = nullptr;
     uint8_t *d_keep = nullptr;

@@ -1,36 +1,101 @@
-// Boundary points of segment loops for the automatic sizing field (App. A):
-// the dense initial set and its trimming.  Host code: the trimming is a
-// serial pass whose result depends on its order (points move and disappear
-// one after another), so it runs on the CPU, with a uniform grid for the
-// nearest-point searches and a bucket grid of segments for the on-boundary
-// test of midpoints.
+// Boundary points for the automatic sizing field (App. A): the dense initial
+// set and its trimming.  Host code: the trimming is a serial pass whose
+// result depends on its order (points move and disappear one after
+// another), so it runs on the CPU, with a uniform grid for the nearest-point
+// searches.  The on-boundary tests evaluate the geometry's signed distance
+// exactly (every primitive, the set operations of Sec. 3.1).
 #include <math.h>
 
 #include <algorithm>
 #include <vector>
 
-#include "launch.hpp"
+#include "prim_sdf.hpp"
+#include "segsdf_dev.hpp"
 
 namespace trime {
 
-std::vector<double> boundary_points(const trime_geometry *geo, double d_s) {
-  std::vector<double> out;
+// The geometry's signed distance at (x, y): every primitive, combined by
+// its set operation (segment loops by brute force).
+double geometry_sdf(const trime_geometry *geo, double x, double y) {
+  double sd = INFINITY;
+  for (int k = 0; k < geo->nprims; k++) {
+    const trime_prim &pr = geo->prims[k];
+    const double t = pr.kind == TRIME_PRIM_SEGMENTS
+                         ? segments_sdf_brute(geo->poly + 2 * (size_t)pr.voff, pr.nv, x, y)
+                         : analytic_sdf(pr, geo->poly, x, y);
+    switch (pr.op) {
+      case TRIME_OP_INIT: sd = t; break;
+      case TRIME_OP_UNION: sd = fmin(sd, t); break;
+      case TRIME_OP_DIFF: sd = fmax(sd, -t); break;
+      default: sd = fmax(sd, t); break;
+    }
+  }
+  return sd;
+}
+
+namespace {
+
+constexpr double TWO_PI = 6.283185307179586;
+
+// The vertices of a closed loop and floor(L / d_s) points splitting each of
+// its segments longer than d_s.
+void loop_points(const double *v, int nv, double d_s, std::vector<double> &out) {
+  for (int k = 0; k < nv; k++) {
+    const int k1 = k + 1 == nv ? 0 : k + 1;
+    const double ax = v[2 * k], ay = v[2 * k + 1], bx = v[2 * k1], by = v[2 * k1 + 1];
+    const double L = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
+    const int64_t pieces = L > d_s ? (int64_t)floor(L / d_s) + 1 : 1;
+    for (int64_t i = 0; i < pieces; i++) {
+      const double t = (double)i / (double)pieces;
+      out.push_back(ax + t * (bx - ax));
+      out.push_back(ay + t * (by - ay));
+    }
+  }
+}
+
+}  // namespace
+
+std::vector<double> boundary_points(const trime_geometry *geo, double d_s, double geps) {
+  std::vector<double> raw, out;
   for (int q = 0; q < geo->nprims; q++) {
     const trime_prim &p = geo->prims[q];
-    if (p.kind != TRIME_PRIM_SEGMENTS) continue;
-    const double *v = geo->poly + 2 * (size_t)p.voff;
-    for (int k = 0; k < p.nv; k++) {
-      const int k1 = k + 1 == p.nv ? 0 : k + 1;
-      const double ax = v[2 * k], ay = v[2 * k + 1], bx = v[2 * k1], by = v[2 * k1 + 1];
-      const double L = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
-      // the vertex, then floor(L / d_s) points splitting a longer segment
-      const int64_t pieces = L > d_s ? (int64_t)floor(L / d_s) + 1 : 1;
-      for (int64_t i = 0; i < pieces; i++) {
-        const double t = (double)i / (double)pieces;
-        out.push_back(ax + t * (bx - ax));
-        out.push_back(ay + t * (by - ay));
+    raw.clear();
+    switch (p.kind) {
+      case TRIME_PRIM_DISK: {
+        const int64_t m = std::max<int64_t>(3, (int64_t)floor(TWO_PI * p.p[2] / d_s) + 1);
+        for (int64_t k = 0; k < m; k++) {
+          const double th = TWO_PI * (double)k / (double)m;
+          raw.push_back(p.p[0] + p.p[2] * cos(th));
+          raw.push_back(p.p[1] + p.p[2] * sin(th));
+        }
+        break;
       }
+      case TRIME_PRIM_ELLIPSE: {
+        const double c = cos(p.p[4]), sn = sin(p.p[4]);
+        const int64_t m = std::max<int64_t>(3, (int64_t)floor(TWO_PI * fmax(p.p[2], p.p[3]) / d_s) + 1);
+        for (int64_t k = 0; k < m; k++) {
+          const double th = TWO_PI * (double)k / (double)m;
+          const double u = p.p[2] * cos(th), w = p.p[3] * sin(th);
+          raw.push_back(p.p[0] + (c * u - sn * w));
+          raw.push_back(p.p[1] + (sn * u + c * w));
+        }
+        break;
+      }
+      case TRIME_PRIM_BOX: {
+        const double v[8] = {p.p[0], p.p[1], p.p[0], p.p[3], p.p[2], p.p[3], p.p[2], p.p[1]};
+        loop_points(v, 4, d_s, raw);
+        break;
+      }
+      default:  // polygon or segment loop
+        loop_points(geo->poly + 2 * (size_t)p.voff, p.nv, d_s, raw);
+        break;
     }
+    // the parts of this primitive's boundary that bound the whole geometry
+    for (size_t i = 0; i < raw.size(); i += 2)
+      if (fabs(geometry_sdf(geo, raw[i], raw[i + 1])) <= geps) {
+        out.push_back(raw[i]);
+        out.push_back(raw[i + 1]);
+      }
   }
   return out;
 }
@@ -54,64 +119,14 @@ struct Buckets {
   int cy(double y) const { return std::min(std::max((int)floor((y - y0) / cs), 0), ny - 1); }
 };
 
-struct Seg {
-  double ax, ay, bx, by;
-};
-
-// Distance from (x, y) to the segment, by the operations of the segment
-// distance everywhere else in the library.
-double seg_dist(const Seg &g, double x, double y) {
-  const double ex = g.bx - g.ax, ey = g.by - g.ay, wx = x - g.ax, wy = y - g.ay;
-  const double L2 = ex * ex + ey * ey;
-  double t = L2 > 0 ? (wx * ex + wy * ey) / L2 : 0.0;
-  t = t < 0 ? 0.0 : (t > 1 ? 1.0 : t);
-  const double qx = wx - t * ex, qy = wy - t * ey;
-  return sqrt(qx * qx + qy * qy);
-}
-
 }  // namespace
 
 // App. A trimming, in place; returns the remaining points in order.
 std::vector<double> trim_boundary(const trime_geometry *geo, double d_s, double geps, const std::vector<double> &in) {
-  // segments of the loops, bucketed by the cells their boxes overlap (cells
-  // of at least geps: a segment within geps of a point meets the 3 x 3
-  // cells around it)
-  std::vector<Seg> segs;
-  double sx0 = INFINITY, sy0 = INFINITY, sx1 = -INFINITY, sy1 = -INFINITY, len = 0;
-  for (int q = 0; q < geo->nprims; q++) {
-    const trime_prim &p = geo->prims[q];
-    if (p.kind != TRIME_PRIM_SEGMENTS) continue;
-    const double *v = geo->poly + 2 * (size_t)p.voff;
-    for (int k = 0; k < p.nv; k++) {
-      const int k1 = k + 1 == p.nv ? 0 : k + 1;
-      Seg g{v[2 * k], v[2 * k + 1], v[2 * k1], v[2 * k1 + 1]};
-      segs.push_back(g);
-      sx0 = fmin(sx0, fmin(g.ax, g.bx));
-      sy0 = fmin(sy0, fmin(g.ay, g.by));
-      sx1 = fmax(sx1, fmax(g.ax, g.bx));
-      sy1 = fmax(sy1, fmax(g.ay, g.by));
-      len += hypot(g.bx - g.ax, g.by - g.ay);
-    }
-  }
   std::vector<double> pts = in;
   const int64_t n = (int64_t)pts.size() / 2;
-  if (segs.empty() || n == 0) return pts;
-  Buckets SB;
-  SB.init(sx0, sy0, sx1, sy1, fmax(len / segs.size(), 2.0 * geps));
-  for (size_t k = 0; k < segs.size(); k++) {
-    const Seg &g = segs[k];
-    for (int j = SB.cy(fmin(g.ay, g.by)); j <= SB.cy(fmax(g.ay, g.by)); j++)
-      for (int i = SB.cx(fmin(g.ax, g.bx)); i <= SB.cx(fmax(g.ax, g.bx)); i++)
-        SB.cell[(size_t)j * SB.nx + i].push_back((int32_t)k);
-  }
-  auto on_boundary = [&](double x, double y) {
-    const int ci = SB.cx(x), cj = SB.cy(y);
-    double d = INFINITY;
-    for (int j = std::max(cj - 1, 0); j <= std::min(cj + 1, SB.ny - 1); j++)
-      for (int i = std::max(ci - 1, 0); i <= std::min(ci + 1, SB.nx - 1); i++)
-        for (int32_t k : SB.cell[(size_t)j * SB.nx + i]) d = fmin(d, seg_dist(segs[k], x, y));
-    return d <= geps;
-  };
+  if (n == 0) return pts;
+  auto on_boundary = [&](double x, double y) { return fabs(geometry_sdf(geo, x, y)) <= geps; };
   // points, bucketed by cells of about d_s (they only ever move to midpoints
   // of two of them, so they stay in the box of the initial set)
   double px0 = INFINITY, py0 = INFINITY, px1 = -INFINITY, py1 = -INFINITY;

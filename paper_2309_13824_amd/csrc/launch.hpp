@@ -174,9 +174,11 @@ size_t grow_sel_bytes();
 int64_t grid_partials(int nx, int ny);
 const char *seg_tree_build(const double *d_v, int nv, double bx0, double by0, double bx1, double by1,
                            double target, SegTree *T, std::vector<void *> &allocs, hipStream_t s);
-// boundary points of the SEGMENTS loops (boundary.hip, host): the dense set
-// of App. A and its trimming
-std::vector<double> boundary_points(const trime_geometry *geo, double d_s);
+// boundary points of the geometry (boundary.hip, host): the dense set of
+// App. A (each primitive's boundary sampled, the points within geps of the
+// whole geometry's boundary kept) and its trimming
+double geometry_sdf(const trime_geometry *geo, double x, double y);
+std::vector<double> boundary_points(const trime_geometry *geo, double d_s, double geps);
 std::vector<double> trim_boundary(const trime_geometry *geo, double d_s, double geps, const std::vector<double> &in);
 // automatic sizing (sizing.hip): medial points of the ns device boundary
 // points from their Voronoi cells clipped to box (written to medial, room

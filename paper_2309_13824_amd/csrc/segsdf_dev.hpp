@@ -7,7 +7,7 @@ namespace trime {
 
 // Distance from (x, y) to segment k of the loop; t: the clamped parameter of
 // the closest point.  The same operations as the reference definition.
-TRIME_D double seg_dist_t(const double *v, int nv, int k, double x, double y, double &t) {
+TRIME_HD double seg_dist_t(const double *v, int nv, int k, double x, double y, double &t) {
   const int k1 = k + 1 == nv ? 0 : k + 1;
   const double ax = v[2 * k], ay = v[2 * k + 1], bx = v[2 * k1], by = v[2 * k1 + 1];
   const double ex = bx - ax, ey = by - ay, wx = x - ax, wy = y - ay;
@@ -18,7 +18,7 @@ TRIME_D double seg_dist_t(const double *v, int nv, int k, double x, double y, do
   return sqrt(qx * qx + qy * qy);
 }
 
-TRIME_D void seg_normal_unit(const double *v, int nv, int k, double &nx, double &ny) {
+TRIME_HD void seg_normal_unit(const double *v, int nv, int k, double &nx, double &ny) {
   const int k1 = k + 1 == nv ? 0 : k + 1;
   const double ex = v[2 * k1] - v[2 * k], ey = v[2 * k1 + 1] - v[2 * k + 1];
   const double L = sqrt(ex * ex + ey * ey);
@@ -28,7 +28,7 @@ TRIME_D void seg_normal_unit(const double *v, int nv, int k, double &nx, double 
 
 // The signed distance at (x, y) from the nearest segment kb, its clamped
 // parameter bt and its distance best.
-TRIME_D double seg_signed(const double *v, int nv, int kb, double bt, double best, double x, double y) {
+TRIME_HD double seg_signed(const double *v, int nv, int kb, double bt, double best, double x, double y) {
   const int k1 = kb + 1 == nv ? 0 : kb + 1;
   const double ax = v[2 * kb], ay = v[2 * kb + 1], bx = v[2 * k1], by = v[2 * k1 + 1];
   double nx, ny;
@@ -45,6 +45,22 @@ TRIME_D double seg_signed(const double *v, int nv, int kb, double bt, double bes
   }
   const double dot = (x - px) * nx + (y - py) * ny;
   return dot > 0 ? -best : best;
+}
+
+// The loop's signed distance by brute force over its segments (host use).
+TRIME_HD double segments_sdf_brute(const double *v, int nv, double x, double y) {
+  double best = INFINITY, bt = 0.0;
+  int kb = -1;
+  for (int k = 0; k < nv; k++) {
+    double t;
+    const double d = seg_dist_t(v, nv, k, x, y, t);
+    if (d < best) {
+      best = d;
+      bt = t;
+      kb = k;
+    }
+  }
+  return kb < 0 ? INFINITY : seg_signed(v, nv, kb, bt, best, x, y);
 }
 
 TRIME_D int64_t cand_cell(const CandGrid &G, double x, double y) {

@@ -42,7 +42,23 @@ CASES = {
     "coast300": lambda: loop_workload(I.coast_loop(300), K=0.2),
     "coast2000": lambda: loop_workload(I.coast_loop(2000), grid_n=512, K=0.05),
     "coast_hole": lambda: with_hole(loop_workload(I.coast_loop(300), K=0.1)),
+    "coast_minus_disk": lambda: csg_workload([I.Prim(I.OP_INIT, I.PRIM_SEGMENTS, (), I.coast_loop(600)),
+                                              I.Prim(I.OP_DIFF, I.PRIM_DISK, (0.5, 0.55, 0.08))]),
+    "box_minus_disks": lambda: csg_workload([I.Prim(I.OP_INIT, I.PRIM_BOX, (0.1, 0.1, 0.9, 0.9)),
+                                             I.Prim(I.OP_DIFF, I.PRIM_DISK, (0.35, 0.4, 0.1)),
+                                             I.Prim(I.OP_DIFF, I.PRIM_DISK, (0.65, 0.62, 0.07)),
+                                             I.Prim(I.OP_DIFF, I.PRIM_ELLIPSE, (0.9, 0.3, 0.1, 0.05, 0.4))],
+                                            grid_n=256),
 }
+
+
+def csg_workload(prims, grid_n=128, K=0.1):
+    """A constructive geometry (the paper's custom shape is a segment loop
+    minus a disk) with automatic sizing."""
+    grid = I.centred_grid(grid_n, 17, int(round(math.log2(grid_n))) + 4, 0.5, 8)
+    wl = I.Workload("csg", prims, I.Sizing(I.SZ_AUTO, K, 0.5), grid, 2000, [], 0)
+    wl.x, wl.y = I.sample_points(wl, np.random.default_rng(1), (0, 0, 1, 1))
+    return wl
 
 
 def with_hole(wl):
@@ -79,7 +95,8 @@ def test_auto_sizing_steps_match_oracle(orc, T, name):
     assert np.array_equal(lfs.cpu().numpy(), au.lfs)
 
 
-@pytest.mark.parametrize("name", ["circle96", "coast300", "coast2000", "coast_hole"])
+@pytest.mark.parametrize("name", ["circle96", "coast300", "coast2000", "coast_hole", "coast_minus_disk",
+                                  "box_minus_disks"])
 def test_auto_sizing_grid_matches_oracle(orc, T, name):
     """The grid built with automatic sizing: mu at every node equals the
     oracle's brute-force minimum over all boundary points, bit for bit; the
