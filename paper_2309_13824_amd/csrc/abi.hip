@@ -8,6 +8,7 @@
 #include "trime_dev.hpp"
 
 #include "launch.hpp"
+#include "setup.hpp"
 
 using namespace trime;
 

@@ -1,7 +1,7 @@
 // Device side of the segment-loop distance (Sec. 3.2), shared by the
 // candidate build and the grid's node kernel.
 #pragma once
-#include "launch.hpp"
+#include "setup.hpp"
 
 namespace trime {
 
