@@ -55,7 +55,7 @@ BYTES_PER_POINT = 37 + 25 + 30 + 64
 # HBM traffic of one launch of the fused kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (first two CVD iterations, scaled by a 1 GiB copy: FETCH x 2.0,
 # WRITE x 1.0), valid for the kernel sources with this digest only.
-TRAFFIC = {"sha1": "c33eca4940fbd74a1094f8d46d57331b1a7ed4e5", "bytes_per_launch": 494486400.5}
+TRAFFIC = {"sha1": "505c4ec1c80583378032e62a3a30902bfc1055b1", "bytes_per_launch": 494124634.5}
 # CVD iterations from the seeded points before the autotuner's timing
 TUNE_FROM = 10
 KERNEL_SOURCES = ["cells.hip", "trime_dev.hpp", "geom_dev.hpp", "exact_dev.hpp", "launch.hpp"]
