@@ -5,6 +5,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -138,6 +139,39 @@ def test_growing_configuration_rejected_on_host(T):
     st.h_scale = 1.5  # not sqrt(20 / 10)
     assert L.trime_run_growing(C.byref(st), C.byref(T.Growing(base, 20, 0.002, 0.6)), None) == 1
     assert b"h_scale" in L.trime_last_error()
+
+
+def test_auto_sizing_arguments_rejected_on_host(T):
+    """trime_auto_sizing: null outputs, a sizing kind other than AUTO, a
+    nonpositive fac_s, a negative K and a bad polygon range return
+    TRIME_EINVAL before any device work; too small outputs return
+    TRIME_ECAPACITY with the boundary-point count."""
+    L = T.lib(require_gpu=False)
+    verts = np.array([[0.2, 0.2], [0.2, 0.8], [0.8, 0.8], [0.8, 0.2]], np.float64).reshape(-1)
+    prims = (T.Prim * 1)()
+    prims[0].op, prims[0].kind, prims[0].voff, prims[0].nv = 0, 4, 0, 4
+    geo = T.Geometry(1, prims, 4, verts.ctypes.data_as(C.POINTER(C.c_double)))
+    grid = T.Grid(64, 64, 0.0, 0.0, 1.0 / 63, 1.0 / 63, 8)
+    ns, nm = C.c_int64(0), C.c_int64(0)
+    good = T.Sizing(4, 0.1, 0.5, 0.0, 0, None, 0, None, 0, 0.0, 0.0)
+    fake = C.c_void_p(256)
+
+    def call(sz, g=geo, s_cap=10 ** 6, m_cap=10 ** 6, out=fake):
+        return L.trime_auto_sizing(C.byref(g), C.byref(sz), C.byref(grid), out, s_cap, C.byref(ns), out, out, m_cap,
+                                   C.byref(nm), out, None)
+
+    assert call(good, out=None) == 1
+    for bad in (T.Sizing(0, 0.1, 0.5, 0.0, 0, None, 0, None, 0, 0.0, 0.0),
+                T.Sizing(4, 0.1, 0.0, 0.0, 0, None, 0, None, 0, 0.0, 0.0),
+                T.Sizing(4, -0.1, 0.5, 0.0, 0, None, 0, None, 0, 0.0, 0.0),
+                T.Sizing(4, 0.1, 0.5, 0.0, 0, None, 0, None, -1, 0.0, 0.0)):
+        assert call(bad) == 1
+        assert b"trime_auto_sizing" in L.trime_last_error()
+    prims[0].nv = 9  # beyond npoly
+    assert call(good) == 1 and b"polygon" in L.trime_last_error()
+    prims[0].nv = 4
+    assert call(good, s_cap=3) == 3  # TRIME_ECAPACITY before any device work
+    assert ns.value > 3 and nm.value == -1
 
 
 def test_batch_arguments_rejected_on_host(T):
