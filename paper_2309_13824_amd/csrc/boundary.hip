@@ -14,24 +14,111 @@
 
 namespace trime {
 
-// The geometry's signed distance at (x, y): every primitive, combined by
-// its set operation (segment loops by brute force).
-double geometry_sdf(const trime_geometry *geo, double x, double y) {
-  double sd = INFINITY;
-  for (int k = 0; k < geo->nprims; k++) {
-    const trime_prim &pr = geo->prims[k];
-    const double t = pr.kind == TRIME_PRIM_SEGMENTS
-                         ? segments_sdf_brute(geo->poly + 2 * (size_t)pr.voff, pr.nv, x, y)
-                         : analytic_sdf(pr, geo->poly, x, y);
-    switch (pr.op) {
-      case TRIME_OP_INIT: sd = t; break;
-      case TRIME_OP_UNION: sd = fmin(sd, t); break;
-      case TRIME_OP_DIFF: sd = fmax(sd, -t); break;
-      default: sd = fmax(sd, t); break;
+namespace {
+
+struct Buckets {
+  double x0 = 0, y0 = 0, cs = 1;
+  int nx = 1, ny = 1;
+  std::vector<std::vector<int32_t>> cell;
+  void init(double bx0, double by0, double bx1, double by1, double size) {
+    const double W = fmax(bx1 - bx0, 1e-300), H = fmax(by1 - by0, 1e-300);
+    cs = fmax(size, fmax(W, H) / 1024.0);
+    nx = (int)fmin(ceil(W / cs) + 1, 1025.0);
+    ny = (int)fmin(ceil(H / cs) + 1, 1025.0);
+    x0 = bx0;
+    y0 = by0;
+    cell.assign((size_t)nx * ny, {});
+  }
+  int cx(double x) const { return std::min(std::max((int)floor((x - x0) / cs), 0), nx - 1); }
+  int cy(double y) const { return std::min(std::max((int)floor((y - y0) / cs), 0), ny - 1); }
+  bool inside(double x, double y) const { return x >= x0 && y >= y0 && x < x0 + nx * cs && y < y0 + ny * cs; }
+};
+
+// A segment loop with its segments bucketed by the cells their boxes meet:
+// the nearest segment (ties to the lower index) by rings of cells outward,
+// settled once nearer than every cell not yet visited; points off the grid
+// search every segment.  Either way the same segment as a brute-force scan.
+struct LoopIndex {
+  const double *v = nullptr;
+  int nv = 0;
+  Buckets B;
+  void build(const double *verts, int n) {
+    v = verts;
+    nv = n;
+    double x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY, len = 0;
+    for (int k = 0; k < nv; k++) {
+      const int k1 = k + 1 == nv ? 0 : k + 1;
+      x0 = fmin(x0, v[2 * k]);
+      y0 = fmin(y0, v[2 * k + 1]);
+      x1 = fmax(x1, v[2 * k]);
+      y1 = fmax(y1, v[2 * k + 1]);
+      len += hypot(v[2 * k1] - v[2 * k], v[2 * k1 + 1] - v[2 * k + 1]);
+    }
+    B.init(x0, y0, x1, y1, len / nv);
+    for (int k = 0; k < nv; k++) {
+      const int k1 = k + 1 == nv ? 0 : k + 1;
+      for (int j = B.cy(fmin(v[2 * k + 1], v[2 * k1 + 1])); j <= B.cy(fmax(v[2 * k + 1], v[2 * k1 + 1])); j++)
+        for (int i = B.cx(fmin(v[2 * k], v[2 * k1])); i <= B.cx(fmax(v[2 * k], v[2 * k1])); i++)
+          B.cell[(size_t)j * B.nx + i].push_back(k);
     }
   }
-  return sd;
-}
+  double sdf(double x, double y) const {
+    if (!B.inside(x, y)) return segments_sdf_brute(v, nv, x, y);
+    double best = INFINITY, bt = 0.0;
+    int kb = -1;
+    const int ci = B.cx(x), cj = B.cy(y);
+    const int rmax = std::max(std::max(ci, B.nx - 1 - ci), std::max(cj, B.ny - 1 - cj));
+    for (int r = 0; r <= rmax; r++) {
+      for (int j = cj - r; j <= cj + r; j++) {
+        if (j < 0 || j >= B.ny) continue;
+        const bool edge_row = j == cj - r || j == cj + r;
+        for (int i = ci - r; i <= ci + r; i += (edge_row || r == 0) ? 1 : 2 * r) {
+          if (i < 0 || i >= B.nx) continue;
+          for (int32_t k : B.cell[(size_t)j * B.nx + i]) {
+            double t;
+            const double d = seg_dist_t(v, nv, k, x, y, t);
+            if (d < best || (d == best && k < kb)) {
+              best = d;
+              bt = t;
+              kb = k;
+            }
+          }
+        }
+      }
+      if (kb >= 0 && best < (double)r * B.cs) break;  // ring r + 1 lies at least r cells away
+    }
+    return kb < 0 ? INFINITY : seg_signed(v, nv, kb, bt, best, x, y);
+  }
+};
+
+}  // namespace
+
+// The geometry's signed distance at (x, y): every primitive, combined by
+// its set operation; segment loops through their indexes.
+struct GeometryEval {
+  const trime_geometry *geo;
+  std::vector<LoopIndex> loops;
+  explicit GeometryEval(const trime_geometry *g) : geo(g), loops((size_t)g->nprims) {
+    for (int k = 0; k < g->nprims; k++)
+      if (g->prims[k].kind == TRIME_PRIM_SEGMENTS) loops[k].build(g->poly + 2 * (size_t)g->prims[k].voff, g->prims[k].nv);
+  }
+  double operator()(double x, double y) const {
+    double sd = INFINITY;
+    for (int k = 0; k < geo->nprims; k++) {
+      const trime_prim &pr = geo->prims[k];
+      const double t = pr.kind == TRIME_PRIM_SEGMENTS ? loops[k].sdf(x, y) : analytic_sdf(pr, geo->poly, x, y);
+      switch (pr.op) {
+        case TRIME_OP_INIT: sd = t; break;
+        case TRIME_OP_UNION: sd = fmin(sd, t); break;
+        case TRIME_OP_DIFF: sd = fmax(sd, -t); break;
+        default: sd = fmax(sd, t); break;
+      }
+    }
+    return sd;
+  }
+};
+
+double geometry_sdf(const trime_geometry *geo, double x, double y) { return GeometryEval(geo)(x, y); }
 
 namespace {
 
@@ -56,6 +143,7 @@ void loop_points(const double *v, int nv, double d_s, std::vector<double> &out) 
 }  // namespace
 
 std::vector<double> boundary_points(const trime_geometry *geo, double d_s, double geps) {
+  const GeometryEval sdf(geo);
   std::vector<double> raw, out;
   for (int q = 0; q < geo->nprims; q++) {
     const trime_prim &p = geo->prims[q];
@@ -92,7 +180,7 @@ std::vector<double> boundary_points(const trime_geometry *geo, double d_s, doubl
     }
     // the parts of this primitive's boundary that bound the whole geometry
     for (size_t i = 0; i < raw.size(); i += 2)
-      if (fabs(geometry_sdf(geo, raw[i], raw[i + 1])) <= geps) {
+      if (fabs(sdf(raw[i], raw[i + 1])) <= geps) {
         out.push_back(raw[i]);
         out.push_back(raw[i + 1]);
       }
@@ -100,33 +188,14 @@ std::vector<double> boundary_points(const trime_geometry *geo, double d_s, doubl
   return out;
 }
 
-namespace {
-
-struct Buckets {
-  double x0 = 0, y0 = 0, cs = 1;
-  int nx = 1, ny = 1;
-  std::vector<std::vector<int32_t>> cell;
-  void init(double bx0, double by0, double bx1, double by1, double size) {
-    const double W = fmax(bx1 - bx0, 1e-300), H = fmax(by1 - by0, 1e-300);
-    cs = fmax(size, fmax(W, H) / 1024.0);
-    nx = (int)fmin(ceil(W / cs) + 1, 1025.0);
-    ny = (int)fmin(ceil(H / cs) + 1, 1025.0);
-    x0 = bx0;
-    y0 = by0;
-    cell.assign((size_t)nx * ny, {});
-  }
-  int cx(double x) const { return std::min(std::max((int)floor((x - x0) / cs), 0), nx - 1); }
-  int cy(double y) const { return std::min(std::max((int)floor((y - y0) / cs), 0), ny - 1); }
-};
-
-}  // namespace
 
 // App. A trimming, in place; returns the remaining points in order.
 std::vector<double> trim_boundary(const trime_geometry *geo, double d_s, double geps, const std::vector<double> &in) {
   std::vector<double> pts = in;
   const int64_t n = (int64_t)pts.size() / 2;
   if (n == 0) return pts;
-  auto on_boundary = [&](double x, double y) { return fabs(geometry_sdf(geo, x, y)) <= geps; };
+  const GeometryEval sdf(geo);
+  auto on_boundary = [&](double x, double y) { return fabs(sdf(x, y)) <= geps; };
   // points, bucketed by cells of about d_s (they only ever move to midpoints
   // of two of them, so they stay in the box of the initial set)
   double px0 = INFINITY, py0 = INFINITY, px1 = -INFINITY, py1 = -INFINITY;
