@@ -56,6 +56,10 @@ BYTES_PER_POINT = 37 + 25 + 30 + 64
 # WRITE_SIZE (first two CVD iterations, scaled by a 1 GiB copy: FETCH x 2.0,
 # WRITE x 1.0), valid for the kernel sources with this digest only.
 TRAFFIC = {"sha1": "505c4ec1c80583378032e62a3a30902bfc1055b1", "bytes_per_launch": 494124634.5}
+# counted flops per point of the DistMesh force gather (edge forces over the
+# adjacency row, forward Euler, treatment checks)
+DM_FLOPS_PER_POINT = 150
+
 # CVD iterations from the seeded points before the autotuner's timing
 TUNE_FROM = 10
 KERNEL_SOURCES = ["cells.hip", "trime_dev.hpp", "geom_dev.hpp", "exact_dev.hpp", "launch.hpp"]
@@ -450,7 +454,10 @@ def schedule_run(args, log):
         if which == "ellipses":
             dens, ms = m.autotune((1.4, 2.0, 2.8), n_iter=2)
             log("  autotune (%s): %s -> %.2f" % (pname, ", ".join("%.1f: %.2f ms" % kv for kv in sorted(ms.items())), dens))
-        for sch in schedules:
+        variants = [(sch, False) for sch in schedules]
+        # DistMesh schedules also as "always": re-triangulating every iteration
+        variants += [(sch, True) for sch in schedules if any(meth == "dm" for meth, _ in sch)]
+        for sch, always in variants:
             iters = sum(k for _, k in sch)
             m.load()
             m.step_hybrid([(sch[0][0], 2)])  # warm-up
@@ -459,25 +466,44 @@ def schedule_run(args, log):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             w0 = time.perf_counter()
             a.record()
-            m.step_hybrid(sch)
+            if always:
+                for meth, k in sch:
+                    if meth == "dm":
+                        m.step_dm(k, fresh=True, always=True)
+                    else:
+                        m.step_cvd(k)
+            else:
+                m.step_hybrid(sch)
             b.record()
             torch.cuda.synchronize()
             wall = time.perf_counter() - w0
             ms_ = a.elapsed_time(b)
             st = m.stats()
-            key = "%s %s" % (pname, "+".join("%d %s" % (k, meth) for meth, k in sch))
+            key = "%s %s%s" % (pname, "+".join("%d %s" % (k, meth) for meth, k in sch),
+                               " (DistMesh re-triangulating every iteration)" if always else "")
             n_cvd = sum(k for meth, k in sch if meth == "cvd")
             n_dm = iters - n_cvd
             n_dm_tri = min(max(st["triangulations"] - n_cvd, 0), n_dm)
             nbytes = wl.n * (n_cvd * ITER_BYTES["cvd"] + n_dm_tri * ITER_BYTES["dm_tri"]
                              + (n_dm - n_dm_tri) * ITER_BYTES["dm"])
             bw = nbytes / (ms_ * 1e-3)
+            # counted arithmetic of the whole run: the cell kernels' work
+            # counters (every triangulation and CVD iteration) and the
+            # DistMesh force gather per DistMesh iteration
+            cell_pts = float(wl.n) * st["triangulations"]
+            flops = (FLOPS_PER["point"] * cell_pts + sum(FLOPS_PER[c] * st["work_" + c]
+                                                          for c in ("candidates", "margins", "cuts", "leaves"))
+                     + DM_FLOPS_PER_POINT * wl.n * n_dm)
+            fl = flops / (ms_ * 1e-3)
             res[key] = {"value": wl.n * iters / (ms_ * 1e-3), "ms_per_step": ms_ / iters, "wall_s": wall,
                         "triangulations": st["triangulations"], "fp64_replays": st["fp64_replays"],
                         "bin_density": dens, "mean_q": st["mean_q"], "min_q": st["min_q"],
                         "whole_iteration_hbm": {"bound": "hbm", "achieved": bw / 1e9, "peak": PEAK_HBM / 1e9,
                                                 "unit": "GB/s", "frac": bw / PEAK_HBM,
-                                                "algorithmic_bytes": nbytes}}
+                                                "algorithmic_bytes": nbytes},
+                        "whole_iteration_valu": {"bound": "alu", "achieved": fl / 1e12, "peak": PEAK_FP32 / 1e12,
+                                                 "unit": "TFLOP/s", "frac": fl / PEAK_FP32,
+                                                 "counted_flops": flops}}
             log("  %s: %.1f ms for %d iterations (%d triangulations), mean q %.4f" % (
                 key, ms_, iters, st["triangulations"], st["mean_q"]))
         del m
