@@ -286,6 +286,26 @@ def stars_run(args, log):
         out["batched_" + name] = total * iters / (bat_ms * 1e-3)
         out["batched_ms_" + name] = bat_ms
         log("  %s batched kernels: %.1f ms for %d iterations" % (name, bat_ms, iters))
+        # the same batch re-triangulating every iteration
+        for m in ms:
+            m.load()
+        b = Batch(ms, method="dm_always", n_iter=2, kind="kernels")
+        b.run(2)  # warm-up
+        for m in ms:
+            m.load()
+        torch.cuda.synchronize()
+        alw_ms = timed(lambda: b.run(iters), b.stream)
+        b.close()
+        out["batched_always_" + name] = total * iters / (alw_ms * 1e-3)
+        log("  %s batched kernels, re-triangulating every iteration: %.1f ms for %d iterations" %
+            (name, alw_ms, iters))
+        for m in ms:  # the flag-mode run's statistics for the roofline below
+            m.load()
+        b = Batch(ms, method="dm", n_iter=2, kind="kernels")
+        torch.cuda.synchronize()
+        b.run(iters)
+        torch.cuda.synchronize()
+        b.close()
         if prec == T.FP32:  # whole-iteration HBM roofline of the timed batch run
             nbytes = 0
             for m in ms:
@@ -320,6 +340,7 @@ def stars_run(args, log):
                                "iterations" % (len(wls), total), "shapes": len(wls), "total_points": total,
                    "seed": 1005},
         "batched_fp64": out["batched_fp64"],
+        "batched_always_fp32": out["batched_always_fp32"], "batched_always_fp64": out["batched_always_fp64"],
         "batched_fp32_over_batched_fp64": out["batched_fp32"] / out["batched_fp64"],
         "whole_iteration_hbm": out["hbm"],
     }

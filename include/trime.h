@@ -273,7 +273,8 @@ typedef struct {
 } trime_state;
 
 /* A fixed hybrid schedule: segments (method, iterations) run in order. */
-enum { TRIME_METHOD_DM = 0, TRIME_METHOD_CVD = 1 };
+enum { TRIME_METHOD_DM = 0, TRIME_METHOD_CVD = 1,
+       TRIME_METHOD_DM_ALWAYS = 2 /* trime_batch_create only: DistMesh re-triangulating every iteration */ };
 typedef struct {
   int32_t nseg;
   const int32_t *method;   /* host, nseg                                     */
@@ -521,8 +522,9 @@ trime_status trime_graph_destroy(trime_graph *g);
    kernel of an iteration once for all shapes: each block finds its shape in
    a table of per-shape arguments (binary search over the per-shape block
    offsets) and runs the same code on that shape's buffers.  Each shape's
-   results equal running it alone with trime_step_dm (flag mode, fresh = 0)
-   or trime_step_cvd; its statistics stay in its own state.
+   results equal running it alone with trime_step_dm (flag mode, fresh = 0;
+   method TRIME_METHOD_DM_ALWAYS: always_retriangulate = 1) or
+   trime_step_cvd; its statistics stay in its own state.
    - states: bound and loaded, no timing events, all with the same precision
      and grid dtype (they must record the same sequence of kernels); they
      must stay bound to the same workspaces while the batch exists, and

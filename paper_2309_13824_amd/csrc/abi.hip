@@ -969,7 +969,7 @@ trime_status trime_batch_destroy(trime_batch *b) {
 
 trime_status trime_batch_create(trime_state *const *states, int32_t nstates, int32_t method, trime_batch **out) {
   if (!states || nstates <= 0 || !out) return fail(TRIME_EINVAL, "trime_batch_create: bad argument");
-  if (method != TRIME_METHOD_DM && method != TRIME_METHOD_CVD)
+  if (method != TRIME_METHOD_DM && method != TRIME_METHOD_CVD && method != TRIME_METHOD_DM_ALWAYS)
     return fail(TRIME_EINVAL, "trime_batch_create: bad method");
   *out = nullptr;
   for (int k = 0; k < nstates; k++) {
@@ -982,8 +982,9 @@ trime_status trime_batch_create(trime_state *const *states, int32_t nstates, int
   std::vector<std::vector<LaunchRec>> logs(nstates);
   for (int k = 0; k < nstates; k++) {
     g_launch_log = &logs[k];
-    trime_status e = method == TRIME_METHOD_DM ? trime_step_dm(states[k], 2, 0, 0, nullptr)
-                                               : trime_step_cvd(states[k], 2, nullptr);
+    trime_status e = method == TRIME_METHOD_CVD ? trime_step_cvd(states[k], 2, nullptr)
+                                                : trime_step_dm(states[k], 2, 0, method == TRIME_METHOD_DM_ALWAYS,
+                                                                nullptr);
     g_launch_log = nullptr;
     if (e) return e;
   }

@@ -220,7 +220,7 @@ class Batch:
         self.kind = kind
         self.stream = torch.cuda.Stream()
         torch.cuda.synchronize()
-        meth = T.METHOD_DM if method == "dm" else T.METHOD_CVD
+        meth = {"dm": T.METHOD_DM, "cvd": T.METHOD_CVD, "dm_always": T.METHOD_DM_ALWAYS}[method]
         self.graph = self.batch = None
         if kind == "kernels":
             self.batch = T.batch_create([m.state for m in self.meshers], meth)

@@ -17,7 +17,7 @@ LIB_PATH = os.environ.get("TRIME_LIB", os.path.join(HERE, "libtrime.so"))
 
 FP64, FP32 = 0, 1
 CAT_OUTER, CAT_INNER, CAT_BOUNDARY = 0, 1, 2
-METHOD_DM, METHOD_CVD = 0, 1
+METHOD_DM, METHOD_CVD, METHOD_DM_ALWAYS = 0, 1, 2
 TRI_PER_POINT = 16
 STATUS = {0: "TRIME_OK", 1: "TRIME_EINVAL", 2: "TRIME_EUNSUPPORTED", 3: "TRIME_ECAPACITY",
           4: "TRIME_EHIP", 5: "TRIME_EDEGENERATE"}
@@ -366,7 +366,8 @@ def batch_graph_create(states, method, n_iter, nstreams, stream):
 
 def batch_create(states, method):
     """A batch running every kernel of an iteration once for all states
-    (method METHOD_DM or METHOD_CVD); synchronises (uploads its tables)."""
+    (method METHOD_DM, METHOD_CVD or METHOD_DM_ALWAYS: DistMesh re-triangulating
+    every iteration); synchronises (uploads its tables)."""
     arr = (C.POINTER(State) * len(states))(*[C.pointer(s) for s in states])
     b = C.c_void_p()
     _check(lib().trime_batch_create(arr, len(states), int(method), C.byref(b)))

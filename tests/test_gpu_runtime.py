@@ -172,8 +172,8 @@ def test_star_polygon_dm_matches_oracle(orc, T):
     assert np.array_equal(gc, cat)
 
 
-@pytest.mark.parametrize("kind", ["graph", "kernels"])
-@pytest.mark.parametrize("method", ["dm", "cvd"])
+@pytest.mark.parametrize("kind,method", [("graph", "dm"), ("graph", "cvd"), ("kernels", "dm"), ("kernels", "cvd"),
+                                         ("kernels", "dm_always")])
 def test_batch_matches_per_shape_runs(orc, T, method, kind):
     """Shapes of uneven size run as one batch (kind "graph": the shapes'
     launches in one graph over several streams; kind "kernels": one launch
@@ -187,6 +187,8 @@ def test_batch_matches_per_shape_runs(orc, T, method, kind):
         m = mesher(w, FP32, grid=g)
         if method == "dm":
             m.step_dm(4, fresh=False)
+        elif method == "dm_always":
+            m.step_dm(4, fresh=False, always=True)
         else:
             m.step_cvd(4)
         alone.append(m.points())
