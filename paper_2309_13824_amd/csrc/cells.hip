@@ -996,7 +996,9 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   // The FP64 centroid pass of one deferred point: its cell's constraints
   // (entry cb of the deferred queue) give the FP64 vertices, then the CVD
   // target and the treatment run in FP64.
-  TRIME_D void centroid_replay(LaneStats &st, int64_t cb) {
+  // lead: the lane that writes the result and counts the work (one point
+  // per wavefront: every lane runs the pass, the leaves spread over them)
+  TRIME_D void centroid_replay(LaneStats &st, int64_t cb, bool lead = true) {
     pid = gld(a.id, k);
     px = gld(a.x, k);
     py = gld(a.y, k);
@@ -1023,6 +1025,7 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       yf = py;
       cf = gld(a.cat, k);
     }
+    if (!lead) return;
     write_cvd(xf, yf, cf);
     st.newton_fail += tc.newton_fail();
     st.trace_fail += tc.trace_fail();
@@ -1542,6 +1545,9 @@ template <class T, class G, int MODE, int VMAX, int B> struct Cells {
 //    point: FP64 vertices from the stored constraints, FP64 CVD target and
 //    treatment.  The cells and triangles of these points were committed by
 //    the fast kernel.
+// Deferred centroids up to this many take one wavefront each.
+constexpr int64_t POST_WAVE_POINTS = 4096;
+
 template <class G, int MODE, int VMAX> struct CellsPost {
   struct Args {
     KArgs a;
@@ -1576,12 +1582,24 @@ template <class G, int MODE, int VMAX> struct CellsPost {
         __syncthreads();
       }
     } else if constexpr (MODE == MODE_CVD) {
+      // deferred FP32 centroids: few of them, one point per wavefront (its
+      // quadrature leaves spread over the lanes: latency); many, one point
+      // per lane (throughput)
       const int64_t cb = (int64_t)blk.id - wg, cg = (int64_t)blk.n - wg;
       int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE3);
-      for (int64_t w = cb * 64 + lane; w < nq; w += cg * 64) {
-        int64_t k = gld(a.queue3, w);
-        Lane<double, G, MODE_CVD, false, V, 64> L(a, PC, lane, k);
-        L.centroid_replay(st, w * CQ_STRIDE);
+      if (nq <= POST_WAVE_POINTS) {
+        for (int64_t w = cb; w < nq; w += cg) {
+          int64_t k = gld(a.queue3, w);
+          Lane<double, G, MODE_CVD, false, VMAX, 1> L(a, P, 0, k);
+          L.centroid_replay(st, w * CQ_STRIDE, lane == 0);
+          __syncthreads();
+        }
+      } else {
+        for (int64_t w = cb * 64 + lane; w < nq; w += cg * 64) {
+          int64_t k = gld(a.queue3, w);
+          Lane<double, G, MODE_CVD, false, V, 64> L(a, PC, lane, k);
+          L.centroid_replay(st, w * CQ_STRIDE);
+        }
       }
     }
     flush_stats<64>(a, st, hist);
@@ -1630,7 +1648,7 @@ constexpr int REPLAY_BLOCK = 64;
 constexpr int REPLAY_VMAX = 32;
 constexpr int WAVE_VMAX = 64;
 constexpr int WAVE_GRID = TRIME_HEAVY_WAVE ? 4096 : 1024;
-constexpr int CENTROID_GRID = 256;
+constexpr int CENTROID_GRID = (int)POST_WAVE_POINTS;  // blocks for the deferred centroids
 static_assert(FAST_VMAX < CQ_STRIDE, "a deferred cell must fit its queue entry");
 
 static int64_t clamp64(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -1644,7 +1662,7 @@ template <class T, class G, int MODE> static void launch_mode(const KArgs &a, hi
   launch<Cells<T, G, MODE, FAST_VMAX, FAST_BLOCK>>(a, nb, s);
   if (a.ev1 && !rec) (void)hipEventRecord((hipEvent_t)a.ev1, s);
   const int wgrid = (int)clamp64(a.n / 512, 8, WAVE_GRID);
-  const int cgrid = (MODE == MODE_CVD && sizeof(T) == 4) ? (int)clamp64(a.n / 2048, 4, CENTROID_GRID) : 0;
+  const int cgrid = (MODE == MODE_CVD && sizeof(T) == 4) ? (int)clamp64(a.n / 128, 4, CENTROID_GRID) : 0;
   using Post = CellsPost<G, MODE, WAVE_VMAX>;
   launch<Post>(typename Post::Args{a, wgrid}, (uint32_t)(wgrid + cgrid), s);
   launch<CellsExact<G, MODE, REPLAY_VMAX, REPLAY_BLOCK>>(a, (uint32_t)clamp64(a.n / 8192, 2, 64), s);
