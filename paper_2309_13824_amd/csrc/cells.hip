@@ -798,13 +798,15 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       swy += w * (double)gy;
     };
     const int D = L - 1;
-    if constexpr (BLOCK == 1) {
-      // one polygon per wavefront: leaf i of the n 2^D leaves goes to lane
-      // i mod 64 (bit path from its fan triangle); the partial sums meet in
-      // a fixed-order tree at lane 0 and are broadcast
-      const int lane = threadIdx.x & 63;
+    if constexpr (BLOCK == 1 || BLOCK == 8) {
+      // one polygon per wavefront (BLOCK 1) or per group of 8 lanes (BLOCK
+      // 8): leaf i of the n 2^D leaves goes to lane i mod g of the group
+      // (bit path from its fan triangle); the partial sums meet in a
+      // fixed-order tree at the group's first lane and are broadcast
+      constexpr int g = BLOCK == 1 ? 64 : 8;
+      const int lane = threadIdx.x & (g - 1);
       const int64_t total = (int64_t)n << D;
-      for (int64_t i = lane; i < total; i += 64) {
+      for (int64_t i = lane; i < total; i += g) {
         int t = (int)(i >> D);
         int64_t b = i & (((int64_t)1 << D) - 1);
         V bx, by, cx_, cy_;
@@ -819,14 +821,14 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
         }
         leaf(x0, y0, x1, y1, x2, y2);
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        sw += __shfl_down(sw, off);
-        swx += __shfl_down(swx, off);
-        swy += __shfl_down(swy, off);
+      for (int off = g / 2; off > 0; off >>= 1) {
+        sw += __shfl_down(sw, off, g);
+        swx += __shfl_down(swx, off, g);
+        swy += __shfl_down(swy, off, g);
       }
-      sw = __shfl(sw, 0);
-      swx = __shfl(swx, 0);
-      swy = __shfl(swy, 0);
+      sw = __shfl(sw, 0, g);
+      swx = __shfl(swx, 0, g);
+      swy = __shfl(swy, 0, g);
       wk.leaves += n << D;
       const double inv = 1.0 / sw;
       cx = (V)(swx * inv);
@@ -1546,7 +1548,7 @@ template <class T, class G, int MODE, int VMAX, int B> struct Cells {
 //    treatment.  The cells and triangles of these points were committed by
 //    the fast kernel.
 // Deferred centroids up to this many take one wavefront each.
-constexpr int64_t POST_WAVE_POINTS = 4096;
+constexpr int64_t POST_WAVE_POINTS = 1024;
 
 template <class G, int MODE, int VMAX> struct CellsPost {
   struct Args {
@@ -1559,7 +1561,7 @@ template <class G, int MODE, int VMAX> struct CellsPost {
     if (cond_off(a)) return;
     constexpr int V = CQ_STRIDE - 1;
     __shared__ VRec<double> P[VMAX][1];
-    __shared__ VRec<double> PC[V][64];
+    __shared__ VRec<double> PC[V][8];
     __shared__ int hist[40];
     __shared__ int sh_s0[64], sh_incl[64];
     __shared__ double sh_ro[8];
@@ -1584,7 +1586,7 @@ template <class G, int MODE, int VMAX> struct CellsPost {
     } else if constexpr (MODE == MODE_CVD) {
       // deferred FP32 centroids: few of them, one point per wavefront (its
       // quadrature leaves spread over the lanes: latency); many, one point
-      // per lane (throughput)
+      // per group of 8 lanes (throughput)
       const int64_t cb = (int64_t)blk.id - wg, cg = (int64_t)blk.n - wg;
       int64_t nq = gld(a.counters, (int64_t)CNT_QUEUE3);
       if (nq <= POST_WAVE_POINTS) {
@@ -1595,10 +1597,15 @@ template <class G, int MODE, int VMAX> struct CellsPost {
           __syncthreads();
         }
       } else {
-        for (int64_t w = cb * 64 + lane; w < nq; w += cg * 64) {
-          int64_t k = gld(a.queue3, w);
-          Lane<double, G, MODE_CVD, false, V, 64> L(a, PC, lane, k);
-          L.centroid_replay(st, w * CQ_STRIDE);
+        // the loop bound is uniform over the block: every group reaches the
+        // shuffles of the quadrature together (idle groups on a dummy point)
+        for (int64_t w0 = cb * 8; w0 < nq; w0 += cg * 8) {
+          const int64_t w = w0 + (lane >> 3);
+          const bool live = w < nq;
+          int64_t k = gld(a.queue3, live ? w : w0);
+          Lane<double, G, MODE_CVD, false, V, 8> L(a, PC, lane >> 3, k);
+          L.centroid_replay(st, (live ? w : w0) * CQ_STRIDE, live && (lane & 7) == 0);
+          __syncthreads();
         }
       }
     }
@@ -1648,7 +1655,7 @@ constexpr int REPLAY_BLOCK = 64;
 constexpr int REPLAY_VMAX = 32;
 constexpr int WAVE_VMAX = 64;
 constexpr int WAVE_GRID = TRIME_HEAVY_WAVE ? 4096 : 1024;
-constexpr int CENTROID_GRID = (int)POST_WAVE_POINTS;  // blocks for the deferred centroids
+constexpr int CENTROID_GRID = 4096;  // blocks for the deferred centroids (8 points each per round)
 static_assert(FAST_VMAX < CQ_STRIDE, "a deferred cell must fit its queue entry");
 
 static int64_t clamp64(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
