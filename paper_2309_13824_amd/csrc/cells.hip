@@ -1543,10 +1543,11 @@ template <class T, class G, int MODE, int VMAX, int B> struct Cells {
 //    (grid-stride): the ring scan, the tests, triangles and quadrature are
 //    shared by the 64 lanes.  Points FP64 cannot decide go on to the exact
 //    queue.
-//  - the blocks after them (CVD): the deferred FP32 centroids, one lane per
-//    point: FP64 vertices from the stored constraints, FP64 CVD target and
-//    treatment.  The cells and triangles of these points were committed by
-//    the fast kernel.
+//  - the blocks after them (CVD): the deferred FP32 centroids, one
+//    wavefront per point while there are few, a group of 8 lanes per point
+//    when many: FP64 vertices from the stored constraints, FP64 CVD target
+//    and treatment, the quadrature leaves spread over the lanes.  The cells
+//    and triangles of these points were committed by the fast kernel.
 // Deferred centroids up to this many take one wavefront each.
 constexpr int64_t POST_WAVE_POINTS = 1024;
 
