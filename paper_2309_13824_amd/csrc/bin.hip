@@ -168,6 +168,30 @@ struct ScanAdd {
   }
 };
 
+// With few tiles, the second pass of its own: each block adds the tile sums
+// before it (a block-wide sum of at most SCAN_FEW_TILES values) to its tile,
+// and block 0 also writes the total, which spares the single-block pass.
+constexpr int64_t SCAN_FEW_TILES = 2048;
+struct ScanAddFew {
+  using Args = ScanArgs;
+  static constexpr int BLOCK = SCAN_BLOCK;
+  TRIME_D static void run(const ScanArgs &A, Blk blk) {
+    __shared__ int smem[SCAN_BLOCK / 64];
+    if (A.cond && gld(A.cond, 0) == 0) return;
+    const int64_t upto = blk.id == 0 ? A.nt : (int64_t)blk.id;  // block 0: every tile, for the total
+    int v = 0;
+    for (int64_t i = threadIdx.x; i < upto; i += SCAN_BLOCK) v += A.sums[i];
+    int total;
+    block_excl_scan(v, smem, total);
+    const int add = blk.id == 0 ? 0 : total;
+    int64_t base = (int64_t)blk.id * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; q++)
+      if (base + q < A.n) A.out[base + q] += add;
+    if (blk.id == 0 && threadIdx.x == 0) A.out[A.n] = total;
+  }
+};
+
 // Exclusive scan of in[0..n) into out[0..n], out[n] = total; skipped when
 // cond is set and *cond == 0.
 void scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t s,
@@ -176,6 +200,10 @@ void scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStrea
   if (nt == 0) nt = 1;
   ScanArgs A{in, out, n, nt, tmp, cond};
   launch<ScanTiles>(A, (uint32_t)nt, s);
+  if (nt <= SCAN_FEW_TILES) {
+    launch<ScanAddFew>(A, (uint32_t)nt, s);
+    return;
+  }
   launch<ScanSums>(A, 1, s);
   launch<ScanAdd>(A, (uint32_t)nt, s);
 }
