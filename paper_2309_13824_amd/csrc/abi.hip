@@ -541,8 +541,9 @@ trime_status trime_state_load(trime_state *st, const double *d_x, const double *
 
 // Binning; with cond set it runs only if *cond != 0 on the device (else the
 // buffer sets are copied in place order), and the host-side swap of the
-// buffer sets is the same either way.
-static void bin_points(trime_state *st, hipStream_t s, const int32_t *cond) {
+// buffer sets is the same either way.  reset >= 0 also clears the stats for
+// the pass that follows (launch_stats_reset's full flag).
+static void bin_points(trime_state *st, hipStream_t s, const int32_t *cond, int32_t reset = -1) {
   KArgs a = make_args(st);
   a.cond = cond;
   GatherArgs g;
@@ -564,7 +565,7 @@ static void bin_points(trime_state *st, hipStream_t s, const int32_t *cond) {
   g.xl = O.xl;
   g.yl = O.yl;
   g.span = O.span;
-  launch_bin(a, g, st->nkeys, st->scan_tmp, s);
+  launch_bin(a, g, st->nkeys, st->scan_tmp, s, reset);
   st->cur_pos ^= 1;
   st->cur_ord ^= 1;
 }
@@ -635,9 +636,8 @@ trime_status trime_step_cvd(trime_state *st, int32_t n_iter, void *stream) {
   if (n_iter < 0) return fail(TRIME_EINVAL, "trime_step_cvd: negative iteration count");
   hipStream_t s = (hipStream_t)stream;
   for (int it = 0; it < n_iter; it++) {
-    bin_points(st, s, nullptr);
+    bin_points(st, s, nullptr, 0);  // with the stats reset of the CVD pass
     KArgs a = make_args(st);
-    launch_stats_reset(a, 0, s);
     launch_cells(a, MODE_CVD, st->grid.dtype_bytes, s);
     launch_finish_extract(a, s);
     st->cur_pos ^= 1;

@@ -18,16 +18,20 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     p[i] = v;
 }
 
-// Zeroes the bin fill counts (grid-stride).
+// Zeroes the bin fill counts (grid-stride).  With reset >= 0, block 0 also
+// clears the stats and counters of the pass that follows the binning (the
+// full flag of the stats reset), which spares that pass a launch of its own.
 struct FillCond {
   struct Args {
     KArgs a;
     int32_t *p;
     int64_t n;
+    int32_t reset;
   };
   static constexpr int BLOCK = 256;
   TRIME_D static void run(const Args &A, Blk b) {
     if (cond_off(A.a)) return;
+    if (A.reset >= 0 && b.id == 0) stats_reset(A.a, A.reset, threadIdx.x);
     for (int64_t i = (int64_t)b.id * BLOCK + threadIdx.x; i < A.n; i += (int64_t)b.n * BLOCK) A.p[i] = 0;
   }
 };
@@ -248,10 +252,11 @@ struct BinSort {
 
 // Gather every per-point array into the new slot order (writes the other
 // buffer set); the positions of the last triangulation become the current
-// ones and the octagon span S is recomputed from the point's cell.  A
+// ones and the octagon span S is recomputed from the point's cell.  The
+// flag of the processing order (1 on the boundary) goes to key[].  A
 // conditional binning without work copies every array in place order
 // instead (the buffer sets still swap), keeping the last-triangulation
-// positions and spans.
+// positions and spans, and leaves the processing order as it was.
 struct BinGather {
   struct Args {
     KArgs a;
@@ -283,30 +288,19 @@ TRIME_D void BinGather::run(const Args &A, Blk blk) {
   g.xlo[s] = x;
   g.ylo[s] = y;
   g.dprevo[s] = g.dprev[k];
-  g.cato[s] = g.cat[k];
+  const uint8_t c = g.cat[k];
+  g.cato[s] = c;
   g.ido[s] = g.id[k];
   g.spano[s] = span_at(a, x, y);
+  a.key[s] = c == TRIME_CAT_BOUNDARY ? 1 : 0;
 }
 
 // Processing order of the cell kernels: the slots of points on the boundary
 // first (their cells reach the octagon walls outside the domain, so they scan
 // the most bins), then all others, each group in slot order.  Heavy points
 // then share wavefronts and start first instead of holding back 64-point
-// wavefronts of light ones.
-struct OrderFlags {
-  struct Args {
-    KArgs a;
-    const uint8_t *cat;
-  };
-  static constexpr int BLOCK = 256;
-  TRIME_D static void run(const Args &A, Blk blk) {
-    const KArgs &a = A.a;
-    int64_t s = (int64_t)blk.id * BLOCK + threadIdx.x;
-    if (s >= a.n || cond_off(a)) return;
-    a.key[s] = A.cat[s] == TRIME_CAT_BOUNDARY ? 1 : 0;
-  }
-};
-
+// wavefronts of light ones.  The flags come from the gather, their exclusive
+// scan from scan_i32.
 struct OrderScatter {
   using Args = KArgs;
   static constexpr int BLOCK = 256;
@@ -322,19 +316,18 @@ struct OrderScatter {
 };
 
 void launch_bin(const KArgs &a, const GatherArgs &g, int64_t nkeys, int32_t *scan_tmp,
-                hipStream_t s) {
+                hipStream_t s, int32_t reset) {
   const int B = 256;
   const uint32_t nb = (uint32_t)((a.n + B - 1) / B);
   // the fill is grid-stride: a grid that grows with the bin count, at most 1024
   const int64_t nf0 = (nkeys + 4 * B - 1) / (4 * B);
   const uint32_t nf = (uint32_t)(nf0 < 1024 ? nf0 : 1024);
-  launch<FillCond>(FillCond::Args{a, a.bin_fill, nkeys}, nf, s);
+  launch<FillCond>(FillCond::Args{a, a.bin_fill, nkeys, reset}, nf, s);
   launch<BinKeys>(a, nb, s);
   scan_i32(a.bin_fill, a.bin_start, nkeys, scan_tmp, s, a.cond);
   launch<BinScatter>(a, nb, s);
   launch<BinSort>(BinSort::Args{a, nkeys}, (uint32_t)((nkeys + B - 1) / B), s);
   launch<BinGather>(BinGather::Args{a, g}, nb, s);
-  launch<OrderFlags>(OrderFlags::Args{a, (const uint8_t *)g.cato}, nb, s);
   scan_i32(a.key, a.perm, a.n, scan_tmp, s, a.cond);
   launch<OrderScatter>(a, nb, s);
 }

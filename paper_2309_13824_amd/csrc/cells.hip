@@ -1393,7 +1393,7 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
         gst(a.deg, k, w);
       }
       if constexpr (MODE == MODE_CVD) {
-        if (defer && n >= CQ_STRIDE) {  // cannot happen: only FP32 lanes (n <= 12) defer
+        if (defer && n >= CQ_STRIDE) {  // cannot happen: only fast-kernel lanes (n < CQ_STRIDE) defer
           atomicOr(&a.counters[CNT_ERR], ERR_POLY_CAP);
           defer = false;
           xf = px;
@@ -1649,7 +1649,7 @@ template <class G, int MODE, int VMAX, int B> struct CellsExact {
 // ------------------------------------------------------------ launchers --
 constexpr int FAST_BLOCK = 128;
 #ifndef TRIME_FAST_VMAX
-#define TRIME_FAST_VMAX 12
+#define TRIME_FAST_VMAX 11
 #endif
 constexpr int FAST_VMAX = TRIME_FAST_VMAX;  // polygon capacity of the fast kernel
 constexpr int REPLAY_BLOCK = 64;

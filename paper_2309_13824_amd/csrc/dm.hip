@@ -402,45 +402,8 @@ struct StatsReset {
   TRIME_D static void run(const Args &A, Blk);
 };
 TRIME_D void StatsReset::run(const Args &A, Blk) {
-  const KArgs &a = A.a;
-  const int full = A.full;
-  if (cond_off(a)) return;
-  trime_stats *S = a.stats;
-  int t = threadIdx.x;
-  if (t < 40) S->hist_beta[t] = 0;
-  if (t == 0) {
-    S->sum_sqrt_alpha = 0;
-    S->sum_sqrt_beta = 0;
-    S->sum_q = 0;
-    S->max_alpha = 0;
-    S->nq = 0;
-    S->ntri = 0;
-    S->nvalid = 0;
-    S->moved = 0;
-    if (full) {
-      S->fp64_replays = 0;
-      S->exact_points = 0;
-      S->exact_calls = 0;
-      S->sos_calls = 0;
-      S->overflow_points = 0;
-      S->newton_fail = 0;
-      S->trace_fail = 0;
-      S->level_cap_hits = 0;
-      S->empty_cells = 0;
-      S->triangulations = 0;
-      S->iterations = 0;
-      S->retri_flag = 1;
-      S->error = 0;
-      S->sum_l2 = 0;
-      S->sum_mu2 = 0;
-      S->fac_mu = 0;
-      S->work_candidates = 0;
-      S->work_margins = 0;
-      S->work_cuts = 0;
-      S->work_leaves = 0;
-    }
-  }
-  if (t < (full ? CNT_NCOUNTERS : CNT_REASON)) a.counters[t] = 0;
+  if (cond_off(A.a)) return;
+  stats_reset(A.a, A.full, threadIdx.x);
 }
 
 void launch_stats_reset(const KArgs &a, int full, hipStream_t s) {

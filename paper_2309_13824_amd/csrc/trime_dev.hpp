@@ -92,6 +92,47 @@ enum { ERR_TRI_CAP = 1, ERR_DEG_CAP = 2, ERR_POLY_CAP = 4, ERR_EXACT_CAP = 8, ER
 enum { WHY_PRED = 1, WHY_VERTEX = 2, WHY_POLY = 3, WHY_AND = 4, WHY_LEVEL = 5, WHY_TREAT = 6,
        WHY_BOX = 7, WHY_HEAVY = 8, WHY_PREC = 9 };
 
+// Clears the quality part of the stats and the per-pass counters, and with
+// full set every run statistic and counter; thread t of one block (at least
+// 64 threads) takes its share.
+TRIME_D void stats_reset(const KArgs &a, int full, int t) {
+  trime_stats *S = a.stats;
+  if (t < 40) S->hist_beta[t] = 0;
+  if (t == 0) {
+    S->sum_sqrt_alpha = 0;
+    S->sum_sqrt_beta = 0;
+    S->sum_q = 0;
+    S->max_alpha = 0;
+    S->nq = 0;
+    S->ntri = 0;
+    S->nvalid = 0;
+    S->moved = 0;
+    if (full) {
+      S->fp64_replays = 0;
+      S->exact_points = 0;
+      S->exact_calls = 0;
+      S->sos_calls = 0;
+      S->overflow_points = 0;
+      S->newton_fail = 0;
+      S->trace_fail = 0;
+      S->level_cap_hits = 0;
+      S->empty_cells = 0;
+      S->triangulations = 0;
+      S->iterations = 0;
+      S->retri_flag = 1;
+      S->error = 0;
+      S->sum_l2 = 0;
+      S->sum_mu2 = 0;
+      S->fac_mu = 0;
+      S->work_candidates = 0;
+      S->work_margins = 0;
+      S->work_cuts = 0;
+      S->work_leaves = 0;
+    }
+  }
+  if (t < (full ? CNT_NCOUNTERS : CNT_REASON)) a.counters[t] = 0;
+}
+
 // ---------------------------------------------------------------- grid ----
 
 template <class G> TRIME_D double gval(const void *p, int64_t k) {
