@@ -36,8 +36,10 @@ struct Buckets {
 
 // A segment loop with its segments bucketed by the cells their boxes meet:
 // the nearest segment (ties to the lower index) by rings of cells outward,
-// settled once nearer than every cell not yet visited; points off the grid
-// search every segment.  Either way the same segment as a brute-force scan.
+// settled once nearer than every cell not yet visited.  Points off the grid,
+// and points so far from the loop that the rings would hold many more cells
+// than the loop has segments, search every segment instead.  Either way the
+// same segment as a brute-force scan.
 struct LoopIndex {
   const double *v = nullptr;
   int nv = 0;
@@ -69,6 +71,7 @@ struct LoopIndex {
     const int ci = B.cx(x), cj = B.cy(y);
     const int rmax = std::max(std::max(ci, B.nx - 1 - ci), std::max(cj, B.ny - 1 - cj));
     for (int r = 0; r <= rmax; r++) {
+      if ((int64_t)(2 * r + 1) * (2 * r + 1) > 2 * (int64_t)nv) return segments_sdf_brute(v, nv, x, y);
       for (int j = cj - r; j <= cj + r; j++) {
         if (j < 0 || j >= B.ny) continue;
         const bool edge_row = j == cj - r || j == cj + r;
