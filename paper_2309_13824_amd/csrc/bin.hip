@@ -224,40 +224,18 @@ struct BinScatter {
   }
 };
 
-// One thread per bin: order its entries by their previous slot (insertion
-// sort), so the new slot order is (key, previous slot): deterministic,
-// whatever order the atomics took.
-struct BinSort {
-  struct Args {
-    KArgs a;
-    int64_t nkeys;
-  };
-  static constexpr int BLOCK = 256;
-  TRIME_D static void run(const Args &A, Blk blk) {
-    const KArgs &a = A.a;
-    int64_t b = (int64_t)blk.id * BLOCK + threadIdx.x;
-    if (b >= A.nkeys || cond_off(a)) return;
-    int s0 = a.bin_start[b], s1 = a.bin_start[b + 1];
-    for (int s = s0 + 1; s < s1; s++) {
-      int v = a.perm[s];
-      int t = s;
-      while (t > s0 && a.perm[t - 1] > v) {
-        a.perm[t] = a.perm[t - 1];
-        t--;
-      }
-      a.perm[t] = v;
-    }
-  }
-};
-
-// Gather every per-point array into the new slot order (writes the other
-// buffer set); the positions of the last triangulation become the current
-// ones and the octagon span S is recomputed from the point's cell.  The
-// flag of the processing order (1 on the boundary) goes to key[].  A
-// conditional binning without work copies every array in place order
-// instead (the buffer sets still swap), keeping the last-triangulation
-// positions and spans, and leaves the processing order as it was.
-struct BinGather {
+// The new slot of every point, and its arrays written there (the other
+// buffer set).  Slots are ordered by (bin key, previous slot): a point's
+// place in its bin is the number of the bin's points with a smaller
+// previous slot, which is deterministic whatever order the atomics of the
+// ranks took.  The positions of the last triangulation become the current
+// ones, the octagon span S is recomputed from the point's cell, and the
+// flag of the processing order (1 on the boundary) goes to rank[] at the
+// new slot.  A conditional binning without work copies every array in
+// place order instead (the buffer sets still swap), keeping the
+// last-triangulation positions and spans, and leaves the processing order
+// as it was.
+struct BinPlace {
   struct Args {
     KArgs a;
     GatherArgs g;
@@ -265,24 +243,27 @@ struct BinGather {
   static constexpr int BLOCK = 256;
   TRIME_D static void run(const Args &A, Blk blk);
 };
-TRIME_D void BinGather::run(const Args &A, Blk blk) {
+TRIME_D void BinPlace::run(const Args &A, Blk blk) {
   const KArgs &a = A.a;
   const GatherArgs &g = A.g;
-  int64_t s = (int64_t)blk.id * BLOCK + threadIdx.x;
-  if (s >= a.n) return;
+  const int64_t k = (int64_t)blk.id * BLOCK + threadIdx.x;
+  if (k >= a.n) return;
   if (cond_off(a)) {
-    g.xo[s] = g.x[s];
-    g.yo[s] = g.y[s];
-    g.dprevo[s] = g.dprev[s];
-    g.cato[s] = g.cat[s];
-    g.ido[s] = g.id[s];
-    g.xlo[s] = g.xl[s];
-    g.ylo[s] = g.yl[s];
-    g.spano[s] = g.span[s];
+    g.xo[k] = g.x[k];
+    g.yo[k] = g.y[k];
+    g.dprevo[k] = g.dprev[k];
+    g.cato[k] = g.cat[k];
+    g.ido[k] = g.id[k];
+    g.xlo[k] = g.xl[k];
+    g.ylo[k] = g.yl[k];
+    g.spano[k] = g.span[k];
     return;
   }
-  int k = a.perm[s];
-  double x = g.x[k], y = g.y[k];
+  const int key = a.key[k];
+  const int s0 = a.bin_start[key], s1 = a.bin_start[key + 1];
+  int s = s0;
+  for (int t = s0; t < s1; t++) s += a.perm[t] < (int)k ? 1 : 0;
+  const double x = g.x[k], y = g.y[k];
   g.xo[s] = x;
   g.yo[s] = y;
   g.xlo[s] = x;
@@ -292,15 +273,16 @@ TRIME_D void BinGather::run(const Args &A, Blk blk) {
   g.cato[s] = c;
   g.ido[s] = g.id[k];
   g.spano[s] = span_at(a, x, y);
-  a.key[s] = c == TRIME_CAT_BOUNDARY ? 1 : 0;
+  a.rank[s] = c == TRIME_CAT_BOUNDARY ? 1 : 0;
 }
 
 // Processing order of the cell kernels: the slots of points on the boundary
 // first (their cells reach the octagon walls outside the domain, so they scan
 // the most bins), then all others, each group in slot order.  Heavy points
 // then share wavefronts and start first instead of holding back 64-point
-// wavefronts of light ones.  The flags come from the gather, their exclusive
-// scan from scan_i32.
+// wavefronts of light ones.  The flags (rank[], from BinPlace) are scanned
+// into perm[]; the slot of the w-th point in processing order goes to
+// order[w].
 struct OrderScatter {
   using Args = KArgs;
   static constexpr int BLOCK = 256;
@@ -310,8 +292,46 @@ struct OrderScatter {
     int before = a.perm[s];  // heavy slots before s
     int heavy = a.perm[a.n];
     if (s == 0) a.counters[CNT_HEAVY] = heavy;
-    int64_t w = a.key[s] ? before : heavy + (s - before);
+    int64_t w = a.rank[s] ? before : heavy + (s - before);
     a.order[w] = (int)s;
+  }
+};
+
+// With few scan tiles, the second scan pass and the order scatter in one:
+// each block sums the tile totals before it and all of them (the number of
+// heavy slots), adds the first to the tile's own exclusive scan and places
+// its slots.
+struct OrderAdd {
+  struct Args {
+    KArgs a;
+    ScanArgs s;
+  };
+  static constexpr int BLOCK = SCAN_BLOCK;
+  TRIME_D static void run(const Args &A, Blk blk) {
+    __shared__ int smem[SCAN_BLOCK / 64];
+    const KArgs &a = A.a;
+    const ScanArgs &S = A.s;
+    if (cond_off(a)) return;
+    int vb = 0, va = 0;
+    for (int64_t i = threadIdx.x; i < S.nt; i += SCAN_BLOCK) {
+      const int t = S.sums[i];
+      va += t;
+      vb += i < (int64_t)blk.id ? t : 0;
+    }
+    int add, heavy;
+    block_excl_scan(vb, smem, add);
+    block_excl_scan(va, smem, heavy);
+    if (blk.id == 0 && threadIdx.x == 0) a.counters[CNT_HEAVY] = heavy;
+    const int64_t base = (int64_t)blk.id * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; q++) {
+      const int64_t s = base + q;
+      if (s < S.n) {
+        const int before = S.out[s] + add;
+        const int64_t w = S.in[s] ? before : heavy + (s - before);
+        a.order[w] = (int)s;
+      }
+    }
   }
 };
 
@@ -326,10 +346,17 @@ void launch_bin(const KArgs &a, const GatherArgs &g, int64_t nkeys, int32_t *sca
   launch<BinKeys>(a, nb, s);
   scan_i32(a.bin_fill, a.bin_start, nkeys, scan_tmp, s, a.cond);
   launch<BinScatter>(a, nb, s);
-  launch<BinSort>(BinSort::Args{a, nkeys}, (uint32_t)((nkeys + B - 1) / B), s);
-  launch<BinGather>(BinGather::Args{a, g}, nb, s);
-  scan_i32(a.key, a.perm, a.n, scan_tmp, s, a.cond);
-  launch<OrderScatter>(a, nb, s);
+  launch<BinPlace>(BinPlace::Args{a, g}, nb, s);
+  // the processing order from the flags in rank[]
+  const int64_t nt = a.n > 0 ? (a.n + SCAN_TILE - 1) / SCAN_TILE : 1;
+  if (nt <= SCAN_FEW_TILES) {
+    const ScanArgs A{a.rank, a.perm, a.n, nt, scan_tmp, a.cond};
+    launch<ScanTiles>(A, (uint32_t)nt, s);
+    launch<OrderAdd>(OrderAdd::Args{a, A}, (uint32_t)nt, s);
+  } else {
+    scan_i32(a.rank, a.perm, a.n, scan_tmp, s, a.cond);
+    launch<OrderScatter>(a, nb, s);
+  }
 }
 
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
