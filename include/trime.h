@@ -242,9 +242,11 @@ typedef struct {
   int32_t *tri;            /* 3 * TRIME_TRI_PER_POINT * n, owner slot major  */
   uint8_t *tri_valid;      /* TRIME_TRI_PER_POINT * n                        */
   int32_t *tri_n;          /* n: owned triangles per slot                    */
-  int32_t *perm;           /* n: new slot -> old slot of the binning         */
-  int32_t *key;            /* n                                              */
-  int32_t *rank;           /* n                                              */
+  int32_t *perm;           /* n + 1: binning scratch (the points of each bin,
+                              then the scan of the processing-order flags)  */
+  int32_t *key;            /* n: bin key of each point (binning scratch)     */
+  int32_t *rank;           /* n: binning scratch (rank in the bin, then the
+                              processing-order flag of each slot)           */
   int32_t *order;          /* n: slots in the order the cell kernels take them
                               (points on the boundary first, they cost most) */
   int32_t *bin_start;      /* nkeys + 1                                      */
@@ -332,7 +334,8 @@ trime_status trime_export_adjacency(const trime_state *st, int32_t *d_deg, int32
 
 /* Sorts the points into Morton-ordered bins of the bin grid (the Voro++
    container blocks of the paper's example code): new slot order by
-   (bin key, id).  Permutes every per-point array into it, sets the positions
+   (bin key, previous slot); the first binning after a load orders each bin
+   by id.  Permutes every per-point array into it, sets the positions
    of the last triangulation to the current ones and the span S of every
    point (Sec. 4.1: S = fac_voro * h of the point's cell). */
 trime_status trime_bin_points(trime_state *st, void *stream);

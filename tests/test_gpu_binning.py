@@ -1,0 +1,92 @@
+"""Binning (Sec. 5, the container blocks of the paper's example code) through
+the C ABI: after trime_bin_points the slots are ordered by the Morton key of
+the point's bin, then by the previous slot; every per-point array moves with
+its point, the last-triangulation positions become the current ones, and the
+processing order of the cell kernels lists the boundary slots first, then
+the others, each group in slot order.  The expected order is computed here
+from the positions and the bin grid the state reports (the Z-order key from
+its bit definition), so these checks hold at any bin size, including bins
+crowded with hundreds of points."""
+import numpy as np
+import pytest
+
+from paper_2309_13824_amd import inputs as I
+from paper_2309_13824_amd import trime as T
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(m, ptr, count, np_dtype):
+    """count elements of a device array inside the state's workspace."""
+    import torch
+    torch.cuda.synchronize()
+    size = np.dtype(np_dtype).itemsize
+    off = ptr - m.ws.data_ptr()
+    assert 0 <= off and off + count * size <= m.ws.numel()
+    return m.ws[off:off + count * size].cpu().numpy().view(np_dtype).copy()
+
+
+def _slots(m):
+    st, n = m.state, m.state.n
+    P, O = st.pos[st.cur_pos], st.ord[st.cur_ord]
+    return {"x": _dev(m, P.x, n, np.float64), "y": _dev(m, P.y, n, np.float64),
+            "dprev": _dev(m, P.dprev, n, np.float64), "cat": _dev(m, P.cat, n, np.uint8),
+            "id": _dev(m, O.id, n, np.int32), "xl": _dev(m, O.xl, n, np.float64),
+            "yl": _dev(m, O.yl, n, np.float64)}
+
+
+def _zorder(bx, by):
+    """Z-order key: bit b of bx at bit 2b, bit b of by at bit 2b + 1."""
+    key = np.zeros(bx.shape, np.int64)
+    for b in range(16):
+        key |= ((bx >> b) & 1) << (2 * b)
+        key |= ((by >> b) & 1) << (2 * b + 1)
+    return key
+
+
+def _keys(st, x, y):
+    inv = 1.0 / st.bw
+    bx = np.clip(np.floor((x - st.bx0) * inv), 0, st.nbx - 1).astype(np.int64)
+    by = np.clip(np.floor((y - st.by0) * inv), 0, st.nby - 1).astype(np.int64)
+    return _zorder(bx, by)
+
+
+def _check_binning(m, before):
+    st, n = m.state, m.state.n
+    keys = _keys(st, before["x"], before["y"])
+    perm = np.lexsort((np.arange(n), keys))  # new slot -> previous slot
+    after = _slots(m)
+    for f in ("x", "y", "dprev", "cat", "id"):
+        np.testing.assert_array_equal(after[f], before[f][perm], err_msg=f)
+    np.testing.assert_array_equal(after["xl"], after["x"])
+    np.testing.assert_array_equal(after["yl"], after["y"])
+    assert np.all(np.diff(keys[perm]) >= 0)
+    bnd = after["cat"] == T.CAT_BOUNDARY
+    want = np.concatenate([np.flatnonzero(bnd), np.flatnonzero(~bnd)]).astype(np.int32)
+    np.testing.assert_array_equal(_dev(m, st.order, n, np.int32), want)
+    return after
+
+
+@pytest.mark.parametrize("density", [0.0, 300.0])
+def test_binning_orders_slots_by_bin_then_previous_slot(density):
+    from paper_2309_13824_amd.mesher import Mesher
+    wl = I.holes20(n=30000, grid_n=256)
+    m = Mesher(wl, precision=T.FP64, bin_density=density)
+    m.load()
+    before = _slots(m)  # after a load, slot = id
+    np.testing.assert_array_equal(before["id"], np.arange(m.state.n, dtype=np.int32))
+    if density > 0:
+        counts = np.bincount(_keys(m.state, before["x"], before["y"]))
+        assert counts.max() >= 200, "the crowded case must put hundreds of points in a bin"
+    m.bin()
+    after = _check_binning(m, before)
+    assert np.any(after["cat"] == T.CAT_BOUNDARY) and np.any(after["cat"] != T.CAT_BOUNDARY)
+    if density > 0:
+        return  # the crowded bins are for the binning alone
+    # the points move (one CVD step, which bins first), then bin again from
+    # the slot order that step left
+    m.step_cvd(1)
+    before = _slots(m)
+    assert not np.array_equal(before["x"], after["x"])
+    m.bin()
+    _check_binning(m, before)
