@@ -168,6 +168,39 @@ def test_dm_one_step_matches_oracle(orc, T, prec, make):
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
+def test_cvd_step_with_deep_levels_matches_oracle(orc, T, prec):
+    """One CVD step with fac_end = 1e-5 and a previous movement d_prev of
+    1e-5 h, so the centroid levels run to the cap (Sec. 4.2 II).  In FP32
+    most level decisions then fall within their error bound, and far more
+    than 1,024 centroids are redone in FP64.  That takes the path with a
+    group of 8 lanes per point. The one-step case from the seeded start
+    redoes a handful and takes one wavefront per point. Positions within
+    the parity tolerance, categories equal."""
+    wl = I.holes20(n=20000, grid_n=512, iters=1)
+    og = orc.build_grid(wl)
+    m = mesher(wl, prec, grid=og, params=T.default_params(fac_end=1e-5))
+    dprev = 1e-5 * h_of(og, wl.x, wl.y)
+    st = m.state
+    off = st.pos[st.cur_pos].dprev - m.ws.data_ptr()  # after a load, slot = id
+    m.ws[off:off + 8 * wl.n].view(m.torch.float64).copy_(m.torch.from_numpy(dprev).to(m.ws.device))
+    m.step_cvd(1)
+    x, y, cat = m.points()
+    cat0 = orc.initial_categories(og, wl.x, wl.y)
+    xr, yr, cr, dr, lev, _ = orc.cvd_step(og, wl.x, wl.y, cat0, dprev, nthreads=8,
+                                          params=orc.default_params(fac_end=1e-5))
+    err = np.hypot(x - xr, y - yr) / h_of(og, xr, yr)
+    deferred = m.replay_reasons()["cvd_level"]
+    print("%d points, fac_end 1e-5, %s: %d centroids redone in FP64, levels %d-%d, max error %.3g h"
+          % (wl.n, "fp64" if prec == FP64 else "fp32", deferred, int(np.min(lev)), int(np.max(lev)), err.max()),
+          flush=True)
+    assert err.max() <= _tol(prec), err.max()
+    assert np.array_equal(cat, cr)
+    assert_no_error(m)
+    if prec == FP32:
+        assert deferred > 1024, deferred
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
 @pytest.mark.parametrize("make", [lambda: I.holes20(n=8000, grid_n=512, iters=1),
                                   lambda: I.annulus(n=6000, grid_n=256)])
 def test_cvd_one_step_matches_oracle(orc, T, prec, make):
@@ -179,6 +212,8 @@ def test_cvd_one_step_matches_oracle(orc, T, prec, make):
     cat0 = orc.initial_categories(og, wl.x, wl.y)
     xr, yr, cr, dr, lev, _ = orc.cvd_step(og, wl.x, wl.y, cat0, np.full(wl.n, -1.0), nthreads=8)
     err = np.hypot(x - xr, y - yr) / h_of(og, xr, yr)
+    print("%d points, %s: %d centroids redone in FP64" % (wl.n, "fp64" if prec == FP64 else "fp32",
+                                                          m.replay_reasons()["cvd_level"]), flush=True)
     assert err.max() <= _tol(prec), err.max()
     assert np.array_equal(cat, cr)
     assert_no_error(m)
