@@ -67,22 +67,29 @@ def _check_binning(m, before):
     return after
 
 
-@pytest.mark.parametrize("density", [0.0, 300.0])
-def test_binning_orders_slots_by_bin_then_previous_slot(density):
+@pytest.mark.parametrize("n,density", [(30000, 0.0), (30000, 300.0), (9000000, 1.0)],
+                         ids=["default", "crowded", "many_tiles"])
+def test_binning_orders_slots_by_bin_then_previous_slot(n, density):
+    """default: then a CVD step and a second binning; crowded: hundreds of
+    points per bin; many_tiles: more than 2,048 scan tiles of 4,096 for both
+    the bin keys and the processing order (the three-pass scan and the
+    separate order scatter)."""
     from paper_2309_13824_amd.mesher import Mesher
-    wl = I.holes20(n=30000, grid_n=256)
+    wl = I.holes20(n=n, grid_n=256)
     m = Mesher(wl, precision=T.FP64, bin_density=density)
     m.load()
     before = _slots(m)  # after a load, slot = id
     np.testing.assert_array_equal(before["id"], np.arange(m.state.n, dtype=np.int32))
-    if density > 0:
+    if density > 100:
         counts = np.bincount(_keys(m.state, before["x"], before["y"]))
         assert counts.max() >= 200, "the crowded case must put hundreds of points in a bin"
+    if n > 2048 * 4096:
+        assert m.state.nkeys > 2048 * 4096, m.state.nkeys
     m.bin()
     after = _check_binning(m, before)
     assert np.any(after["cat"] == T.CAT_BOUNDARY) and np.any(after["cat"] != T.CAT_BOUNDARY)
     if density > 0:
-        return  # the crowded bins are for the binning alone
+        return  # the crowded and large cases are for the binning alone
     # the points move (one CVD step, which bins first), then bin again from
     # the slot order that step left
     m.step_cvd(1)
