@@ -1507,6 +1507,22 @@ TRIME_D void push(const KArgs &a, int which, int64_t k, int why) {
   atomicAdd(&a.counters[CNT_REASON + why], 1);
 }
 
+#ifndef TRIME_XCD_RUN
+#define TRIME_XCD_RUN 8
+#endif
+// The part of the processing order a block takes.  Blocks are dispatched to
+// the 8 XCDs (each with its own L2) in turn; here each XCD takes runs of
+// TRIME_XCD_RUN consecutive blocks, the runs going round the XCDs, so that
+// neighbouring blocks, which read the same bins and positions, share an L2
+// while the work stays spread over the XCDs.  A bijection of [0, nb) (the
+// blocks past the last whole round keep their place).
+TRIME_D uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  constexpr uint32_t C = TRIME_XCD_RUN, G = 8u * TRIME_XCD_RUN;
+  if (C <= 1 || b >= nb - nb % G) return b;
+  const uint32_t x = b & 7u, j = b >> 3;
+  return (j / C) * G + x * C + (j % C);
+}
+
 // Fast kernel: one point per lane, slots in the processing order.  Points it
 // cannot finish (an undecided decision, a polygon beyond its capacity, the
 // grid box within reach) go to the FP64 replay queue.
@@ -1519,7 +1535,7 @@ template <class T, class G, int MODE, int VMAX, int B> struct Cells {
     __shared__ int hist[40];
     zero_hist<B>(hist);
     LaneStats st;
-    int64_t w = (int64_t)blk.id * B + threadIdx.x;
+    int64_t w = (int64_t)xcd_block(blk.id, blk.n) * B + threadIdx.x;
     if (w < a.n && TRIME_HEAVY_WAVE && w < gld(a.counters, (int64_t)CNT_HEAVY)) {
       // points on the boundary (first in the order) scan the most bins: one
       // wavefront per point loads their candidates 64 at a time
