@@ -55,7 +55,7 @@ BYTES_PER_POINT = 37 + 25 + 30 + 64
 # HBM traffic of one launch of the fused kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (first two CVD iterations, scaled by a 1 GiB copy: FETCH x 2.0,
 # WRITE x 1.0), valid for the kernel sources with this digest only.
-TRAFFIC = {"sha1": "21c118b3b8e17d4860fedc7801b989e3e376f3ce", "bytes_per_launch": 341264753.5}
+TRAFFIC = {"sha1": "05db16e10958f712c6a7a92bb2cd27bb3d4934d3", "bytes_per_launch": 341257508.3}
 # counted flops per point of the DistMesh force gather (edge forces over the
 # adjacency row, forward Euler, treatment checks)
 DM_FLOPS_PER_POINT = 150

@@ -1514,13 +1514,20 @@ TRIME_D void push(const KArgs &a, int which, int64_t k, int why) {
 // the 8 XCDs (each with its own L2) in turn; here each XCD takes runs of
 // TRIME_XCD_RUN consecutive blocks, the runs going round the XCDs, so that
 // neighbouring blocks, which read the same bins and positions, share an L2
-// while the work stays spread over the XCDs.  A bijection of [0, nb) (the
-// blocks past the last whole round keep their place).
-TRIME_D uint32_t xcd_block(uint32_t b, uint32_t nb) {
+// while the work stays spread over the XCDs.  b: the block within its shape,
+// p: its block in the launch (a batch puts shapes one after another), whose
+// residue mod 8 names the XCD.  A bijection of [0, nb): the groups of 8 runs
+// are counted from the launch's block 0, and blocks outside a whole group
+// keep their place.
+TRIME_D uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t p) {
   constexpr uint32_t C = TRIME_XCD_RUN, G = 8u * TRIME_XCD_RUN;
-  if (C <= 1 || b >= nb - nb % G) return b;
-  const uint32_t x = b & 7u, j = b >> 3;
-  return (j / C) * G + x * C + (j % C);
+  if (C <= 1) return b;
+  const uint32_t r = (p - b) % G;  // where the shape starts within a group
+  const uint32_t s = b + r;        // position counted from that group's start
+  const uint32_t g0 = s - s % G;
+  if (g0 < r || g0 + G > nb + r) return b;  // a group cut by the shape's ends
+  const uint32_t x = s & 7u, j = (s % G) >> 3;
+  return g0 + x * C + j - r;
 }
 
 // Fast kernel: one point per lane, slots in the processing order.  Points it
@@ -1535,7 +1542,7 @@ template <class T, class G, int MODE, int VMAX, int B> struct Cells {
     __shared__ int hist[40];
     zero_hist<B>(hist);
     LaneStats st;
-    int64_t w = (int64_t)xcd_block(blk.id, blk.n) * B + threadIdx.x;
+    int64_t w = (int64_t)xcd_block(blk.id, blk.n, blockIdx.x) * B + threadIdx.x;
     if (w < a.n && TRIME_HEAVY_WAVE && w < gld(a.counters, (int64_t)CNT_HEAVY)) {
       // points on the boundary (first in the order) scan the most bins: one
       // wavefront per point loads their candidates 64 at a time
