@@ -313,15 +313,12 @@ def test_euler_characteristic_with_hole(orc):
 def test_validity_tests_by_construction(orc):
     wl = I.disk()
     g = orc.build_grid(wl)
-    h = float(g.hcell[0])
     x = np.array([0.0, 0.05, 0.0, 1.2, 1.25, 1.2, 0.97, 0.999, 0.97], float)
     y = np.array([0.0, 0.0, 0.05, 0.0, 0.0, 0.05, -0.02, 0.0, 0.02], float)
     assert orc.triangle_valid(g, x, y, 0, 1, 2) == 1          # Test 1, inner cell
     assert orc.triangle_valid(g, x, y, 3, 4, 5) == 0          # Test 1, outer cell
     assert orc.triangle_valid(g, x, y, 6, 7, 8) == 1          # boundary cell, inside
-    # a sliver spanning across the outside: centroid inside, 1 midpoint inside
-    # is decided by Test 3 (|sdf(c_circ)| / R <= 0.4)
-    assert h > 0
+    # every branch of Tests 2 and 3: tests/test_oracle_validity.py
 
 
 # -------------------------------------------------------------- DistMesh --
