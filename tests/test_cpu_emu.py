@@ -1,0 +1,124 @@
+"""The library's kernels and host code run on the CPU (tests/cpu_emu: a
+stand-in HIP runtime whose block threads are fibers) under
+AddressSanitizer and UndefinedBehaviorSanitizer: whole CVD iterations with
+every pass and the hand-off between them (fast kernel -> FP64 replay and
+deferred-centroid queues -> exact stage), each iteration fed by the previous
+one's output, every buffer of the state in an allocation of its own and the
+queue counts checked against their capacities after every launch.  The
+positions are compared with the oracle's iterations."""
+import os
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2309_13824_amd import inputs as I
+from tests.cpu_emu import build as EB
+
+FP64, FP32 = 0, 1
+
+
+@pytest.fixture(scope="module")
+def exe():
+    return EB.build()
+
+
+def write_case(path, wl, og, prec, density, iters, method=1):
+    g = wl.grid
+    dt = np.float32 if g.dtype_bytes == 4 else np.float64
+    area = float(np.count_nonzero(og.cat)) * g.dx * g.dy  # bin sizing only, as the Mesher passes it
+    with open(path, "wb") as f:
+        f.write(struct.pack("<qiiddddiidii", wl.n, g.nx, g.ny, g.x0, g.y0, g.dx, g.dy, g.dtype_bytes, prec,
+                            density, iters, method))
+        f.write(np.ascontiguousarray(og.sdf, dt).tobytes())
+        f.write(np.ascontiguousarray(og.mu, dt).tobytes())
+        f.write(np.ascontiguousarray(og.cat, np.uint8).tobytes())
+        f.write(np.ascontiguousarray(og.hcell, np.float32).tobytes())
+        f.write(np.array([og.H, og.h_avg, area, 0.0], np.float64).tobytes())
+        f.write(np.ascontiguousarray(wl.x, np.float64).tobytes())
+        f.write(np.ascontiguousarray(wl.y, np.float64).tobytes())
+
+
+def run(exe, tmp_path, wl, og, prec, density, iters, timeout=1800):
+    from paper_2309_13824_amd import trime as T
+    cin, cout = str(tmp_path / "case.bin"), str(tmp_path / "out.bin")
+    write_case(cin, wl, og, prec, density, iters)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([exe, cin, cout], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True,
+                       timeout=timeout, env=env)
+    assert r.returncode == 0, r.stdout[-6000:]
+    print(r.stdout.strip().splitlines()[-1], flush=True)
+    n = wl.n
+    raw = open(cout, "rb").read()
+    its, off = [], 0
+    for _ in range(iters):
+        x = np.frombuffer(raw, np.float64, n, off)
+        y = np.frombuffer(raw, np.float64, n, off + 8 * n)
+        c = np.frombuffer(raw, np.uint8, n, off + 16 * n)
+        its.append((x, y, c))
+        off += 17 * n
+    st = T.Stats.from_buffer_copy(raw[off:off + C_sizeof(T.Stats)])
+    maxq = np.frombuffer(raw, np.int64, 3, off + C_sizeof(T.Stats))
+    return its, st, maxq
+
+
+def C_sizeof(t):
+    import ctypes
+    return ctypes.sizeof(t)
+
+
+def h_of(og, x, y):
+    fx = np.floor((x - og.x0) * (1.0 / og.dx)).astype(int)
+    fy = np.floor((y - og.y0) * (1.0 / og.dy)).astype(int)
+    return og.hcell[fy * (og.nx - 1) + fx].astype(np.float64)
+
+
+def oracle_iterations(orc, og, wl, iters):
+    x, y = wl.x.copy(), wl.y.copy()
+    cat = orc.initial_categories(og, x, y)
+    dprev = np.full(wl.n, -1.0)
+    out = []
+    for _ in range(iters):
+        x, y, cat, dprev, _, _ = orc.cvd_step(og, x, y, cat, dprev, nthreads=8)
+        out.append((x, y, cat))
+    return out
+
+
+def check(its, ref, og, prec):
+    tol = 1e-11 if prec == FP64 else 1e-5
+    for k, ((x, y, c), (xr, yr, cr)) in enumerate(zip(its, ref)):
+        err = np.hypot(x - xr, y - yr) / h_of(og, xr, yr)
+        assert err.max() <= tol * (k + 1), (k, err.max())
+        assert np.array_equal(c, cr), k
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_emulated_cvd_iterations(orc, exe, tmp_path, prec):
+    """Two CVD iterations of a small holes20 case at a grid whose box is
+    within reach of the boundary points' octagons (they take the exact
+    stage): no sanitizer report, queues within capacity, positions as the
+    oracle's."""
+    wl = I.holes20(n=1500, grid_n=128, iters=1)
+    og = orc.build_grid(wl)
+    its, st, maxq = run(exe, tmp_path, wl, og, prec, 3.3, 2)
+    assert st.error == 0
+    assert maxq[1] > 0  # points reached the exact stage (the box within reach)
+    check(its, oracle_iterations(orc, og, wl, 2), og, prec)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("density", [3.3, 1.5, 7.0])
+def test_emulated_bin_size_case(orc, exe, tmp_path, prec, density):
+    """The case of the bin-size independence test at full size: holes20 with
+    20,000 points on a 512^2 grid, three CVD iterations, at three bin
+    densities (points per bin)."""
+    wl = I.holes20(n=20000, grid_n=512, iters=1)
+    og = orc.build_grid(wl)
+    its, st, maxq = run(exe, tmp_path, wl, og, prec, density, 3)
+    print("queues: replay %d, exact %d, deferred %d" % tuple(maxq), flush=True)
+    assert st.error == 0
+    assert maxq[1] > 0
+    check(its, oracle_iterations(orc, og, wl, 3), og, prec)
