@@ -187,7 +187,11 @@ typedef struct {
   int32_t retri_flag;      /* re-triangulate before the next DistMesh step    */
   int32_t error;           /* nonzero: a capacity or internal error occurred  */
   double sum_l2, sum_mu2, fac_mu; /* Eq. 3 of the last DistMesh force step     */
-  /* mesh quality of the valid triangles (Eq. 10-11), last extraction */
+  /* mesh quality of the nq valid triangles of the last extraction or quality
+     pass (Eq. 10-11): sums of sqrt(alpha), sqrt(beta) and q = 1/alpha, with
+     alpha = R_circ / (2 r_in) and beta = l_max / l_min of each triangle.  The
+     device accumulates the sums exactly in quality_acc; trime_stats_read
+     fills these four and the finished values below from it. */
   double sum_sqrt_alpha, sum_sqrt_beta, sum_q, max_alpha;
   int64_t nq;
   int64_t hist_beta[40];   /* beta in [1, 3), 40 bins, last bin open           */
@@ -196,6 +200,18 @@ typedef struct {
      evaluated, polygon cuts, quadrature leaf triangles (Sec. 4.2 II) */
   int64_t work_candidates, work_margins, work_cuts, work_leaves;
   trime_adapt_ctl adapt;   /* the last adaptive run                           */
+  /* Eq. 11 with p = 1/2 and the quality criteria of Sec. 6, finished from the
+     exact sums (0 when nq = 0): M_1/2(alpha) = (sum_sqrt_alpha / nq)^2,
+     M_1/2(beta) = (sum_sqrt_beta / nq)^2, mean q = sum_q / nq, min q =
+     1 / max_alpha.  The adaptive runs take their decisions on the same values,
+     computed the same way on the device. */
+  double half_mean_alpha, half_mean_beta, mean_q, min_q;
+  /* internal: 128-bit fixed-point sums (units of 2^-52; low word first) of
+     sqrt(alpha), sqrt(beta) and q.  Each contribution (a block's or a
+     replayed point's partial sum, in a fixed order) is truncated to the unit,
+     and integer addition does not depend on the order in which the blocks
+     finish, so identical inputs give bit-identical statistics. */
+  uint64_t quality_acc[6];
 } trime_stats;
 
 /* Per-point arrays of a state are kept in "slot" order: the order of the
@@ -268,10 +284,15 @@ typedef struct {
   /* -- point addition (Sec. 3.6) -- */
   int64_t n_cap;           /* caller: capacity for added points (0 -> n); the
                               workspace is laid out for n_cap points       */
-  double h_scale;          /* every h of the grid times this (0 -> 1): a grid
-                              built for N points used with n points takes
-                              sqrt(N / n) (Sec. 3.7)                        */
+  double h_scale;          /* set by trime_state_bind and trime_add_points:
+                              every h of the grid is read times
+                              sqrt(n_grid / n) (Sec. 3.7: the desired edge
+                              length of N points over the same region goes
+                              as 1/sqrt(N))                                  */
   int64_t nkeys_cap;       /* bin keys the workspace holds (set by bind)    */
+  int64_t n_grid;          /* caller: the point count the grid was built for
+                              (n_total of trime_sdf_grid_build; 0 -> n, set
+                              by bind)                                      */
 } trime_state;
 
 /* A fixed hybrid schedule: segments (method, iterations) run in order. */
@@ -420,30 +441,29 @@ trime_status trime_step_adaptive(trime_state *st, const trime_adaptive *cfg, voi
    sqrt(|ab|^2 |bc|^2 |ca|^2) / (2 |(b - a) x (c - a)|), the centroid
    ((x_a + x_b) + x_c) / 3, in FP64.  The new points take the ids n, n + 1,
    ... in the order of (owner id, second id) of their triangles, d_prev = -1,
-   and the category (Sec. 3.5) and octagon span of their position under
-   h_scale_after, which becomes the state's h_scale (0: h_scale unchanged).
-   Afterwards the adjacency is stale and the next DistMesh iteration of an
-   adaptive run re-triangulates (stats->retri_flag = 1, have_prev = 0).  The
-   call synchronises the stream.  Errors: TRIME_EINVAL for n_add < 0,
-   n + n_add > n_cap, more points than valid triangles or a negative or
-   non-finite h_scale_after; TRIME_ECAPACITY when the valid triangles
-   outnumber the key buffer (max_deg n_cap / 4 keys, 4 n_cap for max_deg 16). */
-trime_status trime_add_points(trime_state *st, int64_t n_add, double h_scale_after, void *stream);
+   and the category (Sec. 3.5) and octagon span of their position under the
+   new h_scale = sqrt(n_grid / (n + n_add)) (Sec. 3.7), which the state
+   takes.  Afterwards the adjacency is stale and the next DistMesh iteration
+   of an adaptive run re-triangulates (stats->retri_flag = 1, have_prev = 0).
+   The call synchronises the stream.  Errors: TRIME_EINVAL for n_add < 0,
+   n + n_add > n_cap or more points than valid triangles; TRIME_ECAPACITY
+   when the valid triangles outnumber the key buffer (max_deg n_cap / 4
+   keys, 4 n_cap for max_deg 16). */
+trime_status trime_add_points(trime_state *st, int64_t n_add, void *stream);
 
 /* An adaptive run with point addition (Sec. 3.6): the state starts with its
-   current n points (fac_init N_total of them in the paper), loaded with
-   h_scale = sqrt(n_total / n) (the grid is built for n_total points), and
+   current n points (fac_init N_total of them in the paper; the grid is built
+   for N_total = n_grid points, so h is read times sqrt(n_grid / n)) and
    grows to n_total <= n_cap.  While n < n_total an iteration whose relative
    changes of M_1/2(alpha) and M_1/2(beta) are both below t_add adds
    min(floor(fac_add n), n_total - n) points with trime_add_points, h_scale
-   becoming sqrt(n_total / n) for the new n; the switch and the termination
+   becoming sqrt(n_grid / n) for the new n; the switch and the termination
    tests of trime_step_adaptive apply once all points are in.  The run reads
    the control block after every iteration (synchronising; not for graph
    capture) and returns once the run has stopped or after max_iter
    iterations; read the outcome with trime_stats_read.  Errors: as
    trime_step_adaptive and trime_add_points, and TRIME_EINVAL for n_total
-   outside [n, n_cap], a negative t_add, fac_add <= 0 or an h_scale other
-   than sqrt(n_total / n). */
+   outside [n, n_cap], a negative t_add or fac_add <= 0. */
 typedef struct {
   trime_adaptive base;  /* mode, max_iter and the Table 8 thresholds      */
   int64_t n_total;      /* N_total                                        */
@@ -494,7 +514,9 @@ trime_status trime_auto_sizing(const trime_geometry *geo, const trime_sizing *sz
 /* Mesh quality of the state's valid triangles (Eq. 10-11) into stats. */
 trime_status trime_quality(trime_state *st, void *stream);
 
-/* Copies the device stats to host memory (synchronises the stream). */
+/* Copies the device stats to host memory (synchronises the stream) and
+   finishes the quality fields there: the sums from quality_acc, then
+   M_1/2(alpha), M_1/2(beta), mean q and min q (Eq. 10-11). */
 trime_status trime_stats_read(const trime_state *st, trime_stats *host, void *stream);
 trime_status trime_stats_check(const trime_stats *host);
 
@@ -545,10 +567,16 @@ trime_status trime_batch_run(trime_batch *b, int32_t n_iter, void *stream);
 trime_status trime_batch_destroy(trime_batch *b);
 
 
-/* ---- autotuner (tuning only: no result depends on it) ----------------------
-   The bin size sets how many neighbours a cell scans and how far; the cells
-   do not depend on it (every cut decision is exact and the centroid sums run
-   in a canonical order).  trime_autotune times n_iter CVD iterations (Alg. 2)
+/* ---- autotuner (tuning only) ------------------------------------------------
+   The bin size sets how many neighbours a cell scans and how far, and the
+   slot order.  The combinatorial results do not depend on it: every cut
+   decision is exact, so cells, triangles, validity and adjacency are the
+   same for every bin size.  Floating-point results depend on it only through
+   rounding: a cell's vertex list starts at a vertex that follows the order
+   in which the neighbours were clipped, which sets the order of the centroid
+   and quality sums, so positions after a CVD step and the quality sums agree
+   across bin sizes to rounding (within the precision mode's tolerance), not
+   bit for bit.  trime_autotune times n_iter CVD iterations (Alg. 2)
    from the positions (d_x, d_y) for every candidate density (points per bin)
    and leaves the state bound to d_ws with the fastest one and loaded with
    (d_x, d_y).  d_ws must hold trime_autotune_workspace_bytes() bytes (the

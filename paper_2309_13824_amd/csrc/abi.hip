@@ -146,10 +146,10 @@ trime_status trime_auto_sizing(const trime_geometry *geo, const trime_sizing *sz
   return check_hip("trime_auto_sizing");
 }
 
-trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing *sz,
-                                  const trime_grid *grid, int64_t n_total, void *d_sdf, void *d_mu,
-                                  uint8_t *d_cat, float *d_hcell, trime_grid_scalars *d_scal,
-                                  void *stream) {
+// The argument checks of both grid builds.
+static trime_status grid_build_ok(const trime_geometry *geo, const trime_sizing *sz, const trime_grid *grid,
+                                  int64_t n_total, void *d_sdf, void *d_mu, uint8_t *d_cat, float *d_hcell,
+                                  trime_grid_scalars *d_scal) {
   if (!geo || !sz || !grid_ok(grid) || n_total <= 0 || !d_sdf || !d_mu || !d_cat || !d_hcell || !d_scal)
     return fail(TRIME_EINVAL, "trime_sdf_grid_build: null or invalid argument");
   if (geo->nprims <= 0 || !geo->prims || geo->prims[0].op != TRIME_OP_INIT)
@@ -179,6 +179,15 @@ trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing 
       if (sz->holes[k] < 0 || sz->holes[k] >= geo->nprims)
         return fail(TRIME_EINVAL, "trime_sdf_grid_build: hole index out of range");
   }
+  return TRIME_OK;
+}
+
+trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing *sz,
+                                  const trime_grid *grid, int64_t n_total, void *d_sdf, void *d_mu,
+                                  uint8_t *d_cat, float *d_hcell, trime_grid_scalars *d_scal,
+                                  void *stream) {
+  trime_status e0 = grid_build_ok(geo, sz, grid, n_total, d_sdf, d_mu, d_cat, d_hcell, d_scal);
+  if (e0) return e0;
   hipStream_t s = (hipStream_t)stream;
   // one temporary device buffer: prims | poly | cent | holes | partials |
   // segment candidate trees (their lists are allocated while they are built)
@@ -383,11 +392,18 @@ static void layout(trime_state *st, Layout &L) {
   st->stats = L.take<trime_stats>(1);
 }
 
+// h of the grid is read times sqrt(n_grid / n) with n points in the mesh
+// (Sec. 3.7: the desired edge length of N points goes as 1/sqrt(N)).
+static double h_scale_of(const trime_state *st, int64_t n) {
+  const int64_t ng = st->n_grid > 0 ? st->n_grid : n;
+  return ng == n ? 1.0 : sqrt((double)ng / (double)n);
+}
+
 static trime_status state_ok(const trime_state *st) {
   if (!st || st->n <= 0 || st->n > (int64_t)1 << 30) return fail(TRIME_EINVAL, "state: bad n");
   if (st->n_cap != 0 && (st->n_cap < st->n || st->n_cap > (int64_t)1 << 30))
     return fail(TRIME_EINVAL, "state: n_cap must be 0 or in [n, 2^30]");
-  if (!(st->h_scale >= 0.0) || !isfinite(st->h_scale)) return fail(TRIME_EINVAL, "state: bad h_scale");
+  if (st->n_grid < 0 || st->n_grid > (int64_t)1 << 40) return fail(TRIME_EINVAL, "state: bad n_grid");
   if (st->precision != TRIME_FP64 && st->precision != TRIME_FP32)
     return fail(TRIME_EINVAL, "state: bad precision");
   if (!grid_ok(&st->grid)) return fail(TRIME_EINVAL, "state: bad grid");
@@ -433,6 +449,8 @@ trime_status trime_state_bind(trime_state *st, void *d_ws, size_t bytes, void *s
   if (st->max_deg <= 0) st->max_deg = 16;
   st->cur_pos = 0;
   st->cur_ord = 0;
+  if (st->n_grid == 0) st->n_grid = st->n;
+  st->h_scale = h_scale_of(st, st->n);
   return TRIME_OK;
 }
 
@@ -723,7 +741,7 @@ trime_status trime_step_adaptive(trime_state *st, const trime_adaptive *cfg, voi
 // state; the selection keys overwrite the adjacency (rebuilt by the next
 // triangulation, which an addition always forces).
 
-static trime_status add_points(trime_state *st, int64_t n_add, double h_after, int growing, hipStream_t s) {
+static trime_status add_points(trime_state *st, int64_t n_add, int growing, hipStream_t s) {
   const int64_t n = st->n;
   const int64_t cap = st->n_cap > n ? st->n_cap : n;
   if (n_add < 0 || n + n_add > cap) return fail(TRIME_EINVAL, "trime_add_points: n + n_add exceeds n_cap");
@@ -744,7 +762,7 @@ static trime_status add_points(trime_state *st, int64_t n_add, double h_after, i
     launch_grow_select(a, off, st->adj, nk, sel, n_add, s);
     launch_grow_mark(a, sel, cnt_id, s);
     scan_i32(cnt_id, base, n, st->scan_tmp, s);
-    if (h_after > 0) st->h_scale = h_after;
+    st->h_scale = h_scale_of(st, n + n_add);
     KArgs b = make_args(st);  // new points: categories and spans at the new h
     const trime_posbuf &P = st->pos[st->cur_pos];
     const trime_ordbuf &O = st->ord[st->cur_ord];
@@ -761,18 +779,16 @@ static trime_status add_points(trime_state *st, int64_t n_add, double h_after, i
   return check_hip("trime_add_points");
 }
 
-trime_status trime_add_points(trime_state *st, int64_t n_add, double h_scale_after, void *stream) {
+trime_status trime_add_points(trime_state *st, int64_t n_add, void *stream) {
   trime_status e = bound_ok(st);
   if (e) return e;
-  if (!(h_scale_after >= 0.0) || !isfinite(h_scale_after))
-    return fail(TRIME_EINVAL, "trime_add_points: bad h_scale_after");
   if (n_add < 0 || n_add > (st->n_cap > st->n ? st->n_cap : st->n) - st->n)
     return fail(TRIME_EINVAL, "trime_add_points: n_add must be in [0, n_cap - n]");
   hipStream_t s = (hipStream_t)stream;
   trime_adapt_ctl c;
   TRY_HIP(hipMemcpyAsync(&c, &st->stats->adapt, sizeof c, hipMemcpyDeviceToHost, s), "read control block");
   TRY_HIP(hipStreamSynchronize(s), "read control block (sync)");
-  return add_points(st, n_add, h_scale_after, c.growing, s);
+  return add_points(st, n_add, c.growing, s);
 }
 
 trime_status trime_run_growing(trime_state *st, const trime_growing *cfg, void *stream) {
@@ -786,10 +802,6 @@ trime_status trime_run_growing(trime_state *st, const trime_growing *cfg, void *
     return fail(TRIME_EINVAL, "trime_run_growing: n_total must be in [n, n_cap]");
   if (!(cfg->t_add >= 0.0) || !(cfg->fac_add > 0.0) || !isfinite(cfg->fac_add))
     return fail(TRIME_EINVAL, "trime_run_growing: t_add must be >= 0 and fac_add > 0");
-  const double h0 = sqrt((double)cfg->n_total / (double)st->n);
-  const double hs = st->h_scale > 0 ? st->h_scale : 1.0;
-  if (fabs(hs - h0) > 1e-15 * h0)
-    return fail(TRIME_EINVAL, "trime_run_growing: the state's h_scale must be sqrt(n_total / n)");
   hipStream_t s = (hipStream_t)stream;
   const trime_adaptive *base = &cfg->base;
   launch_adapt_init(make_args(st), base->mode == TRIME_ADAPT_CVD ? TRIME_METHOD_CVD : TRIME_METHOD_DM, s);
@@ -807,7 +819,7 @@ trime_status trime_run_growing(trime_state *st, const trime_growing *cfg, void *
       if (n_add > cfg->n_total - st->n) n_add = cfg->n_total - st->n;
       if (n_add <= 0) continue;
       const int64_t n_new = st->n + n_add;
-      e = add_points(st, n_add, sqrt((double)cfg->n_total / (double)n_new), n_new < cfg->n_total, s);
+      e = add_points(st, n_add, n_new < cfg->n_total, s);
       if (e) return e;
     }
   }
@@ -853,6 +865,7 @@ trime_status trime_stats_read(const trime_state *st, trime_stats *host, void *st
   TRY_HIP(hipMemcpyAsync(host, st->stats, sizeof *host, hipMemcpyDeviceToHost, (hipStream_t)stream),
           "trime_stats_read");
   TRY_HIP(hipStreamSynchronize((hipStream_t)stream), "trime_stats_read (sync)");
+  quality_finish(host);
   return TRIME_OK;
 }
 

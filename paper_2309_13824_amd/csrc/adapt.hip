@@ -85,14 +85,14 @@ __global__ __launch_bounds__(256) void k_adapt_copy(KArgs a) {
 __global__ void k_adapt_post(KArgs a, int hybrid, double t_quality, double t_amax, double t_switch, double t_add) {
   trime_adapt_ctl *c = &a.stats->adapt;
   if (c->stopped) return;
-  const trime_stats *S = a.stats;
+  trime_stats *S = a.stats;
   const int it = c->iters++;
   const bool have = S->nq > 0;
+  quality_finish(S);  // the values trime_stats_read reports
   double cur[3] = {0.0, 0.0, 0.0};
   if (have) {
-    double ma = S->sum_sqrt_alpha / (double)S->nq, mb = S->sum_sqrt_beta / (double)S->nq;
-    cur[0] = ma * ma;
-    cur[1] = mb * mb;
+    cur[0] = S->half_mean_alpha;
+    cur[1] = S->half_mean_beta;
     cur[2] = S->max_alpha;
   }
   bool rel_ok = have && c->have_prev && c->prev[0] > 0.0 && c->prev[1] > 0.0 && c->prev[2] > 0.0;

@@ -1433,6 +1433,25 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   }
 };
 
+// The quality sums of the point a replay kernel just finished, added on
+// their own: which block replays which point follows the queue order, which
+// varies from run to run, so a block's sum over its points would too.  One
+// point per lane (g = 1) or per wavefront (g = 64: its triangles are spread
+// over the lanes and summed in a fixed shuffle order, lane 0 adds them).
+template <int g> TRIME_D void flush_point_quality(const KArgs &a, LaneStats &st) {
+  double sa = st.sa, sb = st.sb, sq = st.sq, am = st.amax;
+  if constexpr (g == 64) {
+    for (int off = 32; off > 0; off >>= 1) {
+      sa += __shfl_down(sa, off);
+      sb += __shfl_down(sb, off);
+      sq += __shfl_down(sq, off);
+      am = fmax(am, __shfl_down(am, off));
+    }
+  }
+  if (g == 1 || (threadIdx.x & 63) == 0) quality_add(a.stats, sa, sb, sq, am);
+  st.sa = st.sb = st.sq = st.amax = 0;
+}
+
 // Block reduction of the lane statistics into the device stats.
 template <int BLOCK> TRIME_D void flush_stats(const KArgs &a, LaneStats &st, int *hist) {
   __shared__ double rs[4][BLOCK / 64];
@@ -1469,10 +1488,7 @@ template <int BLOCK> TRIME_D void flush_stats(const KArgs &a, LaneStats &st, int
     trime_stats *S = a.stats;
     typedef unsigned long long ull;
     if (ri[0][0]) {
-      atomicAdd(&S->sum_sqrt_alpha, rs[0][0]);
-      atomicAdd(&S->sum_sqrt_beta, rs[1][0]);
-      atomicAdd(&S->sum_q, rs[2][0]);
-      atomicMax((ull *)&S->max_alpha, (ull)__double_as_longlong(rs[3][0]));
+      quality_add(S, rs[0][0], rs[1][0], rs[2][0], rs[3][0]);
       atomicAdd((ull *)&S->nq, (ull)ri[0][0]);
     }
     if (ri[1][0]) atomicAdd((ull *)&S->ntri, (ull)ri[1][0]);
@@ -1605,6 +1621,7 @@ template <class G, int MODE, int VMAX> struct CellsPost {
         }
         if (ok) ok = L.finish_wave(lane, st, hist);
         if (!ok && lane == 0) push(a, 2, k, L.why);
+        flush_point_quality<64>(a, st);
         __syncthreads();
       }
     } else if constexpr (MODE == MODE_CVD) {
@@ -1651,7 +1668,9 @@ template <class G, int MODE, int VMAX, int B> struct CellsExact {
     for (int64_t w = (int64_t)blk.id * B + threadIdx.x; w < nq; w += (int64_t)blk.n * B) {
       int64_t k = gld(a.queue2, w);
       Lane<double, G, MODE, true, VMAX, B> L(a, P, threadIdx.x, k);
-      if (!L.run(st, hist)) {  // beyond the polygon capacity, or off the grid: keep the point
+      const bool ok = L.run(st, hist);
+      flush_point_quality<1>(a, st);
+      if (!ok) {  // beyond the polygon capacity, or off the grid: keep the point
         st.overflow++;
         atomicOr(&a.counters[CNT_ERR], ERR_POLY_CAP);
         if constexpr (MODE == MODE_CVD) {

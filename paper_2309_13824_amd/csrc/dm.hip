@@ -380,11 +380,8 @@ __global__ __launch_bounds__(256) void k_quality(KArgs a) {
     amax = fmax(amax, __shfl_down(amax, off));
     nq += __shfl_down(nq, off);
   }
-  if ((threadIdx.x & 63) == 0 && nq) {
-    atomicAdd(&a.stats->sum_sqrt_alpha, sa);
-    atomicAdd(&a.stats->sum_sqrt_beta, sb);
-    atomicAdd(&a.stats->sum_q, sq);
-    atomicMax((unsigned long long *)&a.stats->max_alpha, (unsigned long long)__double_as_longlong(amax));
+  if ((threadIdx.x & 63) == 0 && nq) {  // one wavefront's 64 slots, summed in a fixed order
+    quality_add(a.stats, sa, sb, sq, amax);
     atomicAdd((unsigned long long *)&a.stats->nq, (unsigned long long)nq);
   }
   __syncthreads();

@@ -92,6 +92,69 @@ enum { ERR_TRI_CAP = 1, ERR_DEG_CAP = 2, ERR_POLY_CAP = 4, ERR_EXACT_CAP = 8, ER
 enum { WHY_PRED = 1, WHY_VERTEX = 2, WHY_POLY = 3, WHY_AND = 4, WHY_LEVEL = 5, WHY_TREAT = 6,
        WHY_BOX = 7, WHY_HEAVY = 8, WHY_PREC = 9 };
 
+// ------------------------------------------------ exact quality sums ----
+// The quality sums (Eq. 10-11) are kept as 128-bit fixed-point integers in
+// units of 2^-52 (trime_stats.quality_acc, low word first).  A contribution
+// v >= 0 is truncated to the unit; the sum of truncated values is exact, so
+// it does not depend on the order in which blocks add them.  v = m 2^(e-1075)
+// with the 53-bit significand m, so v 2^52 = m 2^(e-1023).  Values of 2^60 and
+// more (or not finite) saturate at 2^60.
+TRIME_D void fx_add(uint64_t *acc, double v) {
+  if (!(v > 0.0)) return;
+  if (!(v < 0x1p60)) v = 0x1p60;
+  const uint64_t bits = (uint64_t)__double_as_longlong(v);
+  const int e = (int)((bits >> 52) & 0x7ff);
+  if (e == 0) return;  // subnormal: below the unit
+  const uint64_t m = (bits & 0xfffffffffffffull) | 0x10000000000000ull;
+  const int sh = e - 1023;  // <= 59
+  uint64_t lo, hi;
+  if (sh >= 0) {
+    lo = m << sh;
+    hi = sh == 0 ? 0 : m >> (64 - sh);
+  } else if (sh > -64) {
+    lo = m >> (-sh);
+    hi = 0;
+  } else {
+    return;
+  }
+  typedef unsigned long long ull;
+  const uint64_t old = (uint64_t)atomicAdd((ull *)&acc[0], (ull)lo);
+  const uint64_t c = (old + lo < old) ? 1u : 0u;
+  if (hi + c) atomicAdd((ull *)&acc[1], (ull)(hi + c));
+}
+
+TRIME_HD double fx_value(const uint64_t *acc) {
+  return ((double)acc[1] * 0x1p64 + (double)acc[0]) * 0x1p-52;
+}
+
+// The finished quality fields of the stats (Eq. 11 with p = 1/2, mean and
+// min q), from the exact sums; the host (trime_stats_read) and the adaptive
+// control kernel evaluate the same expressions.
+TRIME_HD void quality_finish(trime_stats *S) {
+  S->sum_sqrt_alpha = fx_value(S->quality_acc + 0);
+  S->sum_sqrt_beta = fx_value(S->quality_acc + 2);
+  S->sum_q = fx_value(S->quality_acc + 4);
+  if (S->nq > 0) {
+    const double n = (double)S->nq;
+    const double ma = S->sum_sqrt_alpha / n, mb = S->sum_sqrt_beta / n;
+    S->half_mean_alpha = ma * ma;
+    S->half_mean_beta = mb * mb;
+    S->mean_q = S->sum_q / n;
+    S->min_q = S->max_alpha > 0.0 ? 1.0 / S->max_alpha : 0.0;
+  } else {
+    S->half_mean_alpha = S->half_mean_beta = S->mean_q = S->min_q = 0.0;
+  }
+}
+
+// Adds one partial of the quality sums (a block's or one point's, summed in a
+// fixed order) and its max alpha (ordered as integers: alpha >= 0).
+TRIME_D void quality_add(trime_stats *S, double sa, double sb, double sq, double amax) {
+  fx_add(S->quality_acc + 0, sa);
+  fx_add(S->quality_acc + 2, sb);
+  fx_add(S->quality_acc + 4, sq);
+  if (amax > 0.0) atomicMax((unsigned long long *)&S->max_alpha, (unsigned long long)__double_as_longlong(amax));
+}
+
 // Clears the quality part of the stats and the per-pass counters, and with
 // full set every run statistic and counter; thread t of one block (at least
 // 64 threads) takes its share.
@@ -103,6 +166,8 @@ TRIME_D void stats_reset(const KArgs &a, int full, int t) {
     S->sum_sqrt_beta = 0;
     S->sum_q = 0;
     S->max_alpha = 0;
+    for (int q = 0; q < 6; q++) S->quality_acc[q] = 0;
+    S->half_mean_alpha = S->half_mean_beta = S->mean_q = S->min_q = 0;
     S->nq = 0;
     S->ntri = 0;
     S->nvalid = 0;

@@ -3,7 +3,6 @@ calls the C ABI (paper_2309_13824_amd.trime) for every step."""
 from __future__ import annotations
 
 import ctypes as C
-import math
 
 import numpy as np
 
@@ -71,7 +70,7 @@ class Mesher:
         n0 = wl.n if n_init is None else int(n_init)
         st.n = n0
         st.n_cap = wl.n
-        st.h_scale = math.sqrt(wl.n / n0) if n0 < wl.n else 0.0
+        st.n_grid = wl.n  # the grid is built for all of the workload's points
         st.precision = precision
         st.max_deg = max_deg
         st.bin_density = bin_density
@@ -149,8 +148,8 @@ class Mesher:
         self.n = int(self.state.n)
         return self.stats_raw().as_dict()["adapt"]
 
-    def add_points(self, n_add, h_scale_after=0.0):
-        T.add_points(self.state, n_add, h_scale_after)
+    def add_points(self, n_add):
+        T.add_points(self.state, n_add)
         self.n = int(self.state.n)
 
     def quality(self):

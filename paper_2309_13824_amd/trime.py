@@ -81,21 +81,18 @@ class Stats(C.Structure):
                 ("fac_mu", C.c_double), ("sum_sqrt_alpha", C.c_double), ("sum_sqrt_beta", C.c_double),
                 ("sum_q", C.c_double), ("max_alpha", C.c_double), ("nq", C.c_int64),
                 ("hist_beta", C.c_int64 * 40), ("work_candidates", C.c_int64), ("work_margins", C.c_int64),
-                ("work_cuts", C.c_int64), ("work_leaves", C.c_int64), ("adapt", AdaptCtl)]
+                ("work_cuts", C.c_int64), ("work_leaves", C.c_int64), ("adapt", AdaptCtl),
+                ("half_mean_alpha", C.c_double), ("half_mean_beta", C.c_double), ("mean_q", C.c_double),
+                ("min_q", C.c_double), ("quality_acc", C.c_uint64 * 6)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("hist_beta", "adapt")}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("hist_beta", "adapt", "quality_acc")}
         a = self.adapt
         d["adapt"] = {"method": a.method, "stopped": a.stopped, "iters": a.iters, "switch_iter": a.switch_iter,
                       "stop_iter": a.stop_iter, "reason": a.reason, "growing": a.growing,
                       "last": tuple(a.last[:]),
                       "rel": tuple(a.rel[:])}
         d["hist_beta"] = np.array(self.hist_beta[:], np.int64)
-        nq = max(self.nq, 1)
-        d["half_mean_alpha"] = (self.sum_sqrt_alpha / nq) ** 2
-        d["half_mean_beta"] = (self.sum_sqrt_beta / nq) ** 2
-        d["mean_q"] = self.sum_q / nq
-        d["min_q"] = 1.0 / self.max_alpha if self.max_alpha > 0 else 0.0
         return d
 
 
@@ -120,7 +117,7 @@ class State(C.Structure):
                 ("nbx", C.c_int32), ("nby", C.c_int32), ("lbits", C.c_int32), ("bx0", C.c_double),
                 ("by0", C.c_double), ("bw", C.c_double), ("area_sel", C.c_double), ("nkeys", C.c_int64),
                 ("ev_cells", C.c_void_p * 2), ("n_cap", C.c_int64), ("h_scale", C.c_double),
-                ("nkeys_cap", C.c_int64)]
+                ("nkeys_cap", C.c_int64), ("n_grid", C.c_int64)]
 
 
 ADAPT_DM, ADAPT_CVD, ADAPT_HYBRID = 0, 1, 2
@@ -200,7 +197,7 @@ def lib(require_gpu: bool = True):
         L.trime_batch_create.argtypes = [C.POINTER(st), C.c_int32, C.c_int32, C.POINTER(vp)]
         L.trime_batch_run.argtypes = [vp, C.c_int32, vp]
         L.trime_batch_destroy.argtypes = [vp]
-        L.trime_add_points.argtypes = [st, C.c_int64, C.c_double, vp]
+        L.trime_add_points.argtypes = [st, C.c_int64, vp]
         L.trime_run_growing.argtypes = [st, C.POINTER(Growing), vp]
         i64p = C.POINTER(C.c_int64)
         L.trime_auto_sizing.argtypes = [C.POINTER(Geometry), C.POINTER(Sizing), C.POINTER(Grid), vp, C.c_int64, i64p,
@@ -293,17 +290,18 @@ def step_adaptive(state, mode, max_iter, t_quality=0.001, t_amax=0.005, t_switch
     _check(lib().trime_step_adaptive(C.byref(state), C.byref(cfg), _stream(stream)))
 
 
-def add_points(state, n_add, h_scale_after=0.0, stream=None):
+def add_points(state, n_add, stream=None):
     """Appends the centroids of the n_add valid triangles with the largest
-    circumradius / h (synchronises); h_scale_after > 0 becomes the state's
-    h scale (the new points' categories and spans use it)."""
-    _check(lib().trime_add_points(C.byref(state), int(n_add), float(h_scale_after), _stream(stream)))
+    circumradius / h (synchronises); the state's h scale becomes
+    sqrt(n_grid / n) for the new n (the new points' categories and spans use
+    it)."""
+    _check(lib().trime_add_points(C.byref(state), int(n_add), _stream(stream)))
 
 
 def run_growing(state, mode, max_iter, n_total, t_add=0.002, fac_add=0.6, t_quality=0.001, t_amax=0.005,
                 t_switch=0.0015, stream=None):
-    """Adaptive run with point addition up to n_total points (the state
-    loaded with h_scale = sqrt(n_total / n)); the outcome is in the stats."""
+    """Adaptive run with point addition up to n_total points (h read times
+    sqrt(n_grid / n) as the count grows); the outcome is in the stats."""
     m = {"dm": ADAPT_DM, "cvd": ADAPT_CVD, "hybrid": ADAPT_HYBRID}[mode]
     cfg = Growing(Adaptive(m, int(max_iter), float(t_quality), float(t_amax), float(t_switch)), int(n_total),
                   float(t_add), float(fac_add))

@@ -308,6 +308,10 @@ hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipErrorNotSuppo
 hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
 hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
 hipError_t hipLaunchKernel(const void *, dim3, dim3, void **, size_t, hipStream_t) { return hipErrorNotSupported; }
+hipError_t hipGetDevice(int *d) {
+  *d = 0;
+  return hipSuccess;
+}
 hipError_t hipGetSymbolAddress(void **p, const void *symbol) {
   *p = (void *)symbol;
   return hipSuccess;

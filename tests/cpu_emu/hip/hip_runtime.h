@@ -25,6 +25,7 @@
 #define __forceinline__ inline
 #define __noinline__ __attribute__((noinline))
 #define __shared__ static
+#define __align__(n) __attribute__((aligned(n)))
 #define __launch_bounds__(...)
 
 struct dim3 {
@@ -186,6 +187,7 @@ hipError_t hipGraphExecDestroy(hipGraphExec_t);
 hipError_t hipGraphDestroy(hipGraph_t);
 hipError_t hipLaunchKernel(const void *f, dim3 grid, dim3 block, void **args, size_t shmem, hipStream_t);
 hipError_t hipGetSymbolAddress(void **p, const void *symbol);
+hipError_t hipGetDevice(int *d);
 #define HIP_SYMBOL(x) (&(x))
 
 #define hipLaunchKernelGGL(K, G, B, SH, ST, ...) \

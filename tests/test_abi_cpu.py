@@ -1,7 +1,6 @@
 """The C ABI without a GPU: the library loads, exports every function the
 header declares, and rejects bad arguments on the host before any launch."""
 import ctypes as C
-import math
 import os
 import re
 
@@ -110,9 +109,9 @@ def test_adaptive_configuration_rejected_on_host(T):
 
 def test_growing_configuration_rejected_on_host(T):
     """Point addition and growing runs: a capacity below n, n_add outside
-    [0, n_cap - n], a bad h scale, n_total outside [n, n_cap], a negative
-    t_add, fac_add <= 0 and an h_scale other than sqrt(n_total / n) return
-    TRIME_EINVAL on the host (the state only looks bound, as above)."""
+    [0, n_cap - n], a negative n_grid, n_total outside [n, n_cap], a negative
+    t_add and fac_add <= 0 return TRIME_EINVAL on the host (the state only
+    looks bound, as above)."""
     L = T.lib(require_gpu=False)
     st = T.State()
     st.n = 10
@@ -121,24 +120,24 @@ def test_growing_configuration_rejected_on_host(T):
     st.stats = 512
     st.pos[0].x = 768
     st.n_cap = 5
-    assert L.trime_add_points(C.byref(st), 1, 0.0, None) == 1
+    assert L.trime_add_points(C.byref(st), 1, None) == 1
     assert b"n_cap" in L.trime_last_error()
     st.n_cap = 20
-    for n_add, hs in ((-1, 0.0), (11, 0.0), (1, -1.0), (1, float("inf"))):
-        assert L.trime_add_points(C.byref(st), n_add, hs, None) == 1
+    for n_add in (-1, 11):
+        assert L.trime_add_points(C.byref(st), n_add, None) == 1
         assert b"trime_add_points" in L.trime_last_error()
+    st.n_grid = -5
+    assert L.trime_add_points(C.byref(st), 1, None) == 1
+    assert b"n_grid" in L.trime_last_error()
+    st.n_grid = 20
     base = T.Adaptive(T.ADAPT_HYBRID, 10, 0.001, 0.005, 0.0015)
     assert L.trime_run_growing(C.byref(st), None, None) == 1
-    st.h_scale = math.sqrt(2.0)
     for n_total, t_add, fac in ((9, 0.002, 0.6), (21, 0.002, 0.6), (20, -0.1, 0.6), (20, 0.002, 0.0),
                                 (20, float("nan"), 0.6)):
         assert L.trime_run_growing(C.byref(st), C.byref(T.Growing(base, n_total, t_add, fac)), None) == 1
         assert b"trime_run_growing" in L.trime_last_error()
     bad_mode = T.Adaptive(9, 10, 0.001, 0.005, 0.0015)
     assert L.trime_run_growing(C.byref(st), C.byref(T.Growing(bad_mode, 20, 0.002, 0.6)), None) == 1
-    st.h_scale = 1.5  # not sqrt(20 / 10)
-    assert L.trime_run_growing(C.byref(st), C.byref(T.Growing(base, 20, 0.002, 0.6)), None) == 1
-    assert b"h_scale" in L.trime_last_error()
 
 
 def test_auto_sizing_arguments_rejected_on_host(T):

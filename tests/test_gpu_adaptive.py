@@ -122,3 +122,27 @@ def test_adaptive_run_replays_in_a_graph(orc, T):
         ad = m.stats_raw().as_dict()["adapt"]
         assert (ad["iters"], ad["switch_iter"], ad["stop_iter"], ad["reason"]) == \
             (want_ad["iters"], want_ad["switch_iter"], want_ad["stop_iter"], want_ad["reason"]), r
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_identical_runs_are_bit_identical(T, prec):
+    """Two adaptive hybrid runs from the same input give bit-identical
+    statistics (the quality sums are exact fixed-point sums, so the order in
+    which blocks finish does not matter), the same switch and stop
+    iterations and the same positions; the finished quality fields are
+    Eq. 11 of the sums."""
+    wl = I.holes20(n=20000, grid_n=512, iters=1)
+    out = []
+    for _ in range(2):
+        m = mesher(wl, prec)
+        ctl = m.step_adaptive("hybrid", 60, TQ, TA, TS)
+        st = m.stats_raw()
+        x, y, c = m.points()
+        out.append((bytes(st), ctl["switch_iter"], ctl["stop_iter"], x.tobytes(), y.tobytes(), c.tobytes()))
+        assert st.nq > 0
+        assert st.half_mean_alpha == (st.sum_sqrt_alpha / st.nq) ** 2
+        assert st.half_mean_beta == (st.sum_sqrt_beta / st.nq) ** 2
+        assert st.mean_q == st.sum_q / st.nq and st.min_q == 1.0 / st.max_alpha
+        assert ctl["last"][0] == st.half_mean_alpha and ctl["last"][2] == st.max_alpha
+    print("switch %d, stop %d" % (out[0][1], out[0][2]), flush=True)
+    assert out[0] == out[1]

@@ -59,7 +59,8 @@ def test_added_points_match_oracle(orc, T, name, n_init, n_add, prec):
     tri, valid = m.triangles()
     assert len(tri) == len(mesh.tri) and int(valid.sum()) == int(mesh.valid.sum())
     c0 = m.points()[2]
-    m.add_points(n_add, hs1)
+    assert m.state.h_scale == hs0 and m.state.n_grid == wl.n
+    m.add_points(n_add)
     assert m.n == n_init + n_add and m.state.n == n_init + n_add and m.state.h_scale == hs1
     x, y, c = m.points()
     assert np.array_equal(x[:n_init], x0) and np.array_equal(y[:n_init], y0) and np.array_equal(c[:n_init], c0)

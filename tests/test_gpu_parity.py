@@ -63,8 +63,11 @@ def test_grid_build_matches_oracle(orc, T, make):
         assert np.max(np.abs(sdf - og.sdf) / (np.abs(og.sdf) + 1e-300)) <= 1.2e-7
         assert np.max(np.abs(mu - og.mu) / np.abs(og.mu)) <= 1.2e-7
     else:
-        assert np.max(np.abs(sdf - og.sdf) / (np.abs(og.sdf) + 1e-300)) <= 1e-14
-        assert np.max(np.abs(mu - og.mu) / np.abs(og.mu)) <= 1e-14
+        # FP64 nodes (the unit disk, |x| - 1): within 2 ulp of the distance
+        # |x| ~ 1 before the subtraction, which near the boundary is far more
+        # than 2 ulp of the small result
+        assert np.all(np.abs(sdf - og.sdf) <= 2 * np.spacing(np.abs(og.sdf) + 1.0))
+        assert np.all(np.abs(mu - og.mu) <= 2 * np.spacing(np.abs(og.mu)))
     assert np.array_equal(cat, og.cat)
     assert scal[0] == pytest.approx(og.H, rel=1e-13)
     assert scal[1] == pytest.approx(og.h_avg, rel=1e-12)
@@ -257,5 +260,8 @@ def test_cvd_run_quality_within_one_percent(orc, T, prec):
     assert st["half_mean_alpha"] == pytest.approx(q["half_mean_alpha"], rel=0.01)
     assert st["half_mean_beta"] == pytest.approx(q["half_mean_beta"], rel=0.01)
     hg = st["hist_beta"] / max(st["nq"], 1)
+    # 8,000 triangles spread over 40 bins: the 0.01 bound of the full-size
+    # runs (tests/test_gpu_fullrun.py, 2e5 and 2e6 triangles) is within the
+    # sampling noise of so few, hence twice it here
     assert np.abs(hg - q["hist_beta"]).sum() <= 0.02
     assert_no_error(m)
