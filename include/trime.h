@@ -331,6 +331,24 @@ trime_status trime_sdf_grid_build(const trime_geometry *g, const trime_sizing *s
                                   void *d_mu, uint8_t *d_cat, float *d_hcell,
                                   trime_grid_scalars *d_scal, void *stream);
 
+/* trime_sdf_grid_build for callers that cannot allocate device memory (code
+   under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc): the same grids, bit for bit, with the primitive list, polygon
+   vertices, density centres, hole indices and the partial sums of H in a
+   static device array of 6 MiB that each GPU holds until the process ends,
+   instead of a temporary allocation.  It calls no allocating routine (the
+   host arrays are copied with hipMemcpyAsync).  Every call on a GPU shares
+   that array, so calls that overlap on one GPU race; serialise them (one
+   stream, or an event between them).  Errors: as trime_sdf_grid_build;
+   TRIME_EUNSUPPORTED for SEGMENTS primitives and automatic sizing (their
+   candidate lists need allocations); TRIME_ECAPACITY when the primitive
+   list, vertices, centres, holes and one pair of doubles per 256 grid cells
+   need more than the 6 MiB (a grid of 8192^2 nodes takes 4 MiB). */
+trime_status trime_sdf_grid_build_noalloc(const trime_geometry *g, const trime_sizing *sz,
+                                          const trime_grid *grid, int64_t n_total, void *d_sdf,
+                                          void *d_mu, uint8_t *d_cat, float *d_hcell,
+                                          trime_grid_scalars *d_scal, void *stream);
+
 /* Size of the device workspace of a configured state (bytes, 256-aligned). */
 trime_status trime_state_workspace_bytes(const trime_state *st, size_t *bytes);
 /* Lays the state's buffers out in d_ws (>= workspace bytes).  Synchronous:

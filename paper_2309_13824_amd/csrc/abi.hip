@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/trime.h: argument checks,
 // workspace layout and the launch sequence of each entry point.
 #include <math.h>
+#include <mutex>
 #include <new>
 #include <stdio.h>
 #include <string.h>
@@ -291,6 +292,100 @@ trime_status trime_sdf_grid_build(const trime_geometry *geo, const trime_sizing 
   for (void *a : allocs) (void)hipFreeAsync(a, s);
   (void)hipFreeAsync(buf, s);
   return st;
+}
+
+// ------------------------------------------- grid build without allocation --
+//
+// The scratch of trime_sdf_grid_build_noalloc: the primitive list, polygon
+// vertices, density centres and hole indices copied from the host, and the
+// per-block partial sums of H (written before they are read), in one device
+// array of fixed size.  Each GPU the library runs on holds its own copy until
+// the process ends; every call on a GPU shares it, so calls that overlap on
+// one GPU race.  Host code uses the address hipGetSymbolAddress gives on
+// each device, never the array's name (a host-side stand-in).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)6 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// The scratch's device address on the current device, looked up once per
+// device, with that device current.
+static trime_status noalloc_scratch(void **out) {
+  int dev = -1;
+  TRY_HIP(hipGetDevice(&dev), "trime_sdf_grid_build_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return fail(TRIME_EUNSUPPORTED, "trime_sdf_grid_build_noalloc: device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "trime_sdf_grid_build_noalloc: hipGetSymbolAddress");
+    if (!p) return fail(TRIME_EHIP, "trime_sdf_grid_build_noalloc: no scratch address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TRIME_OK;
+}
+
+trime_status trime_sdf_grid_build_noalloc(const trime_geometry *geo, const trime_sizing *sz,
+                                          const trime_grid *grid, int64_t n_total, void *d_sdf, void *d_mu,
+                                          uint8_t *d_cat, float *d_hcell, trime_grid_scalars *d_scal,
+                                          void *stream) {
+  trime_status e = grid_build_ok(geo, sz, grid, n_total, d_sdf, d_mu, d_cat, d_hcell, d_scal);
+  if (e) return e;
+  for (int k = 0; k < geo->nprims; k++)
+    if (geo->prims[k].kind == TRIME_PRIM_SEGMENTS)
+      return fail(TRIME_EUNSUPPORTED,
+                  "trime_sdf_grid_build_noalloc: segment loops need candidate lists (trime_sdf_grid_build)");
+  if (sz->kind == TRIME_SZ_AUTO)
+    return fail(TRIME_EUNSUPPORTED,
+                "trime_sdf_grid_build_noalloc: automatic sizing needs scratch of its own (trime_sdf_grid_build)");
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t b_prims = sizeof(trime_prim) * (size_t)geo->nprims;
+  const size_t b_poly = sizeof(double) * 2 * (size_t)(geo->npoly > 0 ? geo->npoly : 0);
+  const size_t b_cent = sizeof(double) * 2 * (size_t)(sz->kind == TRIME_SZ_GAUSS_RHO ? sz->ncent : 0);
+  const size_t b_holes = sizeof(int32_t) * (size_t)(sz->kind == TRIME_SZ_HOLE_RAMP ? sz->nholes : 0);
+  const size_t b_part = sizeof(double) * 2 * (size_t)grid_partials(grid->nx, grid->ny);
+  const size_t total = al(b_prims) + al(b_poly) + al(b_cent) + al(b_holes) + al(b_part);
+  if (total > NOALLOC_SCRATCH_BYTES) {
+    snprintf(g_err, sizeof g_err,
+             "trime_sdf_grid_build_noalloc: needs %zu bytes of scratch, %zu available (fewer primitives or "
+             "vertices, or a grid of fewer cells)",
+             total, NOALLOC_SCRATCH_BYTES);
+    return TRIME_ECAPACITY;
+  }
+  void *base = nullptr;
+  e = noalloc_scratch(&base);
+  if (e) return e;
+  hipStream_t s = (hipStream_t)stream;
+  char *q = (char *)base;
+  trime_prim *d_prims = (trime_prim *)q; q += al(b_prims);
+  double *d_poly = (double *)q; q += al(b_poly);
+  double *d_cent = (double *)q; q += al(b_cent);
+  int32_t *d_holes = (int32_t *)q; q += al(b_holes);
+  double *d_part = (double *)q;
+  TRY_HIP(hipMemcpyAsync(d_prims, geo->prims, b_prims, hipMemcpyHostToDevice, s), "copy prims");
+  if (b_poly) TRY_HIP(hipMemcpyAsync(d_poly, geo->poly, b_poly, hipMemcpyHostToDevice, s), "copy poly");
+  if (b_cent) TRY_HIP(hipMemcpyAsync(d_cent, sz->cent, b_cent, hipMemcpyHostToDevice, s), "copy cent");
+  if (b_holes) TRY_HIP(hipMemcpyAsync(d_holes, sz->holes, b_holes, hipMemcpyHostToDevice, s), "copy holes");
+  GridPrims g;
+  memset(&g, 0, sizeof g);
+  g.nprims = geo->nprims;
+  g.prims = d_prims;
+  g.poly = d_poly;
+  g.segs = nullptr;
+  g.sz = *sz;
+  g.cent = d_cent;
+  g.holes = d_holes;
+  g.nx = grid->nx;
+  g.ny = grid->ny;
+  g.x0 = grid->x0;
+  g.y0 = grid->y0;
+  g.dx = grid->dx;
+  g.dy = grid->dy;
+  g.n_total = n_total;
+  launch_grid_build(g, grid->dtype_bytes, d_sdf, d_mu, d_cat, d_hcell, d_scal, d_part, s);
+  return check_hip("trime_sdf_grid_build_noalloc: launch");
 }
 
 // ------------------------------------------------------------ workspace --

@@ -148,7 +148,7 @@ EXPORTED = ["trime_last_error", "trime_version", "trime_default_params", "trime_
             "trime_quality", "trime_stats_read", "trime_stats_check", "trime_autotune_workspace_bytes",
             "trime_autotune", "trime_batch_graph_create", "trime_graph_launch", "trime_graph_destroy",
             "trime_step_adaptive", "trime_batch_create", "trime_batch_run", "trime_batch_destroy",
-            "trime_add_points", "trime_run_growing", "trime_auto_sizing"]
+            "trime_add_points", "trime_run_growing", "trime_auto_sizing", "trime_sdf_grid_build_noalloc"]
 
 _lib = None
 
@@ -170,6 +170,7 @@ def lib(require_gpu: bool = True):
         L.trime_default_params.argtypes = [C.POINTER(Params)]
         L.trime_sdf_grid_build.argtypes = [C.POINTER(Geometry), C.POINTER(Sizing), C.POINTER(Grid), C.c_int64,
                                            vp, vp, vp, vp, vp, vp]
+        L.trime_sdf_grid_build_noalloc.argtypes = L.trime_sdf_grid_build.argtypes
         L.trime_state_workspace_bytes.argtypes = [st, C.POINTER(C.c_size_t)]
         L.trime_state_bind.argtypes = [st, vp, C.c_size_t, vp]
         L.trime_state_load.argtypes = [st, vp, vp, vp]
@@ -240,6 +241,14 @@ def default_params(**kw) -> Params:
 def sdf_grid_build(geometry, sizing, grid, n_total, sdf, mu, cat, hcell, scal, stream=None):
     _check(lib().trime_sdf_grid_build(C.byref(geometry), C.byref(sizing), C.byref(grid), int(n_total),
                                       _ptr(sdf), _ptr(mu), _ptr(cat), _ptr(hcell), _ptr(scal), _stream(stream)))
+
+
+def sdf_grid_build_noalloc(geometry, sizing, grid, n_total, sdf, mu, cat, hcell, scal, stream=None):
+    """trime_sdf_grid_build without any allocation (a static scratch array
+    per GPU; calls overlapping on one GPU race)."""
+    _check(lib().trime_sdf_grid_build_noalloc(C.byref(geometry), C.byref(sizing), C.byref(grid), int(n_total),
+                                              _ptr(sdf), _ptr(mu), _ptr(cat), _ptr(hcell), _ptr(scal),
+                                              _stream(stream)))
 
 
 def state_workspace_bytes(state) -> int:
