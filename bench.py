@@ -152,6 +152,9 @@ def gpu_run(wl, precision, steps, warmup, log, tune=()):
     torch.cuda.synchronize()
     # eager pass: the fused kernel's duration in every iteration
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:  # materialise the events (the library records them again below)
+        a.record(s)
+        b.record(s)
     m.load()
     torch.cuda.synchronize()
     for a, b in ev:
