@@ -293,7 +293,15 @@ typedef struct {
   int64_t n_grid;          /* caller: the point count the grid was built for
                               (n_total of trime_sdf_grid_build; 0 -> n, set
                               by bind)                                      */
+  /* neighbours of each point's last cell, by point id, which the next cell
+     of the point clips first (laid out by bind, cleared by load) */
+  int32_t *warm_n;         /* n_cap: count (0: none)                        */
+  int32_t *warm_id;        /* TRIME_WARM * n_cap: neighbour ids             */
+  int32_t *slot_of_id;     /* n_cap: slot of each point id (binning)        */
 } trime_state;
+
+/* neighbours kept per point for the next cell */
+#define TRIME_WARM 12
 
 /* A fixed hybrid schedule: segments (method, iterations) run in order. */
 enum { TRIME_METHOD_DM = 0, TRIME_METHOD_CVD = 1,

@@ -482,6 +482,9 @@ static void layout(trime_state *st, Layout &L) {
   // FP64 replay queue, exact queue, deferred-centroid queue and its cells
   st->queue = L.take<int32_t>(queue_ints(n));
   st->counters = L.take<int32_t>(CNT_NCOUNTERS);
+  st->warm_n = L.take<int32_t>(n);
+  st->warm_id = L.take<int32_t>((size_t)TRIME_WARM * n);
+  st->slot_of_id = L.take<int32_t>(n);
   int64_t np = dm_partials(n);
   st->partials = L.take<double>(2 * (np > 1 ? np : 1));
   st->stats = L.take<trime_stats>(1);
@@ -615,6 +618,9 @@ static KArgs make_args(const trime_state *st) {
   a.stats = st->stats;
   a.prm = st->params;
   a.h_scale = st->h_scale > 0 ? st->h_scale : 1.0;
+  a.warm_n = st->warm_n;
+  a.warm_id = st->warm_id;
+  a.slot_of_id = st->slot_of_id;
   a.precision = st->precision;
   a.ev0 = st->ev_cells[0];
   a.ev1 = st->ev_cells[1];
@@ -649,6 +655,7 @@ trime_status trime_state_load(trime_state *st, const double *d_x, const double *
   launch_load(a, l, st->grid.dtype_bytes, s);
   launch_fill_i32(st->deg, st->n, 0, s);
   launch_fill_i32(st->tri_n, st->n, 0, s);
+  launch_fill_i32(st->warm_n, st->n_cap > st->n ? st->n_cap : st->n, 0, s);
   return check_hip("trime_state_load");
 }
 

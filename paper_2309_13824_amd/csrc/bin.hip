@@ -271,7 +271,9 @@ TRIME_D void BinPlace::run(const Args &A, Blk blk) {
   g.dprevo[s] = g.dprev[k];
   const uint8_t c = g.cat[k];
   g.cato[s] = c;
-  g.ido[s] = g.id[k];
+  const int id = g.id[k];
+  g.ido[s] = id;
+  if (a.slot_of_id) a.slot_of_id[id] = (int32_t)s;
   g.spano[s] = span_at(a, x, y);
   a.rank[s] = c == TRIME_CAT_BOUNDARY ? 1 : 0;
 }

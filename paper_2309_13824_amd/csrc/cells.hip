@@ -245,6 +245,7 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   int n;
   int why;  // nonzero: the point leaves this kernel (WHY_*)
   T R2;
+  float Emax = 0.0f;  // >= the error bound of every vertex of the polygon (clip_reg)
   ExactCount ec;
   Work wk;
   double cqx = 0, cqy = 0;  // FP64 offset of the candidate being clipped
@@ -408,13 +409,22 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     VRec<T> v[VMAX];
 #pragma unroll
     for (int j = 0; j < VMAX; j++) v[j] = P[j][tid];
+    // a neighbour whose bisector already bounds the cell (clipped first, from
+    // the point's previous cell) is not clipped again: two vertices lie on
+    // its bisector, where the margins vanish
+    uint32_t dup = 0;
+#pragma unroll
+    for (int j = 0; j < VMAX; j++) dup |= (uint32_t)(j < n && v[j].c == c3);
+    if (dup) return;
     const T n1 = fabs(r3.nx) + fabs(r3.ny);
-    const T b0 = (T)12 * u * fabs(r3.s);
+    // one bound for every vertex: the largest vertex error bound of the
+    // polygon stands for each vertex's own (a larger bound only leaves more
+    // margins to the FP64 re-evaluation)
+    const T b = fma(n1, (T)Emax, (T)12 * u * fabs(r3.s));
     uint32_t M = 0, Un = 0;
 #pragma unroll
     for (int j = 0; j < VMAX; j++) {
       T m = fma(r3.nx, v[j].x, fma(r3.ny, v[j].y, -r3.s));
-      T b = fma(n1, (T)v[j].e, b0);
       // as bits, not branches: one exec-mask branch per vertex would cost
       // more than the comparisons
       uint32_t in = j < n, gt = m > b, ge = m >= -b;
@@ -464,22 +474,29 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       why = WHY_VERTEX;
       return;
     }
-    // kept vertex j moves to d(j); the two new vertices go to dn, dn + 1
+    // kept vertex j moves to d(j); the two new vertices go to dn, dn + 1.
+    // R2 bounds |v|^2 of every vertex with the polygon's largest error bound
+    // (vert_r2 grows with the bound): the largest x^2 + y^2 and |x| + |y|
+    // over the vertices, then one bound.
     const bool plain = k0 <= k1;
     const int dn = plain ? k0 : k0 - k1 - 1;
-    T r2 = fmax(vert_r2(x1, y1, e1), vert_r2(x2, y2, e2));
+    Emax = fmax(Emax, fmax(e1, e2));
+    T q2 = fmax(x1 * x1 + y1 * y1, x2 * x2 + y2 * y2);
+    T l1 = fmax(fabs(x1) + fabs(y1), fabs(x2) + fabs(y2));
 #pragma unroll
     for (int j = 0; j < VMAX; j++) {
       if (j < n && !((M >> j) & 1)) {
         int d = plain ? (j < k0 ? j : j - r + 2) : j - (k1 + 1);
         P[d][tid] = v[j];
-        r2 = fmax(r2, vert_r2(v[j].x, v[j].y, v[j].e));
+        q2 = fmax(q2, v[j].x * v[j].x + v[j].y * v[j].y);
+        l1 = fmax(l1, fabs(v[j].x) + fabs(v[j].y));
       }
     }
     set_v(dn, x1, y1, e1, c3);
     set_v(dn + 1, x2, y2, e2, cout);
     n = nn;
-    set_R2(r2);
+    const T E = (T)Emax;
+    set_R2(q2 * ((T)1 + (T)8 * u) + (T)4 * l1 * E + (T)4 * E * E);
   }
 
   TRIME_D void clip_lds(const Row<T> &r3, int c3) {
@@ -1158,12 +1175,58 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     }
   }
 
+  // The neighbours of the point's previous cell (by id, through the slot
+  // of each id in the current binning), clipped before the scan: they are
+  // most of the neighbours of the new cell, so the polygon and its radius
+  // are close to final when the scan starts, the scan's reach and stop tests
+  // prune most bins, and later candidates rarely cut.  The cell does not
+  // depend on the order of the cuts (every decision is exact); the scan still
+  // visits every bin within reach.
+  TRIME_D void warm() {
+    const T u = U<T>::v;
+    const int m = gld(a.warm_n, (int64_t)pid);
+    for (int t = 0; t < m; t++) {
+      const int q = gld(a.slot_of_id, (int64_t)gld(a.warm_id, (int64_t)pid * TRIME_WARM + t));
+      if (q == (int)k) continue;
+      const double qx = gld(a.x, q), qy = gld(a.y, q);
+      Row<T> r3;
+      r3.nx = (T)(qx - px);
+      r3.ny = (T)(qy - py);
+      T sq = r3.nx * r3.nx + r3.ny * r3.ny;
+      r3.s = sq * (T)0.5;
+      if (!(sq * ((T)1 - (T)8 * u) > (T)4 * R2)) {
+        cqx = qx - px;
+        cqy = qy - py;
+        clip(r3, q);
+        if (why || n == 0) return;
+      }
+    }
+  }
+
+  // The ids of the cell's neighbours, for the point's next cell.
+  TRIME_D void keep_neighbours() {
+    int t = 0;
+    for (int j = 0; j < n; j++) {
+      const int c = con(j);
+      if (c >= 0 && t < TRIME_WARM) gst(a.warm_id, (int64_t)pid * TRIME_WARM + t++, gld(a.id, c));
+    }
+    gst(a.warm_n, (int64_t)pid, t);
+  }
+
   // Everything for point k; returns false when the point must be replayed.
   TRIME_D bool run(LaneStats &st, int *hist) {
     if (!begin()) return false;
+    if constexpr (!EXACT) {
+      if (a.warm_n) warm();
+      if (why) return false;
+    }
     scan();
     if (why) return false;
-    return finish(st, hist);
+    if (!finish(st, hist)) return false;
+    if constexpr (!EXACT) {
+      if (a.warm_n) keep_neighbours();
+    }
+    return true;
   }
 
   // The point and its initial polygon; false when the point must leave.
@@ -1305,13 +1368,21 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       // ---- decisions: triangles at the VV vertices, validity.  A CVD step
       // emits only the triangles p owns (smallest id), so it tests only
       // those; extraction needs validity at every vertex (adjacency rows).
-      uint32_t exists = 0, valid = 0;
+      // the vertices to test, as a mask, so that the tests below loop over
+      // them only (a wavefront then runs as many trips as its lane with the
+      // most such vertices, not as its largest polygon)
+      uint32_t test = 0, owned = 0;
       for (int j = 0; j < n; j++) {
         int jin = con(j == 0 ? n - 1 : j - 1), jout = con(j);
         if (jin < 0 || jout < 0) continue;
-        if constexpr (MODE == MODE_CVD) {
-          if (!(pid < gld(a.id, jin) && pid < gld(a.id, jout))) continue;
-        }
+        const uint32_t own = (pid < gld(a.id, jin) && pid < gld(a.id, jout)) ? 1u : 0u;
+        owned |= own << j;
+        test |= (MODE == MODE_CVD ? own : 1u) << j;
+      }
+      uint32_t exists = 0, valid = 0;
+      for (uint32_t m = test; m; m &= m - 1) {
+        const int j = __ffs(m) - 1;
+        int jin = con(j == 0 ? n - 1 : j - 1), jout = con(j);
         int e = inside_octagon(j, jin, jout);
         if (why) return false;
         if (e) e = inside_octagon(j, jout, jin);
@@ -1335,10 +1406,9 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       // ---- commit: nothing below can send the point back
       int nt = 0;
       int64_t tbase = k * TRIME_TRI_PER_POINT;
-      for (int j = 0; j < n; j++) {
-        if (!((exists >> j) & 1)) continue;
+      for (uint32_t m = exists & owned; m; m &= m - 1) {
+        const int j = __ffs(m) - 1;
         int jin = con(j == 0 ? n - 1 : j - 1), jout = con(j);
-        if (!(pid < gld(a.id, jin) && pid < gld(a.id, jout))) continue;
         bool v = (valid >> j) & 1;
         if (nt < TRIME_TRI_PER_POINT) {
           gst(a.tri, (tbase + nt) * 3 + 0, (int32_t)k);

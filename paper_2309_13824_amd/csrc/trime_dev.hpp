@@ -77,6 +77,9 @@ struct KArgs {
   // every h of the grid times this (the grid built for more points than are
   // in the mesh, Sec. 3.7)
   double h_scale;
+  // neighbours of each point's last cell by id (clipped first), and the slot
+  // of each id in the current binning
+  int32_t *warm_n, *warm_id, *slot_of_id;
 };
 
 // Whether a conditional launch has work (uniform over the grid).

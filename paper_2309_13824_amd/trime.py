@@ -117,7 +117,8 @@ class State(C.Structure):
                 ("nbx", C.c_int32), ("nby", C.c_int32), ("lbits", C.c_int32), ("bx0", C.c_double),
                 ("by0", C.c_double), ("bw", C.c_double), ("area_sel", C.c_double), ("nkeys", C.c_int64),
                 ("ev_cells", C.c_void_p * 2), ("n_cap", C.c_int64), ("h_scale", C.c_double),
-                ("nkeys_cap", C.c_int64), ("n_grid", C.c_int64)]
+                ("nkeys_cap", C.c_int64), ("n_grid", C.c_int64), ("warm_n", C.c_void_p),
+                ("warm_id", C.c_void_p), ("slot_of_id", C.c_void_p)]
 
 
 ADAPT_DM, ADAPT_CVD, ADAPT_HYBRID = 0, 1, 2

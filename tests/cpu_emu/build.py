@@ -18,8 +18,13 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
-CSRC = os.path.join(ROOT, "paper_2309_13824_amd", "csrc")
-OUT = os.path.join(HERE, "_build")
+# EMU_SRC: another copy of the package's sources and headers (a directory
+# holding pkg/csrc and include), for trying changes before they are made
+SRC_ROOT = os.environ.get("EMU_SRC")
+CSRC = os.path.join(SRC_ROOT, "pkg", "csrc") if SRC_ROOT else os.path.join(ROOT, "paper_2309_13824_amd", "csrc")
+INCLUDE = os.path.join(SRC_ROOT, "include") if SRC_ROOT else os.path.join(ROOT, "include")
+OUT_NAME = "_build_alt" if SRC_ROOT else "_build"
+OUT = os.path.join(HERE, OUT_NAME)
 EXE = os.path.join(OUT, "run_case")
 CXX = os.environ.get("EMU_CXX", "/opt/rocm/llvm/bin/clang++")
 
@@ -38,7 +43,7 @@ def prepare():
     src = os.path.join(OUT, "pkg", "csrc")
     os.makedirs(src, exist_ok=True)
     os.makedirs(os.path.join(OUT, "include"), exist_ok=True)
-    shutil.copy(os.path.join(ROOT, "include", "trime.h"), os.path.join(OUT, "include", "trime.h"))
+    shutil.copy(os.path.join(INCLUDE, "trime.h"), os.path.join(OUT, "include", "trime.h"))
     for f in os.listdir(CSRC):
         if not f.endswith((".hip", ".hpp")):
             continue

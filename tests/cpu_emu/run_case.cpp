@@ -160,6 +160,11 @@ int main(int argc, char **argv) {
   const int64_t np = trime::dm_partials(n);
   S.partials = (double *)alloc(8 * 2 * (np > 1 ? np : 1));
   S.stats = (trime_stats *)alloc(sizeof(trime_stats));
+#ifdef TRIME_WARM
+  S.warm_n = (int32_t *)alloc(4 * n);
+  S.warm_id = (int32_t *)alloc(4 * TRIME_WARM * n);
+  S.slot_of_id = (int32_t *)alloc(4 * n);
+#endif
   memset(S.counters, 0, 4 * 32);
   emu::after_launch = check_queues;
 
