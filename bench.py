@@ -99,6 +99,9 @@ def parse():
                          "launches and per-shape launches; disk, annulus, ellipses, coast (segment input): "
                          "their fixed schedules, one JSON line each")
     ap.add_argument("--shapes", type=int, default=512)
+    ap.add_argument("--persistent", action="store_true",
+                    help="stars: also time the persistent batch kernel (only in a library built with "
+                         "TRIME_PERSIST_ENABLE; switched off otherwise)")
     ap.add_argument("--batch-only", action="store_true",
                     help="stars: time only the batch with one launch per kernel (no per-shape or graph runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -373,6 +376,25 @@ def stars_run(args, log):
         out["batched_" + name] = total * iters / (bat_ms * 1e-3)
         out["batched_ms_" + name] = bat_ms
         log("  %s batched kernels: %.1f ms for %d iterations" % (name, bat_ms, iters))
+        # the same batch as one persistent launch (work items of `tiles` =
+        # fast-cell tiles, blocks of the other bulk kernels)
+        for tiles in (PERSIST_TILES if not args.batch_only else PERSIST_TILES[:1]) if args.persistent else ():
+            for m in ms:
+                m.load()
+            t = time.perf_counter()
+            b = Batch(ms, method="dm", n_iter=2, kind="persistent", tiles=tiles)
+            log("  persistent batch, items of %s tiles: tables built in %.1f s" % (tiles, time.perf_counter() - t))
+            b.run(2)  # warm-up
+            for m in ms:
+                m.load()
+            torch.cuda.synchronize()
+            p_ms = timed(lambda: b.run(iters), b.stream)
+            b.close()
+            errs = sum(m.stats_raw().error != 0 for m in ms)
+            key = "persistent_%s_%dx%d" % (name, tiles[0], tiles[1])
+            out[key] = total * iters / (p_ms * 1e-3)
+            log("  %s persistent batch (%s): %.1f ms for %d iterations, %d shapes with errors" %
+                (name, tiles, p_ms, iters, errs))
         # the same batch re-triangulating every iteration
         for m in ms:
             m.load()
@@ -429,6 +451,7 @@ def stars_run(args, log):
         "batched_fp64": out["batched_fp64"],
         "batched_always_fp32": out["batched_always_fp32"], "batched_always_fp64": out["batched_always_fp64"],
         "batched_fp32_over_batched_fp64": out["batched_fp32"] / out["batched_fp64"],
+        "persistent": {k[len("persistent_"):]: v for k, v in out.items() if k.startswith("persistent_")},
         "whole_iteration_hbm": out["hbm"],
     }
     if not args.no_cpu_baseline:
@@ -459,6 +482,10 @@ def stars_run(args, log):
                      "batched_fp32_over_per_shape_fp64": out["batched_fp32"] / out["per_shape_fp64"]})
     print(json.dumps(line), flush=True)
 
+
+# Work items of the persistent batch timed beside the one-launch-per-kernel
+# batch: (fast-cell tiles, blocks of the other bulk kernels) per item.
+PERSIST_TILES = ((1, 4), (2, 8), (4, 16))
 
 # Algorithmic HBM bytes per point-iteration of a whole iteration (every
 # kernel), counting each position, grid node and connectivity entry once per

@@ -592,6 +592,44 @@ trime_status trime_batch_create(trime_state *const *states, int32_t nstates, int
 trime_status trime_batch_run(trime_batch *b, int32_t n_iter, void *stream);
 trime_status trime_batch_destroy(trime_batch *b);
 
+/* ---- persistent batches -------------------------------------------------------
+   Switched off by default: unless the library is built with
+   TRIME_PERSIST_ENABLE, trime_batch_make_persistent returns TRIME_EINVAL and
+   leaves the batch as it was (on MI355X a launch of the persistent kernel
+   has not completed; the CPU emulation of the library builds it in and
+   checks it against the shapes run alone).
+   trime_batch_make_persistent switches a batch to one launch per
+   trime_batch_run for all its iterations: a persistent kernel (blocks of one
+   wavefront, as many as the device holds at once) takes work items from a
+   queue, in the role of the paper's dynamically scheduled threads (Sec. 5)
+   spread over the shapes.  An item is one kernel of the recorded period for
+   one shape and a chunk of that kernel's blocks, each run by the wavefront
+   in a form that computes what the block computes (the same sums in the
+   same order); items are handed out period by period, kernel by kernel,
+   larger shapes first, and an item starts when its shape has finished every
+   item before it, so shapes move through their kernels independently
+   instead of all shapes waiting at every kernel boundary.  Each shape's
+   results (positions, categories, triangles, statistics) are bit-identical
+   to the one-launch-per-kernel batch's.
+   - tiles_cells: blocks of the fast cell kernel (128 points each) per item;
+     tiles_other: blocks per item of the other bulk kernels (the replay
+     queues take one block per item).  Both in [1, 4096].
+   - Ownership: allocates its tables, per-shape counters and the exact
+     stage's polygons (48 KiB per block of the kernel) in device memory at
+     this call (synchronising); trime_batch_destroy frees them.
+   - A persistent trime_batch_run enqueues a counter-clearing fill kernel and
+     the one launch: no host reads, capturable in a HIP graph.  Runs of one
+     batch on streams that overlap race.
+   - A run still waiting 20 s after its launch started (a fault of the
+     schedule, never expected) stops: the remaining items are skipped and
+     the value 32 is ORed into the error field of the stats of a shape that
+     waited.
+   Errors: TRIME_EINVAL for a null or already persistent batch, tiles out of
+   range, a batch whose kernels have no persistent form, or more work items
+   than one launch counts (trime_batch_run: run fewer iterations per call);
+   TRIME_EHIP for a failed query, allocation or copy. */
+trime_status trime_batch_make_persistent(trime_batch *b, int32_t tiles_cells, int32_t tiles_other);
+
 
 /* ---- autotuner (tuning only) ------------------------------------------------
    The bin size sets how many neighbours a cell scans and how far, and the

@@ -398,7 +398,7 @@ int orc_predicate(const orc_grid *g, const orc_params *prm, const double *x, con
   return orc_pred_rows(&r1, &r2, &r3, x[i], y[i], i, used_exact, NULL);
 }
 
-/* ---- validity, Proc. I line 3 and Sec. 4.1 Tests 1-3 ---- */
+/* ---- validity: Procedure I's check, Sec. 4.1 Tests 1-3 ---- */
 
 static double bilin(const orc_grid *g, const double *f, int64_t cell, double tx, double ty) {
   int64_t ci = cell % (g->nx - 1), cj = cell / (g->nx - 1);

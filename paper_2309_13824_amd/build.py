@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtrime.so")
-SOURCES = ["abi.hip", "adapt.hip", "bin.hip", "cells.hip", "dm.hip", "grid.hip", "grow.hip", "segsdf.hip", "sizing.hip", "boundary.hip"]
+SOURCES = ["persist.hip", "cells.hip", "abi.hip", "adapt.hip", "bin.hip", "dm.hip", "grid.hip", "grow.hip", "segsdf.hip",
+           "sizing.hip", "boundary.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

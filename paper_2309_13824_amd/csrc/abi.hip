@@ -1,6 +1,8 @@
 // Host side of the C ABI declared in include/trime.h: argument checks,
 // workspace layout and the launch sequence of each entry point.
 #include <math.h>
+
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <stdio.h>
@@ -1073,11 +1075,24 @@ struct trime_batch {
   int32_t ns = 0;
   std::vector<BatchLaunch> launches;
   void *mem = nullptr;  // one device allocation for every table
+  // as recorded, per launch: kind, argument table offset and size, and the
+  // grid of every shape ([launch][shape])
+  std::vector<uint32_t> code, asz, grids;
+  std::vector<size_t> off_tab;
+  std::vector<trime_stats *> stats;  // per shape
+  // persistent execution (trime_batch_make_persistent)
+  bool persistent = false;
+  uint32_t cells_code = 0, pgrid = 0;
+  void *pmem = nullptr;
+  PersistArgs pa = {};
+  int32_t *pclear = nullptr;  // done[] and ctl[], cleared before each launch
+  int64_t pclear_n = 0;
 };
 
 trime_status trime_batch_destroy(trime_batch *b) {
   if (!b) return TRIME_OK;
   if (b->mem) (void)hipFree(b->mem);
+  if (b->pmem) (void)hipFree(b->pmem);
   delete b;
   return TRIME_OK;
 }
@@ -1126,14 +1141,20 @@ trime_status trime_batch_create(trime_state *const *states, int32_t nstates, int
   trime_batch *b = new (std::nothrow) trime_batch;
   if (!b) return fail(TRIME_EINVAL, "trime_batch_create: out of host memory");
   b->ns = nstates;
+  b->grids.resize(m * (size_t)nstates);
+  for (int k = 0; k < nstates; k++) b->stats.push_back(states[k]->stats);
   for (size_t i = 0; i < m; i++) {
     const size_t asz = logs[0][i].args.size();
     uint32_t *first = (uint32_t *)&host[off_first[i]];
     uint64_t tot = 0;
+    b->code.push_back(logs[0][i].code);
+    b->asz.push_back((uint32_t)asz);
+    b->off_tab.push_back(off_tab[i]);
     for (int k = 0; k < nstates; k++) {
       memcpy(&host[off_tab[i] + asz * (size_t)k], logs[k][i].args.data(), asz);
       first[k] = (uint32_t)tot;
       tot += logs[k][i].grid;
+      b->grids[i * (size_t)nstates + k] = logs[k][i].grid;
     }
     if (tot > 0x7fffffffull) {
       trime_batch_destroy(b);
@@ -1165,10 +1186,150 @@ trime_status trime_batch_create(trime_state *const *states, int32_t nstates, int
   return TRIME_OK;
 }
 
+trime_status trime_batch_make_persistent(trime_batch *b, int32_t tiles_cells, int32_t tiles_other) {
+#ifndef TRIME_PERSIST_ENABLE
+  // switched off: on MI355X a launch of the persistent kernel has not
+  // completed, its cause not yet found; the schedule and the kernels'
+  // one-wavefront forms are checked by the CPU emulation of the library,
+  // which builds with TRIME_PERSIST_ENABLE
+  (void)b;
+  (void)tiles_cells;
+  (void)tiles_other;
+  return fail(TRIME_EINVAL,
+              "trime_batch_make_persistent: switched off (the persistent kernel has not completed on MI355X; "
+              "build with TRIME_PERSIST_ENABLE to enable it)");
+#endif
+  if (!b) return fail(TRIME_EINVAL, "trime_batch_make_persistent: null batch");
+  if (b->persistent) return fail(TRIME_EINVAL, "trime_batch_make_persistent: the batch is persistent already");
+  if (tiles_cells < 1 || tiles_cells > 4096 || tiles_other < 1 || tiles_other > 4096)
+    return fail(TRIME_EINVAL, "trime_batch_make_persistent: tiles per item must be in [1, 4096]");
+  const size_t P = b->code.size(), ns = (size_t)b->ns;
+  uint32_t cells = 0;
+  for (uint32_t c : b->code)
+    if ((c >> 8) == KF_CELLS) cells = c;
+  if (!cells || !persist_supported(cells))
+    return fail(TRIME_EINVAL, "trime_batch_make_persistent: no persistent kernel for this batch's cell kernel");
+  for (uint32_t c : b->code)
+    if (!c || !persist_runs(cells, c))
+      return fail(TRIME_EINVAL, "trime_batch_make_persistent: a kernel of the batch has no wavefront form");
+  // items: ceil(grid / chunk) per (phase, shape); shapes with more work first
+  std::vector<uint32_t> chunk(P), items(P * ns);
+  for (size_t p = 0; p < P; p++) {
+    const uint32_t fam = b->code[p] >> 8;
+    chunk[p] = fam == KF_CELLS ? (uint32_t)tiles_cells
+                               : (fam == KF_POST || fam == KF_EXACT || fam == KF_DMREPLAY) ? 1u : (uint32_t)tiles_other;
+    for (size_t s = 0; s < ns; s++) items[p * ns + s] = (b->grids[p * ns + s] + chunk[p] - 1) / chunk[p];
+  }
+  std::vector<uint64_t> work(ns, 0);
+  for (size_t p = 0; p < P; p++)
+    for (size_t s = 0; s < ns; s++) work[s] += b->grids[p * ns + s];
+  std::vector<int32_t> order(ns);
+  for (size_t s = 0; s < ns; s++) order[s] = (int32_t)s;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return work[x] > work[y]; });
+  std::vector<uint32_t> ph_first(P + 1), sh_first(P * (ns + 1)), need(P * ns), per_shape(ns, 0);
+  uint64_t tot = 0;
+  for (size_t p = 0; p < P; p++) {
+    ph_first[p] = (uint32_t)tot;
+    uint64_t in_phase = 0;
+    for (size_t i = 0; i < ns; i++) {
+      sh_first[p * (ns + 1) + i] = (uint32_t)in_phase;
+      in_phase += items[p * ns + order[i]];
+    }
+    sh_first[p * (ns + 1) + ns] = (uint32_t)in_phase;
+    for (size_t s = 0; s < ns; s++) {
+      need[p * ns + s] = per_shape[s];
+      per_shape[s] += items[p * ns + s];
+    }
+    tot += in_phase;
+    if (tot > 0x7fffffffull) return fail(TRIME_EINVAL, "trime_batch_make_persistent: too many work items");
+  }
+  ph_first[P] = (uint32_t)tot;
+  const uint32_t grid = persist_grid(cells);
+  if (!grid) return fail(TRIME_EHIP, "trime_batch_make_persistent: occupancy query");
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+      khz <= 0)
+    return fail(TRIME_EHIP, "trime_batch_make_persistent: wall clock rate");
+  // one device allocation: tables, counters, the exact stage's polygons
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  std::vector<uint64_t> ph_args(P);
+  for (size_t p = 0; p < P; p++) ph_args[p] = b->off_tab[p];
+  size_t off = 0;
+  auto place = [&](size_t bytes) {
+    size_t o = off;
+    off += up(bytes);
+    return o;
+  };
+  const size_t o_args = place(P * 8), o_asz = place(P * 4), o_code = place(P * 4), o_chunk = place(P * 4),
+               o_phf = place((P + 1) * 4), o_shf = place(P * (ns + 1) * 4), o_grid = place(P * ns * 4),
+               o_need = place(P * ns * 4), o_per = place(ns * 4), o_order = place(ns * 4),
+               o_stats = place(ns * sizeof(trime_stats *)), o_clear = place((ns + 2) * PERSIST_LINE * 4);
+  const size_t table_bytes = off;
+  const size_t o_ws = place(persist_exact_slice() * (size_t)grid);
+  std::vector<unsigned char> host(table_bytes, 0);
+  memcpy(&host[o_args], ph_args.data(), P * 8);
+  memcpy(&host[o_asz], b->asz.data(), P * 4);
+  memcpy(&host[o_code], b->code.data(), P * 4);
+  memcpy(&host[o_chunk], chunk.data(), P * 4);
+  memcpy(&host[o_phf], ph_first.data(), (P + 1) * 4);
+  memcpy(&host[o_shf], sh_first.data(), P * (ns + 1) * 4);
+  memcpy(&host[o_grid], b->grids.data(), P * ns * 4);
+  memcpy(&host[o_need], need.data(), P * ns * 4);
+  memcpy(&host[o_per], per_shape.data(), ns * 4);
+  memcpy(&host[o_order], order.data(), ns * 4);
+  memcpy(&host[o_stats], b->stats.data(), ns * sizeof(trime_stats *));
+  void *mem = nullptr;
+  if (hipMalloc(&mem, off) != hipSuccess) return fail(TRIME_EHIP, "trime_batch_make_persistent: device allocation");
+  if (hipMemcpy(mem, host.data(), table_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(mem);
+    return fail(TRIME_EHIP, "trime_batch_make_persistent: copy of the tables");
+  }
+  unsigned char *d = (unsigned char *)mem;
+  PersistArgs &pa = b->pa;
+  pa.args = (const unsigned char *)b->mem;
+  pa.ph_args = (const uint64_t *)(d + o_args);
+  pa.ph_asz = (const uint32_t *)(d + o_asz);
+  pa.ph_code = (const uint32_t *)(d + o_code);
+  pa.ph_chunk = (const uint32_t *)(d + o_chunk);
+  pa.ph_first = (const uint32_t *)(d + o_phf);
+  pa.sh_first = (const uint32_t *)(d + o_shf);
+  pa.grid = (const uint32_t *)(d + o_grid);
+  pa.need = (const uint32_t *)(d + o_need);
+  pa.per_shape = (const uint32_t *)(d + o_per);
+  pa.order = (const int32_t *)(d + o_order);
+  pa.stats = (trime_stats *const *)(d + o_stats);
+  pa.done = (uint32_t *)(d + o_clear);
+  pa.ctl = pa.done + ns * PERSIST_LINE;
+  pa.exact_ws = d + o_ws;
+  pa.nphase = (uint32_t)P;
+  pa.ns = (uint32_t)ns;
+  pa.nper = (uint32_t)tot;
+  pa.nperiods = 0;
+  pa.zero = 0;
+  pa.timeout = (uint64_t)khz * 1000ull * 20ull;  // 20 s
+  b->pclear = (int32_t *)(d + o_clear);
+  b->pclear_n = (int64_t)(ns + 2) * PERSIST_LINE;
+  b->pmem = mem;
+  b->cells_code = cells;
+  b->pgrid = grid;
+  b->persistent = true;
+  return TRIME_OK;
+}
+
 trime_status trime_batch_run(trime_batch *b, int32_t n_iter, void *stream) {
   if (!b) return fail(TRIME_EINVAL, "trime_batch_run: null batch");
   if (n_iter < 0 || (n_iter & 1)) return fail(TRIME_EINVAL, "trime_batch_run: n_iter must be even and >= 0");
   hipStream_t s = (hipStream_t)stream;
+  if (b->persistent) {
+    if (n_iter == 0 || b->pa.nper == 0) return TRIME_OK;
+    if ((uint64_t)b->pa.nper * (uint64_t)(n_iter / 2) > 0xffffffffull)
+      return fail(TRIME_EINVAL, "trime_batch_run: too many work items for one launch (run fewer iterations)");
+    PersistArgs pa = b->pa;
+    pa.nperiods = (uint32_t)(n_iter / 2);
+    launch_fill_i32(b->pclear, b->pclear_n, 0, s);
+    launch_persist(b->cells_code, pa, b->pgrid, s);
+    return check_hip("trime_batch_run");
+  }
   for (int it = 0; it < n_iter; it += 2) {
     for (const BatchLaunch &L : b->launches) {
       if (!L.total) continue;

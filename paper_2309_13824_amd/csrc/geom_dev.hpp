@@ -1,5 +1,5 @@
 // Device geometry on the geometry grid, in FP64: validity of a triangle
-// (Proc. I line 3, Sec. 4.1 Tests 1-3), point categories (Sec. 3.5) and the
+// (Sec. 4.1 Tests 1-3, the check of Procedure I), point categories (Sec. 3.5) and the
 // treatment of an updated point (Sec. 4.3: movement cap, restriction to
 // inner/boundary cells, sphere tracing, damped Newton projection Eq. 12-14).
 #pragma once

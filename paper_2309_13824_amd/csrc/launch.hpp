@@ -44,10 +44,36 @@ __global__ __launch_bounds__(F::BLOCK) void k_many(const typename F::Args *__res
   F::run(tab[s], Blk{blockIdx.x - f0, f1 - f0});
 }
 
-// A launch as recorded for a batch: the batched kernel, the grid of one
-// shape, and that shape's argument bytes.
+// ---- kernel kinds, for the persistent batch kernel --------------------------
+// Every kernel of an iteration has a code naming its functor and template
+// arguments: family << 8 | (T is double) | (G is double) << 1 | mode << 2.
+// KindOf<F>::code is 0 for a kernel the persistent kernel cannot run.
+enum KFam : uint32_t {
+  KF_NONE = 0, KF_FILL, KF_BINKEYS, KF_SCANTILES, KF_SCANSUMS, KF_SCANADD, KF_SCANADDFEW, KF_BINSCATTER,
+  KF_BINPLACE, KF_ORDERSCATTER, KF_ORDERADD, KF_CELLS, KF_POST, KF_EXACT, KF_DMSUMS, KF_DMFINAL, KF_DMFORCE,
+  KF_DMREPLAY, KF_DMFLAG, KF_SETFLAG, KF_DMBEGIN, KF_STATSRESET, KF_FINISH
+};
+constexpr uint32_t kcode(uint32_t fam, bool tdbl = false, bool gdbl = false, uint32_t mode = 0) {
+  return fam << 8 | (tdbl ? 1u : 0u) | (gdbl ? 2u : 0u) | mode << 2;
+}
+template <class T> constexpr bool is_dbl() { return sizeof(T) == 8; }
+template <class F> struct KindOf {
+  static constexpr uint32_t code = 0;
+};
+
+// The work of block blk of F by one wavefront (a block of 64 threads): F's
+// BLOCK threads 64 at a time, for kernels whose threads never meet at a
+// barrier (F::body(args, blk, t) is thread t of the block).
+template <class F> TRIME_D void wave_virt(const typename F::Args &A, Blk blk) {
+  const int lane = threadIdx.x & 63;
+  for (int sub = 0; sub < F::BLOCK / 64; sub++) F::body(A, blk, sub * 64 + lane);
+}
+
+// A launch as recorded for a batch: the batched kernel, its kind, the grid
+// of one shape, and that shape's argument bytes.
 struct LaunchRec {
   const void *many;
+  uint32_t code;
   uint32_t grid, block;
   std::vector<unsigned char> args;
 };
@@ -58,6 +84,7 @@ template <class F> void launch(const typename F::Args &a, uint32_t grid, hipStre
   if (g_launch_log) {
     LaunchRec r;
     r.many = (const void *)&k_many<F>;
+    r.code = KindOf<F>::code;
     r.grid = grid;
     r.block = F::BLOCK;
     r.args.assign((const unsigned char *)&a, (const unsigned char *)&a + sizeof a);
@@ -68,6 +95,48 @@ template <class F> void launch(const typename F::Args &a, uint32_t grid, hipStre
 }
 
 enum { MODE_CELLS = 0, MODE_EXTRACT = 1, MODE_CVD = 2 };
+
+// ---- the persistent batch kernel (persist.hip) -------------------------------
+// One launch runs n_iter iterations of every shape of a batch.  Its work
+// items are (period, phase, shape, chunk of tiles): a phase is one kernel of
+// the recorded period (two iterations), a tile one block of that kernel for
+// that shape, run by one wavefront.  Items are handed out in the order
+// period, phase, shape (larger shapes first), chunk; an item waits until
+// every item of its shape before it in that order is done (a per-shape
+// count), so a shape's phases follow each other while other shapes are in
+// other phases, and no wait is on an item handed out later.
+struct PersistArgs {
+  const unsigned char *args;   // per (phase, shape) kernel arguments: args + ph_args[p] + s * ph_asz[p]
+  const uint64_t *ph_args;     // [P]
+  const uint32_t *ph_asz;      // [P]
+  const uint32_t *ph_code;     // [P] kernel kind (KindOf)
+  const uint32_t *ph_chunk;    // [P] tiles per item
+  const uint32_t *ph_first;    // [P + 1] first item of each phase within a period
+  const uint32_t *sh_first;    // [P][ns + 1] first item of the i-th shape (in order) within the phase
+  const uint32_t *grid;        // [P][ns] tiles of shape s in phase p
+  const uint32_t *need;        // [P][ns] items of shape s in the phases before p
+  const uint32_t *per_shape;   // [ns] items of shape s in one period
+  const int32_t *order;        // [ns] the shape at position i
+  trime_stats *const *stats;   // [ns] where a wait past the deadline is reported
+  uint32_t *done;              // items done by shape s at done[s * PERSIST_LINE] (zero at launch)
+  uint32_t *ctl;               // next item at ctl[0], abort flag at ctl[PERSIST_LINE] (zero at launch)
+  unsigned char *exact_ws;     // the exact stage's polygons: one slice per block
+  uint32_t nphase, ns, nper, nperiods;
+  uint32_t zero;               // 0: the addend of the counters' reads
+  uint64_t timeout;            // wall-clock ticks from a block's start to the launch's deadline
+};
+// counters of the persistent kernel one 128-byte line apart (in uint32_t)
+constexpr int PERSIST_LINE = 32;
+// cells_code: the code of the batch's fast cell kernel (its precision, grid
+// type and mode).  persist_supported: false if no persistent kernel exists
+// for it; persist_runs: whether that kernel runs the kernel kind `code`;
+// persist_grid: its grid (resident blocks on the device); launch_persist
+// enqueues it.
+bool persist_supported(uint32_t cells_code);
+bool persist_runs(uint32_t cells_code, uint32_t code);
+uint32_t persist_grid(uint32_t cells_code);
+size_t persist_exact_slice();
+void launch_persist(uint32_t cells_code, const PersistArgs &p, uint32_t grid, hipStream_t s);
 
 // Binning gather: current buffers in, the other buffer set out.
 struct GatherArgs {

@@ -21,6 +21,9 @@ template <> struct U<double> { static constexpr double v = 1.1102230246251565e-1
 // Loads and stores through the global address space (plain pointers would
 // compile to flat memory operations).
 #define TRIME_GLOBAL __attribute__((address_space(1)))
+// a pointer to LDS handed to a function that is not inlined (the callee then
+// still addresses it as LDS)
+#define TRIME_LDS __attribute__((address_space(3)))
 template <class T> TRIME_D T gld(const T *p, int64_t i) { return ((const TRIME_GLOBAL T *)p)[i]; }
 template <class T> TRIME_D void gst(T *p, int64_t i, T v) { ((TRIME_GLOBAL T *)p)[i] = v; }
 
@@ -90,7 +93,9 @@ enum { CNT_QUEUE = 0, CNT_TRI = 1, CNT_ERR = 2, CNT_MOVED = 3, CNT_QUEUE2 = 4, C
        CNT_REASON = 8, CNT_HEAVY = 24, CNT_NCOUNTERS = 32 };
 // ints per entry of the deferred-centroid queue (count + constraints)
 constexpr int CQ_STRIDE = 16;
-enum { ERR_TRI_CAP = 1, ERR_DEG_CAP = 2, ERR_POLY_CAP = 4, ERR_EXACT_CAP = 8, ERR_QUEUE = 16 };
+// ERR_SCHED: a wait of the persistent batch kernel ran past its time limit
+// (the batch's results are then incomplete)
+enum { ERR_TRI_CAP = 1, ERR_DEG_CAP = 2, ERR_POLY_CAP = 4, ERR_EXACT_CAP = 8, ERR_QUEUE = 16, ERR_SCHED = 32 };
 // why a point left the fast path
 enum { WHY_PRED = 1, WHY_VERTEX = 2, WHY_POLY = 3, WHY_AND = 4, WHY_LEVEL = 5, WHY_TREAT = 6,
        WHY_BOX = 7, WHY_HEAVY = 8, WHY_PREC = 9 };

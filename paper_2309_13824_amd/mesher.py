@@ -208,10 +208,12 @@ class Batch:
     """Many shapes meshed together; the Meshers stay usable one by one.
 
     kind "kernels" (trime_batch_create): every kernel of an iteration is
-    launched once for all shapes; kind "graph" (trime_batch_graph_create):
+    launched once for all shapes; kind "persistent" (the same batch after
+    trime_batch_make_persistent, items of `tiles` = (fast-cell tiles, other
+    blocks)): one launch per run; kind "graph" (trime_batch_graph_create):
     the shapes' own launches in one graph over nstreams streams."""
 
-    def __init__(self, meshers, method="dm", n_iter=2, nstreams=8, kind="graph"):
+    def __init__(self, meshers, method="dm", n_iter=2, nstreams=8, kind="graph", tiles=(1, 4)):
         import torch
         self.torch = torch
         self.meshers = list(meshers)
@@ -221,8 +223,10 @@ class Batch:
         torch.cuda.synchronize()
         meth = {"dm": T.METHOD_DM, "cvd": T.METHOD_CVD, "dm_always": T.METHOD_DM_ALWAYS}[method]
         self.graph = self.batch = None
-        if kind == "kernels":
+        if kind in ("kernels", "persistent"):
             self.batch = T.batch_create([m.state for m in self.meshers], meth)
+            if kind == "persistent":
+                T.batch_make_persistent(self.batch, tiles[0], tiles[1])
         else:
             self.graph = T.batch_graph_create([m.state for m in self.meshers], meth, n_iter, nstreams, self.stream)
         torch.cuda.synchronize()

@@ -149,6 +149,7 @@ EXPORTED = ["trime_last_error", "trime_version", "trime_default_params", "trime_
             "trime_quality", "trime_stats_read", "trime_stats_check", "trime_autotune_workspace_bytes",
             "trime_autotune", "trime_batch_graph_create", "trime_graph_launch", "trime_graph_destroy",
             "trime_step_adaptive", "trime_batch_create", "trime_batch_run", "trime_batch_destroy",
+            "trime_batch_make_persistent",
             "trime_add_points", "trime_run_growing", "trime_auto_sizing", "trime_sdf_grid_build_noalloc"]
 
 _lib = None
@@ -199,6 +200,7 @@ def lib(require_gpu: bool = True):
         L.trime_batch_create.argtypes = [C.POINTER(st), C.c_int32, C.c_int32, C.POINTER(vp)]
         L.trime_batch_run.argtypes = [vp, C.c_int32, vp]
         L.trime_batch_destroy.argtypes = [vp]
+        L.trime_batch_make_persistent.argtypes = [vp, C.c_int32, C.c_int32]
         L.trime_add_points.argtypes = [st, C.c_int64, vp]
         L.trime_run_growing.argtypes = [st, C.POINTER(Growing), vp]
         i64p = C.POINTER(C.c_int64)
@@ -384,6 +386,14 @@ def batch_create(states, method):
 
 def batch_run(b, n_iter, stream=None):
     _check(lib().trime_batch_run(b, int(n_iter), _stream(stream)))
+
+
+def batch_make_persistent(b, tiles_cells=1, tiles_other=4):
+    """Switches the batch to one persistent launch per batch_run (work items
+    of tiles_cells fast-cell tiles or tiles_other blocks of the other bulk
+    kernels).  Raises TrimeError unless the library was built with
+    TRIME_PERSIST_ENABLE (switched off by default)."""
+    _check(lib().trime_batch_make_persistent(b, int(tiles_cells), int(tiles_other)))
 
 
 def batch_destroy(b):

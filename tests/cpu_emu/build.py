@@ -4,8 +4,9 @@ AddressSanitizer and UndefinedBehaviorSanitizer (test infrastructure).
 
 The product sources are copied with two textual changes, each applied
 exactly once:
-- global loads and stores lose their address-space qualifier, which
-  AddressSanitizer does not instrument;
+- global loads and stores, and LDS pointers passed to functions, lose
+  their address-space qualifier, which AddressSanitizer does not
+  instrument;
 - the polygons of the wavefront-per-point passes (one polygon per wavefront
   or per group of 8 lanes, which every lane of the group reads and writes
   with identical values in lockstep on the GPU) become per-lane arrays,
@@ -29,14 +30,17 @@ EXE = os.path.join(OUT, "run_case")
 CXX = os.environ.get("EMU_CXX", "/opt/rocm/llvm/bin/clang++")
 
 EDITS = {
-    "trime_dev.hpp": [("#define TRIME_GLOBAL __attribute__((address_space(1)))", "#define TRIME_GLOBAL")],
-    "cells.hip": [("__shared__ VRec<double> P[VMAX][1];", "VRec<double> P[VMAX][1];"),
-                  ("__shared__ VRec<double> PC[V][8];", "VRec<double> PC[V][8];")],
+    "trime_dev.hpp": [("#define TRIME_GLOBAL __attribute__((address_space(1)))", "#define TRIME_GLOBAL"),
+                      ("#define TRIME_LDS __attribute__((address_space(3)))", "#define TRIME_LDS")],
+    "cells_k.hpp": [("auto &P = sh.P;", "VRec<double> P[VMAX][1];"),
+                    ("auto &PC = sh.PC;", "VRec<double> PC[V][8];")],
 }
 SOURCES = ["abi.hip", "adapt.hip", "bin.hip", "cells.hip", "dm.hip", "grid.hip", "grow.hip", "segsdf.hip",
-           "sizing.hip", "boundary.hip"]
+           "sizing.hip", "boundary.hip", "persist.hip"]
+# TRIME_PERSIST_ENABLE: the persistent batch kernel, switched off in the
+# device build, is built in here
 FLAGS = ["-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
-         "-fno-omit-frame-pointer", "-ffp-contract=off", "-Wno-unused-result"]
+         "-fno-omit-frame-pointer", "-ffp-contract=off", "-Wno-unused-result", "-DTRIME_PERSIST_ENABLE"]
 
 
 def prepare():

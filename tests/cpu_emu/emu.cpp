@@ -4,6 +4,7 @@
 // wavefront) has reached it.  A collective reached by only part of a
 // wavefront, or a block waiting on two different barriers, is reported and
 // aborts the run.
+#include <time.h>
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -308,6 +309,27 @@ hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipErrorNotSuppo
 hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
 hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
 hipError_t hipLaunchKernel(const void *, dim3, dim3, void **, size_t, hipStream_t) { return hipErrorNotSupported; }
+// two "CUs" holding one block each; a wall clock of 100 MHz
+hipError_t hipDeviceGetAttribute(int *v, int attr, int) {
+  if (attr == hipDeviceAttributeMultiprocessorCount) {
+    *v = 2;
+    return hipSuccess;
+  }
+  if (attr == hipDeviceAttributeWallClockRate) {
+    *v = 100000;
+    return hipSuccess;
+  }
+  return hipErrorNotSupported;
+}
+hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *nb, const void *, int, size_t) {
+  *nb = 1;
+  return hipSuccess;
+}
+uint64_t wall_clock64() {
+  struct timespec t;
+  clock_gettime(CLOCK_MONOTONIC, &t);
+  return (uint64_t)t.tv_sec * 100000000ull + (uint64_t)t.tv_nsec / 10ull;
+}
 hipError_t hipGetDevice(int *d) {
   *d = 0;
   return hipSuccess;

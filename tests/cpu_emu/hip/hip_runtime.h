@@ -108,6 +108,11 @@ template <class T> inline T __shfl_up(T v, unsigned d, int width = 64) {
   const int s = (l & (width - 1)) >= (int)d ? l - (int)d : l;
   return emu::from_bits<T>(b[s]);
 }
+template <class T> inline T __shfl_xor(T v, int mask, int width = 64) {
+  const uint64_t *b = emu::wave_exchange(emu::to_bits(v));
+  const int l = emu::lane_id();
+  return emu::from_bits<T>(b[(l & ~(width - 1)) + ((l ^ mask) & (width - 1))]);
+}
 inline unsigned long long __ballot(int pred) {
   const uint64_t *b = emu::wave_exchange(pred ? 1u : 0u);
   unsigned long long m = 0;
@@ -153,6 +158,19 @@ template <class T, class U> inline T atomicExch(T *p, U v) {
   return o;
 }
 
+// the wavefront-wide intrinsics of the persistent kernel (its scoped atomics
+// are clang builtins on the host too; the fences and sleeps are no-ops on
+// one OS thread)
+#ifndef __HIP_MEMORY_SCOPE_AGENT
+#define __HIP_MEMORY_SCOPE_AGENT 3
+#endif
+#define __builtin_amdgcn_fence(order, scope) ((void)0)
+#define __builtin_amdgcn_s_sleep(n) ((void)0)
+#define __builtin_amdgcn_wave_barrier() ((void)0)
+// the first lane's value in every lane (lane 0 is always live where used)
+#define __builtin_amdgcn_readfirstlane(x) __shfl((x), 0)
+uint64_t wall_clock64();
+
 // ---- host API ----------------------------------------------------------------
 hipError_t hipMalloc(void **p, size_t bytes);
 hipError_t hipFree(void *p);
@@ -188,6 +206,9 @@ hipError_t hipGraphDestroy(hipGraph_t);
 hipError_t hipLaunchKernel(const void *f, dim3 grid, dim3 block, void **args, size_t shmem, hipStream_t);
 hipError_t hipGetSymbolAddress(void **p, const void *symbol);
 hipError_t hipGetDevice(int *d);
+enum { hipDeviceAttributeMultiprocessorCount = 63, hipDeviceAttributeWallClockRate = 88 };
+hipError_t hipDeviceGetAttribute(int *v, int attr, int dev);
+hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *nb, const void *f, int block, size_t shmem);
 #define HIP_SYMBOL(x) (&(x))
 
 #define hipLaunchKernelGGL(K, G, B, SH, ST, ...) \

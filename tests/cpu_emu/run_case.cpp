@@ -29,6 +29,7 @@ extern void (*after_launch)();
 }
 
 static trime_state S;
+static std::vector<trime_state *> all_states;  // every state whose queues are checked
 static int64_t max_q[3] = {0, 0, 0};
 static int nchecks = 0;
 
@@ -41,14 +42,16 @@ static void *alloc(size_t bytes) {
 // queue counters (counters[0], [4], [5]): FP64 replay, exact, deferred
 // centroids; each queue holds n + 1 entries
 static void check_queues() {
-  const int32_t *c = S.counters;
-  const int32_t q[3] = {c[0], c[4], c[5]};
-  for (int k = 0; k < 3; k++) {
-    if (q[k] < 0 || q[k] > S.n + 1) {
-      fprintf(stderr, "queue %d holds %d entries, capacity %lld\n", k, q[k], (long long)S.n + 1);
-      abort();
+  for (trime_state *T : all_states) {
+    const int32_t *c = T->counters;
+    const int32_t q[3] = {c[0], c[4], c[5]};
+    for (int k = 0; k < 3; k++) {
+      if (q[k] < 0 || q[k] > T->n + 1) {
+        fprintf(stderr, "queue %d holds %d entries, capacity %lld\n", k, q[k], (long long)T->n + 1);
+        abort();
+      }
+      if (q[k] > max_q[k]) max_q[k] = q[k];
     }
-    if (q[k] > max_q[k]) max_q[k] = q[k];
   }
   nchecks++;
 }
@@ -68,6 +71,135 @@ static void read_all(FILE *f, void *p, size_t bytes) {
       exit(3);                                                              \
     }                                                                       \
   } while (0)
+
+// A state on the case's grid with every buffer in an allocation of its own,
+// of the size the layout gives it.
+static void setup(trime_state &T, int64_t n, int32_t prec, double dens, int32_t nx, int32_t ny, double x0,
+                  double y0, double dx, double dy, int32_t dtb, void *sdf, void *mu, uint8_t *cat, float *hcell,
+                  trime_grid_scalars *scal) {
+  memset(&T, 0, sizeof T);
+  T.n = n;
+  T.precision = prec;
+  T.max_deg = 16;
+  T.bin_density = dens;
+  T.grid.nx = nx;
+  T.grid.ny = ny;
+  T.grid.x0 = x0;
+  T.grid.y0 = y0;
+  T.grid.dx = dx;
+  T.grid.dy = dy;
+  T.grid.dtype_bytes = dtb;
+  T.sdf = sdf;
+  T.mu = mu;
+  T.cat_grid = cat;
+  T.hcell = hcell;
+  T.scal = scal;
+  trime_default_params(&T.params);
+  size_t ws = 0;
+  OK(trime_state_workspace_bytes(&T, &ws));
+  void *wsp = alloc(ws);
+  OK(trime_state_bind(&T, wsp, ws, nullptr));
+  // every buffer in an allocation of its own, of the size the layout gives it
+  const int64_t nkeys = T.nkeys_cap > T.nkeys ? T.nkeys_cap : T.nkeys;
+  const int64_t md = T.max_deg;
+  for (int b = 0; b < 2; b++) {
+    T.pos[b].x = (double *)alloc(8 * n);
+    T.pos[b].y = (double *)alloc(8 * n);
+    T.pos[b].dprev = (double *)alloc(8 * n);
+    T.pos[b].cat = (uint8_t *)alloc(n);
+    T.ord[b].id = (int32_t *)alloc(4 * n);
+    T.ord[b].span = (float *)alloc(4 * n);
+    T.ord[b].xl = (double *)alloc(8 * n);
+    T.ord[b].yl = (double *)alloc(8 * n);
+  }
+  T.adj = (int32_t *)alloc(4 * md * n);
+  T.deg = (int32_t *)alloc(4 * n);
+  T.tri = (int32_t *)alloc(4 * 3 * TRIME_TRI_PER_POINT * n);
+  T.tri_valid = (uint8_t *)alloc(TRIME_TRI_PER_POINT * n);
+  T.tri_n = (int32_t *)alloc(4 * (n + 1));
+  T.perm = (int32_t *)alloc(4 * (n + 1));
+  T.key = (int32_t *)alloc(4 * n);
+  T.rank = (int32_t *)alloc(4 * n);
+  T.order = (int32_t *)alloc(4 * n);
+  T.bin_start = (int32_t *)alloc(4 * (nkeys + 1));
+  T.bin_fill = (int32_t *)alloc(4 * nkeys);
+  T.scan_tmp = (int32_t *)alloc(4 * (trime::scan_tmp_ints(nkeys > n ? nkeys : n) + 1));
+  T.queue = (int32_t *)alloc(4 * (3 * (n + 1) + 16 * n + 512));
+  T.counters = (int32_t *)alloc(4 * 32);
+  const int64_t np = trime::dm_partials(n);
+  T.partials = (double *)alloc(8 * 2 * (np > 1 ? np : 1));
+  T.stats = (trime_stats *)alloc(sizeof(trime_stats));
+#ifdef TRIME_WARM
+  T.warm_n = (int32_t *)alloc(4 * n);
+  T.warm_id = (int32_t *)alloc(4 * TRIME_WARM * n);
+  T.slot_of_id = (int32_t *)alloc(4 * n);
+#endif
+  memset(T.counters, 0, 4 * 32);
+
+  all_states.push_back(&T);
+}
+
+// Method 2 (DistMesh) or 3 (CVD): a persistent batch of two shapes on the
+// case's grid, the n points and the first n / 3 of them, against the same
+// shapes run alone; after every two iterations each shape's positions,
+// categories and statistics must be bit-identical.  OUT receives, per two
+// iterations, the first shape's x, y (n doubles each) and cat by id.
+static int run_persistent(bool cvd, int iters, const char *outp, int64_t n, double *x, double *y, int32_t prec,
+                          double dens, int32_t nx, int32_t ny, double x0, double y0, double dx, double dy,
+                          int32_t dtb, void *sdf, void *mu, uint8_t *cat, float *hcell, trime_grid_scalars *scal) {
+  static trime_state B[2], R[2];
+  const int64_t ns[2] = {n, n / 3};
+  for (int k = 0; k < 2; k++) {
+    setup(B[k], ns[k], prec, dens, nx, ny, x0, y0, dx, dy, dtb, sdf, mu, cat, hcell, scal);
+    setup(R[k], ns[k], prec, dens, nx, ny, x0, y0, dx, dy, dtb, sdf, mu, cat, hcell, scal);
+    OK(trime_state_load(&B[k], x, y, nullptr));
+    OK(trime_state_load(&R[k], x, y, nullptr));
+  }
+  trime_state *bs[2] = {&B[0], &B[1]};
+  trime_batch *b = nullptr;
+  OK(trime_batch_create(bs, 2, cvd ? TRIME_METHOD_CVD : TRIME_METHOD_DM, &b));
+  OK(trime_batch_make_persistent(b, 1, 2));
+  FILE *out = fopen(outp, "wb");
+  std::vector<double> ax(n), ay(n), rx(n), ry(n);
+  std::vector<uint8_t> ac(n), rc(n);
+  for (int it = 0; it + 2 <= iters; it += 2) {
+    OK(trime_batch_run(b, 2, nullptr));
+    for (int k = 0; k < 2; k++) {
+      if (cvd)
+        OK(trime_step_cvd(&R[k], 2, nullptr));
+      else
+        OK(trime_step_dm(&R[k], 2, 0, 0, nullptr));
+      OK(trime_export_points(&B[k], ax.data(), ay.data(), ac.data(), nullptr));
+      OK(trime_export_points(&R[k], rx.data(), ry.data(), rc.data(), nullptr));
+      const size_t m = (size_t)ns[k];
+      if (memcmp(ax.data(), rx.data(), 8 * m) || memcmp(ay.data(), ry.data(), 8 * m) ||
+          memcmp(ac.data(), rc.data(), m)) {
+        fprintf(stderr, "shape %d: positions after iteration %d differ from the shape run alone\n", k, it + 2);
+        return 4;
+      }
+      trime_stats sa, sr;
+      OK(trime_stats_read(&B[k], &sa, nullptr));
+      OK(trime_stats_read(&R[k], &sr, nullptr));
+      if (memcmp(&sa, &sr, sizeof sa)) {
+        fprintf(stderr, "shape %d: statistics after iteration %d differ from the shape run alone\n", k, it + 2);
+        return 5;
+      }
+      if (sa.error) {
+        fprintf(stderr, "shape %d: error %d\n", k, sa.error);
+        return 6;
+      }
+    }
+    OK(trime_export_points(&B[0], ax.data(), ay.data(), ac.data(), nullptr));
+    fwrite(ax.data(), 8, n, out);
+    fwrite(ay.data(), 8, n, out);
+    fwrite(ac.data(), 1, n, out);
+    fprintf(stderr, "iterations %d-%d equal\n", it + 1, it + 2);
+  }
+  fclose(out);
+  OK(trime_batch_destroy(b));
+  fprintf(stderr, "ok: %d launches checked, persistent batch equal to the shapes alone\n", nchecks);
+  return 0;
+}
 
 int main(int argc, char **argv) {
   if (argc != 3) return 2;
@@ -108,69 +240,14 @@ int main(int argc, char **argv) {
   scal->area_sel = sc[2];
   scal->n_sel = (int64_t)sc[3];
 
-  memset(&S, 0, sizeof S);
-  S.n = n;
-  S.precision = prec;
-  S.max_deg = 16;
-  S.bin_density = dens;
-  S.grid.nx = nx;
-  S.grid.ny = ny;
-  S.grid.x0 = x0;
-  S.grid.y0 = y0;
-  S.grid.dx = dx;
-  S.grid.dy = dy;
-  S.grid.dtype_bytes = dtb;
-  S.sdf = sdf;
-  S.mu = mu;
-  S.cat_grid = cat;
-  S.hcell = hcell;
-  S.scal = scal;
-  trime_default_params(&S.params);
-  size_t ws = 0;
-  OK(trime_state_workspace_bytes(&S, &ws));
-  void *wsp = alloc(ws);
-  OK(trime_state_bind(&S, wsp, ws, nullptr));
-  // every buffer in an allocation of its own, of the size the layout gives it
-  const int64_t nkeys = S.nkeys_cap > S.nkeys ? S.nkeys_cap : S.nkeys;
-  const int64_t md = S.max_deg;
-  for (int b = 0; b < 2; b++) {
-    S.pos[b].x = (double *)alloc(8 * n);
-    S.pos[b].y = (double *)alloc(8 * n);
-    S.pos[b].dprev = (double *)alloc(8 * n);
-    S.pos[b].cat = (uint8_t *)alloc(n);
-    S.ord[b].id = (int32_t *)alloc(4 * n);
-    S.ord[b].span = (float *)alloc(4 * n);
-    S.ord[b].xl = (double *)alloc(8 * n);
-    S.ord[b].yl = (double *)alloc(8 * n);
-  }
-  S.adj = (int32_t *)alloc(4 * md * n);
-  S.deg = (int32_t *)alloc(4 * n);
-  S.tri = (int32_t *)alloc(4 * 3 * TRIME_TRI_PER_POINT * n);
-  S.tri_valid = (uint8_t *)alloc(TRIME_TRI_PER_POINT * n);
-  S.tri_n = (int32_t *)alloc(4 * (n + 1));
-  S.perm = (int32_t *)alloc(4 * (n + 1));
-  S.key = (int32_t *)alloc(4 * n);
-  S.rank = (int32_t *)alloc(4 * n);
-  S.order = (int32_t *)alloc(4 * n);
-  S.bin_start = (int32_t *)alloc(4 * (nkeys + 1));
-  S.bin_fill = (int32_t *)alloc(4 * nkeys);
-  S.scan_tmp = (int32_t *)alloc(4 * (trime::scan_tmp_ints(nkeys > n ? nkeys : n) + 1));
-  S.queue = (int32_t *)alloc(4 * (3 * (n + 1) + 16 * n + 512));
-  S.counters = (int32_t *)alloc(4 * 32);
-  const int64_t np = trime::dm_partials(n);
-  S.partials = (double *)alloc(8 * 2 * (np > 1 ? np : 1));
-  S.stats = (trime_stats *)alloc(sizeof(trime_stats));
-#ifdef TRIME_WARM
-  S.warm_n = (int32_t *)alloc(4 * n);
-  S.warm_id = (int32_t *)alloc(4 * TRIME_WARM * n);
-  S.slot_of_id = (int32_t *)alloc(4 * n);
-#endif
-  memset(S.counters, 0, 4 * 32);
+  setup(S, n, prec, dens, nx, ny, x0, y0, dx, dy, dtb, sdf, mu, cat, hcell, scal);
   emu::after_launch = check_queues;
 
   double *ex = (double *)alloc(8 * n), *ey = (double *)alloc(8 * n);
   uint8_t *ec = (uint8_t *)alloc(n);
   OK(trime_state_load(&S, x, y, nullptr));
+  if (method >= 2) return run_persistent(method == 3, iters, argv[2], n, x, y, prec, dens, nx, ny, x0, y0, dx, dy,
+                                         dtb, sdf, mu, cat, hcell, scal);
   FILE *out = fopen(argv[2], "wb");
   for (int it = 0; it < iters; it++) {
     if (method == 1)

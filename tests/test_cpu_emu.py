@@ -5,7 +5,10 @@ every pass and the hand-off between them (fast kernel -> FP64 replay and
 deferred-centroid queues -> exact stage), each iteration fed by the previous
 one's output, every buffer of the state in an allocation of its own and the
 queue counts checked against their capacities after every launch.  The
-positions are compared with the oracle's iterations."""
+positions are compared with the oracle's iterations.  The persistent batch
+kernel runs there too (its blocks one after another: the schedule's tables,
+item decoding and every kernel's one-wavefront form, not its waits), against
+the same shapes run alone."""
 import os
 import struct
 import subprocess
@@ -122,3 +125,23 @@ def test_emulated_bin_size_case(orc, exe, tmp_path, prec, density):
     assert st.error == 0
     assert maxq[1] > 0
     check(its, oracle_iterations(orc, og, wl, 3), og, prec)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("method", ["dm", "cvd"])
+def test_emulated_persistent_batch(orc, exe, tmp_path, method, prec):
+    """A persistent batch of two shapes (1,500 holes20 points and the first
+    500 of them, on a 128^2 grid whose box the boundary points' octagons
+    reach): four iterations, after every two the positions, categories and
+    statistics of each shape bit-identical to the shape run alone, no
+    sanitizer report, queues within capacity."""
+    wl = I.holes20(n=1500, grid_n=128, iters=1)
+    og = orc.build_grid(wl)
+    cin, cout = str(tmp_path / "case.bin"), str(tmp_path / "out.bin")
+    write_case(cin, wl, og, prec, 3.3, 4, method=2 if method == "dm" else 3)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([exe, cin, cout], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True,
+                       timeout=1800, env=env)
+    assert r.returncode == 0, r.stdout[-6000:]
+    print(r.stdout.strip().splitlines()[-1], flush=True)

@@ -206,6 +206,111 @@ def test_batch_matches_per_shape_runs(orc, T, method, kind):
     b.close()
 
 
+PERSIST_SKIP = pytest.mark.skip(reason="the persistent batch kernel is switched off: its launches did not "
+                                   "complete on MI355X (a minimal two-shape, two-iteration batch included) "
+                                   "and the cause is not found; its schedule and one-wavefront kernel forms "
+                                   "are checked in the CPU emulation (tests/test_cpu_emu.py)")
+
+
+@PERSIST_SKIP
+def test_persistent_batch_small(orc, T):
+    """The smallest persistent batch: two star shapes, two DistMesh
+    iterations in one launch, against the shapes run alone."""
+    import torch
+    from paper_2309_13824_amd.mesher import Batch
+    wls = I.stars(count=2, grid_n=256, n_range=(3.0, 3.2), seed=1301)
+    grids = [orc.build_grid(w) for w in wls]
+    alone = []
+    for w, g in zip(wls, grids):
+        m = mesher(w, FP64, grid=g)
+        m.step_dm(2, fresh=False)
+        alone.append(m.points())
+    ms = [mesher(w, FP64, grid=g) for w, g in zip(wls, grids)]
+    b = Batch(ms, method="dm", n_iter=2, kind="persistent")
+    print("persistent batch of %d shapes (%s points): launching" % (len(ms), [w.n for w in wls]), flush=True)
+    b.run(2)
+    torch.cuda.synchronize()
+    print("persistent batch: done, errors %s" % [m.stats_raw().error for m in ms], flush=True)
+    for k, m in enumerate(ms):
+        assert m.stats_raw().error == 0, k
+        x, y, c = m.points()
+        assert np.array_equal(x, alone[k][0]) and np.array_equal(y, alone[k][1]), k
+        assert np.array_equal(c, alone[k][2]), k
+    b.close()
+
+
+@PERSIST_SKIP
+@pytest.mark.parametrize("prec", [FP32, FP64])
+@pytest.mark.parametrize("method", ["dm", "cvd", "dm_always"])
+def test_persistent_batch_matches_per_shape_runs(orc, T, method, prec):
+    """The persistent batch (one launch for all iterations, a per-shape work
+    queue) gives, shape by shape, exactly the points, categories and
+    statistics of running each shape alone; items of one fast-cell tile and
+    of several (5) tiles alike."""
+    import torch
+    from paper_2309_13824_amd.mesher import Batch
+    wls = I.stars(count=7, grid_n=256, n_range=(3.0, 3.8), seed=1205)
+    grids = [orc.build_grid(w) for w in wls]
+    alone = []
+    for w, g in zip(wls, grids):
+        m = mesher(w, prec, grid=g)
+        if method == "dm":
+            m.step_dm(4, fresh=False)
+        elif method == "dm_always":
+            m.step_dm(4, fresh=False, always=True)
+        else:
+            m.step_cvd(4)
+        alone.append((m.points(), bytes(m.stats_raw())))
+    for tiles in [(1, 4), (5, 3)]:
+        ms = [mesher(w, prec, grid=g) for w, g in zip(wls, grids)]
+        print("persistent batch %s %s, tiles per item %s: %d shapes, %d points" % (
+            method, "fp32" if prec == FP32 else "fp64", tiles, len(ms), sum(w.n for w in wls)), flush=True)
+        b = Batch(ms, method=method, n_iter=2, kind="persistent", tiles=tiles)
+        b.run(4)
+        torch.cuda.synchronize()
+        print("  done", flush=True)
+        for k, m in enumerate(ms):
+            x, y, c = m.points()
+            assert np.array_equal(x, alone[k][0][0]) and np.array_equal(y, alone[k][0][1]), (tiles, k)
+            assert np.array_equal(c, alone[k][0][2]), (tiles, k)
+            st = m.stats_raw()
+            assert st.error == 0, (tiles, k, st.error)
+            assert bytes(st) == alone[k][1], (tiles, k)
+        b.close()
+
+
+@PERSIST_SKIP
+def test_persistent_batch_replays_in_a_graph(orc, T):
+    """The persistent batch's run (a fill kernel and one launch) captured in
+    a HIP graph and replayed twice (two iterations each), with eager work in
+    between, equals four iterations of each shape alone."""
+    import torch
+    from paper_2309_13824_amd.mesher import Batch
+    wls = I.stars(count=5, grid_n=256, n_range=(3.0, 3.5), seed=1107)
+    grids = [orc.build_grid(w) for w in wls]
+    alone = []
+    for w, g in zip(wls, grids):
+        m = mesher(w, FP32, grid=g)
+        m.step_dm(4, fresh=False)
+        alone.append(m.points())
+    ms = [mesher(w, FP32, grid=g) for w, g in zip(wls, grids)]
+    b = Batch(ms, method="dm", n_iter=2, kind="persistent")
+    s = b.stream
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        T.batch_run(b.batch, 2, s)
+    for r in range(2):
+        g.replay()
+        torch.cuda.synchronize()
+        ms[0].stats_raw()  # eager work between replays
+    for k, m in enumerate(ms):
+        x, y, c = m.points()
+        assert np.array_equal(x, alone[k][0]) and np.array_equal(y, alone[k][1]), k
+        assert np.array_equal(c, alone[k][2]), k
+    b.close()
+
+
 def test_kernel_batch_replays_in_a_graph(orc, T):
     """The batched launches make no host reads: captured in a HIP graph and
     replayed twice (two iterations each), they equal four iterations of each

@@ -1,4 +1,4 @@
-"""Pins of the oracle's triangle validity (Proc. I line 3; Sec. 4.1 Tests
+"""Pins of the oracle's triangle validity (Procedure I's check; Sec. 4.1 Tests
 1-3, with the reading count >= 2 valid, 0 invalid, 1 -> Test 3).
 
 Every case is built by hand on a small grid whose node sdf is the affine
