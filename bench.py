@@ -65,9 +65,13 @@ DM_FLOPS_PER_POINT = 150
 # non-headline workloads, which have no oracle run in the bench)
 FLOPS_PER = {"candidates": 7, "margins": 6, "cuts": 154, "leaves": 57, "point": 1088}
 
+# XCD runs (blocks of the fused cell kernel one L2 takes in a row) the
+# autotuner tries with each bin density
+XCD_RUNS = (1, 4, 8, 16)
+
 # CVD iterations from the seeded points before the autotuner's timing
 TUNE_FROM = 10
-KERNEL_SOURCES = ["cells.hip", "trime_dev.hpp", "geom_dev.hpp", "exact_dev.hpp", "launch.hpp"]
+KERNEL_SOURCES = ["cells_k.hpp", "cells.hip", "trime_dev.hpp", "geom_dev.hpp", "exact_dev.hpp", "launch.hpp"]
 
 
 def kernel_digest():
@@ -145,9 +149,10 @@ def gpu_run(wl, precision, steps, warmup, log, tune=()):
         m.load()
         m.step_cvd(TUNE_FROM)
         px, py, _ = m.points()
-        density, ms = m.autotune(tune, n_iter=4, x=px, y=py)
-        log("  autotune (%s): %s -> %.2f points per bin" % (
-            name, ", ".join("%.2f: %.3f ms" % (d, t) for d, t in sorted(ms.items())), density))
+        density, ms = m.autotune(tune, n_iter=4, x=px, y=py, xcd_runs=XCD_RUNS)
+        log("  autotune (%s): %s -> %.2f points per bin, XCD run %d" % (
+            name, ", ".join("%.2f/%d: %.3f ms" % (d, r, t) for (d, r), t in sorted(ms.items())), density,
+            m.state.xcd_run))
     m.load()
     for _ in range(warmup):
         m.step_cvd(1)
@@ -708,13 +713,15 @@ def main():
     m32.step_cvd(1)
     xe2, ye2, ce2 = m32.points()
     end_state = (xe2, ye2, ce2, np.hypot(xe2 - xe, ye2 - ye))
+    run32 = m32.state.xcd_run
     out = {"metric": METRIC}
     pit = wl.n * args.steps / (ms32 * 1e-3)
     fp64 = None
     if not args.no_fp64:
         m64, ms64, k64, st64, dens64 = gpu_run(wl, T.FP64, args.steps, args.warmup, log, tune)
         fp64 = {"value": wl.n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps,
-                "kernel_ms": k64, "fp32_over_fp64": ms64 / ms32, "bin_density": dens64}
+                "kernel_ms": k64, "fp32_over_fp64": ms64 / ms32, "bin_density": dens64,
+                "xcd_run": m64.state.xcd_run}
         del m64
         torch.cuda.empty_cache()
     del m32
@@ -760,7 +767,7 @@ def main():
         "config": {"workload": "holes20: unit square minus 20 disks, %d^2 f32 sdf grid, %d points, "
                                "Gaussian density, CVD iterations" % (args.grid, args.n),
                    "n_points": wl.n, "grid": args.grid, "method": "cvd",
-                   "precision": "fp32 + fp64 replay", "seed": wl.seed, "bin_density": dens32,
+                   "precision": "fp32 + fp64 replay", "seed": wl.seed, "bin_density": dens32, "xcd_run": run32,
                    "timing": "one HIP graph of all timed iterations, replayed; the fused kernel's duration "
                              "from an eager pass of the same iterations"},
         "roofline": roof, "cpu_baseline": cpu, "fp64": fp64,

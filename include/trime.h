@@ -293,11 +293,19 @@ typedef struct {
   int64_t n_grid;          /* caller: the point count the grid was built for
                               (n_total of trime_sdf_grid_build; 0 -> n, set
                               by bind)                                      */
-  /* neighbours of each point's last cell, by point id, which the next cell
-     of the point clips first (laid out by bind, cleared by load) */
-  int32_t *warm_n;         /* n_cap: count (0: none)                        */
-  int32_t *warm_id;        /* TRIME_WARM * n_cap: neighbour ids             */
-  int32_t *slot_of_id;     /* n_cap: slot of each point id (binning)        */
+  /* the neighbours of each point's last cell, which the point's next cell
+     clips first: in the buffer set of the slot order they were written in,
+     by slot, as slots of that order (laid out by bind, cleared by load) */
+  int32_t *warm_n[2];      /* n_cap each: count (0: none)                   */
+  int32_t *warm_nb[2];     /* TRIME_WARM * n_cap each: neighbour slots      */
+  int32_t *old_slot;       /* n_cap: each slot's slot before the last binning */
+  int32_t *new_slot;       /* n_cap: the slot each previous slot went to    */
+  /* -- placement (tuning only: results do not depend on it) -- */
+  int32_t xcd_run;         /* caller, 0..256: blocks of the fused cell kernel
+                              that one XCD (one L2) takes in a row, the runs
+                              going round the 8 XCDs (0: 8; 1: the
+                              hardware's own round robin); trime_autotune
+                              picks it                                      */
 } trime_state;
 
 /* neighbours kept per point for the next cell */
@@ -632,27 +640,33 @@ trime_status trime_batch_make_persistent(trime_batch *b, int32_t tiles_cells, in
 
 
 /* ---- autotuner (tuning only) ------------------------------------------------
-   The bin size sets how many neighbours a cell scans and how far, and the
-   slot order.  The combinatorial results do not depend on it: every cut
-   decision is exact, so cells, triangles, validity and adjacency are the
-   same for every bin size.  Floating-point results depend on it only through
-   rounding: a cell's vertex list starts at a vertex that follows the order
-   in which the neighbours were clipped, which sets the order of the centroid
-   and quality sums, so positions after a CVD step and the quality sums agree
-   across bin sizes to rounding (within the precision mode's tolerance), not
-   bit for bit.  trime_autotune times n_iter CVD iterations (Alg. 2)
-   from the positions (d_x, d_y) for every candidate density (points per bin)
-   and leaves the state bound to d_ws with the fastest one and loaded with
-   (d_x, d_y).  d_ws must hold trime_autotune_workspace_bytes() bytes (the
-   largest layout of the candidates).  Synchronises the stream once per
-   candidate; creates and destroys two HIP events; allocates no device
-   memory.  ms_out (host, nd entries, may be null) receives each candidate's
-   time per iteration. */
+   Two settings change the speed and not the results.  The bin size sets how
+   many neighbours a cell scans and how far, and the slot order; the XCD run
+   (trime_state.xcd_run) sets which L2 serves which block of the fused cell
+   kernel.  The combinatorial results depend on neither: every cut decision
+   is exact, so cells, triangles, validity and adjacency are the same for
+   every bin size.  Floating-point results depend on the bin size only
+   through rounding: a cell's vertex list starts at a vertex that follows the
+   order in which the neighbours were clipped, which sets the order of the
+   centroid and quality sums, so positions after a CVD step and the quality
+   sums agree across bin sizes to rounding (within the precision mode's
+   tolerance), not bit for bit; the XCD run moves whole blocks between L2s
+   and changes nothing (bit-identical).  trime_autotune times n_iter CVD
+   iterations (Alg. 2) from the positions (d_x, d_y) for every candidate
+   pair (density, XCD run): densities[nd] in points per bin, xcd_runs[nr]
+   (null or nr = 0: the state's own xcd_run only).  It leaves the state
+   bound to d_ws with the fastest pair and loaded with (d_x, d_y), and
+   returns the pair in best_density and best_run (best_run may be null).
+   d_ws must hold trime_autotune_workspace_bytes() bytes (the largest layout
+   of the densities).  Synchronises the stream once per candidate; creates
+   and destroys two HIP events; allocates no device memory.  ms_out (host,
+   nd * max(nr, 1) entries, density-major, may be null) receives each
+   candidate's time per iteration. */
 trime_status trime_autotune_workspace_bytes(const trime_state *st, const double *densities, int32_t nd,
                                             size_t *bytes);
 trime_status trime_autotune(trime_state *st, void *d_ws, size_t bytes, const double *d_x, const double *d_y,
-                            const double *densities, int32_t nd, int32_t n_iter, double *best_density,
-                            float *ms_out, void *stream);
+                            const double *densities, int32_t nd, const int32_t *xcd_runs, int32_t nr,
+                            int32_t n_iter, double *best_density, int32_t *best_run, float *ms_out, void *stream);
 
 #ifdef __cplusplus
 }

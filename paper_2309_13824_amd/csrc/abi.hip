@@ -484,9 +484,12 @@ static void layout(trime_state *st, Layout &L) {
   // FP64 replay queue, exact queue, deferred-centroid queue and its cells
   st->queue = L.take<int32_t>(queue_ints(n));
   st->counters = L.take<int32_t>(CNT_NCOUNTERS);
-  st->warm_n = L.take<int32_t>(n);
-  st->warm_id = L.take<int32_t>((size_t)TRIME_WARM * n);
-  st->slot_of_id = L.take<int32_t>(n);
+  for (int b = 0; b < 2; b++) {
+    st->warm_n[b] = L.take<int32_t>(n);
+    st->warm_nb[b] = L.take<int32_t>((size_t)TRIME_WARM * n);
+  }
+  st->old_slot = L.take<int32_t>(n);
+  st->new_slot = L.take<int32_t>(n);
   int64_t np = dm_partials(n);
   st->partials = L.take<double>(2 * (np > 1 ? np : 1));
   st->stats = L.take<trime_stats>(1);
@@ -510,6 +513,7 @@ static trime_status state_ok(const trime_state *st) {
   if (!st->sdf || !st->mu || !st->cat_grid || !st->hcell || !st->scal)
     return fail(TRIME_EINVAL, "state: grid arrays missing");
   if (st->max_deg < 0 || st->max_deg > 64) return fail(TRIME_EINVAL, "state: max_deg out of range");
+  if (st->xcd_run < 0 || st->xcd_run > 256) return fail(TRIME_EINVAL, "state: xcd_run outside [0, 256]");
   return TRIME_OK;
 }
 
@@ -620,9 +624,13 @@ static KArgs make_args(const trime_state *st) {
   a.stats = st->stats;
   a.prm = st->params;
   a.h_scale = st->h_scale > 0 ? st->h_scale : 1.0;
-  a.warm_n = st->warm_n;
-  a.warm_id = st->warm_id;
-  a.slot_of_id = st->slot_of_id;
+  a.warm_n = st->warm_n[st->cur_ord];
+  a.warm_nb = st->warm_nb[st->cur_ord];
+  a.warm_n_prev = st->warm_n[st->cur_ord ^ 1];
+  a.warm_nb_prev = st->warm_nb[st->cur_ord ^ 1];
+  a.old_slot = st->old_slot;
+  a.new_slot = st->new_slot;
+  a.xcd_run = st->xcd_run > 0 ? st->xcd_run : 8;
   a.precision = st->precision;
   a.ev0 = st->ev_cells[0];
   a.ev1 = st->ev_cells[1];
@@ -657,7 +665,11 @@ trime_status trime_state_load(trime_state *st, const double *d_x, const double *
   launch_load(a, l, st->grid.dtype_bytes, s);
   launch_fill_i32(st->deg, st->n, 0, s);
   launch_fill_i32(st->tri_n, st->n, 0, s);
-  launch_fill_i32(st->warm_n, st->n_cap > st->n ? st->n_cap : st->n, 0, s);
+  const int64_t ncap = st->n_cap > st->n ? st->n_cap : st->n;
+  launch_fill_i32(st->warm_n[0], ncap, 0, s);
+  launch_fill_i32(st->warm_n[1], ncap, 0, s);
+  launch_iota_i32(st->old_slot, ncap, s);
+  launch_iota_i32(st->new_slot, ncap, s);
   return check_hip("trime_state_load");
 }
 
@@ -1362,10 +1374,17 @@ trime_status trime_autotune_workspace_bytes(const trime_state *st_in, const doub
 }
 
 trime_status trime_autotune(trime_state *st, void *d_ws, size_t bytes, const double *d_x, const double *d_y,
-                            const double *dens, int32_t nd, int32_t n_iter, double *best_density, float *ms_out,
-                            void *stream) {
-  if (!st || !d_ws || !d_x || !d_y || !dens || nd <= 0 || n_iter <= 0 || !best_density)
+                            const double *dens, int32_t nd, const int32_t *runs, int32_t nr, int32_t n_iter,
+                            double *best_density, int32_t *best_run, float *ms_out, void *stream) {
+  if (!st || !d_ws || !d_x || !d_y || !dens || nd <= 0 || n_iter <= 0 || !best_density || nr < 0)
     return fail(TRIME_EINVAL, "trime_autotune: bad argument");
+  const int32_t own = st->xcd_run;
+  if (!runs || nr == 0) {
+    runs = &own;
+    nr = 1;
+  }
+  for (int j = 0; j < nr; j++)
+    if (runs[j] < 0 || runs[j] > 256) return fail(TRIME_EINVAL, "trime_autotune: XCD run outside [0, 256]");
   size_t need = 0;
   trime_status e = trime_autotune_workspace_bytes(st, dens, nd, &need);
   if (e) return e;
@@ -1378,34 +1397,41 @@ trime_status trime_autotune(trime_state *st, void *d_ws, size_t bytes, const dou
     return fail(TRIME_EHIP, "trime_autotune: event");
   }
   double best = dens[0];
+  int32_t best_r = runs[0];
   float best_ms = INFINITY;
   for (int i = 0; i < nd && !e; i++) {
     st->bin_density = dens[i];
     e = trime_state_bind(st, d_ws, bytes, stream);
-    if (!e) e = trime_state_load(st, d_x, d_y, stream);
-    if (!e) e = trime_step_cvd(st, 1, stream);  // warm-up
-    if (!e && hipEventRecord(t0, s) != hipSuccess) e = fail(TRIME_EHIP, "trime_autotune: record");
-    if (!e) e = trime_step_cvd(st, n_iter, stream);
-    if (!e && hipEventRecord(t1, s) != hipSuccess) e = fail(TRIME_EHIP, "trime_autotune: record");
-    if (!e && hipEventSynchronize(t1) != hipSuccess) e = fail(TRIME_EHIP, "trime_autotune: sync");
-    float ms = 0;
-    if (!e && hipEventElapsedTime(&ms, t0, t1) != hipSuccess) e = fail(TRIME_EHIP, "trime_autotune: time");
-    if (e) break;
-    ms /= (float)n_iter;
-    if (ms_out) ms_out[i] = ms;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = dens[i];
+    for (int j = 0; j < nr && !e; j++) {
+      st->xcd_run = runs[j];
+      e = trime_state_load(st, d_x, d_y, stream);
+      if (!e) e = trime_step_cvd(st, 1, stream);  // warm-up
+      if (!e && hipEventRecord(t0, s) != hipSuccess) e = fail(TRIME_EHIP, "trime_autotune: record");
+      if (!e) e = trime_step_cvd(st, n_iter, stream);
+      if (!e && hipEventRecord(t1, s) != hipSuccess) e = fail(TRIME_EHIP, "trime_autotune: record");
+      if (!e && hipEventSynchronize(t1) != hipSuccess) e = fail(TRIME_EHIP, "trime_autotune: sync");
+      float ms = 0;
+      if (!e && hipEventElapsedTime(&ms, t0, t1) != hipSuccess) e = fail(TRIME_EHIP, "trime_autotune: time");
+      if (e) break;
+      ms /= (float)n_iter;
+      if (ms_out) ms_out[(size_t)i * nr + j] = ms;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = dens[i];
+        best_r = runs[j];
+      }
     }
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (e) return e;
   st->bin_density = best;
+  st->xcd_run = best_r;
   e = trime_state_bind(st, d_ws, bytes, stream);
   if (!e) e = trime_state_load(st, d_x, d_y, stream);
   if (e) return e;
   *best_density = best;
+  if (best_run) *best_run = best_r;
   return TRIME_OK;
 }
 

@@ -51,6 +51,16 @@ void launch_bin(const KArgs &a, const GatherArgs &g, int64_t nkeys, int32_t *sca
   }
 }
 
+// p[i] = i (grid-stride).
+__global__ void k_iota_i32(int32_t *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (int32_t)i;
+}
+
+void launch_iota_i32(int32_t *p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota_i32, dim3(256), dim3(256), 0, s, p, n);
+}
+
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3(256), dim3(256), 0, s, p, n, v);
 }

@@ -311,6 +311,10 @@ TRIME_D void BinPlace::body(const Args &A, Blk blk, int t) {
   const int64_t k = (int64_t)blk.id * BLOCK + t;
   if (k >= a.n) return;
   if (cond_off(a)) {
+    if (a.old_slot) {
+      a.old_slot[k] = (int32_t)k;
+      a.new_slot[k] = (int32_t)k;
+    }
     g.xo[k] = g.x[k];
     g.yo[k] = g.y[k];
     g.dprevo[k] = g.dprev[k];
@@ -335,7 +339,10 @@ TRIME_D void BinPlace::body(const Args &A, Blk blk, int t) {
   g.cato[s] = c;
   const int id = g.id[k];
   g.ido[s] = id;
-  if (a.slot_of_id) a.slot_of_id[id] = (int32_t)s;
+  if (a.old_slot) {
+    a.old_slot[s] = (int32_t)k;
+    a.new_slot[k] = (int32_t)s;
+  }
   g.spano[s] = span_at(a, x, y);
   a.rank[s] = c == TRIME_CAT_BOUNDARY ? 1 : 0;
 }

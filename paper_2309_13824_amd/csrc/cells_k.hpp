@@ -1183,12 +1183,22 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   // prune most bins, and later candidates rarely cut.  The cell does not
   // depend on the order of the cuts (every decision is exact); the scan still
   // visits every bin within reach.
+  // The previous cell's neighbours first: the list the point wrote before
+  // the last binning, at its slot then, its entries slots of that order
+  // mapped to this one.  Any list gives the same cell (every cut is exact);
+  // indices outside [0, n) (a list older than the last load or addition of
+  // points) are skipped.
   TRIME_D void warm() {
     const T u = U<T>::v;
-    const int m = gld(a.warm_n, (int64_t)pid);
+    const int64_t ko = gld(a.old_slot, k);
+    if (ko < 0 || ko >= a.n) return;
+    int m = gld(a.warm_n_prev, ko);
+    m = m < 0 ? 0 : (m > TRIME_WARM ? TRIME_WARM : m);
     for (int t = 0; t < m; t++) {
-      const int q = gld(a.slot_of_id, (int64_t)gld(a.warm_id, (int64_t)pid * TRIME_WARM + t));
-      if (q == (int)k) continue;
+      const int e = gld(a.warm_nb_prev, ko * TRIME_WARM + t);
+      if (e < 0 || e >= a.n) continue;
+      const int q = gld(a.new_slot, (int64_t)e);
+      if (q < 0 || q >= a.n || q == (int)k) continue;
       const double qx = gld(a.x, q), qy = gld(a.y, q);
       Row<T> r3;
       r3.nx = (T)(qx - px);
@@ -1204,14 +1214,15 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     }
   }
 
-  // The ids of the cell's neighbours, for the point's next cell.
+  // The slots of the cell's neighbours, for the point's next cell, at the
+  // point's slot.
   TRIME_D void keep_neighbours() {
     int t = 0;
     for (int j = 0; j < n; j++) {
       const int c = con(j);
-      if (c >= 0 && t < TRIME_WARM) gst(a.warm_id, (int64_t)pid * TRIME_WARM + t++, gld(a.id, c));
+      if (c >= 0 && t < TRIME_WARM) gst(a.warm_nb, k * TRIME_WARM + t++, (int32_t)c);
     }
-    gst(a.warm_n, (int64_t)pid, t);
+    gst(a.warm_n, k, t);
   }
 
   // Everything for point k; returns false when the point must be replayed.
@@ -1612,21 +1623,18 @@ TRIME_D void push(const KArgs &a, int which, int64_t k, int why) {
   atomicAdd(&a.counters[CNT_REASON + why], 1);
 }
 
-#ifndef TRIME_XCD_RUN
-#define TRIME_XCD_RUN 8
-#endif
 // The part of the processing order a block takes.  Blocks are dispatched to
-// the 8 XCDs (each with its own L2) in turn; here each XCD takes runs of
-// TRIME_XCD_RUN consecutive blocks, the runs going round the XCDs, so that
-// neighbouring blocks, which read the same bins and positions, share an L2
-// while the work stays spread over the XCDs.  b: the block within its shape,
-// p: its block in the launch (a batch puts shapes one after another), whose
-// residue mod 8 names the XCD.  A bijection of [0, nb): the groups of 8 runs
-// are counted from the launch's block 0, and blocks outside a whole group
-// keep their place.
-TRIME_D uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t p) {
-  constexpr uint32_t C = TRIME_XCD_RUN, G = 8u * TRIME_XCD_RUN;
+// the 8 XCDs (each with its own L2) in turn; here each XCD takes runs of C
+// consecutive blocks (the state's XCD run, 8 by default, tuned), the runs
+// going round the XCDs, so that neighbouring blocks, which read the same
+// bins and positions, share an L2 while the work stays spread over the
+// XCDs.  b: the block within its shape, p: its block in the launch (a batch
+// puts shapes one after another), whose residue mod 8 names the XCD.  A
+// bijection of [0, nb) for every C: the groups of 8 runs are counted from
+// the launch's block 0, and blocks outside a whole group keep their place.
+TRIME_D uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t p, uint32_t C) {
   if (C <= 1) return b;
+  const uint32_t G = 8u * C;
   const uint32_t r = (p - b) % G;  // where the shape starts within a group
   const uint32_t s = b + r;        // position counted from that group's start
   const uint32_t g0 = s - s % G;
@@ -1667,7 +1675,8 @@ template <class T, class G, int MODE, int VMAX, int B> struct Cells {
     __shared__ int hist[40];
     zero_hist<B>(hist);
     LaneStats st;
-    point<B>(a, (int64_t)xcd_block(blk.id, blk.n, blockIdx.x) * B + threadIdx.x, P, threadIdx.x, st, hist);
+    point<B>(a, (int64_t)xcd_block(blk.id, blk.n, blockIdx.x, (uint32_t)a.xcd_run) * B + threadIdx.x, P, threadIdx.x,
+             st, hist);
     flush_stats<B>(a, st, hist);
   }
   // The work of block blk by one wavefront (a block of 64 threads), 64 of

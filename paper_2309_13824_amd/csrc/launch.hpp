@@ -165,6 +165,7 @@ void launch_cells(const KArgs &a, int mode, int grid_bytes, hipStream_t s);
 void launch_bin(const KArgs &a, const GatherArgs &g, int64_t nkeys, int32_t *scan_tmp, hipStream_t s,
                 int32_t reset = -1);
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+void launch_iota_i32(int32_t *p, int64_t n, hipStream_t s);
 void scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp, hipStream_t s,
               const int32_t *cond = nullptr);
 size_t scan_tmp_ints(int64_t n);

@@ -82,7 +82,12 @@ struct KArgs {
   double h_scale;
   // neighbours of each point's last cell by id (clipped first), and the slot
   // of each id in the current binning
-  int32_t *warm_n, *warm_id, *slot_of_id;
+  // warm start: the lists of the previous slot order (read), of this one
+  // (written), and the slot maps of the last binning
+  const int32_t *warm_n_prev, *warm_nb_prev;
+  int32_t *warm_n, *warm_nb;
+  int32_t *old_slot, *new_slot;
+  int32_t xcd_run;  // blocks per XCD run of the fused cell kernel (>= 1)
 };
 
 // Whether a conditional launch has work (uniform over the grid).

@@ -110,10 +110,13 @@ class Mesher:
         ncons = ncons.cpu().numpy()
         return [tuple(int(v) for v in cons[i, :ncons[i]]) if ncons[i] >= 0 else None for i in range(self.n)]
 
-    def autotune(self, densities=(2.0, 3.3, 5.0, 8.0), n_iter=3, x=None, y=None):
-        """Picks the bin density (points per bin) with the fastest CVD
-        iterations on this workload; the state is left loaded with (x, y).
-        The results do not depend on the choice."""
+    def autotune(self, densities=(2.0, 3.3, 5.0, 8.0), n_iter=3, x=None, y=None, xcd_runs=None):
+        """Picks the bin density (points per bin) and, given xcd_runs, the
+        XCD run of the fused cell kernel with the fastest CVD iterations on
+        this workload; the state is left loaded with (x, y).  Returns the
+        density and the ms of every candidate (keyed by density, or by
+        (density, run) when xcd_runs is given).  The results do not depend
+        on the choice."""
         torch = self.torch
         need = T.autotune_workspace_bytes(self.state, densities)
         if need > self.ws.numel():
@@ -122,8 +125,11 @@ class Mesher:
         y = self.wl.y if y is None else y
         self.x_in = torch.as_tensor(np.ascontiguousarray(x, np.float64), device=self.dev)
         self.y_in = torch.as_tensor(np.ascontiguousarray(y, np.float64), device=self.dev)
-        best, ms = T.autotune(self.state, self.ws, self.x_in, self.y_in, densities, n_iter)
-        return best, dict(zip(densities, ms))
+        best, run, ms = T.autotune(self.state, self.ws, self.x_in, self.y_in, densities, n_iter, xcd_runs)
+        if not xcd_runs:
+            return best, dict(zip(densities, ms))
+        keys = [(d, r) for d in densities for r in xcd_runs]
+        return best, dict(zip(keys, ms))
 
     def step_dm(self, n_iter, fresh=True, always=False):
         T.step_dm(self.state, n_iter, fresh, always)

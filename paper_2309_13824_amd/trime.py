@@ -117,8 +117,9 @@ class State(C.Structure):
                 ("nbx", C.c_int32), ("nby", C.c_int32), ("lbits", C.c_int32), ("bx0", C.c_double),
                 ("by0", C.c_double), ("bw", C.c_double), ("area_sel", C.c_double), ("nkeys", C.c_int64),
                 ("ev_cells", C.c_void_p * 2), ("n_cap", C.c_int64), ("h_scale", C.c_double),
-                ("nkeys_cap", C.c_int64), ("n_grid", C.c_int64), ("warm_n", C.c_void_p),
-                ("warm_id", C.c_void_p), ("slot_of_id", C.c_void_p)]
+                ("nkeys_cap", C.c_int64), ("n_grid", C.c_int64), ("warm_n", C.c_void_p * 2),
+                ("warm_nb", C.c_void_p * 2), ("old_slot", C.c_void_p), ("new_slot", C.c_void_p),
+                ("xcd_run", C.c_int32)]
 
 
 ADAPT_DM, ADAPT_CVD, ADAPT_HYBRID = 0, 1, 2
@@ -190,8 +191,8 @@ def lib(require_gpu: bool = True):
         L.trime_stats_check.argtypes = [C.POINTER(Stats)]
         dp = C.POINTER(C.c_double)
         L.trime_autotune_workspace_bytes.argtypes = [st, dp, C.c_int32, C.POINTER(C.c_size_t)]
-        L.trime_autotune.argtypes = [st, vp, C.c_size_t, vp, vp, dp, C.c_int32, C.c_int32, dp,
-                                     C.POINTER(C.c_float), vp]
+        L.trime_autotune.argtypes = [st, vp, C.c_size_t, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                                     C.c_int32, dp, C.POINTER(C.c_int32), C.POINTER(C.c_float), vp]
         L.trime_batch_graph_create.argtypes = [C.POINTER(st), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                                C.POINTER(vp), vp]
         L.trime_graph_launch.argtypes = [vp, vp]
@@ -354,14 +355,19 @@ def autotune_workspace_bytes(state, densities) -> int:
     return n.value
 
 
-def autotune(state, ws, x, y, densities, n_iter, stream=None):
-    """Returns (best density, ms per iteration of each candidate)."""
+def autotune(state, ws, x, y, densities, n_iter, xcd_runs=None, stream=None):
+    """Returns (best density, best XCD run, ms per iteration of each
+    (density, run) candidate, density-major)."""
     d = (C.c_double * len(densities))(*densities)
-    ms = (C.c_float * len(densities))()
+    runs = list(xcd_runs) if xcd_runs else []
+    r = (C.c_int32 * max(len(runs), 1))(*(runs or [0]))
+    ms = (C.c_float * (len(densities) * max(len(runs), 1)))()
     best = C.c_double(0)
+    best_r = C.c_int32(0)
     _check(lib().trime_autotune(C.byref(state), _ptr(ws), ws.numel() * ws.element_size(), _ptr(x), _ptr(y), d,
-                                len(densities), int(n_iter), C.byref(best), ms, _stream(stream)))
-    return best.value, list(ms)
+                                len(densities), r if runs else None, len(runs), int(n_iter), C.byref(best),
+                                C.byref(best_r), ms, _stream(stream)))
+    return best.value, best_r.value, list(ms)
 
 
 def batch_graph_create(states, method, n_iter, nstreams, stream):

@@ -129,11 +129,12 @@ static void setup(trime_state &T, int64_t n, int32_t prec, double dens, int32_t 
   const int64_t np = trime::dm_partials(n);
   T.partials = (double *)alloc(8 * 2 * (np > 1 ? np : 1));
   T.stats = (trime_stats *)alloc(sizeof(trime_stats));
-#ifdef TRIME_WARM
-  T.warm_n = (int32_t *)alloc(4 * n);
-  T.warm_id = (int32_t *)alloc(4 * TRIME_WARM * n);
-  T.slot_of_id = (int32_t *)alloc(4 * n);
-#endif
+  for (int b = 0; b < 2; b++) {
+    T.warm_n[b] = (int32_t *)alloc(4 * n);
+    T.warm_nb[b] = (int32_t *)alloc(4 * TRIME_WARM * n);
+  }
+  T.old_slot = (int32_t *)alloc(4 * n);
+  T.new_slot = (int32_t *)alloc(4 * n);
   memset(T.counters, 0, 4 * 32);
 
   all_states.push_back(&T);

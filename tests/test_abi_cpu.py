@@ -185,6 +185,34 @@ def test_batch_arguments_rejected_on_host(T):
     assert L.trime_batch_destroy(None) == 0
 
 
+def test_placement_and_persistent_batch_rejected_on_host(T):
+    """An XCD run outside [0, 256] is refused by every entry point that
+    checks the state; trime_autotune refuses such a candidate; the
+    persistent batch refuses to switch on (it is built out of the device
+    library), leaving the batch as it was."""
+    L = T.lib(require_gpu=False)
+    st = T.State()
+    st.n = 10
+    st.grid = T.Grid(16, 16, 0.0, 0.0, 0.1, 0.1, 8)
+    st.sdf = st.mu = st.cat_grid = st.hcell = st.scal = 256
+    st.stats = 512
+    st.pos[0].x = 768
+    st.n_cap = 20
+    for bad in (-1, 257):
+        st.xcd_run = bad
+        assert L.trime_add_points(C.byref(st), 1, None) == 1
+        assert b"xcd_run" in L.trime_last_error()
+    st.xcd_run = 0
+    d = (C.c_double * 1)(2.0)
+    runs = (C.c_int32 * 2)(8, 300)
+    best, best_r = C.c_double(0), C.c_int32(0)
+    assert L.trime_autotune(C.byref(st), C.c_void_p(256), 1 << 20, C.c_void_p(256), C.c_void_p(256), d, 1, runs, 2,
+                            2, C.byref(best), C.byref(best_r), None, None) == 1
+    assert b"trime_autotune" in L.trime_last_error()
+    assert L.trime_batch_make_persistent(None, 1, 4) == 1
+    assert b"switched off" in L.trime_last_error()
+
+
 def test_stats_check_codes(T):
     L = T.lib(require_gpu=False)
     s = T.Stats()

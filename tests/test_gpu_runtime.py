@@ -87,20 +87,35 @@ def test_results_do_not_depend_on_bin_size(orc, T, prec):
 
 
 def test_autotuner_picks_a_candidate_and_keeps_results(orc, T):
+    """The autotuner over (bin density, XCD run) picks a candidate pair,
+    leaves the state loaded with the seeded points, and the run it picks
+    gives the results of the default placement bit for bit."""
     wl = I.annulus(n=4000, grid_n=256)
     og = orc.build_grid(wl)
     m = mesher(wl, FP32, grid=og)
     m.step_cvd(2)
     x0, y0, c0 = m.points()
-    cands = (2.0, 3.3, 6.0)
-    best, ms = m.autotune(cands, n_iter=2)
-    assert best in cands
+    cands, runs = (2.0, 3.3, 6.0), (1, 3, 8, 16)
+    best, ms = m.autotune(cands, n_iter=2, xcd_runs=runs)
+    assert best in cands and m.state.xcd_run in runs
+    assert set(ms) == {(d, r) for d in cands for r in runs}
     assert all(v > 0 for v in ms.values())
     m.step_cvd(2)  # the tuner leaves the state loaded with the seeded points
     x1, y1, c1 = m.points()
     err = np.hypot(x1 - x0, y1 - y0) / h_of(og, x0, y0)
     assert err.max() <= 1e-5, err.max()
     assert np.array_equal(c0, c1)
+    # the XCD run moves whole blocks between L2s: bit-identical results
+    for run in runs:
+        m.state.xcd_run = run
+        m.load()
+        m.step_cvd(2)
+        x2, y2, c2 = m.points()
+        m.state.xcd_run = 0
+        m.load()
+        m.step_cvd(2)
+        x3, y3, c3 = m.points()
+        assert np.array_equal(x2, x3) and np.array_equal(y2, y3) and np.array_equal(c2, c3), run
 
 
 def test_graph_capture_replays_match_eager(orc, T):
