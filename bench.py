@@ -55,9 +55,10 @@ FLOPS_PER_POINT_FIXED = 180 + 60
 BYTES_PER_POINT = {"fp32": 16 + 101 + 64 + 37, "fp64": 20 + 101 + 64 + 37}
 
 # HBM traffic of one launch of the fused kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (first two CVD iterations, scaled by a 1 GiB copy: FETCH x 2.0,
+# WRITE_SIZE (the mean of its last two launches in a short run: the timed
+# CVD iteration 2 and the next one; scaled by a 1 GiB copy: FETCH x 2.0,
 # WRITE x 1.0), valid for the kernel sources with this digest only.
-TRAFFIC = {"sha1": "05db16e10958f712c6a7a92bb2cd27bb3d4934d3", "bytes_per_launch": 341257508.3}
+TRAFFIC = {"sha1": "470ae32c3d820b0a4dc5e5753636e12f2d681388", "bytes_per_launch": 491262258.5}
 # counted flops per point of the DistMesh force gather (edge forces over the
 # adjacency row, forward Euler, treatment checks)
 DM_FLOPS_PER_POINT = 150
@@ -767,7 +768,7 @@ def main():
         "config": {"workload": "holes20: unit square minus 20 disks, %d^2 f32 sdf grid, %d points, "
                                "Gaussian density, CVD iterations" % (args.grid, args.n),
                    "n_points": wl.n, "grid": args.grid, "method": "cvd",
-                   "precision": "fp32 + fp64 replay", "seed": wl.seed, "bin_density": dens32, "xcd_run": run32,
+                   "precision": "fp32 cut and octagon margins (fp64 re-evaluation inside their error bound, fp64 replay of points left undecided); vertices, positions and centroid sums in fp64", "seed": wl.seed, "bin_density": dens32, "xcd_run": run32,
                    "timing": "one HIP graph of all timed iterations, replayed; the fused kernel's duration "
                              "from an eager pass of the same iterations"},
         "roofline": roof, "cpu_baseline": cpu, "fp64": fp64,
