@@ -3,7 +3,13 @@
 // collective; a barrier opens once every live thread of the block (or of the
 // wavefront) has reached it.  A collective reached by only part of a
 // wavefront, or a block waiting on two different barriers, is reported and
-// aborts the run.
+// aborts the run.  A thread that sleeps or fences (as the persistent kernel
+// does while it waits and between its work items) parks its block: the
+// scheduler goes on with another block (starting the next one while fewer
+// than SLOTS are under way) and comes back to the parked one in turn, so
+// blocks that wait on each other's progress interleave.  A block runs alone
+// between its parking points (LDS, static here, is shared by the blocks
+// under way).
 #include <time.h>
 #include <hip/hip_runtime.h>
 
@@ -48,7 +54,7 @@ emu_switch:
 
 namespace emu {
 
-enum { RUN = 0, AT_BARRIER = 1, AT_WAVE = 2, DONE = 3 };
+enum { RUN = 0, AT_BARRIER = 1, AT_WAVE = 2, DONE = 3, PARKED = 4 };
 
 struct Fiber {
   void *sp = nullptr;  // saved stack pointer while switched out
@@ -65,13 +71,22 @@ struct Wave {
   uint64_t buf[2][64];
 };
 
+// A block under way: its threads are fibers[f0, f0 + nt) of the pool.
+struct Block {
+  uint32_t idx = 0;
+  int f0 = 0;
+  std::vector<Wave> waves;
+};
+static const int SLOTS = 8;
+
 Fiber *cur = nullptr;
 dim3 block_idx, grid_dim, block_dim;
 static void *sched_sp = nullptr;
 static const void *sched_bottom = nullptr;
 static size_t sched_size = 0;
 static std::vector<Fiber> fibers;
-static std::vector<Wave> waves;
+static Block *cur_block = nullptr;
+static int cur_nt = 0;
 static const std::function<void()> *body = nullptr;
 static const size_t STACK = 1 << 20;
 void (*after_launch)() = nullptr;  // set by a test driver: checks after every launch
@@ -125,8 +140,18 @@ void block_barrier() {
   yield_to_scheduler();
 }
 
+long parks = 0;         // sleeps and fences that parked a thread (read by test drivers)
+long blocks_waited = 0;  // times the scheduler turned to another block
+
+void sleep_park() {
+  parks++;
+  cur->state = PARKED;
+  yield_to_scheduler();
+}
+
 const uint64_t *wave_exchange(uint64_t v) {
   const unsigned g = cur->wgen++ & 1u;
+  std::vector<Wave> &waves = cur_block->waves;
   waves[cur->wave].buf[g][cur->lane] = v;
   cur->state = AT_WAVE;
   yield_to_scheduler();
@@ -146,16 +171,19 @@ static void run_fiber(Fiber &f) {
   cur = nullptr;
 }
 
-// Opens the barriers whose threads have all arrived; false when none could.
-static bool release() {
+// Opens the barriers of block B whose threads have all arrived; false when
+// none could.
+static bool release(Block &B) {
   bool any = false;
-  const int nt = (int)fibers.size();
+  const int nt = cur_nt;
+  Fiber *fib = &fibers[B.f0];
+  std::vector<Wave> &waves = B.waves;
   for (size_t w = 0; w < waves.size(); w++) {
     int waiting = 0, live = 0;
     unsigned gen = 0;
     bool mixed = false;
     for (int t = (int)w * 64; t < nt && t < (int)(w + 1) * 64; t++) {
-      Fiber &f = fibers[t];
+      Fiber &f = fib[t];
       if (f.state == DONE) continue;
       live++;
       if (f.state == AT_WAVE) {
@@ -169,34 +197,59 @@ static bool release() {
     const unsigned g = (gen - 1) & 1u;  // the buffer of the collective they wait at
     for (int l = 0; l < 64; l++) {
       const int t = (int)w * 64 + l;
-      if (t >= nt || fibers[t].state == DONE) waves[w].buf[g][l] = 0;
+      if (t >= nt || fib[t].state == DONE) waves[w].buf[g][l] = 0;
     }
     for (int t = (int)w * 64; t < nt && t < (int)(w + 1) * 64; t++)
-      if (fibers[t].state == AT_WAVE) fibers[t].state = RUN;
+      if (fib[t].state == AT_WAVE) fib[t].state = RUN;
     any = true;
   }
   if (any) return true;
   int live = 0, bar = 0;
-  for (Fiber &f : fibers) {
-    if (f.state == DONE) continue;
+  for (int t = 0; t < nt; t++) {
+    if (fib[t].state == DONE) continue;
     live++;
-    bar += f.state == AT_BARRIER;
+    bar += fib[t].state == AT_BARRIER;
   }
   if (live && bar == live) {
-    for (Fiber &f : fibers)
-      if (f.state == AT_BARRIER) f.state = RUN;
+    for (int t = 0; t < nt; t++)
+      if (fib[t].state == AT_BARRIER) fib[t].state = RUN;
     return true;
   }
   return false;
+}
+
+// Runs block B until it finishes (true) or one of its threads parks (false).
+static bool run_block(Block &B) {
+  block_idx = dim3(B.idx);
+  cur_block = &B;
+  Fiber *fib = &fibers[B.f0];
+  for (int t = 0; t < cur_nt; t++)
+    if (fib[t].state == PARKED) fib[t].state = RUN;
+  for (;;) {
+    bool ran = false, parked = false;
+    for (int t = 0; t < cur_nt; t++)
+      if (fib[t].state == RUN) {
+        run_fiber(fib[t]);
+        ran = true;
+        parked |= fib[t].state == PARKED;
+      }
+    int done = 0;
+    for (int t = 0; t < cur_nt; t++) done += fib[t].state == DONE;
+    if (done == cur_nt) return true;
+    if (parked) return false;
+    if (ran) continue;
+    if (!release(B)) die("deadlock: threads wait at different barriers");
+  }
 }
 
 void launch(dim3 grid, dim3 block, const std::function<void()> &fn) {
   if (block.y != 1 || block.z != 1 || grid.y != 1 || grid.z != 1) die("only 1-D launches are emulated");
   const int nt = (int)block.x;
   if (nt <= 0 || nt > 1024) die("bad block size");
-  if ((int)fibers.size() < nt) {
+  const size_t need = (size_t)SLOTS * nt;
+  if (fibers.size() < need) {
     size_t old = fibers.size();
-    fibers.resize(nt);
+    fibers.resize(need);
     for (size_t t = old; t < fibers.size(); t++) {
       fibers[t].stack = (char *)malloc(STACK);
       fibers[t].ssize = STACK;
@@ -205,15 +258,21 @@ void launch(dim3 grid, dim3 block, const std::function<void()> &fn) {
   grid_dim = grid;
   block_dim = block;
   body = &fn;
-  waves.assign((nt + 63) / 64, Wave{});
-  for (uint32_t b = 0; b < grid.x; b++) {
-    block_idx = dim3(b);
-    for (int t = 0; t < (int)fibers.size(); t++) {
-      Fiber &f = fibers[t];
-      if (t >= nt) {
-        f.state = DONE;
-        continue;
-      }
+  cur_nt = nt;
+  std::vector<Block> slot(SLOTS);
+  std::vector<int> active;  // slots under way, in turn order
+  std::vector<int> free_slots;
+  for (int k = SLOTS - 1; k >= 0; k--) free_slots.push_back(k);
+  uint32_t next = 0;
+  auto start = [&](uint32_t b) {
+    const int k = free_slots.back();
+    free_slots.pop_back();
+    Block &B = slot[k];
+    B.idx = b;
+    B.f0 = k * nt;
+    B.waves.assign((nt + 63) / 64, Wave{});
+    for (int t = 0; t < nt; t++) {
+      Fiber &f = fibers[B.f0 + t];
       f.tid = dim3((uint32_t)t);
       f.lane = t & 63;
       f.wave = t >> 6;
@@ -221,21 +280,22 @@ void launch(dim3 grid, dim3 block, const std::function<void()> &fn) {
       f.wgen = 0;
       f.sp = fresh_stack(f);
     }
-    const int total = nt;
-    for (;;) {
-      bool ran = false;
-      for (int t = 0; t < total; t++)
-        if (fibers[t].state == RUN) {
-          run_fiber(fibers[t]);
-          ran = true;
-        }
-      int done = 0;
-      for (int t = 0; t < total; t++) done += fibers[t].state == DONE;
-      if (done == total) break;
-      if (ran) continue;
-      if (!release()) die("deadlock: threads wait at different barriers");
+    active.push_back(k);
+  };
+  while (next < grid.x || !active.empty()) {
+    if (active.empty()) start(next++);
+    const int k = active.front();
+    active.erase(active.begin());
+    if (run_block(slot[k])) {
+      free_slots.push_back(k);
+      continue;
     }
+    // parked: another block goes first (a new one while a slot is free)
+    blocks_waited++;
+    if (next < grid.x && !free_slots.empty()) start(next++);
+    active.push_back(k);
   }
+  cur_block = nullptr;
   body = nullptr;
   if (after_launch) after_launch();
 }
@@ -309,10 +369,10 @@ hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipErrorNotSuppo
 hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
 hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
 hipError_t hipLaunchKernel(const void *, dim3, dim3, void **, size_t, hipStream_t) { return hipErrorNotSupported; }
-// two "CUs" holding one block each; a wall clock of 100 MHz
+// four "CUs" holding one block each; a wall clock of 100 MHz
 hipError_t hipDeviceGetAttribute(int *v, int attr, int) {
   if (attr == hipDeviceAttributeMultiprocessorCount) {
-    *v = 2;
+    *v = 4;
     return hipSuccess;
   }
   if (attr == hipDeviceAttributeWallClockRate) {
@@ -325,10 +385,12 @@ hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *nb, const void *, i
   *nb = 1;
   return hipSuccess;
 }
+// ticks at a tenth of the 100 MHz it claims: emulated kernels run far slower
+// than the device, and a launch-wide deadline must not pass for that alone
 uint64_t wall_clock64() {
   struct timespec t;
   clock_gettime(CLOCK_MONOTONIC, &t);
-  return (uint64_t)t.tv_sec * 100000000ull + (uint64_t)t.tv_nsec / 10ull;
+  return (uint64_t)t.tv_sec * 10000000ull + (uint64_t)t.tv_nsec / 100ull;
 }
 hipError_t hipGetDevice(int *d) {
   *d = 0;

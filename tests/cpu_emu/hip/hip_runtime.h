@@ -54,6 +54,8 @@ extern Fiber *cur;            // the running thread of the block
 extern dim3 block_idx, grid_dim, block_dim;
 const dim3 &thread_idx();
 void block_barrier();
+// a sleeping thread parks its block (another block runs meanwhile)
+void sleep_park();
 // Exchanges 8 bytes per lane within the wavefront: every live lane of the
 // wavefront stores its value, waits for the others, and gets the buffer.
 const uint64_t *wave_exchange(uint64_t v);
@@ -159,13 +161,15 @@ template <class T, class U> inline T atomicExch(T *p, U v) {
 }
 
 // the wavefront-wide intrinsics of the persistent kernel (its scoped atomics
-// are clang builtins on the host too; the fences and sleeps are no-ops on
-// one OS thread)
+// are clang builtins on the host too).  A sleep and a fence park the block:
+// the persistent kernel sleeps while it waits and fences between work items,
+// so blocks take turns there, as they would run side by side on the device
+// (a fence has nothing to order on one OS thread).
 #ifndef __HIP_MEMORY_SCOPE_AGENT
 #define __HIP_MEMORY_SCOPE_AGENT 3
 #endif
-#define __builtin_amdgcn_fence(order, scope) ((void)0)
-#define __builtin_amdgcn_s_sleep(n) ((void)0)
+#define __builtin_amdgcn_fence(order, scope) emu::sleep_park()
+#define __builtin_amdgcn_s_sleep(n) emu::sleep_park()
 #define __builtin_amdgcn_wave_barrier() ((void)0)
 // the first lane's value in every lane (lane 0 is always live where used)
 #define __builtin_amdgcn_readfirstlane(x) __shfl((x), 0)

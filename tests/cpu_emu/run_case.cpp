@@ -26,6 +26,7 @@ int dm_partials(int64_t n);
 }
 namespace emu {
 extern void (*after_launch)();
+extern long parks, blocks_waited;
 }
 
 static trime_state S;
@@ -198,7 +199,8 @@ static int run_persistent(bool cvd, int iters, const char *outp, int64_t n, doub
   }
   fclose(out);
   OK(trime_batch_destroy(b));
-  fprintf(stderr, "ok: %d launches checked, persistent batch equal to the shapes alone\n", nchecks);
+  fprintf(stderr, "ok: %d launches checked, persistent batch equal to the shapes alone; %ld parked threads (sleeps "
+          "and fences), %ld turns to another block\n", nchecks, emu::parks, emu::blocks_waited);
   return 0;
 }
 
