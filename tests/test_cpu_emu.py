@@ -6,9 +6,10 @@ deferred-centroid queues -> exact stage), each iteration fed by the previous
 one's output, every buffer of the state in an allocation of its own and the
 queue counts checked against their capacities after every launch.  The
 positions are compared with the oracle's iterations.  The persistent batch
-kernel runs there too (its blocks one after another: the schedule's tables,
-item decoding and every kernel's one-wavefront form, not its waits), against
-the same shapes run alone."""
+kernel runs there too, its blocks taking turns where a block sleeps in a wait
+or fences between two work items (the schedule's tables, item decoding and
+waits, and every kernel's one-wavefront form), against the same shapes run
+alone."""
 import os
 import struct
 import subprocess
@@ -132,9 +133,10 @@ def test_emulated_bin_size_case(orc, exe, tmp_path, prec, density):
 def test_emulated_persistent_batch(orc, exe, tmp_path, method, prec):
     """A persistent batch of two shapes (1,500 holes20 points and the first
     500 of them, on a 128^2 grid whose box the boundary points' octagons
-    reach): four iterations, after every two the positions, categories and
-    statistics of each shape bit-identical to the shape run alone, no
-    sanitizer report, queues within capacity."""
+    reach), four blocks taking turns: four iterations, after every two the
+    positions, categories and statistics of each shape bit-identical to the
+    shape run alone, no sanitizer report, queues within capacity, and the
+    blocks did wait on each other."""
     wl = I.holes20(n=1500, grid_n=128, iters=1)
     og = orc.build_grid(wl)
     cin, cout = str(tmp_path / "case.bin"), str(tmp_path / "out.bin")
@@ -144,4 +146,7 @@ def test_emulated_persistent_batch(orc, exe, tmp_path, method, prec):
     r = subprocess.run([exe, cin, cout], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True,
                        timeout=1800, env=env)
     assert r.returncode == 0, r.stdout[-6000:]
-    print(r.stdout.strip().splitlines()[-1], flush=True)
+    last = r.stdout.strip().splitlines()[-1]
+    print(last, flush=True)
+    turns = int(last.split(",")[-1].split()[0])
+    assert turns > 0, last  # the blocks took turns
