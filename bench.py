@@ -700,6 +700,17 @@ def schedule_run(args, log):
                          "exact predicates"}
         log("  cpu oracle: full run %.2f s on %d threads" % (secs, threads))
         _, perr = oracle_first_step(wl, "dm", precs, threads, log)
+    elif which == "ellipses" and not args.no_cpu_baseline:
+        # the oracle needs minutes at 10^7 points on the 8192^2 grid: the same
+        # recipe at 2 10^6 points on a 1024^2 grid, the first DistMesh step
+        sample = I.ellipses(n=2000000, grid_n=1024)
+        secs, perr = oracle_first_step(sample, "dm", precs, threads, log)
+        perr["what"] = ("one DistMesh step from the seeded start, every point of the same recipe at %d points on a "
+                        "1024^2 grid, |p - p_oracle| / h" % sample.n)
+        cpu = {"value": sample.n / secs, "unit": "point-iterations/s", "cores": threads, "kind": "oracle",
+               "sample": "the first DistMesh iteration (triangulation with quality, then the step) of the ellipses "
+                         "recipe at %d points on a 1024^2 grid, FP64 with exact predicates" % sample.n}
+        log("  cpu oracle: first DistMesh iteration at %d points %.2f s on %d threads" % (sample.n, secs, threads))
     elif which in ("annulus", "coast") and not args.no_cpu_baseline:
         secs, perr = oracle_first_step(wl, wl.schedule[0][0], precs, threads, log)
         cpu = {"value": wl.n / secs, "unit": "point-iterations/s", "cores": threads, "kind": "oracle",
