@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_adapt_move(KArgs a) {
   bool mv = false;
   if (k < a.n && a.cat[k] == TRIME_CAT_INNER) {
     double x = a.x[k], y = a.y[k];
-    int64_t cell;
+    GCell cell;
     double tx, ty;
     if (locate(a, x, y, cell, tx, ty)) {
       double dx = a.xn[k] - x, dy = a.yn[k] - y;

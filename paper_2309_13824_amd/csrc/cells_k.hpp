@@ -702,16 +702,32 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     }
   }
 
+  // The octagon of a point with span Sq (walls at distance Sq along the
+  // axes, |x| + |y| = Dq on the diagonals) holds the disc of radius
+  // r = min(Sq, Dq / sqrt 2) about the point.  Cell vertex v lies on the
+  // bisector of p and the point, so its distance from the point is |v|:
+  // true when the bound on |v|^2 is below r^2 (the float products below
+  // round up by at most 2^-23 relative, which the factor 0.99999 covers).
+  TRIME_D static bool within_inradius(const VRec<T> &v, float Sq) {
+    if (!(Sq > 0.0f)) return false;
+    const float Dq = 1.41421356f * Sq;
+    const float r2 = fminf(Sq * Sq, 0.5f * (Dq * Dq)) * 0.99999f;
+    return vert_r2(v.x, v.y, v.e) < (T)r2;
+  }
+
   // Is cell vertex j (circumcentre of p, q and `other`) inside the octagon
-  // of the point in slot q?  1 inside, 0 outside; may set why.
+  // of the point in slot q?  1 inside, 0 outside; may set why.  Nearly
+  // every vertex is decided by the inradius alone; the walls decide the
+  // rest.
   TRIME_D int inside_octagon(int j, int q, int other) {
     const T u = U<T>::v;
     VRec<T> v = P[j][tid];
+    float Sq = gld(a.span, q), Dq = 1.41421356f * Sq;
+    if (within_inradius(v, Sq)) return 1;
     T E = (T)v.e;
     double qxd = gld(a.x, q), qyd = gld(a.y, q);
     T qx = (T)(qxd - px), qy = (T)(qyd - py);
     T cx = v.x - qx, cy = v.y - qy;
-    float Sq = gld(a.span, q), Dq = 1.41421356f * Sq;
     T base = E + (T)2 * u * (fabs(qx) + fabs(qy)) + (T)2 * u * (fabs(cx) + fabs(cy));
     for (int w = 0; w < 8; w++) {
       int nx, ny;
@@ -738,8 +754,14 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   }
 
   TRIME_D bool valid_triangle(int s1, int s2) {
-    int i0 = pid, i1 = gld(a.id, s1), i2 = gld(a.id, s2);
-    double x0 = px, y0 = py, x1 = gld(a.x, s1), y1 = gld(a.y, s1), x2 = gld(a.x, s2), y2 = gld(a.y, s2);
+    return valid_triangle_at(gld(a.id, s1), gld(a.x, s1), gld(a.y, s1), gld(a.id, s2), gld(a.x, s2),
+                             gld(a.y, s2));
+  }
+  // Tests 1-3 of the triangle of p and the points with ids i1, i2 at (x1, y1),
+  // (x2, y2), its vertices taken in increasing id order.
+  TRIME_D bool valid_triangle_at(int i1, double x1, double y1, int i2, double x2, double y2) {
+    int i0 = pid;
+    double x0 = px, y0 = py;
     if (i0 > i1) { int t = i0; i0 = i1; i1 = t; double w = x0; x0 = x1; x1 = w; w = y0; y0 = y1; y1 = w; }
     if (i1 > i2) { int t = i1; i1 = i2; i2 = t; double w = x1; x1 = x2; x2 = w; w = y1; y1 = y2; y2 = w; }
     if (i0 > i1) { int t = i0; i0 = i1; i1 = t; double w = x0; x0 = x1; x1 = w; w = y0; y0 = y1; y1 = w; }
@@ -782,11 +804,11 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   // cell (up to the octagon, 5h) would move its centroid by more than the
   // 1e-5 h the FP32 mode allows.
   template <class V, class GetV>
-  TRIME_D void level_centroid(int L, V fxf, V fyf, int64_t cx0, int64_t cy0, GetV &getv, V &cx, V &cy) {
+  TRIME_D void level_centroid(int L, V fxf, V fyf, int cx0, int cy0, GetV &getv, V &cx, V &cy) {
     double sw = 0, swx = 0, swy = 0;
     const V idx = (V)a.inv_dx, idy = (V)a.inv_dy;
     const G *mu = (const G *)a.mu;
-    const int64_t nxc = a.nx - 2, nyc = a.ny - 2;
+    const int nxc = a.nx - 2, nyc = a.ny - 2;
     int64_t last = -1;  // the four node values of the last grid cell are kept
     V m00 = 0, m10 = 0, m01 = 0, m11 = 0;
     auto leaf = [&](V x0, V y0, V x1, V y1, V x2, V y2) {
@@ -795,13 +817,15 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       // mu at p + g: bilinear in its cell (cells clamped to the grid)
       V fx = fxf + gx * idx, fy = fyf + gy * idy;
       V flx = floor(fx), fly = floor(fy);
-      int64_t ci = cx0 + (int64_t)flx, cj = cy0 + (int64_t)fly;
+      // the leaf lies within the octagon of p: its cell offset is a few
+      // cells, so the sums stay in int (p's cell index is below nx, ny)
+      int ci = cx0 + sat_int(flx), cj = cy0 + sat_int(fly);
       V tx = fx - flx, ty = fy - fly;
       if (ci < 0) { ci = 0; tx = 0; }
       if (ci > nxc) { ci = nxc; tx = 1; }
       if (cj < 0) { cj = 0; ty = 0; }
       if (cj > nyc) { cj = nyc; ty = 1; }
-      int64_t n0 = cj * a.nx + ci;
+      int64_t n0 = (int64_t)cj * a.nx + ci;
       if (n0 != last) {
         m00 = (V)gld(mu, n0);
         m10 = (V)gld(mu, n0 + 1);
@@ -918,7 +942,7 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     double eps = fmax((dp < 0 ? h : dp) / h, a.prm.fac_end);
     V E = (V)(sqrt((double)A) * eps);
     double fx0 = (px - a.gx0) * a.inv_dx, fy0 = (py - a.gy0) * a.inv_dy;
-    int64_t cx0 = (int64_t)floor(fx0), cy0 = (int64_t)floor(fy0);
+    const int cx0 = sat_int(floor(fx0)), cy0 = sat_int(floor(fy0));  // p's cell: 0 <= fx0 < nx - 1
     V fxf = (V)(fx0 - (double)cx0), fyf = (V)(fy0 - (double)cy0);
     V R = sqrt((V)R2);
     V c0x = 0, c0y = 0, c1x = 0, c1y = 0;
@@ -988,7 +1012,7 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   // CVD target (Sec. 4.2 II) and treatment (Sec. 4.3) of p; false when an
   // FP32 decision lies within its error bound (why = WHY_LEVEL / WHY_TREAT).
   TRIME_D bool target_and_treat(double &xf, double &yf, uint8_t &cf, int &cap_hit, TreatCount &tc) {
-    int64_t cell;
+    GCell cell;
     double tx, ty;
     locate(a, px, py, cell, tx, ty);
     double h = (double)cell_h(a, cell);
@@ -1373,6 +1397,40 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
 
   // Everything after the cell: decisions, CVD target and treatment, then
   // the commit of the outputs; false when the point must leave.
+  // Bit j of nb: edge j of the polygon is a bisector (its constraint a
+  // point, not a wall); of gt: a bisector of a point with a larger id than
+  // p.  Small polygons issue every id load at once.
+  TRIME_D void edge_masks(uint32_t &nb, uint32_t &gt) const {
+    nb = 0;
+    gt = 0;
+    if constexpr (VMAX <= 16) {
+      int ids[VMAX];
+#pragma unroll
+      for (int j = 0; j < VMAX; j++) {
+        const int c = j < n ? con(j) : -1;
+        ids[j] = gld(a.id, c >= 0 ? (int64_t)c : k);
+        nb |= (uint32_t)(c >= 0) << j;
+      }
+#pragma unroll
+      for (int j = 0; j < VMAX; j++) gt |= (uint32_t)(ids[j] > pid) << j;
+      gt &= nb;
+    } else {
+      for (int j = 0; j < n; j++) {
+        const int c = con(j);
+        if (c < 0) continue;
+        nb |= 1u << j;
+        if (gld(a.id, c) > pid) gt |= 1u << j;
+      }
+    }
+  }
+  // Bit j: bit j - 1 of m (cyclically over the n edges); vertex j lies
+  // between edges j - 1 and j.
+  TRIME_D uint32_t prev_edge(uint32_t m) const {
+    if (n <= 0) return 0u;
+    const uint32_t full = n >= 32 ? 0xffffffffu : (1u << n) - 1u;
+    return ((m << 1) | (m >> (n - 1))) & full;
+  }
+
   TRIME_D bool finish(LaneStats &st, int *hist) {
     if constexpr (MODE == MODE_CELLS) {
       write_cell();
@@ -1383,25 +1441,26 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       // the vertices to test, as a mask, so that the tests below loop over
       // them only (a wavefront then runs as many trips as its lane with the
       // most such vertices, not as its largest polygon)
-      uint32_t test = 0, owned = 0;
-      for (int j = 0; j < n; j++) {
-        int jin = con(j == 0 ? n - 1 : j - 1), jout = con(j);
-        if (jin < 0 || jout < 0) continue;
-        const uint32_t own = (pid < gld(a.id, jin) && pid < gld(a.id, jout)) ? 1u : 0u;
-        owned |= own << j;
-        test |= (MODE == MODE_CVD ? own : 1u) << j;
-      }
+      uint32_t nb, gt;
+      edge_masks(nb, gt);
+      const uint32_t owned = gt & prev_edge(gt), test = MODE == MODE_CVD ? owned : nb & prev_edge(nb);
       uint32_t exists = 0, valid = 0;
       for (uint32_t m = test; m; m &= m - 1) {
         const int j = __ffs(m) - 1;
         int jin = con(j == 0 ? n - 1 : j - 1), jout = con(j);
-        int e = inside_octagon(j, jin, jout);
+        // every load of the vertex at once: the spans for the octagon tests,
+        // ids and positions for Tests 1-3
+        const float S1 = gld(a.span, jin), S2 = gld(a.span, jout);
+        const int i1 = gld(a.id, jin), i2 = gld(a.id, jout);
+        const double x1 = gld(a.x, jin), y1 = gld(a.y, jin), x2 = gld(a.x, jout), y2 = gld(a.y, jout);
+        const VRec<T> v = P[j][tid];
+        int e = within_inradius(v, S1) ? 1 : inside_octagon(j, jin, jout);
         if (why) return false;
-        if (e) e = inside_octagon(j, jout, jin);
+        if (e) e = within_inradius(v, S2) ? 1 : inside_octagon(j, jout, jin);
         if (why) return false;
         if (!e) continue;
         exists |= 1u << j;
-        if (valid_triangle(jin, jout)) valid |= 1u << j;
+        if (valid_triangle_at(i1, x1, y1, i2, x2, y2)) valid |= 1u << j;
       }
       // ---- CVD target and treatment; an FP32 decision within its bound
       // defers them to the FP64 centroid pass (the cell is final)

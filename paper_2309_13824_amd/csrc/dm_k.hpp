@@ -178,7 +178,7 @@ TRIME_D bool dm_point(const KArgs &a, int64_t k, int &moved, TreatCount &tc) {
     Fy += w * dy;
   }
   double xnew = px + a.prm.dt * (double)Fx, ynew = py + a.prm.dt * (double)Fy;
-  int64_t cell;
+  GCell cell;
   double tx, ty;
   double band = 0.0;
   if (sizeof(T) == 4 && locate(a, px, py, cell, tx, ty)) band = 1e-6 * (double)cell_h(a, cell);

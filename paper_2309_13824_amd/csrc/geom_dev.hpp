@@ -17,7 +17,7 @@ namespace trime {
 template <class G>
 TRIME_D bool tri_valid(const KArgs &a, double ax, double ay, double bx, double by, double cx,
                        double cy) {
-  int64_t cell;
+  GCell cell;
   double tx, ty;
   double gx = ((ax + bx) + cx) / 3.0, gy = ((ay + by) + cy) / 3.0;
   if (!locate(a, gx, gy, cell, tx, ty)) return false;
@@ -57,7 +57,7 @@ TRIME_D bool tri_valid(const KArgs &a, double ax, double ay, double bx, double b
 // `unsure` is raised when a comparison falls within `band`.
 template <class G>
 TRIME_D uint8_t point_category(const KArgs &a, double x, double y, double band, bool &unsure) {
-  int64_t cell;
+  GCell cell;
   double tx, ty;
   if (!locate(a, x, y, cell, tx, ty)) return TRIME_CAT_OUTER;
   uint8_t c = cell_cat(a, cell);
@@ -78,7 +78,7 @@ struct TreatCount {
 
 template <class G>
 TRIME_D bool sdf_probe(const KArgs &a, double x, double y, double &s, double &ge) {
-  int64_t cell;
+  GCell cell;
   double tx, ty;
   if (!locate(a, x, y, cell, tx, ty)) return false;
   s = bilinear<G>(a, a.sdf, cell, tx, ty);
@@ -144,11 +144,10 @@ TRIME_D bool newton_project(const KArgs &a, double xn, double yn, double band, d
                             double &yf, bool &unsure) {
   double xk = xn, yk = yn;
   for (int it = 0; it < a.prm.T_newton; it++) {
-    int64_t cell;
+    GCell cell;
     double tx, ty;
     if (!locate(a, xk, yk, cell, tx, ty)) return false;
-    int64_t ci = cell % (a.nx - 1), cj = cell / (a.nx - 1);
-    int64_t n0 = cj * a.nx + ci;
+    const int64_t n0 = node_index(a, cell);
     double s00 = gval<G>(a.sdf, n0), s10 = gval<G>(a.sdf, n0 + 1);
     double s01 = gval<G>(a.sdf, n0 + a.nx), s11 = gval<G>(a.sdf, n0 + a.nx + 1);
     double f = (s00 * (1.0 - tx) + s10 * tx) * (1.0 - ty) + (s01 * (1.0 - tx) + s11 * tx) * ty;
@@ -184,7 +183,7 @@ template <class G>
 TRIME_D void treat(const KArgs &a, double xo, double yo, uint8_t cat_old, double xnew, double ynew,
                    double band, double &xf, double &yf, uint8_t &catf, bool &unsure,
                    TreatCount &tc) {
-  int64_t cell;
+  GCell cell;
   double tx, ty;
   if (locate(a, xo, yo, cell, tx, ty)) {
     double T = a.prm.fac_pt * (double)cell_h(a, cell);

@@ -217,15 +217,29 @@ template <class G> TRIME_D double gval(const void *p, int64_t k) {
   return (double)gld((const G *)p, k);
 }
 
+// An integral float or double v as an int, saturated at +-2^24: the grid
+// indices and offsets this converts are far smaller, and every caller clamps
+// its result to the grid (one conversion instead of the 64-bit sequence).
+template <class V> TRIME_D int sat_int(V v) { return (int)fmin(fmax(v, (V)-16777216.0), (V)16777216.0); }
+
+// A grid cell by column i and row j; the cell arrays hold cell (i, j) at
+// j (nx - 1) + i, the node arrays its lower-left node at j nx + i.
+struct GCell {
+  int i, j;
+};
+TRIME_D int64_t cell_index(const KArgs &a, const GCell &c) { return (int64_t)c.j * (a.nx - 1) + c.i; }
+TRIME_D int64_t node_index(const KArgs &a, const GCell &c) { return (int64_t)c.j * a.nx + c.i; }
+
 // Cell of (x, y): f = (x - x0) * (1/dx), cell = floor(f), t = f - cell.
 // Returns false off the grid.
-TRIME_D bool locate(const KArgs &a, double x, double y, int64_t &cell, double &tx, double &ty) {
+TRIME_D bool locate(const KArgs &a, double x, double y, GCell &cell, double &tx, double &ty) {
   double fx = (x - a.gx0) * a.inv_dx;
   double fy = (y - a.gy0) * a.inv_dy;
   if (!(fx >= 0.0) || !(fy >= 0.0)) return false;
   double ix = floor(fx), iy = floor(fy);
   if (ix >= (double)(a.nx - 1) || iy >= (double)(a.ny - 1)) return false;
-  cell = (int64_t)iy * (a.nx - 1) + (int64_t)ix;
+  cell.i = (int)ix;  // 0 <= ix < nx - 1 (checked above)
+  cell.j = (int)iy;
   tx = fx - ix;
   ty = fy - iy;
   return true;
@@ -233,18 +247,17 @@ TRIME_D bool locate(const KArgs &a, double x, double y, int64_t &cell, double &t
 
 // Bilinear value inside a cell: (f00 (1-tx) + f10 tx)(1-ty) + (f01 (1-tx) + f11 tx) ty.
 template <class G>
-TRIME_D double bilinear(const KArgs &a, const void *f, int64_t cell, double tx, double ty) {
-  int64_t ci = cell % (a.nx - 1), cj = cell / (a.nx - 1);
-  int64_t n0 = cj * a.nx + ci;
+TRIME_D double bilinear(const KArgs &a, const void *f, const GCell &cell, double tx, double ty) {
+  const int64_t n0 = node_index(a, cell);
   double f00 = gval<G>(f, n0), f10 = gval<G>(f, n0 + 1);
   double f01 = gval<G>(f, n0 + a.nx), f11 = gval<G>(f, n0 + a.nx + 1);
   return (f00 * (1.0 - tx) + f10 * tx) * (1.0 - ty) + (f01 * (1.0 - tx) + f11 * tx) * ty;
 }
 
-TRIME_D uint8_t cell_cat(const KArgs &a, int64_t cell) { return gld(a.cgrid, cell); }
+TRIME_D uint8_t cell_cat(const KArgs &a, const GCell &cell) { return gld(a.cgrid, cell_index(a, cell)); }
 // h of a cell, scaled for the current point count (fl32(h * h_scale))
-TRIME_D float cell_h(const KArgs &a, int64_t cell) {
-  const float h = gld(a.hcell, cell);
+TRIME_D float cell_h(const KArgs &a, const GCell &cell) {
+  const float h = gld(a.hcell, cell_index(a, cell));
   return a.h_scale == 1.0 ? h : (float)((double)h * a.h_scale);
 }
 TRIME_D double h_avg(const KArgs &a) {
@@ -252,7 +265,7 @@ TRIME_D double h_avg(const KArgs &a) {
 }
 
 // geps of a cell (Sec. 3.7): fac_geps * min(h_cell, h_avg).
-TRIME_D double geps_of(const KArgs &a, int64_t cell) {
+TRIME_D double geps_of(const KArgs &a, const GCell &cell) {
   return a.prm.fac_geps * fmin((double)cell_h(a, cell), h_avg(a));
 }
 
@@ -263,7 +276,9 @@ template <class G> TRIME_D double mu_clamped(const KArgs &a, double x, double y)
   ix = fmin(fmax(ix, 0.0), (double)(a.nx - 2));
   iy = fmin(fmax(iy, 0.0), (double)(a.ny - 2));
   double tx = fmin(fmax(fx - ix, 0.0), 1.0), ty = fmin(fmax(fy - iy, 0.0), 1.0);
-  int64_t cell = (int64_t)iy * (a.nx - 1) + (int64_t)ix;
+  GCell cell;
+  cell.i = (int)ix;  // clamped to [0, nx - 2]
+  cell.j = (int)iy;
   return bilinear<G>(a, a.mu, cell, tx, ty);
 }
 
@@ -288,7 +303,7 @@ TRIME_D void bin_of(const KArgs &a, double x, double y, int &bx, int &by) {
 // Span S of the octagon of a point (Sec. 4.1): fac_voro * h of its cell, in
 // float; D = fl32(fl32(sqrt 2) * S).
 TRIME_D float span_at(const KArgs &a, double x, double y) {
-  int64_t cell;
+  GCell cell;
   double tx, ty;
   if (!locate(a, x, y, cell, tx, ty)) return -1.0f;
   return (float)a.prm.fac_voro * cell_h(a, cell);
