@@ -617,16 +617,24 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     }
   }
 
-  // Scan the rings of bins around p, one bin per step, nearest bins first.
-  // The scan is bound by the latency of dependent loads, so the range of
-  // the next bin is loaded while the candidates of the current bin are
-  // clipped, and the candidates of a bin are loaded two at a time (four
-  // would take the FP32 kernel past the registers of three wavefronts per
-  // SIMD).  A bin whose distance from p exceeds the reach 2 R (R of the
-  // cell when the bin is fetched, never smaller than later) is not loaded.
-  // The loop is one bin per trip with a single back edge: branches that
-  // skip a bin inside the loop let the compiler split it into nested loops
-  // in which the lanes wait on each other's loads.
+  // Scan the rings of bins around p, nearest bins first.  The scan is bound
+  // by the latency of dependent loads and by the lanes of a wavefront
+  // waiting on the lane with the most candidates, so:
+  //  - the bins go in groups, ring 0 alone, then two bins of a ring at a
+  //    time (rings have 8 r bins), and one loop takes the candidates of both
+  //    bins of a group: a trip then waits on the largest pair of bins, not on
+  //    the largest bin twice over;
+  //  - the ranges of the next group's bins are loaded while the current
+  //    group's candidates are clipped, and the candidates are loaded two at a
+  //    time (four would take the FP32 kernel past the registers of three
+  //    wavefronts per SIMD);
+  //  - a bin whose distance from p exceeds the reach 2 R (R of the cell when
+  //    the bin is fetched, never smaller than later) is not loaded.
+  // Every candidate is still tested against the current R, in the same order
+  // as one bin at a time, so the clips are the same.  The loop is one group
+  // per trip with a single back edge: branches that skip a bin inside the
+  // loop let the compiler split it into nested loops in which the lanes wait
+  // on each other's loads.
   TRIME_D void fetch_bin(int r, int bi, int bx, int by, double ox, double oy, int &s, int &se) const {
     int dx, dy;
     ring_bin_near(r, bi, dx, dy);
@@ -651,23 +659,27 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     double ox = px - (a.bx0 + bx * a.bw), oy = py - (a.by0 + by * a.bw);
     double edge = fmax(0.0, fmin(fmin(ox, a.bw - ox), fmin(oy, a.bw - oy)));
     const int rmax = max(a.nbx, a.nby);
-    int r = 0, bi = 0, nbr = 1;
-    int cs, ce;
-    fetch_bin(0, 0, bx, by, ox, oy, cs, ce);
+    // the current group: ring r from bin bi, ranges [as, ae) and [bs, be)
+    int r = 0, bi = 0;
+    int as, ae, bs = 0, be = 0;
+    fetch_bin(0, 0, bx, by, ox, oy, as, ae);
     for (;;) {
-      int r1 = r, bi1 = bi + 1, nbr1 = nbr;
-      if (bi1 == nbr1) {
-        r1++;
+      int r1 = r, bi1 = bi + 2;
+      if (r == 0 || bi1 == 8 * r) {
+        r1 = r + 1;
         bi1 = 0;
-        nbr1 = 8 * r1;
       }
-      int ns, ne;
-      fetch_bin(r1, bi1, bx, by, ox, oy, ns, ne);
+      int nas, nae, nbs, nbe;
+      fetch_bin(r1, bi1, bx, by, ox, oy, nas, nae);
+      fetch_bin(r1, bi1 + 1, bx, by, ox, oy, nbs, nbe);
+      const int na = ae - as, nt = na + (be - bs);
       double qx0 = 0, qx1 = 0, qy0 = 0, qy1 = 0;
-      for (int s = cs; s < ce; s++) {
-        const int t = (s - cs) & 1;
-        if (t == 0) {  // the next two candidates of the bin, loads in flight together
-          int s1 = min(s + 1, ce - 1);
+      for (int i = 0; i < nt; i++) {
+        const int t = i & 1;
+        const int s = i < na ? as + i : bs + (i - na);
+        if (t == 0) {  // the next two candidates of the group, loads in flight together
+          const int i1 = min(i + 1, nt - 1);
+          const int s1 = i1 < na ? as + i1 : bs + (i1 - na);
           qx0 = gld(a.x, s);
           qy0 = gld(a.y, s);
           qx1 = gld(a.x, s1);
@@ -692,9 +704,10 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       }
       r = r1;
       bi = bi1;
-      nbr = nbr1;
-      cs = ns;
-      ce = ne;
+      as = nas;
+      ae = nae;
+      bs = nbs;
+      be = nbe;
       if (bi == 0) {  // ring r - 1 done: stop when ring r is out of reach
         double dmin = (r - 1) * a.bw + edge;
         if (r > rmax || dmin * dmin > 4.0 * (double)R2 * 1.00001) return;
