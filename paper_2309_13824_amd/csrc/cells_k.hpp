@@ -38,6 +38,13 @@
 
 namespace trime {
 
+// bins per group of the lane scan (a divisor of 8)
+#ifndef TRIME_SCAN_GROUP
+#define TRIME_SCAN_GROUP 4
+#endif
+constexpr int SCAN_GROUP = TRIME_SCAN_GROUP;
+static_assert(8 % SCAN_GROUP == 0, "a ring's bins must split into whole groups");
+
 template <class T> struct Row {
   T nx, ny, s;
 };
@@ -620,10 +627,10 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   // Scan the rings of bins around p, nearest bins first.  The scan is bound
   // by the latency of dependent loads and by the lanes of a wavefront
   // waiting on the lane with the most candidates, so:
-  //  - the bins go in groups, ring 0 alone, then two bins of a ring at a
-  //    time (rings have 8 r bins), and one loop takes the candidates of both
-  //    bins of a group: a trip then waits on the largest pair of bins, not on
-  //    the largest bin twice over;
+  //  - the bins go in groups, ring 0 alone, then SCAN_GROUP bins of a ring
+  //    at a time (rings have 8 r bins), and one loop takes the candidates of
+  //    every bin of a group: a trip then waits on the largest group of bins,
+  //    not on the largest bin once per bin;
   //  - the ranges of the next group's bins are loaded while the current
   //    group's candidates are clipped, and the candidates are loaded two at a
   //    time (four would take the FP32 kernel past the registers of three
@@ -654,32 +661,46 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
 
   TRIME_D void scan() {
     const T u = U<T>::v;
+    constexpr int NG = SCAN_GROUP;
     int bx, by;
     bin_of(a, px, py, bx, by);
     double ox = px - (a.bx0 + bx * a.bw), oy = py - (a.by0 + by * a.bw);
     double edge = fmax(0.0, fmin(fmin(ox, a.bw - ox), fmin(oy, a.bw - oy)));
     const int rmax = max(a.nbx, a.nby);
-    // the current group: ring r from bin bi, ranges [as, ae) and [bs, be)
+    // the current group: ring r from bin bi, bin g's candidates in [gs[g], ge[g])
     int r = 0, bi = 0;
-    int as, ae, bs = 0, be = 0;
-    fetch_bin(0, 0, bx, by, ox, oy, as, ae);
+    int gs[NG], ge[NG];
+    fetch_bin(0, 0, bx, by, ox, oy, gs[0], ge[0]);
+#pragma unroll
+    for (int g = 1; g < NG; g++) gs[g] = ge[g] = 0;
     for (;;) {
-      int r1 = r, bi1 = bi + 2;
+      int r1 = r, bi1 = bi + NG;
       if (r == 0 || bi1 == 8 * r) {
         r1 = r + 1;
         bi1 = 0;
       }
-      int nas, nae, nbs, nbe;
-      fetch_bin(r1, bi1, bx, by, ox, oy, nas, nae);
-      fetch_bin(r1, bi1 + 1, bx, by, ox, oy, nbs, nbe);
-      const int na = ae - as, nt = na + (be - bs);
+      int ns[NG], ne[NG];
+#pragma unroll
+      for (int g = 0; g < NG; g++) fetch_bin(r1, bi1 + g, bx, by, ox, oy, ns[g], ne[g]);
+      // candidate i of the group: slot gs[g] + i - c[g - 1] for the bin g
+      // whose running count c[g] first exceeds i
+      int c[NG];
+#pragma unroll
+      for (int g = 0; g < NG; g++) c[g] = (g ? c[g - 1] : 0) + (ge[g] - gs[g]);
+      const int nt = c[NG - 1];
+      auto slot = [&](int i) {
+        int sl = gs[0] + i;
+#pragma unroll
+        for (int g = 1; g < NG; g++)
+          if (i >= c[g - 1]) sl = gs[g] + (i - c[g - 1]);
+        return sl;
+      };
       double qx0 = 0, qx1 = 0, qy0 = 0, qy1 = 0;
       for (int i = 0; i < nt; i++) {
         const int t = i & 1;
-        const int s = i < na ? as + i : bs + (i - na);
+        const int s = slot(i);
         if (t == 0) {  // the next two candidates of the group, loads in flight together
-          const int i1 = min(i + 1, nt - 1);
-          const int s1 = i1 < na ? as + i1 : bs + (i1 - na);
+          const int s1 = slot(min(i + 1, nt - 1));
           qx0 = gld(a.x, s);
           qy0 = gld(a.y, s);
           qx1 = gld(a.x, s1);
@@ -704,10 +725,11 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       }
       r = r1;
       bi = bi1;
-      as = nas;
-      ae = nae;
-      bs = nbs;
-      be = nbe;
+#pragma unroll
+      for (int g = 0; g < NG; g++) {
+        gs[g] = ns[g];
+        ge[g] = ne[g];
+      }
       if (bi == 0) {  // ring r - 1 done: stop when ring r is out of reach
         double dmin = (r - 1) * a.bw + edge;
         if (r > rmax || dmin * dmin > 4.0 * (double)R2 * 1.00001) return;
