@@ -404,15 +404,18 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   // Cut the polygon by constraint c3 (row r3).  Small polygons go through
   // registers: all records are read at once, the margins are taken with
   // every load in flight, and the kept records are written back to their new
-  // places (no dependent LDS round trips per vertex).
-  TRIME_D void clip(const Row<T> &r3, int c3) {
+  // places (no dependent LDS round trips per vertex).  DUP false: c3 is
+  // known not to bound the polygon yet (the previous cell's distinct
+  // neighbours; one that did would leave its margins undecided and send the
+  // point to the FP64 replay).
+  template <bool DUP = true> TRIME_D void clip(const Row<T> &r3, int c3) {
     if constexpr (VMAX <= 16 && !EXACT)
-      clip_reg(r3, c3);
+      clip_reg<DUP>(r3, c3);
     else
       clip_lds(r3, c3);
   }
 
-  TRIME_D void clip_reg(const Row<T> &r3, int c3) {
+  template <bool DUP> TRIME_D void clip_reg(const Row<T> &r3, int c3) {
     const T u = U<T>::v;
     VRec<T> v[VMAX];
 #pragma unroll
@@ -420,10 +423,12 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     // a neighbour whose bisector already bounds the cell (clipped first, from
     // the point's previous cell) is not clipped again: two vertices lie on
     // its bisector, where the margins vanish
-    uint32_t dup = 0;
+    if constexpr (DUP) {
+      uint32_t dup = 0;
 #pragma unroll
-    for (int j = 0; j < VMAX; j++) dup |= (uint32_t)(j < n && v[j].c == c3);
-    if (dup) return;
+      for (int j = 0; j < VMAX; j++) dup |= (uint32_t)(j < n && v[j].c == c3);
+      if (dup) return;
+    }
     const T n1 = fabs(r3.nx) + fabs(r3.ny);
     // one bound for every vertex: the largest vertex error bound of the
     // polygon stands for each vertex's own (a larger bound only leaves more
@@ -1267,7 +1272,7 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
       if (!(sq * ((T)1 - (T)8 * u) > (T)4 * R2)) {
         cqx = qx - px;
         cqy = qy - py;
-        clip(r3, q);
+        clip<false>(r3, q);
         if (why || n == 0) return;
       }
     }
