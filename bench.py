@@ -58,7 +58,7 @@ BYTES_PER_POINT = {"fp32": 16 + 101 + 64 + 37, "fp64": 20 + 101 + 64 + 37}
 # WRITE_SIZE (the mean of its last two launches in a short run: the timed
 # CVD iteration 2 and the next one; scaled by a 1 GiB copy: FETCH x 2.0,
 # WRITE x 1.0), valid for the kernel sources with this digest only.
-TRAFFIC = {"sha1": "6cb96647ba0c4cea093c6d5d9a1e8b2b87ab9efc", "bytes_per_launch": 535954255.8}
+TRAFFIC = {"sha1": "6cb96647ba0c4cea093c6d5d9a1e8b2b87ab9efc", "bytes_per_launch": 533330262.2}
 # counted flops per point of the DistMesh force gather (edge forces over the
 # adjacency row, forward Euler, treatment checks)
 DM_FLOPS_PER_POINT = 150
@@ -94,7 +94,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
-    ap.add_argument("--tune", type=str, default="1.0,1.4,2.0,2.8",
+    ap.add_argument("--tune", type=str, default="1.4,2.0,2.4,2.8,3.2,3.6",
                     help="bin densities (points per bin) the autotuner tries before the timed run; "
                          "empty for the default 3.3")
     ap.add_argument("--workload", default="holes20",
@@ -629,7 +629,7 @@ def schedule_run(args, log):
         m = Mesher(wl, precision=prec)
         dens = 3.3
         if which == "ellipses":
-            dens, ms = m.autotune((1.4, 2.0, 2.8), n_iter=2)
+            dens, ms = m.autotune((1.4, 2.0, 2.4, 2.8, 3.2, 3.6), n_iter=2)
             log("  autotune (%s): %s -> %.2f" % (pname, ", ".join("%.1f: %.2f ms" % kv for kv in sorted(ms.items())), dens))
         variants = [(sch, False) for sch in schedules]
         # DistMesh schedules also as "always": re-triangulating every iteration
