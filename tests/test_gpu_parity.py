@@ -144,6 +144,42 @@ def test_triangles_and_adjacency_match_oracle(orc, T, prec, make):
     assert_no_error(m)
 
 
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("fac_voro", [1.2, 0.8])
+def test_binding_octagons_match_oracle(orc, T, prec, fac_voro):
+    """Octagon spans of 1.2 h and 0.8 h (Sec. 4.1) instead of 5 h: the AND
+    rule removes the triangles whose circumcentre lies outside a vertex's
+    octagon (about 1,400 and 6,500 of the 15,700 here), so the octagon
+    tests are decided by the walls as well as by the octagon's inradius,
+    and cells are cut by their own octagon.  Extraction (triangles,
+    validity, adjacency) equals the oracle's run with the same span, and so
+    do the positions and categories after one CVD step."""
+    wl = I.holes20(n=8000, grid_n=512, iters=1)
+    og = orc.build_grid(wl)
+    prm, oprm = T.default_params(fac_voro=fac_voro), orc.default_params(fac_voro=fac_voro)
+    m = mesher(wl, prec, grid=og, params=prm)
+    m.bin()
+    m.extract()
+    tri, valid = m.triangles()
+    adj = m.adjacency()
+    ref = orc.triangulate(og, wl.x, wl.y, params=oprm)
+    full = orc.triangulate(og, wl.x, wl.y)
+    assert len(ref.tri) < len(full.tri)  # the octagons bind
+    assert tri_set(tri, valid) == tri_set(ref.tri, ref.valid)
+    rows = [tuple(int(v) for v in ref.col[ref.rowptr[i]:ref.rowptr[i + 1]]) for i in range(wl.n)]
+    assert adj == rows
+    assert_no_error(m)
+    m = mesher(wl, prec, grid=og, params=prm)
+    m.step_cvd(1)
+    x, y, cat = m.points()
+    cat0 = orc.initial_categories(og, wl.x, wl.y, params=oprm)
+    xr, yr, cr, _, _, _ = orc.cvd_step(og, wl.x, wl.y, cat0, np.full(wl.n, -1.0), nthreads=8, params=oprm)
+    err = np.hypot(x - xr, y - yr) / h_of(og, xr, yr)
+    assert err.max() <= _tol(prec), err.max()
+    assert np.array_equal(cat, cr)
+    assert_no_error(m)
+
+
 # --------------------------------------------------------------- one step --
 
 def _tol(prec):
