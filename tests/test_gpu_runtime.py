@@ -86,6 +86,37 @@ def test_results_do_not_depend_on_bin_size(orc, T, prec):
         assert adj == ref[4], dens
 
 
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_bin_density_changes_only_the_order_of_sums(orc, T, prec):
+    """On the annulus (6,000 points, 256^2 grid), three CVD iterations at
+    2.0, 3.2 and 6.0 points per bin give the same categories and positions
+    within the parity tolerance, and in FP64 the same triangles and
+    adjacency: every cut decision is exact, only the order of the centroid
+    sums changes with the binning."""
+    wl = I.annulus(n=6000, grid_n=256)
+    og = orc.build_grid(wl)
+    tol = 1e-12 if prec == FP64 else 1e-5
+    ref = None
+    for dens in (3.2, 2.0, 6.0):
+        m = mesher(wl, prec, grid=og, bin_density=dens)
+        m.step_cvd(3)
+        x, y, c = m.points()
+        m.bin()
+        m.extract()
+        tris = tri_set(m)
+        adj = m.adjacency()
+        assert m.stats_raw().error == 0, dens
+        if ref is None:
+            ref = (x, y, c, tris, adj)
+            continue
+        err = np.hypot(x - ref[0], y - ref[1]) / h_of(og, ref[0], ref[1])
+        assert err.max() <= tol, (dens, err.max())
+        assert np.array_equal(c, ref[2]), dens
+        if prec == FP64:
+            assert tris == ref[3], dens
+            assert adj == ref[4], dens
+
+
 def test_autotuner_picks_a_candidate_and_keeps_results(orc, T):
     """The autotuner over (bin density, XCD run) picks a candidate pair,
     leaves the state loaded with the seeded points, and the run it picks
