@@ -58,7 +58,7 @@ BYTES_PER_POINT = {"fp32": 16 + 101 + 64 + 37, "fp64": 20 + 101 + 64 + 37}
 # WRITE_SIZE (the mean of its last two launches in a short run: the timed
 # CVD iteration 2 and the next one; scaled by a 1 GiB copy: FETCH x 2.0,
 # WRITE x 1.0), valid for the kernel sources with this digest only.
-TRAFFIC = {"sha1": "6cb96647ba0c4cea093c6d5d9a1e8b2b87ab9efc", "bytes_per_launch": 533330262.2}
+TRAFFIC = {"sha1": "bfb116058c78e1664fa486ba774400ebbb0cced1", "bytes_per_launch": 582924283.2}
 # counted flops per point of the DistMesh force gather (edge forces over the
 # adjacency row, forward Euler, treatment checks)
 DM_FLOPS_PER_POINT = 150

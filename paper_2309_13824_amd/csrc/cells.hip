@@ -9,10 +9,11 @@ static int64_t clamp64(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo :
 // The queue passes get grids that grow with the point count (their queues
 // hold a small fraction of the points), up to the sizes that fill the chip.
 template <class T, class G, int MODE> static void launch_mode(const KArgs &a, hipStream_t s) {
-  const uint32_t nb = (uint32_t)((a.n + FAST_BLOCK - 1) / FAST_BLOCK);
+  constexpr int FB = fast_block<T>();
+  const uint32_t nb = (uint32_t)((a.n + FB - 1) / FB);
   const bool rec = g_launch_log != nullptr;
   if (a.ev0 && !rec) (void)hipEventRecord((hipEvent_t)a.ev0, s);
-  launch<Cells<T, G, MODE, FAST_VMAX, FAST_BLOCK>>(a, nb, s);
+  launch<Cells<T, G, MODE, FAST_VMAX, FB>>(a, nb, s);
   if (a.ev1 && !rec) (void)hipEventRecord((hipEvent_t)a.ev1, s);
   const int wgrid = (int)clamp64(a.n / 512, 8, WAVE_GRID);
   const int cgrid = (MODE == MODE_CVD && sizeof(T) == 4) ? (int)clamp64(a.n / 128, 4, CENTROID_GRID) : 0;

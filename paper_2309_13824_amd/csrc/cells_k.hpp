@@ -1933,7 +1933,19 @@ template <class G, int MODE, int VMAX, int B> struct CellsExact {
 };
 
 // Shapes of the cell kernels as the launchers use them.
-constexpr int FAST_BLOCK = 128;
+// Lanes (points) per block of the fast kernel.  FP32: 256, whose 45 KB of
+// polygon records let three blocks share a CU, still three wavefronts per
+// SIMD (the VGPR limit); the larger blocks ran 1.5% faster over 40
+// iterations at holes20 than 128 (64: 12% slower).  FP64: 128 (its 24-byte
+// records hold it at two wavefronts per SIMD either way; 256 ran 1.5%
+// slower).
+#ifndef TRIME_FAST_BLOCK_F32
+#define TRIME_FAST_BLOCK_F32 256
+#endif
+#ifndef TRIME_FAST_BLOCK_F64
+#define TRIME_FAST_BLOCK_F64 128
+#endif
+template <class T> constexpr int fast_block() { return sizeof(T) == 4 ? TRIME_FAST_BLOCK_F32 : TRIME_FAST_BLOCK_F64; }
 #ifndef TRIME_FAST_VMAX
 #define TRIME_FAST_VMAX 11
 #endif
@@ -1946,7 +1958,7 @@ constexpr int CENTROID_GRID = 4096;  // blocks for the deferred centroids (8 poi
 static_assert(FAST_VMAX < CQ_STRIDE, "a deferred cell must fit its queue entry");
 
 // kinds (persistent batch kernel): the shapes the launchers use
-template <class T, class G, int MODE> struct KindOf<Cells<T, G, MODE, FAST_VMAX, FAST_BLOCK>> {
+template <class T, class G, int MODE, int B> struct KindOf<Cells<T, G, MODE, FAST_VMAX, B>> {
   static constexpr uint32_t code = kcode(KF_CELLS, is_dbl<T>(), is_dbl<G>(), MODE);
 };
 template <class G, int MODE> struct KindOf<CellsPost<G, MODE, WAVE_VMAX>> {
