@@ -58,7 +58,7 @@ BYTES_PER_POINT = {"fp32": 16 + 101 + 64 + 37, "fp64": 20 + 101 + 64 + 37}
 # WRITE_SIZE (the mean of its last two launches in a short run: the timed
 # CVD iteration 2 and the next one; scaled by a 1 GiB copy: FETCH x 2.0,
 # WRITE x 1.0), valid for the kernel sources with this digest only.
-TRAFFIC = {"sha1": "bfb116058c78e1664fa486ba774400ebbb0cced1", "bytes_per_launch": 582924283.2}
+TRAFFIC = {"sha1": "30729575070d1117d4baa4d31bf3d45323ebfb78", "bytes_per_launch": 437379257.3}
 # counted flops per point of the DistMesh force gather (edge forces over the
 # adjacency row, forward Euler, treatment checks)
 DM_FLOPS_PER_POINT = 150
@@ -97,6 +97,9 @@ def parse():
     ap.add_argument("--tune", type=str, default="1.4,2.0,2.4,2.8,3.2,3.6",
                     help="bin densities (points per bin) the autotuner tries before the timed run; "
                          "empty for the default 3.3")
+    ap.add_argument("--xcd-runs", type=str, default=",".join(str(r) for r in XCD_RUNS),
+                    help="XCD runs (blocks of the fused cell kernel one L2 takes in a row) the autotuner "
+                         "tries with each density; one value pins it (the HBM counters depend on it)")
     ap.add_argument("--workload", default="holes20",
                     choices=["holes20", "stars", "disk", "annulus", "ellipses", "coast"],
                     help="holes20: the headline CVD run; stars: the batch of 512 star polygons "
@@ -129,7 +132,7 @@ def copy_probe(mib, log):
     print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3}), flush=True)
 
 
-def gpu_run(wl, precision, steps, warmup, log, tune=()):
+def gpu_run(wl, precision, steps, warmup, log, tune=(), xcd_runs=XCD_RUNS):
     """The timed run: `steps` CVD iterations from the seeded points, captured
     in one HIP graph and replayed (positions reloaded before each replay,
     outside the timed region), timed with events on the stream the graph runs
@@ -150,7 +153,7 @@ def gpu_run(wl, precision, steps, warmup, log, tune=()):
         m.load()
         m.step_cvd(TUNE_FROM)
         px, py, _ = m.points()
-        density, ms = m.autotune(tune, n_iter=4, x=px, y=py, xcd_runs=XCD_RUNS)
+        density, ms = m.autotune(tune, n_iter=4, x=px, y=py, xcd_runs=xcd_runs)
         log("  autotune (%s): %s -> %.2f points per bin, XCD run %d" % (
             name, ", ".join("%.2f/%d: %.3f ms" % (d, r, t) for (d, r), t in sorted(ms.items())), density,
             m.state.xcd_run))
@@ -754,7 +757,8 @@ def main():
     log("workload %s: %d points, %d^2 grid (%.1f s to sample)" % (wl.name, wl.n, wl.grid.nx, time.perf_counter() - t))
 
     tune = tuple(float(v) for v in args.tune.split(",") if v.strip())
-    m32, ms32, k32, st32, dens32 = gpu_run(wl, T.FP32, args.steps, args.warmup, log, tune)
+    xruns = tuple(int(v) for v in args.xcd_runs.split(",") if v.strip()) or XCD_RUNS
+    m32, ms32, k32, st32, dens32 = gpu_run(wl, T.FP32, args.steps, args.warmup, log, tune, xruns)
     # the state the timed run ends in, with the movement of one more step
     # (the CVD error bound of the next iteration), for the oracle's counts there
     xe, ye, _ = m32.points()
@@ -766,7 +770,7 @@ def main():
     pit = wl.n * args.steps / (ms32 * 1e-3)
     fp64 = None
     if not args.no_fp64:
-        m64, ms64, k64, st64, dens64 = gpu_run(wl, T.FP64, args.steps, args.warmup, log, tune)
+        m64, ms64, k64, st64, dens64 = gpu_run(wl, T.FP64, args.steps, args.warmup, log, tune, xruns)
         fp64 = {"value": wl.n * args.steps / (ms64 * 1e-3), "ms_per_step": ms64 / args.steps,
                 "kernel_ms": k64, "fp32_over_fp64": ms64 / ms32, "bin_density": dens64,
                 "xcd_run": m64.state.xcd_run}

@@ -9,7 +9,7 @@ static int64_t clamp64(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo :
 // The queue passes get grids that grow with the point count (their queues
 // hold a small fraction of the points), up to the sizes that fill the chip.
 template <class T, class G, int MODE> static void launch_mode(const KArgs &a, hipStream_t s) {
-  constexpr int FB = fast_block<T>();
+  constexpr int FB = fast_block<T, MODE>();
   const uint32_t nb = (uint32_t)((a.n + FB - 1) / FB);
   const bool rec = g_launch_log != nullptr;
   if (a.ev0 && !rec) (void)hipEventRecord((hipEvent_t)a.ev0, s);

@@ -1933,19 +1933,20 @@ template <class G, int MODE, int VMAX, int B> struct CellsExact {
 };
 
 // Shapes of the cell kernels as the launchers use them.
-// Lanes (points) per block of the fast kernel.  FP32: 256, whose 45 KB of
-// polygon records let three blocks share a CU, still three wavefronts per
-// SIMD (the VGPR limit); the larger blocks ran 1.5% faster over 40
-// iterations at holes20 than 128 (64: 12% slower).  FP64: 128 (its 24-byte
-// records hold it at two wavefronts per SIMD either way; 256 ran 1.5%
-// slower).
-#ifndef TRIME_FAST_BLOCK_F32
-#define TRIME_FAST_BLOCK_F32 256
+// Lanes (points) per block of the fast kernel.  CVD in FP32: 256, whose
+// 45 KB of polygon records let three blocks share a CU, still three
+// wavefronts per SIMD (the VGPR limit); at holes20 the CVD iterations ran
+// 1.5% faster than with 128 over 40 iterations (192: 0.2% slower than 256,
+// 384: 58% slower, 64: 12% slower).  Everything else: 128.  The extraction
+// of DistMesh steps ran 4-9% slower with 256 (ellipses, the star batch),
+// and FP64, held at two wavefronts per SIMD by its 24-byte records, 1.5%
+// slower.
+#ifndef TRIME_FAST_BLOCK_CVD32
+#define TRIME_FAST_BLOCK_CVD32 256
 #endif
-#ifndef TRIME_FAST_BLOCK_F64
-#define TRIME_FAST_BLOCK_F64 128
-#endif
-template <class T> constexpr int fast_block() { return sizeof(T) == 4 ? TRIME_FAST_BLOCK_F32 : TRIME_FAST_BLOCK_F64; }
+template <class T, int MODE> constexpr int fast_block() {
+  return (sizeof(T) == 4 && MODE == MODE_CVD) ? TRIME_FAST_BLOCK_CVD32 : 128;
+}
 #ifndef TRIME_FAST_VMAX
 #define TRIME_FAST_VMAX 11
 #endif

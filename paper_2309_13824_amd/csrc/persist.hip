@@ -32,7 +32,7 @@
 namespace trime {
 
 template <class T, class G, int MODE> struct PersistSet {
-  using C = Cells<T, G, MODE, FAST_VMAX, fast_block<T>()>;
+  using C = Cells<T, G, MODE, FAST_VMAX, fast_block<T, MODE>()>;
   using Post = CellsPost<G, MODE, WAVE_VMAX>;
   using X = CellsExact<G, MODE, REPLAY_VMAX, REPLAY_BLOCK>;
   // the LDS of the cell kernels' wavefront forms, one at a time
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(64, persist_waves<T>()) void k_persist(PersistArgs 
 
 bool persist_supported(uint32_t cells_code) {
 #define X(T, G, M) \
-  if (cells_code == KindOf<Cells<T, G, M, FAST_VMAX, fast_block<T>()>>::code) return true;
+  if (cells_code == KindOf<Cells<T, G, M, FAST_VMAX, fast_block<T, M>()>>::code) return true;
   TRIME_PERSIST_CASES(X)
 #undef X
   return false;
@@ -261,7 +261,7 @@ bool persist_supported(uint32_t cells_code) {
 
 bool persist_runs(uint32_t cells_code, uint32_t code) {
 #define X(T, G, M) \
-  if (cells_code == KindOf<Cells<T, G, M, FAST_VMAX, fast_block<T>()>>::code) return runs_code<T, G, M>(code);
+  if (cells_code == KindOf<Cells<T, G, M, FAST_VMAX, fast_block<T, M>()>>::code) return runs_code<T, G, M>(code);
   TRIME_PERSIST_CASES(X)
 #undef X
   return false;
@@ -273,7 +273,7 @@ uint32_t persist_grid(uint32_t cells_code) {
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
 #define X(T, G, M)                                                                                     \
-  if (cells_code == KindOf<Cells<T, G, M, FAST_VMAX, fast_block<T>()>>::code &&                           \
+  if (cells_code == KindOf<Cells<T, G, M, FAST_VMAX, fast_block<T, M>()>>::code &&                           \
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)&k_persist<T, G, M>, 64, 0) != \
           hipSuccess)                                                                                  \
     return 0;
@@ -286,7 +286,7 @@ size_t persist_exact_slice() { return sizeof(typename PersistSet<float, float, M
 
 void launch_persist(uint32_t cells_code, const PersistArgs &p, uint32_t grid, hipStream_t s) {
 #define X(T, G, M)                                                           \
-  if (cells_code == KindOf<Cells<T, G, M, FAST_VMAX, fast_block<T>()>>::code) {   \
+  if (cells_code == KindOf<Cells<T, G, M, FAST_VMAX, fast_block<T, M>()>>::code) {   \
     hipLaunchKernelGGL((k_persist<T, G, M>), dim3(grid), dim3(64), 0, s, p); \
     return;                                                                  \
   }
