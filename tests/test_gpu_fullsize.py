@@ -1,6 +1,7 @@
 """Parity at the headline size: the holes20 workload with 10^6 points on its
-4096^2 grid, in the configuration the benchmark times (2 points per bin,
-the fused kernel with its replays), every point and every triangle compared
+4096^2 grid, in the configuration the benchmark times (3.2 points per bin,
+the density its autotuner picks on the current kernels; the fused kernel with
+its replays), every point and every triangle compared
 with the oracle.  The grid is the oracle's, uploaded."""
 import os
 
@@ -43,7 +44,7 @@ def oracle_mesh(orc, full):
 
 def mesher(wl, prec, grid):
     from paper_2309_13824_amd.mesher import Mesher
-    m = Mesher(wl, precision=prec, grid=grid, bin_density=2.0)
+    m = Mesher(wl, precision=prec, grid=grid, bin_density=3.2)
     m.load()
     return m
 
