@@ -634,8 +634,9 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
   // waiting on the lane with the most candidates, so:
   //  - the bins go in groups, ring 0 alone, then SCAN_GROUP bins of a ring
   //    at a time (rings have 8 r bins), and one loop takes the candidates of
-  //    every bin of a group: a trip then waits on the largest group of bins,
-  //    not on the largest bin once per bin;
+  //    every bin of a group: the wavefront makes as many trips as its lane
+  //    with the most candidates in the whole group, instead of, bin by bin,
+  //    as many as the lane with the most in that bin;
   //  - the ranges of the next group's bins are loaded while the current
   //    group's candidates are clipped, and the candidates are loaded two at a
   //    time (four would take the FP32 kernel past the registers of three
