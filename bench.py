@@ -217,15 +217,20 @@ def cpu_info():
     """Model of the host CPU, the cores this process may use, and the
     thread count the oracle's all-core runs take (at most 16: the host's
     share per GPU)."""
-    model = "unknown"
+    # the model name, and the family, model and stepping numbers that tell
+    # apart CPUs a virtual machine reports under a generic name
+    fields = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
+                if not line.strip():
                     break
+                k, _, v = line.partition(":")
+                fields[k.strip()] = v.strip()
     except OSError:
         pass
+    model = fields.get("model name", "unknown")
+    cpu_id = " ".join("%s %s" % (k, fields[k]) for k in ("cpu family", "model", "stepping") if k in fields)
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -235,7 +240,7 @@ def cpu_info():
         phys = psutil.cpu_count(logical=False)
     except Exception:
         phys = None
-    return {"model": model, "cpus_available": avail, "physical_cores_machine": phys,
+    return {"model": model, "cpu_id": cpu_id, "cpus_available": avail, "physical_cores_machine": phys,
             "threads_all": max(1, min(16, avail))}
 
 
@@ -277,8 +282,8 @@ def cpu_baseline(wl, log, bin_density=0.0, end_state=None):
     t = time.perf_counter()
     og = orc.build_grid(wl)
     cats = orc.initial_categories(og, wl.x, wl.y)
-    log("  cpu oracle setup (grid, categories) %.1f s; cpu %s, %d cpus available" % (
-        time.perf_counter() - t, info["model"], info["cpus_available"]))
+    log("  cpu oracle setup (grid, categories) %.1f s; cpu %s (%s), %d cpus available" % (
+        time.perf_counter() - t, info["model"], info["cpu_id"], info["cpus_available"]))
     secs, first, counts0 = oracle_iteration(orc, og, wl.x, wl.y, cats, np.full(wl.n, -1.0), threads)
     log("  cpu oracle, one iteration over %d points: %.2f s on %d threads" % (wl.n, secs, threads))
     counts = {"start": counts0}
@@ -296,7 +301,7 @@ def cpu_baseline(wl, log, bin_density=0.0, end_state=None):
                      "predicates" % wl.n,
            "single_thread": {"value": small.n / secs1, "unit": "point-iterations/s", "cores": 1,
                              "sample": "the same iteration of the same recipe at %d points" % small.n},
-           "cpu_model": info["model"], "cpus_available": info["cpus_available"],
+           "cpu_model": info["model"], "cpu_id": info["cpu_id"], "cpus_available": info["cpus_available"],
            "physical_cores_machine": info["physical_cores_machine"]}
     return cpu, counts, position_error(wl, og, first[:3], bin_density, log)
 

@@ -52,3 +52,14 @@ def test_algorithmic_bytes_per_point():
     read in the cell scan (4 bytes per point)."""
     assert bench.BYTES_PER_POINT["fp64"] - bench.BYTES_PER_POINT["fp32"] == 4
     assert bench.BYTES_PER_POINT["fp32"] == 218
+
+
+def test_cpu_info_names_the_host():
+    """The CPU baseline records the model name and, where /proc/cpuinfo has
+    them, the family, model and stepping numbers."""
+    info = bench.cpu_info()
+    assert info["model"]
+    assert 1 <= info["threads_all"] <= 16
+    assert info["threads_all"] <= info["cpus_available"]
+    if os.path.exists("/proc/cpuinfo"):
+        assert "cpu family" in info["cpu_id"] or info["cpu_id"] == ""
