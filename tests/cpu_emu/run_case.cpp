@@ -6,12 +6,18 @@
 //
 //   run_case IN OUT
 // IN: int64 n; int32 nx, ny; double x0, y0, dx, dy; int32 dtype_bytes,
-//     precision; double bin_density; int32 iters, method (1 CVD, 0 DM);
+//     precision; double bin_density; int32 iters, method (1 CVD, 0 DM,
+//     2 and 3 the persistent batch, 4 one binning, the cells and one
+//     extraction with their exports);
 //     then sdf and mu (nx ny values of dtype), cat ((nx-1)(ny-1) bytes),
 //     hcell ((nx-1)(ny-1) float), the scalars (4 doubles: H, h_avg,
 //     area_sel, n_sel), x and y (n doubles each).
 // OUT: per iteration x, y (n doubles each) and cat (n bytes) by id, then the
 //     trime_stats struct and the largest queue counts seen (3 int64).
+//     Method 4 writes instead: the cells (ncons, n int32; cons, n * 64
+//     int32), the triangle count (int64), the triangles (3 * count int32) and
+//     their validity (count bytes), max_deg (int32), the adjacency (deg, n
+//     int32; col, n * max_deg int32), then the stats and queue counts.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -249,9 +255,34 @@ int main(int argc, char **argv) {
   double *ex = (double *)alloc(8 * n), *ey = (double *)alloc(8 * n);
   uint8_t *ec = (uint8_t *)alloc(n);
   OK(trime_state_load(&S, x, y, nullptr));
-  if (method >= 2) return run_persistent(method == 3, iters, argv[2], n, x, y, prec, dens, nx, ny, x0, y0, dx, dy,
+  if (method == 2 || method == 3) return run_persistent(method == 3, iters, argv[2], n, x, y, prec, dens, nx, ny, x0, y0, dx, dy,
                                          dtb, sdf, mu, cat, hcell, scal);
   FILE *out = fopen(argv[2], "wb");
+  if (method == 4) {
+    const int32_t cap = 64;
+    int32_t *cons = (int32_t *)alloc(4 * (size_t)n * cap), *ncons = (int32_t *)alloc(4 * n);
+    const trime_cells cells = {cap, cons, ncons};
+    OK(trime_bin_points(&S, nullptr));
+    OK(trime_voronoi_cells(&S, &cells, nullptr));
+    OK(trime_delaunay_extract(&S, nullptr));
+    const int64_t tcap = (int64_t)n * TRIME_TRI_PER_POINT;
+    int32_t *tri = (int32_t *)alloc(12 * tcap);
+    uint8_t *valid = (uint8_t *)alloc(tcap);
+    int64_t *count = (int64_t *)alloc(8);
+    OK(trime_export_triangles(&S, tri, valid, tcap, count, nullptr));
+    const int32_t md = S.max_deg;
+    int32_t *deg = (int32_t *)alloc(4 * n), *col = (int32_t *)alloc(4 * (size_t)n * md);
+    OK(trime_export_adjacency(&S, deg, col, nullptr));
+    fwrite(ncons, 4, n, out);
+    fwrite(cons, 4, (size_t)n * cap, out);
+    fwrite(count, 8, 1, out);
+    fwrite(tri, 4, 3 * (size_t)*count, out);
+    fwrite(valid, 1, (size_t)*count, out);
+    fwrite(&md, 4, 1, out);
+    fwrite(deg, 4, n, out);
+    fwrite(col, 4, (size_t)n * md, out);
+    iters = 0;
+  }
   for (int it = 0; it < iters; it++) {
     if (method == 1)
       OK(trime_step_cvd(&S, 1, nullptr));

@@ -112,6 +112,67 @@ def test_emulated_cvd_iterations(orc, exe, tmp_path, prec):
     check(its, oracle_iterations(orc, og, wl, 2), og, prec)
 
 
+def run_method(exe, tmp_path, wl, og, prec, method, iters=1):
+    cin, cout = str(tmp_path / "case.bin"), str(tmp_path / "out.bin")
+    write_case(cin, wl, og, prec, 3.3, iters, method=method)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([exe, cin, cout], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True,
+                       timeout=600, env=env)
+    assert r.returncode == 0, r.stdout[-6000:]
+    return open(cout, "rb").read()
+
+
+def parse_cells_and_mesh(raw, n):
+    """Method 4's output: cells by id, the triangles with validity, the
+    adjacency rows by id, then the stats."""
+    from paper_2309_13824_amd import trime as T
+    cap, off = 64, 0
+    ncons = np.frombuffer(raw, np.int32, n, off); off += 4 * n
+    cons = np.frombuffer(raw, np.int32, n * cap, off).reshape(n, cap); off += 4 * n * cap
+    cnt = int(np.frombuffer(raw, np.int64, 1, off)[0]); off += 8
+    tri = np.frombuffer(raw, np.int32, 3 * cnt, off).reshape(cnt, 3); off += 12 * cnt
+    valid = np.frombuffer(raw, np.uint8, cnt, off); off += cnt
+    md = int(np.frombuffer(raw, np.int32, 1, off)[0]); off += 4
+    deg = np.frombuffer(raw, np.int32, n, off); off += 4 * n
+    col = np.frombuffer(raw, np.int32, n * md, off).reshape(n, md); off += 4 * n * md
+    st = T.Stats.from_buffer_copy(raw[off:off + C_sizeof(T.Stats)])
+    cells = [tuple(int(v) for v in cons[i, :ncons[i]]) if ncons[i] >= 0 else None for i in range(n)]
+    tris = {(tuple(int(v) for v in t), int(f)) for t, f in zip(tri, valid)}
+    rows = [tuple(int(v) for v in col[i, :deg[i]]) for i in range(n)]
+    return cells, tris, rows, st
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_emulated_tiny_inputs(orc, exe, tmp_path, n, prec):
+    """One to five points in a box (every cell reaches the box, so every
+    point takes the FP64 replay): the cells, the triangles with validity and
+    the adjacency after one binning and extraction, two CVD iterations and
+    one DistMesh step, each against the oracle, with no sanitizer report and
+    the queues within capacity."""
+    wl = I.random_box(n, seed=5 + n)
+    og = orc.build_grid(wl)
+    cells, tris, rows, st = parse_cells_and_mesh(run_method(exe, tmp_path, wl, og, prec, 4), n)
+    assert st.error == 0
+    ref_cells, _ = orc.cells(og, wl.x, wl.y)
+    assert cells == ref_cells
+    ref = orc.triangulate(og, wl.x, wl.y)
+    assert tris == {(tuple(int(v) for v in t), int(f)) for t, f in zip(ref.tri, ref.valid)}
+    assert rows == [tuple(int(v) for v in ref.col[ref.rowptr[i]:ref.rowptr[i + 1]]) for i in range(n)]
+    its, st, _ = run(exe, tmp_path, wl, og, prec, 3.3, 2)
+    assert st.error == 0
+    check(its, oracle_iterations(orc, og, wl, 2), og, prec)
+    raw = run_method(exe, tmp_path, wl, og, prec, 0)
+    x, y, c = (np.frombuffer(raw, np.float64, n, 0), np.frombuffer(raw, np.float64, n, 8 * n),
+               np.frombuffer(raw, np.uint8, n, 16 * n))
+    cat0 = orc.initial_categories(og, wl.x, wl.y)
+    xr, yr, cr, _, _, _ = orc.dm_step(og, wl.x, wl.y, cat0, ref)
+    err = np.hypot(x - xr, y - yr) / h_of(og, xr, yr)
+    assert err.max() <= (1e-12 if prec == FP64 else 1e-5), err.max()
+    assert np.array_equal(c, cr)
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("prec", [FP64, FP32])
 @pytest.mark.parametrize("density", [3.3, 1.5, 7.0])

@@ -118,6 +118,45 @@ def test_duplicate_points_empty_cell(orc, T):
     assert got[17] == () and len(got[5]) > 0
 
 
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_tiny_inputs_match_oracle(orc, T, n, prec):
+    """One to five points in a box: every cell reaches the box, so every
+    point takes the FP64 replay; one point has the whole box as its cell and
+    two points have no triangle.  Cells, triangles with validity and
+    adjacency after one binning and extraction, one CVD step and one
+    DistMesh step, each against the oracle."""
+    wl = I.random_box(n, seed=5 + n)
+    og = orc.build_grid(wl)
+    print("tiny input: %d points, %s" % (n, "fp64" if prec == FP64 else "fp32"), flush=True)
+    m = mesher(wl, prec, grid=og)
+    m.bin()
+    ref_cells, _ = orc.cells(og, wl.x, wl.y)
+    assert m.cells() == ref_cells
+    m.extract()
+    tri, valid = m.triangles()
+    ref = orc.triangulate(og, wl.x, wl.y)
+    assert tri_set(tri, valid) == tri_set(ref.tri, ref.valid)
+    assert m.adjacency() == [tuple(int(v) for v in ref.col[ref.rowptr[i]:ref.rowptr[i + 1]]) for i in range(n)]
+    assert_no_error(m)
+    cat0 = orc.initial_categories(og, wl.x, wl.y)
+    m = mesher(wl, prec, grid=og)
+    m.step_cvd(1)
+    x, y, cat = m.points()
+    xr, yr, cr, _, _, _ = orc.cvd_step(og, wl.x, wl.y, cat0, np.full(n, -1.0), nthreads=1)
+    assert (np.hypot(x - xr, y - yr) / h_of(og, xr, yr)).max() <= _tol(prec)
+    assert np.array_equal(cat, cr)
+    assert_no_error(m)
+    m = mesher(wl, prec, grid=og)
+    m.step_dm(1, fresh=True, always=True)
+    x, y, cat = m.points()
+    xr, yr, cr, moved, _, _ = orc.dm_step(og, wl.x, wl.y, cat0, ref)
+    assert (np.hypot(x - xr, y - yr) / h_of(og, xr, yr)).max() <= _tol(prec)
+    assert np.array_equal(cat, cr)
+    assert m.stats()["moved"] == moved
+    assert_no_error(m)
+
+
 # -------------------------------------------------------------- extraction --
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
