@@ -238,7 +238,7 @@ typedef struct {
    by trime_state_bind in one caller-allocated workspace. */
 typedef struct {
   /* -- configuration (caller) -- */
-  int64_t n;               /* number of points                               */
+  int64_t n;               /* number of points, 1 .. 2^30                    */
   int32_t precision;       /* TRIME_FP64 or TRIME_FP32                       */
   int32_t max_deg;         /* adjacency row capacity (0 -> 16)               */
   double bin_density;      /* mean points per bin (0 -> 3.3, Sec. 6 example) */
@@ -365,7 +365,9 @@ trime_status trime_sdf_grid_build_noalloc(const trime_geometry *g, const trime_s
                                           void *d_mu, uint8_t *d_cat, float *d_hcell,
                                           trime_grid_scalars *d_scal, void *stream);
 
-/* Size of the device workspace of a configured state (bytes, 256-aligned). */
+/* Size of the device workspace of a configured state (bytes, 256-aligned).
+   TRIME_EINVAL for n outside 1 .. 2^30, a bad precision or grid, or missing
+   grid arrays; reads the grid scalars from the device. */
 trime_status trime_state_workspace_bytes(const trime_state *st, size_t *bytes);
 /* Lays the state's buffers out in d_ws (>= workspace bytes).  Synchronous:
    reads the grid scalars from the device. */

@@ -69,9 +69,11 @@ def test_null_and_bad_arguments_rejected_on_host(T):
     st.sdf = st.mu = st.cat_grid = st.hcell = st.scal = 256
     assert L.trime_step_cvd(C.byref(st), 1, None) == 1
     assert L.trime_bin_points(C.byref(st), None) == 1
-    # negative n
-    st.n = -5
-    assert L.trime_state_workspace_bytes(C.byref(st), C.byref(b)) == 1
+    # negative, zero and too large n (at most 2^30 points)
+    for n in (-5, 0, (1 << 30) + 1):
+        st.n = n
+        assert L.trime_state_workspace_bytes(C.byref(st), C.byref(b)) == 1
+        assert b"bad n" in L.trime_last_error()
     # bad precision
     st.n = 10
     st.precision = 7
