@@ -629,9 +629,12 @@ void orc_quality(const double *x, const double *y, const int32_t *tri, const uin
     sb += sqrt(be);
     sq += 1.0 / al;
     if (al > amax) amax = al;
-    int bin = (int)floor((be - 1.0) / 2.0 * 40.0);
-    if (bin < 0) bin = 0;
-    if (bin > 39) bin = 39;
+    /* 40 bins of width 0.05 from beta = 1, the last one open; the bin is
+       chosen before converting, since beta has no upper bound (a valid
+       triangle can have an edge many orders shorter than the others) */
+    double fb = floor((be - 1.0) / 2.0 * 40.0);
+    int bin = 39;
+    if (fb < 39.0) bin = fb > 0.0 ? (int)fb : 0;
     st->hist_beta[bin] += 1.0;
     cnt++;
   }

@@ -54,6 +54,22 @@ def test_quality_statistics_closed_forms(orc):
     assert np.allclose(h, ref, rtol=0, atol=1e-15)
 
 
+@pytest.mark.parametrize("edge", [1e-3, 1e-9, 1e-13])
+def test_quality_histogram_last_bin_holds_any_large_beta(orc, edge):
+    """A valid triangle with one edge far shorter than the others: beta =
+    longest / shortest edge is ~1e3, ~1e9 or ~1e13, beyond the range of an
+    int once scaled to a bin index, and still counts in the open last bin."""
+    x = np.array([0.0, edge, 0.5])
+    y = np.array([0.0, 0.0, 1.0])
+    tri = np.array([[0, 1, 2]], np.int32)
+    q = orc.quality(x, y, tri, np.array([1], np.uint8))
+    beta = math.hypot(0.5, 1.0) / edge
+    assert q["half_mean_beta"] == pytest.approx(beta, rel=1e-9)
+    ref = np.zeros(40)
+    ref[39] = 1.0
+    assert np.array_equal(q["hist_beta"], ref)
+
+
 def test_quality_half_mean_between_mean_and_geometric_mean(orc):
     """M_1/2 of Eq. 11 lies between the geometric and the arithmetic mean
     (power-mean inequality), equal to both only for equal values."""
