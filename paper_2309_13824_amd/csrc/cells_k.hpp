@@ -1134,8 +1134,7 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
     st.sq += 1.0 / al;
     st.amax = fmax(st.amax, al);
     st.nq++;
-    int bin = (int)floor((be - 1.0) / 2.0 * 40.0);
-    bin = bin < 0 ? 0 : (bin > 39 ? 39 : bin);
+    const int bin = beta_bin(be);
     atomicAdd(&hist[bin], 1);
   }
 
@@ -1546,8 +1545,7 @@ template <class T, class G, int MODE, bool EXACT, int VMAX, int BLOCK> struct La
           st.sq += 1.0 / al;
           st.amax = fmax(st.amax, al);
           st.nq++;
-          int bin = (int)floor((be - 1.0) / 2.0 * 40.0);
-          bin = bin < 0 ? 0 : (bin > 39 ? 39 : bin);
+          const int bin = beta_bin(be);
           atomicAdd(&hist[bin], 1);
         }
       }

@@ -155,8 +155,7 @@ __global__ __launch_bounds__(256) void k_quality(KArgs a) {
       sq += 1.0 / al;
       amax = fmax(amax, al);
       nq++;
-      int bin = (int)floor((be - 1.0) / 2.0 * 40.0);
-      bin = bin < 0 ? 0 : (bin > 39 ? 39 : bin);
+      const int bin = beta_bin(be);
       atomicAdd(&hist[bin], 1);
     }
   }

@@ -222,6 +222,15 @@ template <class G> TRIME_D double gval(const void *p, int64_t k) {
 // its result to the grid (one conversion instead of the 64-bit sequence).
 template <class V> TRIME_D int sat_int(V v) { return (int)fmin(fmax(v, (V)-16777216.0), (V)16777216.0); }
 
+// Bin of beta in the quality histogram (Eq. 11): 40 bins of width 0.05 from
+// beta = 1, the last one open (beta >= 2.95, and the infinite or undefined
+// beta of a triangle with a zero edge).  The bin is picked in floating point
+// before the conversion, so a beta of any size converts in range.
+TRIME_D int beta_bin(double be) {
+  const double f = floor((be - 1.0) / 2.0 * 40.0);
+  return f < 39.0 ? (f > 0.0 ? (int)f : 0) : 39;
+}
+
 // A grid cell by column i and row j; the cell arrays hold cell (i, j) at
 // j (nx - 1) + i, the node arrays its lower-left node at j nx + i.
 struct GCell {

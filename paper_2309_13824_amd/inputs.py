@@ -438,4 +438,28 @@ def random_box(n: int = 30, seed: int = 7, grid_n: int = 64, lo: float = 0.0, hi
     return wl
 
 
+def degenerate(kind: str) -> Workload:
+    """Small point sets in the unit box that the exact predicates must
+    settle: "collinear" (six points on one horizontal line, no triangle),
+    "coincident" (four copies of one point: one takes the whole box, the
+    others have empty cells), "near" (three points 1e-13 apart plus two far
+    ones: triangles with beta near 1e12)."""
+    if kind == "collinear":
+        wl = random_box(6, seed=3)
+        wl.x[:] = [0.1, 0.3, 0.5, 0.7, 0.9, 0.2]
+        wl.y[:] = 0.5
+    elif kind == "coincident":
+        wl = random_box(4, seed=3)
+        wl.x[:] = 0.37
+        wl.y[:] = 0.61
+    elif kind == "near":
+        wl = random_box(5, seed=3)
+        wl.x[:] = [0.5, 0.5 + 1e-13, 0.5, 0.2, 0.8]
+        wl.y[:] = [0.5, 0.5, 0.5 + 1e-13, 0.3, 0.7]
+    else:
+        raise ValueError("unknown degenerate case %r" % kind)
+    wl.name = "degenerate_" + kind
+    return wl
+
+
 WORKLOADS = {"disk": disk, "annulus": annulus, "holes20": holes20, "ellipses": ellipses}

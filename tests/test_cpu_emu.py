@@ -143,15 +143,24 @@ def parse_cells_and_mesh(raw, n):
     return cells, tris, rows, st
 
 
+TINY = [1, 2, 3, 5, "collinear", "coincident", "near"]
+
+
+def tiny_workload(case):
+    return I.random_box(case, seed=5 + case) if isinstance(case, int) else I.degenerate(case)
+
+
 @pytest.mark.parametrize("prec", [FP64, FP32])
-@pytest.mark.parametrize("n", [1, 2, 3, 5])
-def test_emulated_tiny_inputs(orc, exe, tmp_path, n, prec):
-    """One to five points in a box (every cell reaches the box, so every
-    point takes the FP64 replay): the cells, the triangles with validity and
-    the adjacency after one binning and extraction, two CVD iterations and
-    one DistMesh step, each against the oracle, with no sanitizer report and
-    the queues within capacity."""
-    wl = I.random_box(n, seed=5 + n)
+@pytest.mark.parametrize("case", TINY)
+def test_emulated_tiny_inputs(orc, exe, tmp_path, case, prec):
+    """One to five points in a box, and the degenerate sets (collinear,
+    coincident, 1e-13 apart); every cell reaches the box, so every point
+    takes the FP64 replay.  The cells, the triangles with validity and the
+    adjacency after one binning and extraction, two CVD iterations and one
+    DistMesh step, each against the oracle, with no sanitizer report and the
+    queues within capacity."""
+    wl = tiny_workload(case)
+    n = wl.n
     og = orc.build_grid(wl)
     cells, tris, rows, st = parse_cells_and_mesh(run_method(exe, tmp_path, wl, og, prec, 4), n)
     assert st.error == 0
@@ -160,6 +169,8 @@ def test_emulated_tiny_inputs(orc, exe, tmp_path, n, prec):
     ref = orc.triangulate(og, wl.x, wl.y)
     assert tris == {(tuple(int(v) for v in t), int(f)) for t, f in zip(ref.tri, ref.valid)}
     assert rows == [tuple(int(v) for v in ref.col[ref.rowptr[i]:ref.rowptr[i + 1]]) for i in range(n)]
+    q = orc.quality(wl.x, wl.y, ref.tri, ref.valid)
+    assert np.array_equal(st.as_dict()["hist_beta"], np.round(q["hist_beta"] * q["ntri"]).astype(np.int64))
     its, st, _ = run(exe, tmp_path, wl, og, prec, 3.3, 2)
     assert st.error == 0
     check(its, oracle_iterations(orc, og, wl, 2), og, prec)

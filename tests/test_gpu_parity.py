@@ -119,16 +119,18 @@ def test_duplicate_points_empty_cell(orc, T):
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
-@pytest.mark.parametrize("n", [1, 2, 3, 5])
-def test_tiny_inputs_match_oracle(orc, T, n, prec):
-    """One to five points in a box: every cell reaches the box, so every
-    point takes the FP64 replay; one point has the whole box as its cell and
-    two points have no triangle.  Cells, triangles with validity and
-    adjacency after one binning and extraction, one CVD step and one
-    DistMesh step, each against the oracle."""
-    wl = I.random_box(n, seed=5 + n)
+@pytest.mark.parametrize("case", [1, 2, 3, 5, "collinear", "coincident", "near"])
+def test_tiny_inputs_match_oracle(orc, T, case, prec):
+    """One to five points in a box, and the degenerate sets (collinear,
+    coincident, 1e-13 apart): every cell reaches the box, so every point
+    takes the FP64 replay; one point has the whole box as its cell and two
+    points have no triangle.  Cells, triangles with validity and adjacency
+    after one binning and extraction, one CVD step and one DistMesh step,
+    each against the oracle."""
+    wl = I.random_box(case, seed=5 + case) if isinstance(case, int) else I.degenerate(case)
+    n = wl.n
     og = orc.build_grid(wl)
-    print("tiny input: %d points, %s" % (n, "fp64" if prec == FP64 else "fp32"), flush=True)
+    print("tiny input: %s, %d points, %s" % (wl.name, n, "fp64" if prec == FP64 else "fp32"), flush=True)
     m = mesher(wl, prec, grid=og)
     m.bin()
     ref_cells, _ = orc.cells(og, wl.x, wl.y)
@@ -138,6 +140,8 @@ def test_tiny_inputs_match_oracle(orc, T, n, prec):
     ref = orc.triangulate(og, wl.x, wl.y)
     assert tri_set(tri, valid) == tri_set(ref.tri, ref.valid)
     assert m.adjacency() == [tuple(int(v) for v in ref.col[ref.rowptr[i]:ref.rowptr[i + 1]]) for i in range(n)]
+    q = orc.quality(wl.x, wl.y, ref.tri, ref.valid)
+    assert np.array_equal(m.stats()["hist_beta"], np.round(q["hist_beta"] * q["ntri"]).astype(np.int64))
     assert_no_error(m)
     cat0 = orc.initial_categories(og, wl.x, wl.y)
     m = mesher(wl, prec, grid=og)
