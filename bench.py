@@ -58,7 +58,7 @@ BYTES_PER_POINT = {"fp32": 16 + 101 + 64 + 37, "fp64": 20 + 101 + 64 + 37}
 # WRITE_SIZE (the mean of its last two launches in a short run: the timed
 # CVD iteration 2 and the next one; scaled by a 1 GiB copy: FETCH x 2.0,
 # WRITE x 1.0), valid for the kernel sources with this digest only.
-TRAFFIC = {"sha1": "e2cae13b6c59519b27877b89042404962d07fb5a", "bytes_per_launch": 437379257.3}
+TRAFFIC = {"sha1": "63db500238238aecf79a8ff6a761f832047ad13e", "bytes_per_launch": 437414752.9}
 # counted flops per point of the DistMesh force gather (edge forces over the
 # adjacency row, forward Euler, treatment checks)
 DM_FLOPS_PER_POINT = 150
