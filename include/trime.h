@@ -374,7 +374,9 @@ trime_status trime_state_workspace_bytes(const trime_state *st, size_t *bytes);
 trime_status trime_state_bind(trime_state *st, void *d_ws, size_t bytes, void *stream);
 /* Copies positions (device, by id) into the state (slot = id until the first
    binning), sets categories (Sec. 3.5), d_prev = -1 (the first CVD
-   iteration uses h) and clears the stats. */
+   iteration uses h) and clears the stats.  Positions belong inside the
+   grid's box: a point outside it has no cell, is kept where it is by every
+   step, and sets trime_stats.error. */
 trime_status trime_state_load(trime_state *st, const double *d_x, const double *d_y, void *stream);
 /* Current positions and categories, scattered back to id order (device). */
 trime_status trime_export_points(const trime_state *st, double *d_x, double *d_y, uint8_t *d_cat,

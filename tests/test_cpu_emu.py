@@ -184,6 +184,34 @@ def test_emulated_tiny_inputs(orc, exe, tmp_path, case, prec):
     assert np.array_equal(c, cr)
 
 
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("method", [1, 0, 4])
+def test_emulated_points_off_the_grid(orc, exe, tmp_path, method, prec):
+    """Two points outside the grid's box (one just below it, one far away)
+    among 600 disk points: a CVD step, a DistMesh step, and the cells and
+    extraction run with no sanitizer report and the queues within capacity;
+    the two points keep their positions and the stats carry the error."""
+    wl = I.disk(n=600)
+    wl.x[2], wl.y[2] = 0.0, -1.25
+    wl.x[3], wl.y[3] = 5.0, 7.0
+    og = orc.build_grid(wl)
+    raw = run_method(exe, tmp_path, wl, og, prec, method)
+    n = wl.n
+    if method == 4:
+        st = parse_cells_and_mesh(raw, n)[3]
+    else:
+        x, y = np.frombuffer(raw, np.float64, n, 0), np.frombuffer(raw, np.float64, n, 8 * n)
+        assert (x[2], y[2], x[3], y[3]) == (0.0, -1.25, 5.0, 7.0)
+        assert np.all(np.isfinite(x)) and np.all(np.isfinite(y))
+        st = T_stats(raw[17 * n:])
+    assert st.error != 0
+
+
+def T_stats(raw):
+    from paper_2309_13824_amd import trime as T
+    return T.Stats.from_buffer_copy(raw[:C_sizeof(T.Stats)])
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("prec", [FP64, FP32])
 @pytest.mark.parametrize("density", [3.3, 1.5, 7.0])

@@ -161,6 +161,34 @@ def test_tiny_inputs_match_oracle(orc, T, case, prec):
     assert_no_error(m)
 
 
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_points_off_the_grid_are_kept_and_flagged(orc, T, prec):
+    """Two points outside the grid's box among 600 disk points: a CVD step
+    and a DistMesh step keep them where they are, every other position stays
+    finite, and the stats carry the error; the cells and extraction flag it
+    as well (the same cases run in the CPU emulation under the sanitizers)."""
+    wl = I.disk(n=600)
+    wl.x[2], wl.y[2] = 0.0, -1.25
+    wl.x[3], wl.y[3] = 5.0, 7.0
+    og = orc.build_grid(wl)
+    print("off-grid points, %s" % ("fp64" if prec == FP64 else "fp32"), flush=True)
+    for step in ("cvd", "dm"):
+        m = mesher(wl, prec, grid=og)
+        if step == "cvd":
+            m.step_cvd(1)
+        else:
+            m.step_dm(1, fresh=True, always=True)
+        x, y, _ = m.points()
+        assert (x[2], y[2], x[3], y[3]) == (0.0, -1.25, 5.0, 7.0)
+        assert np.all(np.isfinite(x)) and np.all(np.isfinite(y))
+        assert m.stats_raw().error != 0
+    m = mesher(wl, prec, grid=og)
+    m.bin()
+    m.cells()
+    m.extract()
+    assert m.stats_raw().error != 0
+
+
 # -------------------------------------------------------------- extraction --
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
