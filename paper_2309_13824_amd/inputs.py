@@ -443,7 +443,8 @@ def degenerate(kind: str) -> Workload:
     settle: "collinear" (six points on one horizontal line, no triangle),
     "coincident" (four copies of one point: one takes the whole box, the
     others have empty cells), "near" (three points 1e-13 apart plus two far
-    ones: triangles with beta near 1e12)."""
+    ones: triangles with beta near 1e12), "disk_ties" (disk points on the
+    boundary circle, on grid nodes and on an exact lattice block)."""
     if kind == "collinear":
         wl = random_box(6, seed=3)
         wl.x[:] = [0.1, 0.3, 0.5, 0.7, 0.9, 0.2]
@@ -456,6 +457,17 @@ def degenerate(kind: str) -> Workload:
         wl = random_box(5, seed=3)
         wl.x[:] = [0.5, 0.5 + 1e-13, 0.5, 0.2, 0.8]
         wl.y[:] = [0.5, 0.5, 0.5 + 1e-13, 0.3, 0.7]
+    elif kind == "disk_ties":
+        # 600 disk points, four of them exactly on the circle, two on grid
+        # nodes, and an exact 4 x 4 lattice block (cocircular quadruples)
+        wl = disk(n=600)
+        g = wl.grid
+        wl.x[:4] = [1.0, 0.0, -1.0, 0.0]
+        wl.y[:4] = [0.0, 1.0, 0.0, -1.0]
+        wl.x[4], wl.y[4] = g.x0 + 100 * g.dx, g.y0 + 120 * g.dy
+        wl.x[5], wl.y[5] = g.x0 + 101 * g.dx, g.y0 + 120 * g.dy
+        wl.x[6:22] = 0.3 + 0.01 * np.repeat(np.arange(4), 4)
+        wl.y[6:22] = 0.2 + 0.01 * np.tile(np.arange(4), 4)
     else:
         raise ValueError("unknown degenerate case %r" % kind)
     wl.name = "degenerate_" + kind

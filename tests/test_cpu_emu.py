@@ -143,7 +143,7 @@ def parse_cells_and_mesh(raw, n):
     return cells, tris, rows, st
 
 
-TINY = [1, 2, 3, 5, "collinear", "coincident", "near"]
+TINY = [1, 2, 3, 5, "collinear", "coincident", "near", "disk_ties"]
 
 
 def tiny_workload(case):
@@ -153,9 +153,9 @@ def tiny_workload(case):
 @pytest.mark.parametrize("prec", [FP64, FP32])
 @pytest.mark.parametrize("case", TINY)
 def test_emulated_tiny_inputs(orc, exe, tmp_path, case, prec):
-    """One to five points in a box, and the degenerate sets (collinear,
-    coincident, 1e-13 apart); every cell reaches the box, so every point
-    takes the FP64 replay.  The cells, the triangles with validity and the
+    """One to five points in a box, the degenerate sets (collinear,
+    coincident, 1e-13 apart), and 600 disk points with some on the boundary
+    circle, on grid nodes and on a lattice block (exact-stage ties).  The cells, the triangles with validity and the
     adjacency after one binning and extraction, two CVD iterations and one
     DistMesh step, each against the oracle, with no sanitizer report and the
     queues within capacity."""

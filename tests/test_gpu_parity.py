@@ -119,12 +119,14 @@ def test_duplicate_points_empty_cell(orc, T):
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
-@pytest.mark.parametrize("case", [1, 2, 3, 5, "collinear", "coincident", "near"])
+@pytest.mark.parametrize("case", [1, 2, 3, 5, "collinear", "coincident", "near", "disk_ties"])
 def test_tiny_inputs_match_oracle(orc, T, case, prec):
-    """One to five points in a box, and the degenerate sets (collinear,
-    coincident, 1e-13 apart): every cell reaches the box, so every point
-    takes the FP64 replay; one point has the whole box as its cell and two
-    points have no triangle.  Cells, triangles with validity and adjacency
+    """One to five points in a box, the degenerate sets (collinear,
+    coincident, 1e-13 apart), and 600 disk points with some on the boundary
+    circle, on grid nodes and on a lattice block (exact-stage ties).  In the
+    small sets every cell reaches the box, so every point takes the FP64
+    replay; one point has the whole box as its cell and two points have no
+    triangle.  Cells, triangles with validity and adjacency
     after one binning and extraction, one CVD step and one DistMesh step,
     each against the oracle."""
     wl = I.random_box(case, seed=5 + case) if isinstance(case, int) else I.degenerate(case)
