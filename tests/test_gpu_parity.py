@@ -163,6 +163,23 @@ def test_tiny_inputs_match_oracle(orc, T, case, prec):
     assert_no_error(m)
 
 
+@pytest.mark.parametrize("cap", [4, 5, 6])
+def test_cells_beyond_the_output_capacity(orc, T, cap):
+    """trime_cells with room for cap constraints per point: a cell with more
+    reports -1 and writes nothing, the others equal the oracle's."""
+    wl = I.random_box(300, seed=21)
+    og = orc.build_grid(wl)
+    m = mesher(wl, FP32, grid=og)
+    m.bin()
+    got = m.cells(cap=cap)
+    ref, _ = orc.cells(og, wl.x, wl.y)
+    over = [i for i in range(wl.n) if len(ref[i]) > cap]
+    assert 0 < len(over) < wl.n
+    for i in range(wl.n):
+        assert got[i] == (None if len(ref[i]) > cap else ref[i]), i
+    assert_no_error(m)
+
+
 @pytest.mark.parametrize("prec", [FP64, FP32])
 def test_points_off_the_grid_are_kept_and_flagged(orc, T, prec):
     """Two points outside the grid's box among 600 disk points: a CVD step
