@@ -181,6 +181,27 @@ def test_cells_beyond_the_output_capacity(orc, T, cap):
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
+def test_adjacency_rows_beyond_max_deg(orc, T, prec):
+    """An adjacency capacity of 4 neighbours, below what most points have:
+    the extraction flags the degree overflow, and each row holds
+    min(degree, 4) of the oracle's neighbours of that point."""
+    wl = I.random_box(300, seed=21)
+    og = orc.build_grid(wl)
+    m = mesher(wl, prec, grid=og, max_deg=4)
+    m.bin()
+    m.extract()
+    rows = m.adjacency()
+    ref = orc.triangulate(og, wl.x, wl.y)
+    full = [set(int(v) for v in ref.col[ref.rowptr[i]:ref.rowptr[i + 1]]) for i in range(wl.n)]
+    assert any(len(f) > 4 for f in full)
+    for i in range(wl.n):
+        assert len(rows[i]) == min(len(full[i]), 4), i
+        assert set(rows[i]) <= full[i], i
+        assert list(rows[i]) == sorted(rows[i]), i
+    assert m.stats_raw().error & 2
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
 def test_points_off_the_grid_are_kept_and_flagged(orc, T, prec):
     """Two points outside the grid's box among 600 disk points: a CVD step
     and a DistMesh step keep them where they are, every other position stays
